@@ -1,0 +1,166 @@
+#!/usr/bin/env python3
+"""Benchmark of adaptive image ray-tracing on one MI355X.
+
+Workload (the uniform colliding-winds case): 256^3 float32 field with two
+wind sources and a shocked shell (seed 0), j = rho^2 T^0.5, kappa =
+rho T^-1.5; 64x64 coarse image, 5 refinement levels (2048^2 effective),
+xi_crit = 0.5, three views (+z, +x, (1,1,1)/sqrt3).  One step = plain AIR of
+the three views in one call: march every level, refinement test, 2:1
+closure, compaction, canonical quadtree, raster assembly and float64 flux.
+Beside it: the fixed 2048^2 image of the same views.
+
+Prints one JSON line.  `value` is plain-AIR rays/s over the whole job (all
+tree nodes traced, inputs resident in HBM, host overhead included)."""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "rays/s & per-image time: learned AIR vs plain AIR vs fixed-res, 1 GPU"
+HBM_PEAK_GBS = 8000.0
+N0, LMAX, XI_CRIT, SEED, NGRID = 64, 5, 0.5, 0, 256
+# algorithmic bytes of the march: per (ray, cell) visit the three float32
+# field values; per ray its queue entry (8 B) and results (I, N, visits: 12 B,
+# state byte)
+BYTES_PER_VISIT = 12
+BYTES_PER_RAY_QUEUE = 8 + 12 + 1
+BYTES_PER_RAY_FIXED = 8  # I and N written to the raster
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def traffic_from_profile(kernel):
+    """HBM bytes per launch from the committed counter summary, if it was
+    taken on the current kernel source (else None)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "march_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = open(os.path.join(ROOT, "paper_1010_5534_amd", "csrc", "march.hip"), "rb").read()
+    if rec.get("source_sha256") != hashlib.sha256(src).hexdigest():
+        return None
+    return rec.get(kernel)
+
+
+def cpu_baseline(g, f, views):
+    """The FP64 oracle on the host cores: plain AIR of the same three views."""
+    import oracle
+    oracle.lib()
+    t = time.perf_counter()
+    nodes = 0
+    for v in views:
+        nodes += oracle.air(g, f, v, N0, LMAX, XI_CRIT).nodes
+    dt = time.perf_counter() - t
+    return dict(value=nodes / dt, unit="rays/s", cores=oracle.num_threads(), kind="oracle",
+                sample=f"full plain AIR of the 3 views ({nodes} rays) in {dt:.2f} s, FP64, OpenMP",
+                seconds=dt)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--skip-fixed", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the adaptive render of one scene runs on one device; "
+              "multi-GPU sharding is described in DESIGN.md and not run here", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1010_5534_amd import air, inputs
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    log("generating winds2 field", NGRID)
+    g, f = inputs.winds2(SEED, NGRID)
+    views = inputs.winds2_views()
+    ctx = air.Context(0)
+    scene = air.upload(g, f)
+    prm = air.params(N0, LMAX, XI_CRIT)
+    torch.cuda.synchronize()
+
+    def plain():
+        return ctx.render(scene, views, prm)
+
+    def fixed():
+        return ctx.render_fixed(scene, views, N0, LMAX)
+
+    def timed(fn, steps, warmup):
+        for _ in range(warmup):
+            out = fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        dev_ms, march_ms, stats = 0.0, 0.0, None
+        for _ in range(steps):
+            out = fn()
+            stats = out[-1]
+            dev_ms += stats["ms_total"]
+            march_ms += stats["ms_march"]
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / steps
+        return out, wall, dev_ms / steps, march_ms / steps, stats
+
+    log("plain AIR")
+    out_p, wall_p, dev_p, march_p, st_p = timed(plain, args.steps, args.warmup)
+    trees, img_p, flux_p, _ = out_p
+    rays_p = st_p["rays"]
+    res = dict(metric=METRIC, value=rays_p / wall_p, unit="rays/s", n_gpus=1, steps=args.steps,
+               warmup=args.warmup, ms_per_step=wall_p * 1e3, higher_is_better=True, scaling="weak",
+               vs_baseline=None, dtype="f32", data="synthetic",
+               config=dict(workload=f"winds2 {NGRID}^3 seed {SEED}, {N0}x{N0} coarse, {LMAX} levels "
+                                    f"({N0 << LMAX}^2 effective), xi_crit {XI_CRIT}, 3 views (+z, +x, diag)",
+                           views=3, coarse=N0, levels=LMAX, grid=NGRID))
+    per_level = st_p["rays_per_level"][:LMAX + 1]
+    res["plain_air"] = dict(rays=rays_p, rays_per_level=per_level, hits=st_p["hits"], visits=st_p["visits"],
+                            leaves=st_p["leaves"], flagged=st_p["flagged"], balance=st_p["balance"],
+                            ms_wall=wall_p * 1e3, ms_device=dev_p, ms_march=march_p,
+                            per_image_ms=wall_p * 1e3 / len(views), rays_per_s_device=rays_p / (dev_p * 1e-3))
+    bytes_p = st_p["visits"] * BYTES_PER_VISIT + rays_p * BYTES_PER_RAY_QUEUE
+    achieved = bytes_p / (march_p * 1e-3) / 1e9
+    res["roofline"] = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
+                           frac=achieved / HBM_PEAK_GBS, traffic=traffic_from_profile("k_march_queue"),
+                           kernel="k_march_queue", launches=st_p["march_launches"],
+                           avg_launch_ms=march_p / st_p["march_launches"],
+                           bytes_per_launch=bytes_p / st_p["march_launches"],
+                           bytes_rule=f"{BYTES_PER_VISIT} B/visit + {BYTES_PER_RAY_QUEUE} B/ray")
+
+    if not args.skip_fixed:
+        log("fixed-resolution image")
+        out_f, wall_f, dev_f, march_f, st_f = timed(fixed, max(2, args.steps // 2), 1)
+        img_f, flux_f, _ = out_f
+        rays_f = st_f["rays"]
+        bytes_f = st_f["visits"] * BYTES_PER_VISIT + rays_f * BYTES_PER_RAY_FIXED
+        res["fixed"] = dict(rays=rays_f, hits=st_f["hits"], visits=st_f["visits"], ms_wall=wall_f * 1e3,
+                            ms_device=dev_f, ms_march=march_f, per_image_ms=wall_f * 1e3 / len(views),
+                            rays_per_s=rays_f / wall_f,
+                            march_roofline=dict(achieved=bytes_f / (march_f * 1e-3) / 1e9, unit="GB/s",
+                                                frac=bytes_f / (march_f * 1e-3) / 1e9 / HBM_PEAK_GBS))
+        # Table-1 style accuracy: AIR flux against the fixed image's flux
+        res["air_vs_fixed"] = dict(speedup=wall_f / wall_p, ray_reduction=rays_f / rays_p,
+                                   flux_rel_err=[float((flux_f[k][0] - flux_p[k][0]) / flux_f[k][0])
+                                                 for k in range(len(views))])
+    res["learned_air"] = None
+
+    if not args.no_cpu_baseline:
+        log("oracle CPU baseline")
+        cb = cpu_baseline(g, f, views)
+        res["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
+    else:
+        res["cpu_baseline"] = None
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,211 @@
+/*
+ * air.h -- C ABI of the MI355X (gfx950) adaptive image ray-tracing library.
+ *
+ * Method: Parkin 2010, "Adaptive image ray-tracing for astrophysical
+ * simulations" (MNRAS Letter).  Section 2 defines the scheme: a coarse base
+ * image (step i), one ray per pixel integrating a quantity through the
+ * simulation grid (step ii), a scan of the image with a truncation-error test
+ * and a 2:1 level rule between adjacent pixels (step iii), refinement with
+ * tree book-keeping (step iv), repeated until nothing refines or a resolution
+ * cap (step v), then integration and output (step vi).  Section 3 gives the
+ * error estimate (Eq. 2 in 1-D, Eq. 3 in 2-D), the refinement threshold
+ * xi >= xi_crit, and the flux definition used in Table 1.
+ *
+ * Conventions shared by every call:
+ *  - All array arguments marked "device" are HIP device pointers owned by the
+ *    caller; the library never frees or retains them after the call returns.
+ *    Host pointers are marked "host".
+ *  - Work is enqueued on `stream` (a hipStream_t passed as void*; NULL = the
+ *    null stream).  Calls that return host results (counts, flux, stats)
+ *    synchronise that stream before returning.
+ *  - Field arrays are float32, x fastest: index x + nx*(y + ny*z) on a uniform
+ *    grid; block-major (block b's bs^3 cells from b*bs^3, x fastest inside)
+ *    on a block-AMR grid.
+ *  - Image pixel (L, i, j) of a view: level L, i along e_u, j along e_v,
+ *    e_u = normalise(up x dir), e_v = dir x e_u; the level-L raster has
+ *    R_L = coarse_n * 2^L pixels a side, pixel size width / R_L, and the
+ *    pixel's ray passes through its centre along +dir (front to back from
+ *    the observer).  Rasters are row-major: index j*R + i.
+ *  - A context is not thread-safe: use one per host thread.
+ *  - Every call returns an air_status; on failure, air_last_error() holds a
+ *    message and the outputs are undefined.  No exception crosses the ABI.
+ */
+#ifndef AIR_H
+#define AIR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t air_status;
+#define AIR_OK 0
+#define AIR_EINVAL (-1)    /* bad argument, detected on the host before any launch */
+#define AIR_ENOMEM (-2)    /* device allocation failed */
+#define AIR_EDEVICE (-3)   /* a HIP call failed; air_last_error() has its text */
+#define AIR_ECAPACITY (-4) /* an output buffer is too small: tree->n_nodes holds the size needed */
+#define AIR_ENOTSUP (-5)   /* combination not supported by this build */
+
+#define AIR_MAX_LEVELS 12 /* image levels 0..11 */
+#define AIR_MAX_BANDS 8
+#define AIR_MAX_VIEWS 4096
+
+/* grid kinds */
+#define AIR_GRID_UNIFORM 0
+#define AIR_GRID_BLOCK_AMR 1
+/* field kinds */
+#define AIR_FIELD_RHO_J_KAPPA 0 /* rho, emissivity j, opacity kappa: one band */
+#define AIR_FIELD_RHO_T 1       /* rho, T; band b: kappa = k0_b rho T^-s_b, j = rho^2 T^q_b */
+
+/* node state bits (air_tree.state) */
+#define AIR_NODE_EXIST 1u
+#define AIR_NODE_TESTED 2u    /* base pixel or child of a flagged pixel: eligible for the test */
+#define AIR_NODE_FLAGGED 4u   /* the test asked for refinement (xi >= xi_crit) */
+#define AIR_NODE_BALANCE 8u   /* created only to keep the 2:1 level rule; never tested */
+#define AIR_NODE_REFINED 16u  /* has four children */
+#define AIR_NODE_EVALUATED 32u /* the test was evaluated at this node */
+
+/* Simulation grid (section 3 uses a block-structured AMR grid; the
+ * uniform grid is the one-level special case). */
+typedef struct {
+  int32_t kind;     /* AIR_GRID_* */
+  int32_t n[3];     /* uniform: cells per axis.  AMR: base blocks per axis */
+  double lo[3];     /* box corner; the box is [lo, hi) with half-open cells */
+  double hi[3];
+  int32_t bs;        /* AMR: cells per block edge (power of two, <= 32) */
+  int32_t max_level; /* AMR: deepest block level (ratio-2 refinement) */
+  int32_t n_blocks;  /* AMR: number of blocks; base blocks first, x fastest */
+  const int32_t* block_level; /* device [n_blocks] */
+  const int32_t* block_coord; /* device [n_blocks][3]: block coordinate at its own level */
+  const int32_t* block_child; /* device [n_blocks]: first of 8 children (offset cx+2cy+4cz) or -1 */
+} air_grid;
+
+/* Cell data (device, float32). */
+typedef struct {
+  int32_t kind;    /* AIR_FIELD_* */
+  int32_t n_bands; /* 1 for AIR_FIELD_RHO_J_KAPPA; 1..AIR_MAX_BANDS for AIR_FIELD_RHO_T */
+  const float* rho;   /* density: the column N integrates it */
+  const float* emis;  /* emissivity (RHO_J_KAPPA) */
+  const float* kappa; /* opacity (RHO_J_KAPPA) */
+  const float* temp;  /* temperature (RHO_T) */
+  double band[AIR_MAX_BANDS][3]; /* host values (k0, s, q) per band (RHO_T) */
+} air_field;
+
+/* Orthographic view (section 3 uses a face-on view along an axis). */
+typedef struct {
+  double dir[3];    /* looking direction (need not be unit length) */
+  double up[3];     /* up hint; must not be parallel to dir */
+  double center[3]; /* image centre in grid coordinates */
+  double width;     /* image side length in grid units */
+} air_view;
+
+/* Refinement parameters (sections 2 and 3). */
+typedef struct {
+  int32_t coarse_n;  /* N0: base image is N0 x N0 (step i) */
+  int32_t max_level; /* number of refinements allowed (step v cap) */
+  float xi_crit_I;   /* refine iff xi(I) >= xi_crit_I; > 1 disables (xi <= 1) */
+  float xi_crit_N;   /* same for the column density N; several variables are OR-ed */
+  float band_weight[AIR_MAX_BANDS]; /* the tested intensity is sum_b w_b I_b */
+  uint32_t flags;    /* reserved, must be 0 */
+} air_params;
+
+/* Pixel quadtree in canonical order: by level, then coarse pixel (row-major),
+ * then Morton order inside the coarse pixel, so the four children of a node
+ * are consecutive.  All arrays are device memory of `capacity` entries
+ * supplied by the caller; a NULL array is skipped. */
+typedef struct {
+  int64_t capacity;                     /* in: entries in each array below */
+  int64_t n_nodes;                      /* out: nodes = rays traced */
+  int64_t n_per_level[AIR_MAX_LEVELS];  /* out */
+  int64_t n_leaves;                     /* out */
+  int8_t* level;       /* device */
+  int32_t* ix;         /* device: pixel index along e_u at its level */
+  int32_t* iy;         /* device: pixel index along e_v */
+  int32_t* parent;     /* device: node index of the parent, -1 at level 0 */
+  int32_t* first_child;/* device: node index of the first of 4 children, or -1 */
+  uint8_t* state;      /* device: AIR_NODE_* bits */
+  float* I;            /* device [n_bands][capacity]: intensity per band */
+  float* N;            /* device: column density */
+  float* xi_I;         /* device: xi of the tested intensity, NaN if not evaluated */
+  float* xi_N;         /* device: xi of N, NaN if not evaluated */
+  int32_t* visits;     /* device: cells crossed by the node's ray */
+} air_tree;
+
+/* Counters of one call (host). */
+typedef struct {
+  int64_t rays;                          /* rays traced (all tree nodes) */
+  int64_t rays_per_level[AIR_MAX_LEVELS];
+  int64_t hits;                          /* rays that crossed the grid */
+  int64_t visits;                        /* (ray, cell) segments marched */
+  int64_t leaves;
+  int64_t tested;                        /* nodes where the test was evaluated */
+  int64_t flagged;
+  int64_t balance;                       /* nodes created by the 2:1 rule */
+  int32_t depth;                         /* deepest level reached */
+  int32_t march_launches;                /* march kernel launches in the call */
+  double ms_total;  /* device time of the call, first kernel to last (HIP events on the stream) */
+  double ms_march;  /* device time of the march kernels, summed over levels */
+  double ms_test;   /* device time of the test / 2:1 closure / compaction kernels */
+} air_stats;
+
+typedef struct air_ctx air_ctx;
+
+/* Create a context on HIP device `device`.  The context owns device
+ * workspace (per-level pixel maps, work queue, counters) that grows on demand
+ * and is freed by air_destroy. */
+air_status air_create(air_ctx** out, int32_t device);
+void air_destroy(air_ctx* ctx);
+/* Message for the last failure on this context ("" if none). */
+const char* air_last_error(const air_ctx* ctx);
+
+/*
+ * Plain AIR for n_views views of one grid (section 2 steps i-vi), the views
+ * refined level by level in lockstep.  For each view:
+ *  - every base pixel is traced and tested;
+ *  - at level L < max_level every tested node's xi is computed from its 3x3
+ *    level-L neighbourhood (a missing neighbour takes the value of the
+ *    covering level-(L-1) node; a direction without both neighbours inside
+ *    the image is dropped with the mixed terms);
+ *  - flagged nodes get 4 tested children, and the 2:1 rule (edge and corner
+ *    neighbours) is closed by refining coarser nodes, whose children are
+ *    balance nodes;
+ *  - all new nodes are traced before the next level.
+ * Outputs (each may be NULL):
+ *  trees   host array [n_views] of air_tree with caller device buffers;
+ *  images  device [n_views][n_bands + 1][R][R], R = coarse_n * 2^max_level:
+ *          the leaves painted over their squares, bands then N;
+ *  flux    host [n_views][n_bands]: sum over leaves of pixel area x I_b,
+ *          reduced in double precision in a fixed order;
+ *  stats   host, summed over views.
+ * Errors: EINVAL (checked before any launch), ECAPACITY (a tree's capacity
+ * is below its node count; n_nodes holds the count), EDEVICE, ENOMEM.
+ */
+air_status air_render(air_ctx* ctx, const air_grid* grid, const air_field* field, const air_view* views,
+                      int32_t n_views, const air_params* params, air_tree* trees, float* images,
+                      double* flux, air_stats* stats, void* stream);
+
+/*
+ * Fixed-resolution baseline (section 3, Table 1 "Fixed"): every pixel of the
+ * level-`level` raster of each view is traced.  images: device
+ * [n_views][n_bands + 1][R][R] with R = coarse_n * 2^level (NULL skips the
+ * write, the rays are still traced); flux: host [n_views][n_bands] or NULL.
+ */
+air_status air_render_fixed(air_ctx* ctx, const air_grid* grid, const air_field* field,
+                            const air_view* views, int32_t n_views, int32_t coarse_n, int32_t level,
+                            float* images, double* flux, air_stats* stats, void* stream);
+
+/*
+ * Trace n individual pixels of one view (section 2 step ii), e.g. to sample
+ * a large image.  level/ix/iy: device [n]; I: device [n_bands][n]; N, visits
+ * (nullable): device [n].
+ */
+air_status air_trace_pixels(air_ctx* ctx, const air_grid* grid, const air_field* field,
+                            const air_view* view, int32_t coarse_n, int64_t n, const int32_t* level,
+                            const int32_t* ix, const int32_t* iy, float* I, float* N, int32_t* visits,
+                            void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AIR_H */

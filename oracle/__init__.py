@@ -62,12 +62,13 @@ def lib():
         _lib.orc_xi.argtypes = [vp, C.c_int, C.c_int]
         _lib.orc_xi.restype = C.c_double
         _lib.orc_air.argtypes = [vp, vp, vp, C.c_int, C.c_int, C.c_double, C.c_double, vp, vp,
-                                 vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+                                 vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         _lib.orc_air.restype = C.c_int64
         _lib.orc_paint_leaves.argtypes = [C.c_int, C.c_int, vp, vp, vp]
         _lib.orc_leaf_flux.argtypes = [C.c_int, C.c_int, C.c_double, vp, vp]
         _lib.orc_leaf_flux.restype = C.c_double
         _lib.orc_num_threads.restype = C.c_int
+        _lib.orc_xi_sens.argtypes = [C.c_int64, vp, vp, vp, C.c_double, vp, vp]
     return _lib
 
 
@@ -237,6 +238,7 @@ def air(grid, field, view, N0, Lmax, xi_crit_I=0.5, xi_crit_N=2.0, band_w=None, 
     rmin = np.zeros(total) if want_rho_range else None
     rmax = np.zeros(total) if want_rho_range else None
     counts = np.zeros(Lmax + 1, dtype=np.int64)
+    born = np.zeros(total, dtype=np.int8)
     w = None if band_w is None else np.ascontiguousarray(band_w, dtype=np.float64)
     ff = None if force_flags is None else np.ascontiguousarray(force_flags, dtype=np.uint8)
     v = _view(view)
@@ -247,7 +249,7 @@ def air(grid, field, view, N0, Lmax, xi_crit_I=0.5, xi_crit_N=2.0, band_w=None, 
         gp = fp = None
     n = lib().orc_air(gp, fp, C.addressof(v), N0, Lmax, float(xi_crit_I), float(xi_crit_N), _p(w), _p(ff),
                       state.ctypes.data, xiI.ctypes.data, xiN.ctypes.data, I.ctypes.data, N.ctypes.data,
-                      lm.ctypes.data, nv.ctypes.data, _p(rmin), _p(rmax), counts.ctypes.data)
+                      lm.ctypes.data, nv.ctypes.data, _p(rmin), _p(rmax), counts.ctypes.data, born.ctypes.data)
     if n < 0:
         raise RuntimeError(f"oracle AIR failed: {n}")
     offs = np.concatenate([[0], np.cumsum(sizes)])
@@ -257,6 +259,7 @@ def air(grid, field, view, N0, Lmax, xi_crit_I=0.5, xi_crit_N=2.0, band_w=None, 
 
     t = Tree(N0, Lmax, int(n), counts, split(state), split(xiI), split(xiN), split(I), split(N), split(lm),
              split(nv), state, I, N)
+    t.born = split(born)
     if want_rho_range:
         t.rmin = split(rmin)
         t.rmax = split(rmax)
@@ -275,3 +278,45 @@ def leaf_flux(tree: Tree, width: float, vals_flat: np.ndarray) -> float:
     v = np.ascontiguousarray(vals_flat, dtype=np.float64)
     return float(lib().orc_leaf_flux(tree.N0, tree.Lmax, float(width), tree.flat_state.ctypes.data,
                                      v.ctypes.data))
+
+
+def xi_sensitivity(stencils: np.ndarray, hx: np.ndarray, hy: np.ndarray, delta: float):
+    """(xi, bound): xi of each 3x3 stencil and the first-order bound on its
+    change when every input moves by relative delta."""
+    p = np.ascontiguousarray(stencils, dtype=np.float64).reshape(-1, 9)
+    n = p.shape[0]
+    hx = np.ascontiguousarray(hx, dtype=np.int32)
+    hy = np.ascontiguousarray(hy, dtype=np.int32)
+    xi_ = np.zeros(n)
+    out = np.zeros(n)
+    lib().orc_xi_sens(n, p.ctypes.data, hx.ctypes.data, hy.ctypes.data, float(delta), xi_.ctypes.data,
+                      out.ctypes.data)
+    return xi_, out
+
+
+def stencils(tree: Tree, L: int, which: str = "I", band_w=None):
+    """3x3 level-L stencils of every tested node of the oracle tree (the
+    covering level-(L-1) value where a level-L neighbour does not exist),
+    with the image-edge flags.  Returns (positions (j, i), p[n, 9], hx, hy)."""
+    R = tree.N0 << L
+    st = tree.state[L]
+    js, is_ = np.nonzero((st & TESTED) > 0)
+    if which == "N":
+        val = [tree.N[l] for l in range(tree.Lmax + 1)]
+    else:
+        nb = tree.I[0].shape[0]
+        w = np.ones(nb) if band_w is None else np.asarray(band_w, dtype=float)[:nb]
+        val = [np.tensordot(w, tree.I[l], axes=1) for l in range(tree.Lmax + 1)]
+    p = np.zeros((len(js), 9))
+    for b in (-1, 0, 1):
+        for a in (-1, 0, 1):
+            qj, qi = js + b, is_ + a
+            ok = (qi >= 0) & (qj >= 0) & (qi < R) & (qj < R)
+            qjc, qic = np.clip(qj, 0, R - 1), np.clip(qi, 0, R - 1)
+            # existence when level L was tested: created before step L
+            ex = ((st[qjc, qic] & EXIST) > 0) & (tree.born[L][qjc, qic] < L)
+            v = np.where(ex, val[L][qjc, qic], val[L - 1][qjc // 2, qic // 2] if L > 0 else 0.0)
+            p[:, (b + 1) * 3 + (a + 1)] = np.where(ok, v, 0.0)
+    hx = ((is_ > 0) & (is_ < R - 1)).astype(np.int32)
+    hy = ((js > 0) & (js < R - 1)).astype(np.int32)
+    return (js, is_), p, hx, hy

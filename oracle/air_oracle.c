@@ -395,6 +395,8 @@ typedef struct {
   int32_t *lmax, *nvis;
   int64_t total;
   const uint8_t* force_flags; /* test hook: flags per position instead of the criterion */
+  int8_t* born;               /* step that created each node (-1: base image), may be NULL */
+  int step;
   int64_t *nl, *nl_i, *nl_j;  /* list of nodes created in the current step */
   int64_t n_new, cap_new;
   int err;
@@ -423,6 +425,7 @@ static void refine(tree_t* t, int L, int64_t i, int64_t j, uint8_t kind) {
   for (int b = 0; b < 2; ++b)
     for (int a = 0; a < 2; ++a) {
       t->state[pos(t, L + 1, 2 * i + a, 2 * j + b)] |= (uint8_t)(ORC_EXIST | kind);
+      if (t->born) t->born[pos(t, L + 1, 2 * i + a, 2 * j + b)] = (int8_t)t->step;
       push_new(t, L + 1, 2 * i + a, 2 * j + b);
     }
 }
@@ -499,12 +502,13 @@ static double stencil_value(const tree_t* t, int L, int64_t i, int64_t j, int wh
  * given, a tested node is flagged iff force_flags[pos] != 0 and no ray is
  * traced (grid and field may then be NULL).
  * Returns the number of nodes (rays traced), or a negative error.
- * counts[L] receives the node count per level.
+ * counts[L] receives the node count per level; born (may be NULL) the step
+ * that created each node (-1 for the base image).
  */
 int64_t orc_air(const orc_grid* g, const orc_field* f, const orc_view* v, int N0, int Lmax,
                 double xc_I, double xc_N, const double* band_w, const uint8_t* force_flags,
                 uint8_t* state, double* xiI, double* xiN, double* I, double* N, int32_t* lmax,
-                int32_t* nvis, double* rmin, double* rmax, int64_t* counts) {
+                int32_t* nvis, double* rmin, double* rmax, int64_t* counts, int8_t* born) {
   if (N0 < 1 || Lmax < 0 || Lmax > ORC_MAXL - 1) return -1;
   tree_t t;
   memset(&t, 0, sizeof t);
@@ -524,7 +528,9 @@ int64_t orc_air(const orc_grid* g, const orc_field* f, const orc_view* v, int N0
   t.rmin = rmin;
   t.rmax = rmax;
   t.force_flags = force_flags;
+  t.born = born;
   memset(state, 0, (size_t)t.total);
+  if (born) memset(born, -1, (size_t)t.total);
   for (int64_t k = 0; k < t.total; ++k) {
     xiI[k] = NAN;
     xiN[k] = NAN;
@@ -574,6 +580,7 @@ int64_t orc_air(const orc_grid* g, const orc_field* f, const orc_view* v, int N0
       }
     if (nflag == 0) break;
     t.n_new = 0;
+    t.step = L;
     /* steps iii-iv: 2:1 closure around every flagged pixel, then refine */
     for (int64_t j = 0; j < R; ++j)
       for (int64_t i = 0; i < R; ++i) {
@@ -652,4 +659,32 @@ int orc_num_threads(void) {
 #else
   return 1;
 #endif
+}
+
+/* ------------------------------------------------- parity-test helper */
+/* First-order bound on how far xi can move when each stencil value p_k
+ * moves by a relative amount delta (the value tolerance of a float32
+ * evaluation): sum over k of the larger change of xi under p_k -> p_k (1 +-
+ * delta).  A flag decided by a float32 path can differ from this oracle's
+ * only where |xi - xi_crit| is within this bound.  p is [n][9]; the result
+ * is written to out[n]. */
+void orc_xi_sens(int64_t n, const double* p, const int32_t* hx, const int32_t* hy, double delta, double* xi,
+                 double* out) {
+#pragma omp parallel for schedule(static)
+  for (int64_t k = 0; k < n; ++k) {
+    double q[9];
+    memcpy(q, p + 9 * k, sizeof q);
+    double x0 = orc_xi(q, hx[k], hy[k]), s = 0.0;
+    for (int m = 0; m < 9; ++m) {
+      double v = q[m], h = fabs(v) * delta, worst = 0.0;
+      q[m] = v + h;
+      worst = fmax(worst, fabs(orc_xi(q, hx[k], hy[k]) - x0));
+      q[m] = v - h;
+      worst = fmax(worst, fabs(orc_xi(q, hx[k], hy[k]) - x0));
+      q[m] = v;
+      s += worst;
+    }
+    xi[k] = x0;
+    out[k] = s;
+  }
 }

@@ -1,0 +1,314 @@
+"""ctypes binding to libair.so (the HIP library).  Argument marshalling
+only: every step of the rendering runs in the library's kernels; torch
+provides device memory and the stream.  Names follow include/air.h."""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libair.so")
+
+AIR_OK, AIR_EINVAL, AIR_ENOMEM, AIR_EDEVICE, AIR_ECAPACITY, AIR_ENOTSUP = 0, -1, -2, -3, -4, -5
+MAX_LEVELS, MAX_BANDS, MAX_VIEWS = 12, 8, 4096
+GRID_UNIFORM, GRID_BLOCK_AMR = 0, 1
+FIELD_RHO_J_KAPPA, FIELD_RHO_T = 0, 1
+NODE_EXIST, NODE_TESTED, NODE_FLAGGED, NODE_BALANCE, NODE_REFINED, NODE_EVALUATED = 1, 2, 4, 8, 16, 32
+
+EXPORTS = ("air_create", "air_destroy", "air_last_error", "air_render", "air_render_fixed", "air_trace_pixels")
+
+
+class AirError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"AIR error {code}: {msg}")
+        self.code = code
+
+
+class air_grid(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("n", C.c_int32 * 3), ("lo", C.c_double * 3), ("hi", C.c_double * 3),
+                ("bs", C.c_int32), ("max_level", C.c_int32), ("n_blocks", C.c_int32),
+                ("block_level", C.c_void_p), ("block_coord", C.c_void_p), ("block_child", C.c_void_p)]
+
+
+class air_field(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("n_bands", C.c_int32), ("rho", C.c_void_p), ("emis", C.c_void_p),
+                ("kappa", C.c_void_p), ("temp", C.c_void_p), ("band", (C.c_double * 3) * MAX_BANDS)]
+
+
+class air_view(C.Structure):
+    _fields_ = [("dir", C.c_double * 3), ("up", C.c_double * 3), ("center", C.c_double * 3), ("width", C.c_double)]
+
+
+class air_params(C.Structure):
+    _fields_ = [("coarse_n", C.c_int32), ("max_level", C.c_int32), ("xi_crit_I", C.c_float),
+                ("xi_crit_N", C.c_float), ("band_weight", C.c_float * MAX_BANDS), ("flags", C.c_uint32)]
+
+
+class air_tree(C.Structure):
+    _fields_ = [("capacity", C.c_int64), ("n_nodes", C.c_int64), ("n_per_level", C.c_int64 * MAX_LEVELS),
+                ("n_leaves", C.c_int64), ("level", C.c_void_p), ("ix", C.c_void_p), ("iy", C.c_void_p),
+                ("parent", C.c_void_p), ("first_child", C.c_void_p), ("state", C.c_void_p), ("I", C.c_void_p),
+                ("N", C.c_void_p), ("xi_I", C.c_void_p), ("xi_N", C.c_void_p), ("visits", C.c_void_p)]
+
+
+class air_stats(C.Structure):
+    _fields_ = [("rays", C.c_int64), ("rays_per_level", C.c_int64 * MAX_LEVELS), ("hits", C.c_int64),
+                ("visits", C.c_int64), ("leaves", C.c_int64), ("tested", C.c_int64), ("flagged", C.c_int64),
+                ("balance", C.c_int64), ("depth", C.c_int32), ("march_launches", C.c_int32),
+                ("ms_total", C.c_double), ("ms_march", C.c_double), ("ms_test", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libair.so; raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        vp = C.c_void_p
+        L.air_create.argtypes = [C.POINTER(vp), C.c_int32]
+        L.air_create.restype = C.c_int32
+        L.air_destroy.argtypes = [vp]
+        L.air_destroy.restype = None
+        L.air_last_error.argtypes = [vp]
+        L.air_last_error.restype = C.c_char_p
+        L.air_render.argtypes = [vp, vp, vp, vp, C.c_int32, vp, vp, vp, vp, vp, vp]
+        L.air_render.restype = C.c_int32
+        L.air_render_fixed.argtypes = [vp, vp, vp, vp, C.c_int32, C.c_int32, C.c_int32, vp, vp, vp, vp]
+        L.air_render_fixed.restype = C.c_int32
+        L.air_trace_pixels.argtypes = [vp, vp, vp, vp, C.c_int32, C.c_int64, vp, vp, vp, vp, vp, vp, vp]
+        L.air_trace_pixels.restype = C.c_int32
+        _lib = L
+    return _lib
+
+
+def _torch():
+    import torch
+    return torch
+
+
+@dataclasses.dataclass
+class DeviceScene:
+    """Grid and field resident in device memory (torch tensors)."""
+
+    grid: air_grid
+    field: air_field
+    tensors: list
+    n_bands: int
+
+
+def upload(grid, field, device="cuda") -> DeviceScene:
+    """Copy an inputs.Grid / inputs.Field to the GPU once."""
+    torch = _torch()
+    keep = []
+
+    def dev(a, dtype):
+        if a is None:
+            return None
+        t = torch.from_numpy(np.ascontiguousarray(a).reshape(-1)).to(device=device, dtype=dtype)
+        keep.append(t)
+        return t.data_ptr()
+
+    g = air_grid()
+    g.kind = grid.kind
+    g.n[:] = [int(x) for x in grid.n]
+    g.lo[:] = [float(x) for x in grid.lo]
+    g.hi[:] = [float(x) for x in grid.hi]
+    g.bs = grid.bs
+    g.max_level = grid.max_level
+    g.n_blocks = grid.n_blocks
+    if grid.kind == GRID_BLOCK_AMR:
+        g.block_level = dev(grid.block_level, torch.int32)
+        g.block_coord = dev(grid.block_coord, torch.int32)
+        g.block_child = dev(grid.block_child, torch.int32)
+    f = air_field()
+    f.kind = field.kind
+    f.n_bands = field.n_bands
+    f.rho = dev(field.rho, torch.float32)
+    f.emis = dev(field.emis, torch.float32)
+    f.kappa = dev(field.kappa, torch.float32)
+    f.temp = dev(field.temp, torch.float32)
+    if field.bands is not None:
+        for b in range(field.n_bands):
+            for k in range(3):
+                f.band[b][k] = float(field.bands[b][k])
+    return DeviceScene(g, f, keep, field.n_bands)
+
+
+def _views(views) -> C.Array:
+    arr = (air_view * len(views))()
+    for k, v in enumerate(views):
+        arr[k].dir[:] = [float(x) for x in v.dir]
+        arr[k].up[:] = [float(x) for x in v.up]
+        arr[k].center[:] = [float(x) for x in v.center]
+        arr[k].width = float(v.width)
+    return arr
+
+
+def params(coarse_n, max_level, xi_crit_I=0.5, xi_crit_N=2.0, band_weight=None) -> air_params:
+    p = air_params()
+    p.coarse_n = coarse_n
+    p.max_level = max_level
+    p.xi_crit_I = xi_crit_I
+    p.xi_crit_N = xi_crit_N
+    w = [1.0] * MAX_BANDS if band_weight is None else list(band_weight) + [0.0] * (MAX_BANDS - len(band_weight))
+    p.band_weight[:] = [float(x) for x in w[:MAX_BANDS]]
+    p.flags = 0
+    return p
+
+
+def stats_dict(s: air_stats) -> dict:
+    return dict(rays=s.rays, rays_per_level=list(s.rays_per_level), hits=s.hits, visits=s.visits, leaves=s.leaves,
+                tested=s.tested, flagged=s.flagged, balance=s.balance, depth=s.depth,
+                march_launches=s.march_launches, ms_total=s.ms_total, ms_march=s.ms_march, ms_test=s.ms_test)
+
+
+@dataclasses.dataclass
+class Tree:
+    """Pixel quadtree of one view (device tensors, canonical order)."""
+
+    n_nodes: int
+    n_per_level: list
+    n_leaves: int
+    level: object
+    ix: object
+    iy: object
+    parent: object
+    first_child: object
+    state: object
+    I: object
+    N: object
+    xi_I: object
+    xi_N: object
+    visits: object
+
+
+class Context:
+    """One air_ctx on one device."""
+
+    def __init__(self, device: int = 0):
+        torch = _torch()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the AIR library runs on the GPU only")
+        self.device = device
+        self._p = C.c_void_p()
+        rc = lib().air_create(C.byref(self._p), device)
+        if rc != AIR_OK:
+            raise AirError(rc, "air_create failed")
+
+    def close(self):
+        if self._p:
+            lib().air_destroy(self._p)
+            self._p = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc != AIR_OK:
+            raise AirError(rc, lib().air_last_error(self._p).decode())
+
+    def _stream(self):
+        return _torch().cuda.current_stream(self.device).cuda_stream
+
+    def _alloc_tree(self, cap, nb):
+        torch = _torch()
+        dev = f"cuda:{self.device}"
+        t = dict(level=torch.empty(cap, dtype=torch.int8, device=dev),
+                 ix=torch.empty(cap, dtype=torch.int32, device=dev),
+                 iy=torch.empty(cap, dtype=torch.int32, device=dev),
+                 parent=torch.empty(cap, dtype=torch.int32, device=dev),
+                 first_child=torch.empty(cap, dtype=torch.int32, device=dev),
+                 state=torch.empty(cap, dtype=torch.uint8, device=dev),
+                 I=torch.empty((nb, cap), dtype=torch.float32, device=dev),
+                 N=torch.empty(cap, dtype=torch.float32, device=dev),
+                 xi_I=torch.empty(cap, dtype=torch.float32, device=dev),
+                 xi_N=torch.empty(cap, dtype=torch.float32, device=dev),
+                 visits=torch.empty(cap, dtype=torch.int32, device=dev))
+        s = air_tree()
+        s.capacity = cap
+        for k, v in t.items():
+            setattr(s, k, v.data_ptr())
+        return s, t
+
+    def render(self, scene: DeviceScene, views: Sequence, prm: air_params, want_tree=True, want_image=True,
+               want_flux=True, capacity: Optional[int] = None):
+        """Plain AIR over the views.  Returns (trees, images, flux, stats)."""
+        torch = _torch()
+        V, nb = len(views), scene.n_bands
+        R = prm.coarse_n << prm.max_level
+        bound = sum((prm.coarse_n << L) ** 2 for L in range(prm.max_level + 1))
+        cap = min(bound, capacity or (1 << 21))
+        vs = _views(views)
+        images = torch.empty((V, nb + 1, R, R), dtype=torch.float32, device=f"cuda:{self.device}") \
+            if want_image else None
+        flux = np.zeros((V, nb), dtype=np.float64) if want_flux else None
+        st = air_stats()
+        while True:
+            trees = (air_tree * V)() if want_tree else None
+            keep = []
+            if want_tree:
+                for k in range(V):
+                    s, t = self._alloc_tree(cap, nb)
+                    trees[k] = s
+                    keep.append(t)
+            rc = lib().air_render(self._p, C.addressof(scene.grid), C.addressof(scene.field), C.addressof(vs), V,
+                                  C.addressof(prm), C.addressof(trees) if want_tree else None,
+                                  images.data_ptr() if want_image else None,
+                                  flux.ctypes.data if want_flux else None, C.addressof(st), self._stream())
+            if rc == AIR_ECAPACITY and want_tree:
+                cap = max(trees[k].n_nodes for k in range(V))
+                continue
+            self._check(rc)
+            break
+        out = []
+        if want_tree:
+            for k in range(V):
+                n = trees[k].n_nodes
+                t = keep[k]
+                out.append(Tree(n, list(trees[k].n_per_level), trees[k].n_leaves,
+                                **{name: (t[name][:, :n] if name == "I" else t[name][:n]) for name in t}))
+        return out, images, flux, stats_dict(st)
+
+    def render_fixed(self, scene: DeviceScene, views: Sequence, coarse_n: int, level: int, want_image=True,
+                     want_flux=True):
+        torch = _torch()
+        V, nb = len(views), scene.n_bands
+        R = coarse_n << level
+        vs = _views(views)
+        images = torch.empty((V, nb + 1, R, R), dtype=torch.float32, device=f"cuda:{self.device}") \
+            if (want_image or want_flux) else None
+        flux = np.zeros((V, nb), dtype=np.float64) if want_flux else None
+        st = air_stats()
+        rc = lib().air_render_fixed(self._p, C.addressof(scene.grid), C.addressof(scene.field), C.addressof(vs), V,
+                                    coarse_n, level, images.data_ptr() if images is not None else None,
+                                    flux.ctypes.data if want_flux else None, C.addressof(st), self._stream())
+        self._check(rc)
+        return images, flux, stats_dict(st)
+
+    def trace_pixels(self, scene: DeviceScene, view, coarse_n: int, level, ix, iy):
+        torch = _torch()
+        dev = f"cuda:{self.device}"
+        lv = torch.as_tensor(np.asarray(level, dtype=np.int32), device=dev)
+        xi = torch.as_tensor(np.asarray(ix, dtype=np.int32), device=dev)
+        yi = torch.as_tensor(np.asarray(iy, dtype=np.int32), device=dev)
+        n = lv.numel()
+        I = torch.empty((scene.n_bands, n), dtype=torch.float32, device=dev)
+        N = torch.empty(n, dtype=torch.float32, device=dev)
+        vis = torch.empty(n, dtype=torch.int32, device=dev)
+        vs = _views([view])
+        rc = lib().air_trace_pixels(self._p, C.addressof(scene.grid), C.addressof(scene.field), C.addressof(vs),
+                                    coarse_n, n, lv.data_ptr(), xi.data_ptr(), yi.data_ptr(), I.data_ptr(),
+                                    N.data_ptr(), vis.data_ptr(), self._stream())
+        self._check(rc)
+        return I, N, vis

@@ -1,0 +1,173 @@
+// Internal declarations shared by the HIP kernels and the host API of the
+// AIR library.  Not part of the ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/air.h"
+
+namespace air {
+
+constexpr int MAXL = AIR_MAX_LEVELS;
+constexpr int MAXB = AIR_MAX_BANDS;
+constexpr int WAVE = 64;
+
+// node state bits beyond the public ones: set by the march once the node's
+// values are written (the refinement test reads only traced values)
+constexpr uint8_t ST_TRACED = 64u;
+
+// view, precomputed on the host in double precision
+struct DevView {
+  double d[3], eu[3], ev[3], c[3];
+  double width;
+};
+
+// grid geometry
+struct Geo {
+  int kind;
+  int n[3];       // uniform: cells per axis; AMR: base blocks per axis
+  double lo[3], hi[3];
+  double h[3];    // uniform cell size; AMR: base block size
+  int bs, max_level, n_blocks;
+  const int* bchild;
+  const int* bcoord;
+  const int* blevel;
+};
+
+// cell data
+struct Fld {
+  int kind, nb;
+  const float* rho;
+  const float* emis;
+  const float* kappa;
+  const float* temp;
+  float k0[MAXB], s[MAXB], q[MAXB];
+};
+
+// image pyramid layout: per view, levels 0..Lmax of dense maps indexed by
+// the forest-Morton key (coarse pixel row-major, Morton inside it)
+struct Img {
+  int N0, Lmax, V;
+  int64_t S;              // positions per view (padded)
+  int64_t off[MAXL + 1];  // level offsets inside a view (multiples of 256)
+};
+
+// counters (uint64) in device memory
+enum : int {
+  CTR_CURSOR = 0,         // queue append cursor
+  CTR_OVERFLOW = 1,       // set when an append would pass the capacity
+  CTR_LSTART = 2,         // [MAXL + 2] queue start of each level
+  CTR_TILE = CTR_LSTART + MAXL + 2,  // [MAXL + 1] march tile tickets per level
+  CTR_HITS = CTR_TILE + MAXL + 1,
+  CTR_VISITS,
+  CTR_TESTED,
+  CTR_FLAGGED,
+  CTR_BALANCE,
+  CTR_LEAVES,
+  CTR_NODES,              // [MAXL] per-level node counts
+  CTR_COUNT = CTR_NODES + MAXL
+};
+
+struct Work {
+  uint8_t* state;   // [V*S]
+  float* valI;      // [nb][V*S]
+  float* valN;      // [V*S]
+  float* xiI;       // [V*S]
+  float* xiN;       // [V*S]
+  int* visits;      // [V*S]
+  float* rmin;      // [V*N0*N0] level-0 density range (feature maps), may be null
+  float* rmax;
+  uint64_t* queue;  // work queue entries
+  uint64_t qcap;
+  unsigned long long* ctr;  // [CTR_COUNT]
+};
+
+// ------------------------------------------------------------ Morton keys
+__host__ __device__ inline uint32_t spread2(uint32_t x) {
+  x &= 0x0000ffffu;
+  x = (x | (x << 8)) & 0x00ff00ffu;
+  x = (x | (x << 4)) & 0x0f0f0f0fu;
+  x = (x | (x << 2)) & 0x33333333u;
+  x = (x | (x << 1)) & 0x55555555u;
+  return x;
+}
+__host__ __device__ inline uint32_t squeeze2(uint32_t x) {
+  x &= 0x55555555u;
+  x = (x | (x >> 1)) & 0x33333333u;
+  x = (x | (x >> 2)) & 0x0f0f0f0fu;
+  x = (x | (x >> 4)) & 0x00ff00ffu;
+  x = (x | (x >> 8)) & 0x0000ffffu;
+  return x;
+}
+// key of pixel (i, j) at level L: coarse pixel index, then Morton code of
+// the position inside it (i in even bits, j in odd bits).  The parent of key
+// k is k >> 2 and its children are 4k..4k+3.
+__host__ __device__ inline uint32_t key_of(uint32_t i, uint32_t j, int L, int N0) {
+  uint32_t mask = (1u << L) - 1u;
+  uint32_t root = (j >> L) * (uint32_t)N0 + (i >> L);
+  return (root << (2 * L)) | spread2(i & mask) | (spread2(j & mask) << 1);
+}
+__host__ __device__ inline void coords_of(uint32_t key, int L, int N0, uint32_t& i, uint32_t& j) {
+  uint32_t root = key >> (2 * L);
+  uint32_t m = key & ((1u << (2 * L)) - 1u);
+  i = ((root % (uint32_t)N0) << L) | squeeze2(m);
+  j = ((root / (uint32_t)N0) << L) | squeeze2(m >> 1);
+}
+
+// queue entry: view (24 bits) | level (8) | key (32)
+__host__ __device__ inline uint64_t qentry(uint32_t v, uint32_t L, uint32_t key) {
+  return ((uint64_t)v << 40) | ((uint64_t)L << 32) | key;
+}
+__host__ __device__ inline void qdecode(uint64_t e, uint32_t& v, uint32_t& L, uint32_t& key) {
+  key = (uint32_t)e;
+  L = (uint32_t)(e >> 32) & 0xffu;
+  v = (uint32_t)(e >> 40);
+}
+
+// ------------------------------------------------------------- launches
+// kernels are defined in march.hip and tree.hip; the host API calls these
+struct MarchArgs {
+  Geo g;
+  Fld f;
+  Img img;
+  Work w;
+  const DevView* views;
+};
+
+hipError_t launch_init(const MarchArgs& a, hipStream_t s);
+hipError_t launch_march_queue(const MarchArgs& a, int L, int grid_blocks, hipStream_t s);
+hipError_t launch_refine(const MarchArgs& a, int L, float xcI, float xcN, const float* w, int grid_blocks,
+                         hipStream_t s);
+hipError_t launch_march_fixed(const MarchArgs& a, int level, float* images, int grid_blocks, hipStream_t s);
+hipError_t launch_trace_pixels(const MarchArgs& a, int64_t n, const int32_t* level, const int32_t* ix,
+                               const int32_t* iy, float* I, float* N, int32_t* visits, hipStream_t s);
+hipError_t launch_count(const MarchArgs& a, unsigned long long* chunk_counts, int64_t n_chunks,
+                        unsigned long long* vstat, hipStream_t s);
+hipError_t launch_scan(unsigned long long* chunk_counts, int64_t n_chunks, hipStream_t s);
+hipError_t launch_emit(const MarchArgs& a, const unsigned long long* chunk_offsets, int64_t n_chunks,
+                       int32_t* id_map, hipStream_t s);
+struct TreeOut {
+  int8_t* level;
+  int32_t* ix;
+  int32_t* iy;
+  int32_t* parent;
+  int32_t* first_child;
+  uint8_t* state;
+  float* I;
+  float* N;
+  float* xi_I;
+  float* xi_N;
+  int32_t* visits;
+  int64_t capacity;
+};
+hipError_t launch_write_tree(const MarchArgs& a, const unsigned long long* chunk_offsets, const int32_t* id_map,
+                             const TreeOut* outs, hipStream_t s);
+hipError_t launch_assemble(const MarchArgs& a, float* images, hipStream_t s);
+hipError_t launch_flux(const MarchArgs& a, double* partial, int64_t n_chunks, double* flux_dev,
+                       hipStream_t s);
+hipError_t launch_fixed_flux(const float* images, int V, int nb, int64_t R, double pix_area, double* partial,
+                             double* flux_dev, hipStream_t s);
+
+constexpr int64_t CHUNK = 4096;  // positions per block in counting passes
+
+}  // namespace air

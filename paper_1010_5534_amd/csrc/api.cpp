@@ -1,0 +1,502 @@
+// Host side of the AIR C ABI: argument validation, device workspace, and the
+// level-synchronous launch sequence (section 2 steps i-vi).  All device work
+// of one call is enqueued on the caller's stream; the host waits once, at
+// the end, to return counts and fluxes.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "air_common.h"
+
+using namespace air;
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+struct air_ctx {
+  int device = 0;
+  int num_cus = 256;
+  std::string err;
+  DevBuf state, valI, valN, xiI, xiN, visits, rmin, rmax, queue, ctr, chunk, vstat, idmap, partial, flux,
+      views, touts;
+  unsigned long long* host_ctr = nullptr;  // pinned
+  double* host_flux = nullptr;             // pinned
+  unsigned long long* host_vstat = nullptr;
+  size_t host_vstat_n = 0;
+  size_t host_flux_n = 0;
+  void* stage = nullptr;  // pinned staging for small uploads
+  size_t stage_n = 0;
+  // timing events: [0] start, [1] end, then a pair around every march and
+  // every test launch
+  static constexpr int NEV = 2 + 4 * AIR_MAX_LEVELS;
+  hipEvent_t ev[NEV] = {};
+};
+
+namespace {
+
+air_status fail(air_ctx* c, air_status code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  return code;
+}
+
+#define HIPCHK(ctx, expr)                                                                   \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess) return fail(ctx, AIR_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+air_status ensure(air_ctx* c, DevBuf& b, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  if (b.bytes >= bytes) return AIR_OK;
+  if (b.p) {
+    (void)hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+  size_t want = bytes + bytes / 8;  // slack so slightly larger calls do not reallocate
+  if (hipMalloc(&b.p, want) != hipSuccess) {
+    b.p = nullptr;
+    (void)hipGetLastError();
+    return fail(c, AIR_ENOMEM, "device allocation of %zu bytes failed", want);
+  }
+  b.bytes = want;
+  return AIR_OK;
+}
+
+air_status ensure_host(air_ctx* c, void** p, size_t* have, size_t bytes) {
+  if (*have >= bytes && *p) return AIR_OK;
+  if (*p) (void)hipHostFree(*p);
+  *p = nullptr;
+  if (hipHostMalloc(p, bytes) != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return fail(c, AIR_ENOMEM, "pinned host allocation of %zu bytes failed", bytes);
+  }
+  *have = bytes;
+  return AIR_OK;
+}
+
+bool finite3(const double* v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
+
+air_status check_grid(air_ctx* c, const air_grid* g) {
+  if (!g) return fail(c, AIR_EINVAL, "grid is NULL");
+  if (g->kind != AIR_GRID_UNIFORM && g->kind != AIR_GRID_BLOCK_AMR)
+    return fail(c, AIR_EINVAL, "grid kind %d unknown", g->kind);
+  if (g->kind == AIR_GRID_BLOCK_AMR) return fail(c, AIR_ENOTSUP, "block-AMR grids are not supported by this call");
+  for (int a = 0; a < 3; ++a) {
+    if (g->n[a] < 1 || g->n[a] > (1 << 20)) return fail(c, AIR_EINVAL, "grid n[%d] = %d out of range", a, g->n[a]);
+    if (!std::isfinite(g->lo[a]) || !std::isfinite(g->hi[a]) || !(g->hi[a] > g->lo[a]))
+      return fail(c, AIR_EINVAL, "grid box on axis %d is empty or not finite", a);
+  }
+  if ((int64_t)g->n[0] * g->n[1] * g->n[2] > (int64_t)INT32_MAX)
+    return fail(c, AIR_EINVAL, "grid has more than 2^31 cells");
+  return AIR_OK;
+}
+
+air_status check_field(air_ctx* c, const air_field* f) {
+  if (!f) return fail(c, AIR_EINVAL, "field is NULL");
+  if (!f->rho) return fail(c, AIR_EINVAL, "field rho is NULL");
+  if (f->kind == AIR_FIELD_RHO_J_KAPPA) {
+    if (f->n_bands != 1) return fail(c, AIR_EINVAL, "a rho/j/kappa field has exactly one band");
+    if (!f->emis || !f->kappa) return fail(c, AIR_EINVAL, "field emis/kappa is NULL");
+  } else if (f->kind == AIR_FIELD_RHO_T) {
+    if (f->n_bands < 1 || f->n_bands > AIR_MAX_BANDS)
+      return fail(c, AIR_EINVAL, "n_bands %d out of range 1..%d", f->n_bands, AIR_MAX_BANDS);
+    if (!f->temp) return fail(c, AIR_EINVAL, "field temp is NULL");
+    for (int b = 0; b < f->n_bands; ++b)
+      if (!finite3(f->band[b])) return fail(c, AIR_EINVAL, "band %d parameters not finite", b);
+  } else {
+    return fail(c, AIR_EINVAL, "field kind %d unknown", f->kind);
+  }
+  return AIR_OK;
+}
+
+air_status make_view(air_ctx* c, const air_view* v, DevView& out) {
+  if (!finite3(v->dir) || !finite3(v->up) || !finite3(v->center) || !std::isfinite(v->width) || !(v->width > 0))
+    return fail(c, AIR_EINVAL, "view has a non-finite value or width <= 0");
+  double nd = std::sqrt(v->dir[0] * v->dir[0] + v->dir[1] * v->dir[1] + v->dir[2] * v->dir[2]);
+  if (!(nd > 0)) return fail(c, AIR_EINVAL, "view direction is zero");
+  for (int a = 0; a < 3; ++a) out.d[a] = v->dir[a] / nd;
+  const double* u = v->up;
+  const double* d = out.d;
+  double x[3] = {u[1] * d[2] - u[2] * d[1], u[2] * d[0] - u[0] * d[2], u[0] * d[1] - u[1] * d[0]};
+  double nx = std::sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+  double nu = std::sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+  if (!(nx > 1e-12 * nu)) return fail(c, AIR_EINVAL, "view up vector is zero or parallel to dir");
+  for (int a = 0; a < 3; ++a) out.eu[a] = x[a] / nx;
+  out.ev[0] = d[1] * out.eu[2] - d[2] * out.eu[1];
+  out.ev[1] = d[2] * out.eu[0] - d[0] * out.eu[2];
+  out.ev[2] = d[0] * out.eu[1] - d[1] * out.eu[0];
+  for (int a = 0; a < 3; ++a) out.c[a] = v->center[a];
+  out.width = v->width;
+  return AIR_OK;
+}
+
+void fill_geo(const air_grid* g, Geo& G) {
+  std::memset(&G, 0, sizeof G);
+  G.kind = g->kind;
+  for (int a = 0; a < 3; ++a) {
+    G.n[a] = g->n[a];
+    G.lo[a] = g->lo[a];
+    G.hi[a] = g->hi[a];
+    G.h[a] = (g->hi[a] - g->lo[a]) / (double)g->n[a];
+  }
+}
+
+void fill_fld(const air_field* f, Fld& F) {
+  std::memset(&F, 0, sizeof F);
+  F.kind = f->kind;
+  F.nb = f->kind == AIR_FIELD_RHO_J_KAPPA ? 1 : f->n_bands;
+  F.rho = f->rho;
+  F.emis = f->emis;
+  F.kappa = f->kappa;
+  F.temp = f->temp;
+  for (int b = 0; b < F.nb && f->kind == AIR_FIELD_RHO_T; ++b) {
+    F.k0[b] = (float)f->band[b][0];
+    F.s[b] = (float)f->band[b][1];
+    F.q[b] = (float)f->band[b][2];
+  }
+}
+
+int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+air_status upload_views(air_ctx* c, const air_view* views, int V, hipStream_t s, const DevView** out) {
+  std::vector<DevView> hv(V);
+  for (int k = 0; k < V; ++k) {
+    air_status st = make_view(c, &views[k], hv[k]);
+    if (st) return st;
+  }
+  air_status st = ensure(c, c->views, sizeof(DevView) * V);
+  if (st) return st;
+  if ((st = ensure_host(c, &c->stage, &c->stage_n, sizeof(DevView) * V))) return st;
+  std::memcpy(c->stage, hv.data(), sizeof(DevView) * V);
+  HIPCHK(c, hipMemcpyAsync(c->views.p, c->stage, sizeof(DevView) * V, hipMemcpyHostToDevice, s));
+  *out = (const DevView*)c->views.p;
+  return AIR_OK;
+}
+
+int march_blocks(const air_ctx* c) { return c->num_cus * 8; }
+
+}  // namespace
+
+extern "C" {
+
+air_status air_create(air_ctx** out, int32_t device) {
+  if (!out) return AIR_EINVAL;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) {
+    (void)hipGetLastError();
+    return AIR_EINVAL;
+  }
+  air_ctx* c = new air_ctx();
+  c->device = device;
+  if (hipSetDevice(device) != hipSuccess) {
+    delete c;
+    return AIR_EDEVICE;
+  }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+    c->num_cus = prop.multiProcessorCount;
+  size_t have = 0;
+  if (ensure_host(c, (void**)&c->host_ctr, &have, sizeof(unsigned long long) * CTR_COUNT)) {
+    delete c;
+    return AIR_ENOMEM;
+  }
+  for (int k = 0; k < air_ctx::NEV; ++k)
+    if (hipEventCreate(&c->ev[k]) != hipSuccess) {
+      air_destroy(c);
+      return AIR_EDEVICE;
+    }
+  *out = c;
+  return AIR_OK;
+}
+
+void air_destroy(air_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  for (DevBuf* b : {&c->state, &c->valI, &c->valN, &c->xiI, &c->xiN, &c->visits, &c->rmin, &c->rmax, &c->queue,
+                    &c->ctr, &c->chunk, &c->vstat, &c->idmap, &c->partial, &c->flux, &c->views, &c->touts})
+    if (b->p) (void)hipFree(b->p);
+  if (c->host_ctr) (void)hipHostFree(c->host_ctr);
+  if (c->host_flux) (void)hipHostFree(c->host_flux);
+  if (c->host_vstat) (void)hipHostFree(c->host_vstat);
+  if (c->stage) (void)hipHostFree(c->stage);
+  for (int k = 0; k < air_ctx::NEV; ++k)
+    if (c->ev[k]) (void)hipEventDestroy(c->ev[k]);
+  delete c;
+}
+
+const char* air_last_error(const air_ctx* c) { return c ? c->err.c_str() : "context is NULL"; }
+
+air_status air_render(air_ctx* c, const air_grid* grid, const air_field* field, const air_view* views,
+                      int32_t n_views, const air_params* prm, air_tree* trees, float* images, double* flux,
+                      air_stats* stats, void* stream) {
+  if (!c) return AIR_EINVAL;
+  c->err.clear();
+  air_status st;
+  if ((st = check_grid(c, grid))) return st;
+  if ((st = check_field(c, field))) return st;
+  if (!views || n_views < 1 || n_views > AIR_MAX_VIEWS)
+    return fail(c, AIR_EINVAL, "n_views %d out of range 1..%d", n_views, AIR_MAX_VIEWS);
+  if (!prm) return fail(c, AIR_EINVAL, "params is NULL");
+  const int N0 = prm->coarse_n, Lm = prm->max_level;
+  if (N0 < 1 || N0 > 65536) return fail(c, AIR_EINVAL, "coarse_n %d out of range", N0);
+  if (Lm < 0 || Lm >= AIR_MAX_LEVELS) return fail(c, AIR_EINVAL, "max_level %d out of range 0..%d", Lm, AIR_MAX_LEVELS - 1);
+  if ((double)N0 * N0 * std::pow(4.0, Lm) > 4294967295.0)
+    return fail(c, AIR_EINVAL, "coarse_n^2 * 4^max_level exceeds 2^32 pixels per view");
+  if (!std::isfinite(prm->xi_crit_I) || !std::isfinite(prm->xi_crit_N) || prm->xi_crit_I < 0 || prm->xi_crit_N < 0)
+    return fail(c, AIR_EINVAL, "xi_crit must be finite and >= 0");
+  if (prm->flags != 0) return fail(c, AIR_EINVAL, "params.flags must be 0");
+  for (int k = 0; trees && k < n_views; ++k)
+    if (trees[k].capacity < 0) return fail(c, AIR_EINVAL, "tree %d capacity < 0", k);
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, AIR_EDEVICE, "hipSetDevice failed");
+  hipStream_t s = (hipStream_t)stream;
+
+  MarchArgs A;
+  std::memset(&A, 0, sizeof A);
+  fill_geo(grid, A.g);
+  fill_fld(field, A.f);
+  const int nb = A.f.nb, V = n_views;
+  A.img.N0 = N0;
+  A.img.Lmax = Lm;
+  A.img.V = V;
+  int64_t off = 0;
+  for (int L = 0; L <= Lm; ++L) {
+    A.img.off[L] = off;
+    off = round_up(off + ((int64_t)N0 * N0 << (2 * L)), 256);
+  }
+  for (int L = Lm + 1; L <= MAXL; ++L) A.img.off[L] = round_up(off, 256);
+  // positions per view, padded so views start on a counting chunk and the
+  // level after Lmax (the children written at Lmax-1's test) stays in range
+  const int64_t S = round_up(off, CHUNK);
+  A.img.S = S;
+  const int64_t VS = (int64_t)V * S;
+  const int64_t n_chunks = VS / CHUNK;
+  if ((st = ensure(c, c->state, VS))) return st;
+  if ((st = ensure(c, c->valI, 4 * VS * nb))) return st;
+  if ((st = ensure(c, c->valN, 4 * VS))) return st;
+  if ((st = ensure(c, c->xiI, 4 * VS))) return st;
+  if ((st = ensure(c, c->xiN, 4 * VS))) return st;
+  if ((st = ensure(c, c->visits, 4 * VS))) return st;
+  if ((st = ensure(c, c->queue, 8 * VS))) return st;
+  if ((st = ensure(c, c->ctr, 8 * CTR_COUNT))) return st;
+  if ((st = ensure(c, c->chunk, 8 * (n_chunks + 1)))) return st;
+  if ((st = ensure(c, c->vstat, 8 * V * (MAXL + 1)))) return st;
+  if ((st = ensure(c, c->partial, 8 * n_chunks * nb))) return st;
+  if ((st = ensure(c, c->flux, 8 * V * nb))) return st;
+  if (trees) {
+    if ((st = ensure(c, c->idmap, 4 * VS))) return st;
+    if ((st = ensure(c, c->touts, sizeof(TreeOut) * V))) return st;
+  }
+  A.w.state = (uint8_t*)c->state.p;
+  A.w.valI = (float*)c->valI.p;
+  A.w.valN = (float*)c->valN.p;
+  A.w.xiI = (float*)c->xiI.p;
+  A.w.xiN = (float*)c->xiN.p;
+  A.w.visits = (int*)c->visits.p;
+  A.w.queue = (uint64_t*)c->queue.p;
+  A.w.qcap = (uint64_t)VS;
+  A.w.ctr = (unsigned long long*)c->ctr.p;
+  if ((st = upload_views(c, views, V, s, &A.views))) return st;
+
+  float w[MAXB];
+  for (int b = 0; b < MAXB; ++b) w[b] = b < nb ? prm->band_weight[b] : 0.0f;
+
+  // the level loop: trace the queue of new nodes, then test, close and
+  // compact; the queue bounds live in device counters, so no host round trip
+  hipEvent_t* ev = c->ev;
+  HIPCHK(c, hipEventRecord(ev[0], s));
+  HIPCHK(c, launch_init(A, s));
+  for (int L = 0; L <= Lm; ++L) {
+    HIPCHK(c, hipEventRecord(ev[2 + 4 * L], s));
+    HIPCHK(c, launch_march_queue(A, L, march_blocks(c), s));
+    HIPCHK(c, hipEventRecord(ev[3 + 4 * L], s));
+    if (L < Lm) HIPCHK(c, launch_refine(A, L, prm->xi_crit_I, prm->xi_crit_N, w, 2048, s));
+    HIPCHK(c, hipEventRecord(ev[4 + 4 * L], s));
+  }
+  unsigned long long* chunk = (unsigned long long*)c->chunk.p;
+  unsigned long long* vstat = (unsigned long long*)c->vstat.p;
+  HIPCHK(c, hipMemsetAsync(vstat, 0, 8 * V * (MAXL + 1), s));
+  HIPCHK(c, launch_count(A, chunk, n_chunks, vstat, s));
+  if (trees) {
+    HIPCHK(c, launch_scan(chunk, n_chunks, s));
+    HIPCHK(c, launch_emit(A, chunk, n_chunks, (int32_t*)c->idmap.p, s));
+    std::vector<TreeOut> to(V);
+    for (int k = 0; k < V; ++k) {
+      const air_tree& t = trees[k];
+      to[k] = TreeOut{t.level, t.ix, t.iy, t.parent, t.first_child, t.state, t.I, t.N, t.xi_I, t.xi_N,
+                      t.visits, t.capacity};
+    }
+    // the views' staging copy above must land before the buffer is reused
+    HIPCHK(c, hipStreamSynchronize(s));
+    if ((st = ensure_host(c, &c->stage, &c->stage_n, sizeof(TreeOut) * V))) return st;
+    std::memcpy(c->stage, to.data(), sizeof(TreeOut) * V);
+    HIPCHK(c, hipMemcpyAsync(c->touts.p, c->stage, sizeof(TreeOut) * V, hipMemcpyHostToDevice, s));
+    HIPCHK(c, launch_write_tree(A, chunk, (const int32_t*)c->idmap.p, (const TreeOut*)c->touts.p, s));
+  }
+  if (images) HIPCHK(c, launch_assemble(A, images, s));
+  if (flux) HIPCHK(c, launch_flux(A, (double*)c->partial.p, n_chunks, (double*)c->flux.p, s));
+
+  HIPCHK(c, hipEventRecord(ev[1], s));
+  // one wait: counters, per-view counts, fluxes
+  if ((st = ensure_host(c, (void**)&c->host_vstat, &c->host_vstat_n, 8 * V * (MAXL + 1)))) return st;
+  HIPCHK(c, hipMemcpyAsync(c->host_ctr, A.w.ctr, 8 * CTR_COUNT, hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipMemcpyAsync(c->host_vstat, vstat, 8 * V * (MAXL + 1), hipMemcpyDeviceToHost, s));
+  if (flux) {
+    if ((st = ensure_host(c, (void**)&c->host_flux, &c->host_flux_n, 8 * V * nb))) return st;
+    HIPCHK(c, hipMemcpyAsync(c->host_flux, c->flux.p, 8 * V * nb, hipMemcpyDeviceToHost, s));
+  }
+  HIPCHK(c, hipStreamSynchronize(s));
+  const unsigned long long* hc = c->host_ctr;
+  if (hc[CTR_OVERFLOW]) return fail(c, AIR_EDEVICE, "internal work queue overflow");
+  if (flux) std::memcpy(flux, c->host_flux, 8 * V * nb);
+  if (stats) {
+    std::memset(stats, 0, sizeof *stats);
+    stats->hits = (int64_t)hc[CTR_HITS];
+    stats->visits = (int64_t)hc[CTR_VISITS];
+    stats->leaves = (int64_t)hc[CTR_LEAVES];
+    stats->tested = (int64_t)hc[CTR_TESTED];
+    stats->flagged = (int64_t)hc[CTR_FLAGGED];
+    stats->balance = (int64_t)hc[CTR_BALANCE];
+    for (int L = 0; L < MAXL; ++L) {
+      stats->rays_per_level[L] = (int64_t)hc[CTR_NODES + L];
+      stats->rays += stats->rays_per_level[L];
+      if (hc[CTR_NODES + L]) stats->depth = L;
+    }
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, ev[0], ev[1]) == hipSuccess) stats->ms_total = ms;
+    for (int L = 0; L <= Lm; ++L) {
+      if (hipEventElapsedTime(&ms, ev[2 + 4 * L], ev[3 + 4 * L]) == hipSuccess) stats->ms_march += ms;
+      if (hipEventElapsedTime(&ms, ev[3 + 4 * L], ev[4 + 4 * L]) == hipSuccess) stats->ms_test += ms;
+    }
+    stats->march_launches = Lm + 1;
+  }
+  air_status res = AIR_OK;
+  for (int k = 0; trees && k < V; ++k) {
+    const unsigned long long* vs = c->host_vstat + (size_t)k * (MAXL + 1);
+    int64_t n = 0;
+    for (int L = 0; L < MAXL; ++L) {
+      trees[k].n_per_level[L] = (int64_t)vs[L];
+      n += (int64_t)vs[L];
+    }
+    trees[k].n_nodes = n;
+    trees[k].n_leaves = (int64_t)vs[MAXL];
+    if (n > trees[k].capacity)
+      res = fail(c, AIR_ECAPACITY, "tree %d needs %lld nodes, capacity %lld", k, (long long)n,
+                 (long long)trees[k].capacity);
+  }
+  return res;
+}
+
+air_status air_render_fixed(air_ctx* c, const air_grid* grid, const air_field* field, const air_view* views,
+                            int32_t n_views, int32_t coarse_n, int32_t level, float* images, double* flux,
+                            air_stats* stats, void* stream) {
+  if (!c) return AIR_EINVAL;
+  c->err.clear();
+  air_status st;
+  if ((st = check_grid(c, grid))) return st;
+  if ((st = check_field(c, field))) return st;
+  if (!views || n_views < 1 || n_views > AIR_MAX_VIEWS)
+    return fail(c, AIR_EINVAL, "n_views %d out of range 1..%d", n_views, AIR_MAX_VIEWS);
+  if (coarse_n < 1 || level < 0 || level >= AIR_MAX_LEVELS)
+    return fail(c, AIR_EINVAL, "coarse_n %d / level %d out of range", coarse_n, level);
+  const int64_t R = (int64_t)coarse_n << level;
+  if ((double)R * R > 4294967295.0) return fail(c, AIR_EINVAL, "raster exceeds 2^32 pixels per view");
+  if (flux && !images) return fail(c, AIR_EINVAL, "flux needs the image buffer");
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, AIR_EDEVICE, "hipSetDevice failed");
+  hipStream_t s = (hipStream_t)stream;
+  MarchArgs A;
+  std::memset(&A, 0, sizeof A);
+  fill_geo(grid, A.g);
+  fill_fld(field, A.f);
+  const int nb = A.f.nb;
+  A.img.N0 = coarse_n;
+  A.img.Lmax = level;
+  A.img.V = n_views;
+  if ((st = ensure(c, c->ctr, 8 * CTR_COUNT))) return st;
+  A.w.ctr = (unsigned long long*)c->ctr.p;
+  if ((st = upload_views(c, views, n_views, s, &A.views))) return st;
+  HIPCHK(c, hipMemsetAsync(A.w.ctr, 0, 8 * CTR_COUNT, s));
+  HIPCHK(c, hipEventRecord(c->ev[0], s));
+  HIPCHK(c, hipEventRecord(c->ev[2], s));
+  HIPCHK(c, launch_march_fixed(A, level, images, march_blocks(c), s));
+  HIPCHK(c, hipEventRecord(c->ev[3], s));
+  const int64_t cpp = (R * R + CHUNK - 1) / CHUNK;
+  if (flux) {
+    if ((st = ensure(c, c->partial, 8 * (size_t)n_views * nb * cpp))) return st;
+    if ((st = ensure(c, c->flux, 8 * (size_t)n_views * nb))) return st;
+    // every view has the same pixel size only if widths agree: reduce per view
+    std::vector<double> area(n_views);
+    for (int k = 0; k < n_views; ++k) {
+      double px = views[k].width / (double)R;
+      area[k] = px * px;
+    }
+    for (int k = 0; k < n_views; ++k)
+      HIPCHK(c, launch_fixed_flux(images + (size_t)k * (nb + 1) * R * R, 1, nb, R, area[k],
+                                  (double*)c->partial.p + (size_t)k * nb * cpp, (double*)c->flux.p + k * nb, s));
+  }
+  HIPCHK(c, hipEventRecord(c->ev[1], s));
+  HIPCHK(c, hipMemcpyAsync(c->host_ctr, A.w.ctr, 8 * CTR_COUNT, hipMemcpyDeviceToHost, s));
+  if (flux) {
+    if ((st = ensure_host(c, (void**)&c->host_flux, &c->host_flux_n, 8 * n_views * nb))) return st;
+    HIPCHK(c, hipMemcpyAsync(c->host_flux, c->flux.p, 8 * n_views * nb, hipMemcpyDeviceToHost, s));
+  }
+  HIPCHK(c, hipStreamSynchronize(s));
+  if (flux) std::memcpy(flux, c->host_flux, 8 * n_views * nb);
+  if (stats) {
+    std::memset(stats, 0, sizeof *stats);
+    stats->rays = (int64_t)n_views * R * R;
+    stats->rays_per_level[level] = stats->rays;
+    stats->hits = (int64_t)c->host_ctr[CTR_HITS];
+    stats->visits = (int64_t)c->host_ctr[CTR_VISITS];
+    stats->leaves = stats->rays;
+    stats->depth = level;
+    stats->march_launches = 1;
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, c->ev[0], c->ev[1]) == hipSuccess) stats->ms_total = ms;
+    if (hipEventElapsedTime(&ms, c->ev[2], c->ev[3]) == hipSuccess) stats->ms_march = ms;
+  }
+  return AIR_OK;
+}
+
+air_status air_trace_pixels(air_ctx* c, const air_grid* grid, const air_field* field, const air_view* view,
+                            int32_t coarse_n, int64_t n, const int32_t* level, const int32_t* ix,
+                            const int32_t* iy, float* I, float* N, int32_t* visits, void* stream) {
+  if (!c) return AIR_EINVAL;
+  c->err.clear();
+  air_status st;
+  if ((st = check_grid(c, grid))) return st;
+  if ((st = check_field(c, field))) return st;
+  if (!view) return fail(c, AIR_EINVAL, "view is NULL");
+  if (coarse_n < 1 || n < 0) return fail(c, AIR_EINVAL, "coarse_n or n out of range");
+  if (n > 0 && (!level || !ix || !iy || !I)) return fail(c, AIR_EINVAL, "level/ix/iy/I must not be NULL");
+  if (n == 0) return AIR_OK;
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, AIR_EDEVICE, "hipSetDevice failed");
+  hipStream_t s = (hipStream_t)stream;
+  MarchArgs A;
+  std::memset(&A, 0, sizeof A);
+  fill_geo(grid, A.g);
+  fill_fld(field, A.f);
+  A.img.N0 = coarse_n;
+  A.img.V = 1;
+  if ((st = upload_views(c, view, 1, s, &A.views))) return st;
+  HIPCHK(c, launch_trace_pixels(A, n, level, ix, iy, I, N, visits, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  return AIR_OK;
+}
+
+}  // extern "C"

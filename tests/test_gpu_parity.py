@@ -1,0 +1,308 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
+same seeded inputs.  Values within 1e-5 relative per node; flags identical
+except at nodes the oracle itself marks ambiguous (see parity.py); misses
+exactly zero."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle
+import parity
+from paper_1010_5534_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1010_5534_amd import air
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = air.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def gauss():
+    from paper_1010_5534_amd import air
+    g, f = inputs.gaussian()
+    return g, f, air.upload(g, f)
+
+
+def test_fixed_levels_match_oracle(ctx, gauss):
+    g, f, scene = gauss
+    v = inputs.gaussian_view()
+    for L in range(5):
+        say(f"fixed gaussian64 N0=16 L={L}")
+        img, flux, st = ctx.render_fixed(scene, [v], 16, L)
+        ref = oracle.render_fixed(g, f, v, 16, L)
+        gi = img[0].cpu().numpy().astype(np.float64)
+        assert parity.rel_err(gi[0], ref["I"][0]).max() <= 1e-5
+        assert parity.rel_err(gi[1], ref["N"]).max() <= 1e-5
+        R = 16 << L
+        exact_flux = float(np.sum(ref["I"][0])) / (R * R)
+        assert flux[0][0] == pytest.approx(exact_flux, rel=1e-5)
+        assert st["rays"] == R * R and st["hits"] == R * R
+
+
+@pytest.mark.parametrize("direction", [(1, 1, 1), (1, 0, 0), (0.3, -0.8, 0.52), (0, 1, 0), (-1, -0.2, 0.1)])
+def test_fixed_oblique_views(ctx, direction):
+    from paper_1010_5534_amd import air
+    g, f = inputs.winds2(seed=1, n=48)
+    scene = air.upload(g, f)
+    v = inputs.view_for(direction)
+    say(f"fixed winds2 n=48 dir={direction} N0=12 L=3")
+    img, _, st = ctx.render_fixed(scene, [v], 12, 3)
+    ref = oracle.render_fixed(g, f, v, 12, 3)
+    gi = img[0].cpu().numpy().astype(np.float64)
+    assert parity.rel_err(gi[0], ref["I"][0]).max() <= 1e-5
+    assert parity.rel_err(gi[1], ref["N"]).max() <= 1e-5
+    # misses are exact zeros on both sides
+    assert np.array_equal(gi[0] == 0, ref["I"][0] == 0)
+
+
+@pytest.mark.parametrize("xc", [0.2, 0.5, 0.8])
+def test_air_tree_parity_gaussian(ctx, gauss, xc):
+    from paper_1010_5534_amd import air
+    g, f, scene = gauss
+    v = inputs.gaussian_view()
+    say(f"air gaussian64 N0=16 Lmax=4 xi_crit={xc}")
+    trees, img, flux, st = ctx.render(scene, [v], air.params(16, 4, xc))
+    t = oracle.air(g, f, v, 16, 4, xc)
+    gd = parity.gpu_dense(trees[0], 16, 4, 1)
+    rep = parity.compare(gd, t, xc)
+    say({k: (v if not isinstance(v, list) else len(v)) for k, v in rep.items()})
+    parity.assert_parity(rep)
+    assert st["rays"] == trees[0].n_nodes
+    if rep["flips"] == 0:
+        assert trees[0].n_nodes == t.nodes
+        ref_flux = oracle.leaf_flux(t, 1.0, t.flat_I[0])
+        assert flux[0][0] == pytest.approx(ref_flux, rel=1e-5)
+        ref_img = oracle.paint_leaves(t, t.flat_I[0])
+        assert parity.rel_err(img[0, 0].cpu().numpy(), ref_img).max() <= 1e-5
+
+
+def test_full_refinement_equals_fixed_bitwise(ctx, gauss):
+    from paper_1010_5534_amd import air
+    g, f, scene = gauss
+    v = inputs.gaussian_view()
+    trees, img, flux, st = ctx.render(scene, [v], air.params(16, 4, 0.0))
+    assert trees[0].n_per_level[:5] == [(16 << L) ** 2 for L in range(5)]
+    fimg, fflux, _ = ctx.render_fixed(scene, [v], 16, 4)
+    assert torch.equal(img, fimg)
+
+
+def test_no_refinement_above_one(ctx, gauss):
+    from paper_1010_5534_amd import air
+    g, f, scene = gauss
+    trees, img, flux, st = ctx.render(scene, [inputs.gaussian_view()], air.params(16, 4, 1.01))
+    assert trees[0].n_nodes == 256 and st["rays"] == 256 and st["flagged"] == 0
+
+
+def test_batched_views_equal_single_views_bitwise(ctx):
+    from paper_1010_5534_amd import air
+    g, f = inputs.winds2(seed=2, n=64)
+    scene = air.upload(g, f)
+    views = inputs.winds2_views()
+    prm = air.params(16, 3, 0.5)
+    trees, img, flux, _ = ctx.render(scene, views, prm)
+    for k, v in enumerate(views):
+        t1, i1, f1, _ = ctx.render(scene, [v], prm)
+        assert t1[0].n_nodes == trees[k].n_nodes
+        for name in ("level", "ix", "iy", "parent", "first_child", "state", "I", "N", "visits"):
+            assert torch.equal(getattr(t1[0], name), getattr(trees[k], name)), name
+        assert torch.equal(i1[0], img[k])
+        assert f1[0][0] == flux[k][0]
+
+
+def test_run_twice_bitwise(ctx):
+    from paper_1010_5534_amd import air
+    g, f = inputs.winds2(seed=3, n=64)
+    scene = air.upload(g, f)
+    prm = air.params(16, 4, 0.3)
+    a = ctx.render(scene, inputs.winds2_views(), prm)
+    b = ctx.render(scene, inputs.winds2_views(), prm)
+    for ta, tb in zip(a[0], b[0]):
+        assert ta.n_nodes == tb.n_nodes
+        assert torch.equal(ta.I, tb.I) and torch.equal(ta.state, tb.state)
+        # bit patterns, so the NaN of non-evaluated nodes compares equal
+        assert torch.equal(ta.xi_I.view(torch.int32), tb.xi_I.view(torch.int32))
+    assert torch.equal(a[1], b[1])
+    assert np.array_equal(a[2], b[2])
+
+
+@pytest.mark.parametrize("seed,direction", [(0, (0, 0, 1)), (4, (1, 1, 1)), (5, (0.2, 0.9, -0.4))])
+def test_air_tree_parity_winds(ctx, seed, direction):
+    from paper_1010_5534_amd import air
+    g, f = inputs.winds2(seed=seed, n=64)
+    scene = air.upload(g, f)
+    v = inputs.view_for(direction)
+    say(f"air winds2 n=64 seed={seed} dir={direction} N0=16 Lmax=4")
+    trees, img, flux, st = ctx.render(scene, [v], air.params(16, 4, 0.5))
+    t = oracle.air(g, f, v, 16, 4, 0.5)
+    rep = parity.compare(parity.gpu_dense(trees[0], 16, 4, 1), t, 0.5)
+    say({k: (v if not isinstance(v, list) else len(v)) for k, v in rep.items()})
+    parity.assert_parity(rep)
+
+
+def test_multiband_rho_t(ctx):
+    from paper_1010_5534_amd import air
+    bands = inputs.default_bands(4)
+    g, f = inputs.winds2(seed=6, n=48, kind=inputs.FIELD_RHO_T, bands=bands)
+    scene = air.upload(g, f)
+    v = inputs.view_for((0.4, 0.5, 0.77))
+    w = [1.0, 0.5, 2.0, 0.25]
+    say("air winds2 rho/T 4 bands n=48 N0=12 Lmax=3")
+    trees, img, flux, st = ctx.render(scene, [v], air.params(12, 3, 0.5, band_weight=w))
+    t = oracle.air(g, f, v, 12, 3, 0.5, band_w=w)
+    rep = parity.compare(parity.gpu_dense(trees[0], 12, 3, 4), t, 0.5, band_w=w)
+    say({k: (v if not isinstance(v, list) else len(v)) for k, v in rep.items()})
+    parity.assert_parity(rep)
+    fimg, fflux, _ = ctx.render_fixed(scene, [v], 12, 3)
+    ref = oracle.render_fixed(g, f, v, 12, 3)
+    for b in range(4):
+        assert parity.rel_err(fimg[0, b].cpu().numpy(), ref["I"][b]).max() <= 1e-5
+
+
+def test_column_refinement_variable(ctx, gauss):
+    """N as a second refinement variable, OR-ed with I."""
+    from paper_1010_5534_amd import air
+    g, f, scene = gauss
+    v = inputs.gaussian_view()
+    trees, _, _, _ = ctx.render(scene, [v], air.params(16, 3, 1.01, 0.5))
+    t = oracle.air(g, f, v, 16, 3, 1.01, 0.5)
+    rep = parity.compare(parity.gpu_dense(trees[0], 16, 3, 1), t, 1.01, 0.5)
+    parity.assert_parity(rep)
+    assert t.nodes > 256
+
+
+@pytest.mark.parametrize("N0,Lmax", [(1, 3), (13, 2), (7, 0), (2, 5)])
+def test_ragged_and_degenerate_images(ctx, N0, Lmax):
+    from paper_1010_5534_amd import air
+    g, f = inputs.winds2(seed=7, n=40)
+    scene = air.upload(g, f)
+    v = inputs.view_for((0.1, 0.2, 1.0), width=1.3)
+    say(f"air winds2 n=40 N0={N0} Lmax={Lmax}")
+    trees, img, flux, st = ctx.render(scene, [v], air.params(N0, Lmax, 0.3))
+    t = oracle.air(g, f, v, N0, Lmax, 0.3)
+    rep = parity.compare(parity.gpu_dense(trees[0], N0, Lmax, 1), t, 0.3)
+    parity.assert_parity(rep)
+
+
+def test_view_missing_the_grid(ctx, gauss):
+    from paper_1010_5534_amd import air
+    g, f, scene = gauss
+    v = inputs.View((0, 0, 1), (0, 1, 0), (5.0, 5.0, 0.5), 1.0)
+    trees, img, flux, st = ctx.render(scene, [v], air.params(8, 3, 0.0))
+    assert st["hits"] == 0
+    assert torch.count_nonzero(img).item() == 0 and flux[0][0] == 0.0
+
+
+def test_offset_box_nonuniform_cells(ctx):
+    from paper_1010_5534_amd import air
+    rng = np.random.default_rng(9)
+    n = (20, 33, 17)
+    shape = (n[2], n[1], n[0])
+    g = inputs.Grid(inputs.GRID_UNIFORM, n, (-0.7, 0.1, 2.0), (0.9, 1.3, 2.6))
+    f = inputs.Field(0, rng.uniform(0.1, 2, shape).astype(np.float32),
+                     rng.uniform(0.1, 2, shape).astype(np.float32), rng.uniform(0.1, 3, shape).astype(np.float32))
+    scene = air.upload(g, f)
+    v = inputs.View((0.3, -0.4, 0.8), (0, 0, 1), (0.1, 0.7, 2.3), 2.0)
+    img, _, _ = ctx.render_fixed(scene, [v], 10, 3)
+    ref = oracle.render_fixed(g, f, v, 10, 3)
+    assert parity.rel_err(img[0, 0].cpu().numpy(), ref["I"][0]).max() <= 1e-5
+    assert parity.rel_err(img[0, 1].cpu().numpy(), ref["N"]).max() <= 1e-5
+
+
+def test_trace_pixels_matches_oracle(ctx):
+    from paper_1010_5534_amd import air
+    g, f = inputs.winds2(seed=0, n=64)
+    scene = air.upload(g, f)
+    v = inputs.view_for((1, 1, 1))
+    rng = np.random.default_rng(1)
+    L = rng.integers(0, 6, 3000)
+    R = 16 << L
+    i = (rng.uniform(size=3000) * R).astype(np.int64)
+    j = (rng.uniform(size=3000) * R).astype(np.int64)
+    I, N, vis = ctx.trace_pixels(scene, v, 16, L, i, j)
+    ref = oracle.trace_pixels(g, f, v, 16, L, i, j)
+    assert parity.rel_err(I[0].cpu().numpy(), ref["I"][0]).max() <= 1e-5
+    assert parity.rel_err(N.cpu().numpy(), ref["N"]).max() <= 1e-5
+
+
+def test_argument_errors(ctx, gauss):
+    from paper_1010_5534_amd import air
+    g, f, scene = gauss
+    v = inputs.gaussian_view()
+    bad = [
+        (inputs.View((0, 0, 0), (0, 1, 0), (0.5, 0.5, 0.5), 1.0), air.params(8, 2)),
+        (inputs.View((0, 1, 0), (0, 2, 0), (0.5, 0.5, 0.5), 1.0), air.params(8, 2)),
+        (inputs.View((0, 0, 1), (0, 1, 0), (0.5, 0.5, 0.5), float("nan")), air.params(8, 2)),
+        (v, air.params(0, 2)),
+        (v, air.params(8, 12)),
+        (v, air.params(4096, 10)),
+        (v, air.params(8, 2, -0.1)),
+    ]
+    for view, prm in bad:
+        with pytest.raises(air.AirError) as e:
+            ctx.render(scene, [view], prm, want_tree=False, want_image=False, want_flux=False)
+        assert e.value.code == air.AIR_EINVAL
+    prm = air.params(8, 2)
+    prm.flags = 1
+    with pytest.raises(air.AirError):
+        ctx.render(scene, [v], prm, want_tree=False, want_image=False, want_flux=False)
+    # a block-AMR grid through the uniform path is refused before any launch
+    ga = inputs.amr_from_predicate(2, 4, 1, lambda *a: False)
+    fa = inputs.Field(0, np.ones(ga.n_cells, np.float32), np.ones(ga.n_cells, np.float32),
+                      np.ones(ga.n_cells, np.float32))
+    with pytest.raises(air.AirError) as e:
+        ctx.render(air.upload(ga, fa), [v], air.params(8, 2), want_tree=False, want_image=False, want_flux=False)
+    assert e.value.code == air.AIR_ENOTSUP
+
+
+def test_capacity_error_reports_needed_size(ctx, gauss):
+    import ctypes as C
+    from paper_1010_5534_amd import air
+    g, f, scene = gauss
+    v = inputs.gaussian_view()
+    prm = air.params(16, 4, 0.5)
+    trees = (air.air_tree * 1)()
+    s, keep = ctx._alloc_tree(100, 1)
+    trees[0] = s
+    vs = air._views([v])
+    rc = air.lib().air_render(ctx._p, C.addressof(scene.grid), C.addressof(scene.field), C.addressof(vs), 1,
+                              C.addressof(prm), C.addressof(trees), None, None, None,
+                              torch.cuda.current_stream().cuda_stream)
+    assert rc == air.AIR_ECAPACITY
+    full, _, _, _ = ctx.render(scene, [v], prm)
+    assert trees[0].n_nodes == full[0].n_nodes > 100
+
+
+def test_tree_links_consistent(ctx, gauss):
+    from paper_1010_5534_amd import air
+    g, f, scene = gauss
+    trees, _, _, _ = ctx.render(scene, [inputs.gaussian_view()], air.params(16, 4, 0.5))
+    t = trees[0]
+    lv = t.level.cpu().numpy().astype(int)
+    ix, iy = t.ix.cpu().numpy(), t.iy.cpu().numpy()
+    par, fc = t.parent.cpu().numpy(), t.first_child.cpu().numpy()
+    st = t.state.cpu().numpy()
+    assert np.all(np.diff(lv) >= 0)  # canonical order: by level
+    for k in np.nonzero(lv > 0)[0][:5000]:
+        p = par[k]
+        assert lv[p] == lv[k] - 1 and ix[p] == ix[k] // 2 and iy[p] == iy[k] // 2
+    for k in np.nonzero(fc >= 0)[0][:5000]:
+        c = fc[k]
+        assert np.all(par[c:c + 4] == k)
+        assert set(zip(ix[c:c + 4] - 2 * ix[k], iy[c:c + 4] - 2 * iy[k])) == {(0, 0), (1, 0), (0, 1), (1, 1)}
+    assert np.array_equal(fc >= 0, (st & air.NODE_REFINED) > 0)
