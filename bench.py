@@ -87,7 +87,7 @@ def main():
     g, f = inputs.winds2(SEED, NGRID)
     views = inputs.winds2_views()
     ctx = air.Context(0)
-    scene = air.upload(g, f)
+    scene = ctx.prepare(air.upload(g, f))
     prm = air.params(N0, LMAX, XI_CRIT)
     torch.cuda.synchronize()
 

@@ -90,6 +90,8 @@ typedef struct {
   const float* kappa; /* opacity (RHO_J_KAPPA) */
   const float* temp;  /* temperature (RHO_T) */
   double band[AIR_MAX_BANDS][3]; /* host values (k0, s, q) per band (RHO_T) */
+  const void* packed; /* device, may be NULL: the march layout written by air_field_pack for these
+                         arrays; when NULL every call packs into context memory first */
 } air_field;
 
 /* Orthographic view (section 3 uses a face-on view along an axis). */
@@ -150,6 +152,24 @@ typedef struct {
 } air_stats;
 
 typedef struct air_ctx air_ctx;
+
+/* Bytes of the march layout of a field on a uniform grid, or a negative
+ * air_status for invalid arguments. */
+int64_t air_field_packed_bytes(const air_grid* grid, const air_field* field);
+
+/*
+ * Write the march layout of `field` into `packed` (device, `bytes` >=
+ * air_field_packed_bytes): the cells are grouped in 2x2x2 bricks (brick
+ * index x fastest over ceil(n/2) bricks per axis; cell inside the brick
+ * x&1 | (y&1)<<1 | (z&1)<<2) and each cell's values are adjacent, 16 B
+ * (rho, j, kappa, 0) for RHO_J_KAPPA or 8 B (rho, T) for RHO_T, so one brick
+ * of a one-band field is one 128-byte cache line and a visit is one load.
+ * Pass the buffer as field->packed to later calls; it holds a copy, so it
+ * must be packed again after the arrays change.  Errors: EINVAL (sizes,
+ * NULL pointers), ENOTSUP (block-AMR grids, packed size >= 4 GiB).
+ */
+air_status air_field_pack(air_ctx* ctx, const air_grid* grid, const air_field* field, void* packed,
+                          int64_t bytes, void* stream);
 
 /* Create a context on HIP device `device`.  The context owns device
  * workspace (per-level pixel maps, work queue, counters) that grows on demand

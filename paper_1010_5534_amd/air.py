@@ -19,7 +19,8 @@ GRID_UNIFORM, GRID_BLOCK_AMR = 0, 1
 FIELD_RHO_J_KAPPA, FIELD_RHO_T = 0, 1
 NODE_EXIST, NODE_TESTED, NODE_FLAGGED, NODE_BALANCE, NODE_REFINED, NODE_EVALUATED = 1, 2, 4, 8, 16, 32
 
-EXPORTS = ("air_create", "air_destroy", "air_last_error", "air_render", "air_render_fixed", "air_trace_pixels")
+EXPORTS = ("air_create", "air_destroy", "air_last_error", "air_render", "air_render_fixed", "air_trace_pixels",
+           "air_field_packed_bytes", "air_field_pack")
 
 
 class AirError(RuntimeError):
@@ -36,7 +37,8 @@ class air_grid(C.Structure):
 
 class air_field(C.Structure):
     _fields_ = [("kind", C.c_int32), ("n_bands", C.c_int32), ("rho", C.c_void_p), ("emis", C.c_void_p),
-                ("kappa", C.c_void_p), ("temp", C.c_void_p), ("band", (C.c_double * 3) * MAX_BANDS)]
+                ("kappa", C.c_void_p), ("temp", C.c_void_p), ("band", (C.c_double * 3) * MAX_BANDS),
+                ("packed", C.c_void_p)]
 
 
 class air_view(C.Structure):
@@ -85,6 +87,10 @@ def lib():
         L.air_render_fixed.restype = C.c_int32
         L.air_trace_pixels.argtypes = [vp, vp, vp, vp, C.c_int32, C.c_int64, vp, vp, vp, vp, vp, vp, vp]
         L.air_trace_pixels.restype = C.c_int32
+        L.air_field_packed_bytes.argtypes = [vp, vp]
+        L.air_field_packed_bytes.restype = C.c_int64
+        L.air_field_pack.argtypes = [vp, vp, vp, vp, C.c_int64, vp]
+        L.air_field_pack.restype = C.c_int32
         _lib = L
     return _lib
 
@@ -220,6 +226,20 @@ class Context:
 
     def _stream(self):
         return _torch().cuda.current_stream(self.device).cuda_stream
+
+    def prepare(self, scene: DeviceScene) -> DeviceScene:
+        """Write the field's march layout once (air_field_pack) and attach it,
+        so renders skip the per-call packing."""
+        torch = _torch()
+        nbytes = lib().air_field_packed_bytes(C.addressof(scene.grid), C.addressof(scene.field))
+        if nbytes < 0:
+            raise AirError(int(nbytes), "air_field_packed_bytes failed")
+        buf = torch.empty(int(nbytes), dtype=torch.uint8, device=f"cuda:{self.device}")
+        self._check(lib().air_field_pack(self._p, C.addressof(scene.grid), C.addressof(scene.field), buf.data_ptr(),
+                                         int(nbytes), self._stream()))
+        scene.tensors.append(buf)
+        scene.field.packed = buf.data_ptr()
+        return scene
 
     def _alloc_tree(self, cap, nb):
         torch = _torch()

@@ -11,6 +11,7 @@ namespace air {
 constexpr int MAXL = AIR_MAX_LEVELS;
 constexpr int MAXB = AIR_MAX_BANDS;
 constexpr int WAVE = 64;
+constexpr int MAX_SEG = 8;  // at most 8 waves (sub-intervals) per ray tile
 
 // node state bits beyond the public ones: set by the march once the node's
 // values are written (the refinement test reads only traced values)
@@ -19,6 +20,7 @@ constexpr uint8_t ST_TRACED = 64u;
 // view, precomputed on the host in double precision
 struct DevView {
   double d[3], eu[3], ev[3], c[3];
+  double inv_d[3];  // 1/d per axis (0 where d = 0)
   double width;
 };
 
@@ -28,6 +30,8 @@ struct Geo {
   int n[3];       // uniform: cells per axis; AMR: base blocks per axis
   double lo[3], hi[3];
   double h[3];    // uniform cell size; AMR: base block size
+  double inv_h[3];
+  int seg_shift;  // rays are traced by 2^seg_shift lanes (equal parameter sub-intervals)
   int bs, max_level, n_blocks;
   const int* bchild;
   const int* bcoord;
@@ -37,6 +41,9 @@ struct Geo {
 // cell data
 struct Fld {
   int kind, nb;
+  const void* packed;  // bricked march layout (see air_field_pack)
+  uint32_t packed_bytes;
+  int bnx, bny, bnz;   // bricks per axis
   const float* rho;
   const float* emis;
   const float* kappa;
@@ -58,15 +65,15 @@ enum : int {
   CTR_OVERFLOW = 1,       // set when an append would pass the capacity
   CTR_LSTART = 2,         // [MAXL + 2] queue start of each level
   CTR_TILE = CTR_LSTART + MAXL + 2,  // [MAXL + 1] march tile tickets per level
+  // march statistics, spread over CTR_SLOTS addresses so that concurrent
+  // blocks rarely add to the same word (same-address atomics serialise)
   CTR_HITS = CTR_TILE + MAXL + 1,
-  CTR_VISITS,
-  CTR_TESTED,
-  CTR_FLAGGED,
-  CTR_BALANCE,
-  CTR_LEAVES,
-  CTR_NODES,              // [MAXL] per-level node counts
-  CTR_COUNT = CTR_NODES + MAXL
+  CTR_VISITS = CTR_HITS + 64,
+  CTR_COUNT = CTR_VISITS + 64
 };
+constexpr int CTR_SLOTS = 64;
+// per (view, level) record of the tree counters, filled by the reduce pass
+enum : int { VS_NODES = 0, VS_LEAVES, VS_TESTED, VS_FLAGGED, VS_BALANCE, VS_N };
 
 struct Work {
   uint8_t* state;   // [V*S]
@@ -135,14 +142,24 @@ struct MarchArgs {
 };
 
 hipError_t launch_init(const MarchArgs& a, hipStream_t s);
+hipError_t launch_pack(const Geo& g, const Fld& f, void* packed, hipStream_t s);
+// bytes per packed cell
+inline int packed_cell_bytes(int field_kind) { return field_kind == AIR_FIELD_RHO_J_KAPPA ? 16 : 8; }
+
+// packed index of cell (x, y, z): 2x2x2 bricks, x fastest
+__host__ __device__ inline int brick_index(int x, int y, int z, int bnx, int bny) {
+  return ((((z >> 1) * bny + (y >> 1)) * bnx + (x >> 1)) << 3) | (x & 1) | ((y & 1) << 1) | ((z & 1) << 2);
+}
 hipError_t launch_march_queue(const MarchArgs& a, int L, int grid_blocks, hipStream_t s);
 hipError_t launch_refine(const MarchArgs& a, int L, float xcI, float xcN, const float* w, int grid_blocks,
                          hipStream_t s);
 hipError_t launch_march_fixed(const MarchArgs& a, int level, float* images, int grid_blocks, hipStream_t s);
 hipError_t launch_trace_pixels(const MarchArgs& a, int64_t n, const int32_t* level, const int32_t* ix,
                                const int32_t* iy, float* I, float* N, int32_t* visits, hipStream_t s);
-hipError_t launch_count(const MarchArgs& a, unsigned long long* chunk_counts, int64_t n_chunks,
-                        unsigned long long* vstat, hipStream_t s);
+// per chunk: existing nodes (chunk_counts) and the other counters
+// (chunk_stats[VS_N][n_chunks]); then per (view, level) sums in vstat
+hipError_t launch_count(const MarchArgs& a, unsigned long long* chunk_counts, unsigned* chunk_stats,
+                        int64_t n_chunks, unsigned long long* vstat, hipStream_t s);
 hipError_t launch_scan(unsigned long long* chunk_counts, int64_t n_chunks, hipStream_t s);
 hipError_t launch_emit(const MarchArgs& a, const unsigned long long* chunk_offsets, int64_t n_chunks,
                        int32_t* id_map, hipStream_t s);
@@ -168,6 +185,6 @@ hipError_t launch_flux(const MarchArgs& a, double* partial, int64_t n_chunks, do
 hipError_t launch_fixed_flux(const float* images, int V, int nb, int64_t R, double pix_area, double* partial,
                              double* flux_dev, hipStream_t s);
 
-constexpr int64_t CHUNK = 4096;  // positions per block in counting passes
+constexpr int64_t CHUNK = 4096;  // positions per block in counting passes; levels start on a chunk
 
 }  // namespace air

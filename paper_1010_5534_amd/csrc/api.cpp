@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -24,9 +25,10 @@ struct DevBuf {
 struct air_ctx {
   int device = 0;
   int num_cus = 256;
+  int seg_shift_override = -1;  // AIR_SEG_SHIFT: tuning knob for the lanes per ray
   std::string err;
-  DevBuf state, valI, valN, xiI, xiN, visits, rmin, rmax, queue, ctr, chunk, vstat, idmap, partial, flux,
-      views, touts;
+  DevBuf state, valI, valN, xiI, xiN, visits, rmin, rmax, queue, ctr, chunk, cstat, vstat, idmap, partial, flux,
+      views, touts, pack;
   unsigned long long* host_ctr = nullptr;  // pinned
   double* host_flux = nullptr;             // pinned
   unsigned long long* host_vstat = nullptr;
@@ -101,8 +103,8 @@ air_status check_grid(air_ctx* c, const air_grid* g) {
     if (!std::isfinite(g->lo[a]) || !std::isfinite(g->hi[a]) || !(g->hi[a] > g->lo[a]))
       return fail(c, AIR_EINVAL, "grid box on axis %d is empty or not finite", a);
   }
-  if ((int64_t)g->n[0] * g->n[1] * g->n[2] > (int64_t)INT32_MAX)
-    return fail(c, AIR_EINVAL, "grid has more than 2^31 cells");
+  if ((int64_t)g->n[0] * g->n[1] * g->n[2] >= ((int64_t)1 << 30))
+    return fail(c, AIR_EINVAL, "grid has 2^30 cells or more (field arrays must stay below 4 GiB)");
   return AIR_OK;
 }
 
@@ -140,7 +142,10 @@ air_status make_view(air_ctx* c, const air_view* v, DevView& out) {
   out.ev[0] = d[1] * out.eu[2] - d[2] * out.eu[1];
   out.ev[1] = d[2] * out.eu[0] - d[0] * out.eu[2];
   out.ev[2] = d[0] * out.eu[1] - d[1] * out.eu[0];
-  for (int a = 0; a < 3; ++a) out.c[a] = v->center[a];
+  for (int a = 0; a < 3; ++a) {
+    out.c[a] = v->center[a];
+    out.inv_d[a] = out.d[a] != 0.0 ? 1.0 / out.d[a] : 0.0;
+  }
   out.width = v->width;
   return AIR_OK;
 }
@@ -153,10 +158,17 @@ void fill_geo(const air_grid* g, Geo& G) {
     G.lo[a] = g->lo[a];
     G.hi[a] = g->hi[a];
     G.h[a] = (g->hi[a] - g->lo[a]) / (double)g->n[a];
+    G.inv_h[a] = (double)g->n[a] / (g->hi[a] - g->lo[a]);
   }
+  // lanes per ray: about 32 cells of the longest axis per lane, 1..16 lanes;
+  // fixed by the grid alone so every path traces a ray identically
+  int nmax = std::max(g->n[0], std::max(g->n[1], g->n[2]));
+  int sh = 0;
+  while ((1 << sh) < MAX_SEG && (32 << sh) < nmax) ++sh;
+  G.seg_shift = sh;
 }
 
-void fill_fld(const air_field* f, Fld& F) {
+void fill_fld(const air_field* f, const air_grid* g, Fld& F) {
   std::memset(&F, 0, sizeof F);
   F.kind = f->kind;
   F.nb = f->kind == AIR_FIELD_RHO_J_KAPPA ? 1 : f->n_bands;
@@ -164,11 +176,33 @@ void fill_fld(const air_field* f, Fld& F) {
   F.emis = f->emis;
   F.kappa = f->kappa;
   F.temp = f->temp;
+  F.packed = f->packed;
+  F.bnx = (g->n[0] + 1) / 2;
+  F.bny = (g->n[1] + 1) / 2;
+  F.bnz = (g->n[2] + 1) / 2;
+  F.packed_bytes = (uint32_t)(8ll * F.bnx * F.bny * F.bnz * packed_cell_bytes(f->kind));
   for (int b = 0; b < F.nb && f->kind == AIR_FIELD_RHO_T; ++b) {
     F.k0[b] = (float)f->band[b][0];
     F.s[b] = (float)f->band[b][1];
     F.q[b] = (float)f->band[b][2];
   }
+}
+
+int64_t packed_bytes_of(const air_grid* g, const air_field* f) {
+  const int64_t bricks = (int64_t)((g->n[0] + 1) / 2) * ((g->n[1] + 1) / 2) * ((g->n[2] + 1) / 2);
+  return 8 * bricks * packed_cell_bytes(f->kind);
+}
+
+// point the march at a packed layout: the caller's, or one written now
+air_status ensure_packed(air_ctx* c, const air_grid* g, const air_field* f, MarchArgs& A, hipStream_t s) {
+  const int64_t need = packed_bytes_of(g, f);
+  if (need >= ((int64_t)1 << 32)) return fail(c, AIR_ENOTSUP, "packed field of %lld bytes exceeds 4 GiB", (long long)need);
+  if (f->packed) return AIR_OK;
+  air_status st = ensure(c, c->pack, (size_t)need);
+  if (st) return st;
+  A.f.packed = c->pack.p;
+  HIPCHK(c, launch_pack(A.g, A.f, c->pack.p, s));
+  return AIR_OK;
 }
 
 int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
@@ -188,7 +222,11 @@ air_status upload_views(air_ctx* c, const air_view* views, int V, hipStream_t s,
   return AIR_OK;
 }
 
-int march_blocks(const air_ctx* c) { return c->num_cus * 8; }
+// a multiple of 8 blocks (one share per XCD), about 16 waves per CU
+int march_blocks(const air_ctx* c, int seg_shift) {
+  const int per_cu = std::max(1, 16 >> seg_shift);
+  return std::max(8, (c->num_cus * per_cu + 7) / 8 * 8);
+}
 
 }  // namespace
 
@@ -211,6 +249,10 @@ air_status air_create(air_ctx** out, int32_t device) {
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
     c->num_cus = prop.multiProcessorCount;
+  if (const char* e = std::getenv("AIR_SEG_SHIFT")) {
+    const int v = std::atoi(e);
+    if (v >= 0 && (1 << v) <= MAX_SEG) c->seg_shift_override = v;
+  }
   size_t have = 0;
   if (ensure_host(c, (void**)&c->host_ctr, &have, sizeof(unsigned long long) * CTR_COUNT)) {
     delete c;
@@ -229,7 +271,8 @@ void air_destroy(air_ctx* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   for (DevBuf* b : {&c->state, &c->valI, &c->valN, &c->xiI, &c->xiN, &c->visits, &c->rmin, &c->rmax, &c->queue,
-                    &c->ctr, &c->chunk, &c->vstat, &c->idmap, &c->partial, &c->flux, &c->views, &c->touts})
+                    &c->ctr, &c->chunk, &c->cstat, &c->vstat, &c->idmap, &c->partial, &c->flux, &c->views,
+                    &c->touts, &c->pack})
     if (b->p) (void)hipFree(b->p);
   if (c->host_ctr) (void)hipHostFree(c->host_ctr);
   if (c->host_flux) (void)hipHostFree(c->host_flux);
@@ -269,20 +312,21 @@ air_status air_render(air_ctx* c, const air_grid* grid, const air_field* field, 
   MarchArgs A;
   std::memset(&A, 0, sizeof A);
   fill_geo(grid, A.g);
-  fill_fld(field, A.f);
+  if (c->seg_shift_override >= 0) A.g.seg_shift = c->seg_shift_override;
+  fill_fld(field, grid, A.f);
   const int nb = A.f.nb, V = n_views;
   A.img.N0 = N0;
   A.img.Lmax = Lm;
   A.img.V = V;
+  // every level starts on a counting chunk, so a chunk belongs to one
+  // (view, level)
   int64_t off = 0;
   for (int L = 0; L <= Lm; ++L) {
     A.img.off[L] = off;
-    off = round_up(off + ((int64_t)N0 * N0 << (2 * L)), 256);
+    off = round_up(off + ((int64_t)N0 * N0 << (2 * L)), CHUNK);
   }
-  for (int L = Lm + 1; L <= MAXL; ++L) A.img.off[L] = round_up(off, 256);
-  // positions per view, padded so views start on a counting chunk and the
-  // level after Lmax (the children written at Lmax-1's test) stays in range
-  const int64_t S = round_up(off, CHUNK);
+  for (int L = Lm + 1; L <= MAXL; ++L) A.img.off[L] = off;
+  const int64_t S = off;
   A.img.S = S;
   const int64_t VS = (int64_t)V * S;
   const int64_t n_chunks = VS / CHUNK;
@@ -295,7 +339,8 @@ air_status air_render(air_ctx* c, const air_grid* grid, const air_field* field, 
   if ((st = ensure(c, c->queue, 8 * VS))) return st;
   if ((st = ensure(c, c->ctr, 8 * CTR_COUNT))) return st;
   if ((st = ensure(c, c->chunk, 8 * (n_chunks + 1)))) return st;
-  if ((st = ensure(c, c->vstat, 8 * V * (MAXL + 1)))) return st;
+  if ((st = ensure(c, c->cstat, 4 * VS_N * n_chunks))) return st;
+  if ((st = ensure(c, c->vstat, 8 * (size_t)V * MAXL * VS_N))) return st;
   if ((st = ensure(c, c->partial, 8 * n_chunks * nb))) return st;
   if ((st = ensure(c, c->flux, 8 * V * nb))) return st;
   if (trees) {
@@ -312,6 +357,7 @@ air_status air_render(air_ctx* c, const air_grid* grid, const air_field* field, 
   A.w.qcap = (uint64_t)VS;
   A.w.ctr = (unsigned long long*)c->ctr.p;
   if ((st = upload_views(c, views, V, s, &A.views))) return st;
+  if ((st = ensure_packed(c, grid, field, A, s))) return st;
 
   float w[MAXB];
   for (int b = 0; b < MAXB; ++b) w[b] = b < nb ? prm->band_weight[b] : 0.0f;
@@ -323,15 +369,14 @@ air_status air_render(air_ctx* c, const air_grid* grid, const air_field* field, 
   HIPCHK(c, launch_init(A, s));
   for (int L = 0; L <= Lm; ++L) {
     HIPCHK(c, hipEventRecord(ev[2 + 4 * L], s));
-    HIPCHK(c, launch_march_queue(A, L, march_blocks(c), s));
+    HIPCHK(c, launch_march_queue(A, L, march_blocks(c, A.g.seg_shift), s));
     HIPCHK(c, hipEventRecord(ev[3 + 4 * L], s));
-    if (L < Lm) HIPCHK(c, launch_refine(A, L, prm->xi_crit_I, prm->xi_crit_N, w, 2048, s));
+    if (L < Lm) HIPCHK(c, launch_refine(A, L, prm->xi_crit_I, prm->xi_crit_N, w, c->num_cus * 4, s));
     HIPCHK(c, hipEventRecord(ev[4 + 4 * L], s));
   }
   unsigned long long* chunk = (unsigned long long*)c->chunk.p;
   unsigned long long* vstat = (unsigned long long*)c->vstat.p;
-  HIPCHK(c, hipMemsetAsync(vstat, 0, 8 * V * (MAXL + 1), s));
-  HIPCHK(c, launch_count(A, chunk, n_chunks, vstat, s));
+  HIPCHK(c, launch_count(A, chunk, (unsigned*)c->cstat.p, n_chunks, vstat, s));
   if (trees) {
     HIPCHK(c, launch_scan(chunk, n_chunks, s));
     HIPCHK(c, launch_emit(A, chunk, n_chunks, (int32_t*)c->idmap.p, s));
@@ -353,9 +398,10 @@ air_status air_render(air_ctx* c, const air_grid* grid, const air_field* field, 
 
   HIPCHK(c, hipEventRecord(ev[1], s));
   // one wait: counters, per-view counts, fluxes
-  if ((st = ensure_host(c, (void**)&c->host_vstat, &c->host_vstat_n, 8 * V * (MAXL + 1)))) return st;
+  const size_t vstat_bytes = 8 * (size_t)V * MAXL * VS_N;
+  if ((st = ensure_host(c, (void**)&c->host_vstat, &c->host_vstat_n, vstat_bytes))) return st;
   HIPCHK(c, hipMemcpyAsync(c->host_ctr, A.w.ctr, 8 * CTR_COUNT, hipMemcpyDeviceToHost, s));
-  HIPCHK(c, hipMemcpyAsync(c->host_vstat, vstat, 8 * V * (MAXL + 1), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipMemcpyAsync(c->host_vstat, vstat, vstat_bytes, hipMemcpyDeviceToHost, s));
   if (flux) {
     if ((st = ensure_host(c, (void**)&c->host_flux, &c->host_flux_n, 8 * V * nb))) return st;
     HIPCHK(c, hipMemcpyAsync(c->host_flux, c->flux.p, 8 * V * nb, hipMemcpyDeviceToHost, s));
@@ -366,16 +412,22 @@ air_status air_render(air_ctx* c, const air_grid* grid, const air_field* field, 
   if (flux) std::memcpy(flux, c->host_flux, 8 * V * nb);
   if (stats) {
     std::memset(stats, 0, sizeof *stats);
-    stats->hits = (int64_t)hc[CTR_HITS];
-    stats->visits = (int64_t)hc[CTR_VISITS];
-    stats->leaves = (int64_t)hc[CTR_LEAVES];
-    stats->tested = (int64_t)hc[CTR_TESTED];
-    stats->flagged = (int64_t)hc[CTR_FLAGGED];
-    stats->balance = (int64_t)hc[CTR_BALANCE];
-    for (int L = 0; L < MAXL; ++L) {
-      stats->rays_per_level[L] = (int64_t)hc[CTR_NODES + L];
+    for (int k = 0; k < CTR_SLOTS; ++k) {
+      stats->hits += (int64_t)hc[CTR_HITS + k];
+      stats->visits += (int64_t)hc[CTR_VISITS + k];
+    }
+    for (int v = 0; v < V; ++v)
+      for (int L = 0; L <= Lm; ++L) {
+        const unsigned long long* r = c->host_vstat + ((size_t)v * MAXL + L) * VS_N;
+        stats->rays_per_level[L] += (int64_t)r[VS_NODES];
+        stats->leaves += (int64_t)r[VS_LEAVES];
+        stats->tested += (int64_t)r[VS_TESTED];
+        stats->flagged += (int64_t)r[VS_FLAGGED];
+        stats->balance += (int64_t)r[VS_BALANCE];
+      }
+    for (int L = 0; L <= Lm; ++L) {
       stats->rays += stats->rays_per_level[L];
-      if (hc[CTR_NODES + L]) stats->depth = L;
+      if (stats->rays_per_level[L]) stats->depth = L;
     }
     float ms = 0.0f;
     if (hipEventElapsedTime(&ms, ev[0], ev[1]) == hipSuccess) stats->ms_total = ms;
@@ -387,14 +439,17 @@ air_status air_render(air_ctx* c, const air_grid* grid, const air_field* field, 
   }
   air_status res = AIR_OK;
   for (int k = 0; trees && k < V; ++k) {
-    const unsigned long long* vs = c->host_vstat + (size_t)k * (MAXL + 1);
-    int64_t n = 0;
+    int64_t n = 0, leaves = 0;
     for (int L = 0; L < MAXL; ++L) {
-      trees[k].n_per_level[L] = (int64_t)vs[L];
-      n += (int64_t)vs[L];
+      const unsigned long long* r = c->host_vstat + ((size_t)k * MAXL + L) * VS_N;
+      trees[k].n_per_level[L] = L <= Lm ? (int64_t)r[VS_NODES] : 0;
+      if (L <= Lm) {
+        n += (int64_t)r[VS_NODES];
+        leaves += (int64_t)r[VS_LEAVES];
+      }
     }
     trees[k].n_nodes = n;
-    trees[k].n_leaves = (int64_t)vs[MAXL];
+    trees[k].n_leaves = leaves;
     if (n > trees[k].capacity)
       res = fail(c, AIR_ECAPACITY, "tree %d needs %lld nodes, capacity %lld", k, (long long)n,
                  (long long)trees[k].capacity);
@@ -422,7 +477,8 @@ air_status air_render_fixed(air_ctx* c, const air_grid* grid, const air_field* f
   MarchArgs A;
   std::memset(&A, 0, sizeof A);
   fill_geo(grid, A.g);
-  fill_fld(field, A.f);
+  if (c->seg_shift_override >= 0) A.g.seg_shift = c->seg_shift_override;
+  fill_fld(field, grid, A.f);
   const int nb = A.f.nb;
   A.img.N0 = coarse_n;
   A.img.Lmax = level;
@@ -430,10 +486,11 @@ air_status air_render_fixed(air_ctx* c, const air_grid* grid, const air_field* f
   if ((st = ensure(c, c->ctr, 8 * CTR_COUNT))) return st;
   A.w.ctr = (unsigned long long*)c->ctr.p;
   if ((st = upload_views(c, views, n_views, s, &A.views))) return st;
+  if ((st = ensure_packed(c, grid, field, A, s))) return st;
   HIPCHK(c, hipMemsetAsync(A.w.ctr, 0, 8 * CTR_COUNT, s));
   HIPCHK(c, hipEventRecord(c->ev[0], s));
   HIPCHK(c, hipEventRecord(c->ev[2], s));
-  HIPCHK(c, launch_march_fixed(A, level, images, march_blocks(c), s));
+  HIPCHK(c, launch_march_fixed(A, level, images, march_blocks(c, A.g.seg_shift), s));
   HIPCHK(c, hipEventRecord(c->ev[3], s));
   const int64_t cpp = (R * R + CHUNK - 1) / CHUNK;
   if (flux) {
@@ -461,8 +518,10 @@ air_status air_render_fixed(air_ctx* c, const air_grid* grid, const air_field* f
     std::memset(stats, 0, sizeof *stats);
     stats->rays = (int64_t)n_views * R * R;
     stats->rays_per_level[level] = stats->rays;
-    stats->hits = (int64_t)c->host_ctr[CTR_HITS];
-    stats->visits = (int64_t)c->host_ctr[CTR_VISITS];
+    for (int k = 0; k < CTR_SLOTS; ++k) {
+      stats->hits += (int64_t)c->host_ctr[CTR_HITS + k];
+      stats->visits += (int64_t)c->host_ctr[CTR_VISITS + k];
+    }
     stats->leaves = stats->rays;
     stats->depth = level;
     stats->march_launches = 1;
@@ -490,12 +549,40 @@ air_status air_trace_pixels(air_ctx* c, const air_grid* grid, const air_field* f
   MarchArgs A;
   std::memset(&A, 0, sizeof A);
   fill_geo(grid, A.g);
-  fill_fld(field, A.f);
+  if (c->seg_shift_override >= 0) A.g.seg_shift = c->seg_shift_override;
+  fill_fld(field, grid, A.f);
   A.img.N0 = coarse_n;
   A.img.V = 1;
   if ((st = upload_views(c, view, 1, s, &A.views))) return st;
+  if ((st = ensure_packed(c, grid, field, A, s))) return st;
   HIPCHK(c, launch_trace_pixels(A, n, level, ix, iy, I, N, visits, s));
   HIPCHK(c, hipStreamSynchronize(s));
+  return AIR_OK;
+}
+
+int64_t air_field_packed_bytes(const air_grid* grid, const air_field* field) {
+  air_status st;
+  if ((st = check_grid(nullptr, grid))) return st;
+  if ((st = check_field(nullptr, field))) return st;
+  return packed_bytes_of(grid, field);
+}
+
+air_status air_field_pack(air_ctx* c, const air_grid* grid, const air_field* field, void* packed, int64_t bytes,
+                          void* stream) {
+  if (!c) return AIR_EINVAL;
+  c->err.clear();
+  air_status st;
+  if ((st = check_grid(c, grid))) return st;
+  if ((st = check_field(c, field))) return st;
+  const int64_t need = packed_bytes_of(grid, field);
+  if (!packed || bytes < need) return fail(c, AIR_EINVAL, "packed buffer of %lld bytes, %lld needed", (long long)bytes, (long long)need);
+  if (need >= ((int64_t)1 << 32)) return fail(c, AIR_ENOTSUP, "packed field of %lld bytes exceeds 4 GiB", (long long)need);
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, AIR_EDEVICE, "hipSetDevice failed");
+  MarchArgs A;
+  std::memset(&A, 0, sizeof A);
+  fill_geo(grid, A.g);
+  fill_fld(field, grid, A.f);
+  HIPCHK(c, launch_pack(A.g, A.f, packed, (hipStream_t)stream));
   return AIR_OK;
 }
 

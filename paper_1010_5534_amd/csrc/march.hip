@@ -23,6 +23,7 @@ namespace air {
 namespace {
 
 constexpr float LOG2E_F = 1.4426950408889634f;
+constexpr int KB = 4;  // cells per load batch in the march
 
 struct ff {
   float hi, lo;
@@ -72,98 +73,139 @@ __device__ __forceinline__ float seg_weight(float x) {
   return (1.0f - e) * __builtin_amdgcn_rcpf(x);
 }
 
-template <int NB>
-struct RayRes {
-  float I[NB];
-  float N;
-  int nvis;
-  bool hit;
-  float rmin, rmax;
+// raw cell data: (rho, j, kappa) or (rho, T)
+template <int FK>
+struct Raw {
+  float rho, a, b;
 };
 
-// per-cell optics of band b
-template <int NB, int FK>
-struct Optics {
-  float rho;
-  float j[NB], k[NB];
-};
+// The packed field (air_field_pack): one 16-byte (rho, j, kappa, 0) or
+// 8-byte (rho, T) record per cell in 2x2x2 bricks.  Loads go through a
+// buffer resource: a 32-bit byte offset, and 0 past num_records, so an index
+// can never leave the array.  The loads are bound to the LLVM buffer-load
+// intrinsics directly (the vector-returning clang builtins shrink to one
+// dword with this toolchain).
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+__device__ f32x4 buffer_load_f32x4(i32x4 rsrc, int voffset, int soffset, int aux) __asm("llvm.amdgcn.raw.buffer.load.v4f32");
+__device__ f32x2 buffer_load_f32x2(i32x4 rsrc, int voffset, int soffset, int aux) __asm("llvm.amdgcn.raw.buffer.load.v2f32");
 
-template <int NB, int FK>
-__device__ __forceinline__ void load_optics(const Fld& f, int idx, Optics<NB, FK>& o) {
+constexpr int RSRC_WORD3 = 0x00020000;  // raw 32-bit buffer on gfx9-class GPUs
+
+__device__ __forceinline__ i32x4 field_rsrc(const Fld& f) {
+  const uint64_t a = (uint64_t)f.packed;
+  i32x4 r;
+  r[0] = (int)(uint32_t)a;
+  r[1] = (int)((uint32_t)(a >> 32) & 0xffffu);  // stride 0
+  r[2] = (int)f.packed_bytes;                   // num_records in bytes
+  r[3] = RSRC_WORD3;
+  return r;
+}
+
+template <int FK>
+__device__ __forceinline__ Raw<FK> load_raw(i32x4 R, int cell) {
+  Raw<FK> r;
   if constexpr (FK == AIR_FIELD_RHO_J_KAPPA) {
-    o.rho = f.rho[idx];
-    o.j[0] = f.emis[idx];
-    o.k[0] = f.kappa[idx];
+    const f32x4 q = buffer_load_f32x4(R, (int)((unsigned)cell * 16u), 0, 0);
+    r.rho = q[0];
+    r.a = q[1];
+    r.b = q[2];
   } else {
-    float r = f.rho[idx];
-    float T = f.temp[idx];
-    o.rho = r;
-    float lt = __builtin_amdgcn_logf(T);  // log2 T
-    float r2 = r * r;
+    const f32x2 q = buffer_load_f32x2(R, (int)((unsigned)cell * 8u), 0, 0);
+    r.rho = q[0];
+    r.a = q[1];
+    r.b = 0.0f;
+  }
+  return r;
+}
+
+// emissivity and opacity of each band from the raw cell data
+template <int NB, int FK>
+__device__ __forceinline__ void optics(const Fld& f, const Raw<FK>& r, float* j, float* k) {
+  if constexpr (FK == AIR_FIELD_RHO_J_KAPPA) {
+    j[0] = r.a;
+    k[0] = r.b;
+  } else {
+    const float lt = __builtin_amdgcn_logf(r.a);  // log2 T
+    const float r2 = r.rho * r.rho;
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
-      o.k[b] = f.k0[b] * r * __builtin_amdgcn_exp2f(-f.s[b] * lt);
-      o.j[b] = r2 * __builtin_amdgcn_exp2f(f.q[b] * lt);
+      k[b] = f.k0[b] * r.rho * __builtin_amdgcn_exp2f(-f.s[b] * lt);
+      j[b] = r2 * __builtin_amdgcn_exp2f(f.q[b] * lt);
     }
   }
 }
 
-// Ray x(t) = o + t d (d unit) through the uniform grid, DDA from the entry.
-template <int NB, int FK, bool RANGE>
-__device__ void march_uniform(const Geo& g, const Fld& f, const double o[3], const double d[3],
-                              RayRes<NB>& r) {
-#pragma unroll
-  for (int b = 0; b < NB; ++b) r.I[b] = 0.0f;
-  r.N = 0.0f;
-  r.nvis = 0;
-  r.hit = false;
-  r.rmin = 0.0f;
-  r.rmax = 0.0f;
+// partial result of one sub-interval of a ray, optical depth counted from
+// the sub-interval's start
+template <int NB>
+struct Seg {
+  float I[NB], tau[NB];
+  float N;
+  float rmin, rmax;
+};
 
-  // slab entry / exit, float64
-  double t0 = -__builtin_huge_val(), t1 = __builtin_huge_val();
+// entry / exit of the grid box, float64; false if the ray misses
+__device__ __forceinline__ bool slab(const Geo& g, const double o[3], const double d[3],
+                                     const double inv_d[3], double& t0, double& t1) {
+  t0 = -__builtin_huge_val();
+  t1 = __builtin_huge_val();
   bool inside = true;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     if (d[a] != 0.0) {
-      double ta = (g.lo[a] - o[a]) / d[a], tb = (g.hi[a] - o[a]) / d[a];
+      const double ta = (g.lo[a] - o[a]) * inv_d[a], tb = (g.hi[a] - o[a]) * inv_d[a];
       t0 = fmax(t0, fmin(ta, tb));
       t1 = fmin(t1, fmax(ta, tb));
     } else if (!(o[a] >= g.lo[a] && o[a] < g.hi[a])) {
       inside = false;
     }
   }
-  if (!inside || !(t0 < t1)) return;
+  return inside && t0 < t1;
+}
 
-  // entry and exit cells (the cell just after t0 / just before t1), the
-  // number of cells crossed, and the first crossing of each axis relative
-  // to the entry, all from float64
+// cell of axis a just after (after = true) or just before parameter t
+__device__ __forceinline__ int cell_at(const Geo& g, const double o[3], const double d[3], int a, double t,
+                                       bool after) {
+  const double u = (o[a] + t * d[a] - g.lo[a]) * g.inv_h[a];
+  int k;
+  if (d[a] > 0.0)
+    k = after ? (int)floor(u) : (int)ceil(u) - 1;
+  else if (d[a] < 0.0)
+    k = after ? (int)ceil(u) - 1 : (int)floor(u);
+  else
+    k = (int)floor(u);
+  return min(max(k, 0), g.n[a] - 1);
+}
+
+// cells crossed between ta and tb (both inside the box)
+__device__ __forceinline__ int cells_between(const Geo& g, const double o[3], const double d[3], double ta,
+                                             double tb) {
+  int n = 1;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) n += abs(cell_at(g, o, d, a, tb, false) - cell_at(g, o, d, a, ta, true));
+  return n;
+}
+
+// March the sub-interval [ta, tb] of the ray x(t) = o + t d (d unit) through
+// the uniform grid: DDA from the cell just after ta to the cell just before
+// tb, optical depth from 0 at ta.
+template <int NB, int FK, bool RANGE>
+__device__ void march_interval(const Geo& g, const Fld& f, const double o[3], const double d[3],
+                               const double inv_d[3], double ta, double tb, Seg<NB>& r) {
   int c[3], st[3], nvis = 1;
   ff T0[3], D[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    const int n = g.n[a];
-    double u0 = (o[a] + t0 * d[a] - g.lo[a]) / g.h[a];
-    double u1 = (o[a] + t1 * d[a] - g.lo[a]) / g.h[a];
-    int k0, k1;
-    if (d[a] > 0.0) {
-      k0 = (int)floor(u0);
-      k1 = (int)ceil(u1) - 1;
-    } else if (d[a] < 0.0) {
-      k0 = (int)ceil(u0) - 1;
-      k1 = (int)floor(u1);
-    } else {
-      k0 = k1 = (int)floor(u0);
-    }
-    k0 = min(max(k0, 0), n - 1);
-    k1 = min(max(k1, 0), n - 1);
+    const int k0 = cell_at(g, o, d, a, ta, true), k1 = cell_at(g, o, d, a, tb, false);
     c[a] = k0;
     nvis += abs(k1 - k0);
     if (d[a] != 0.0) {
-      int m = d[a] > 0.0 ? k0 + 1 : k0;
-      double tf = (g.lo[a] + (double)m * g.h[a] - o[a]) / d[a] - t0;
+      const int m = d[a] > 0.0 ? k0 + 1 : k0;
+      const double tf = (g.lo[a] + (double)m * g.h[a] - o[a]) * inv_d[a] - ta;
       T0[a] = ff_of(tf);
-      D[a] = ff_of(g.h[a] / fabs(d[a]));
+      D[a] = ff_of(g.h[a] * fabs(inv_d[a]));
       st[a] = d[a] > 0.0 ? 1 : -1;
     } else {
       T0[a] = {__builtin_huge_valf(), 0.0f};
@@ -171,8 +213,10 @@ __device__ void march_uniform(const Geo& g, const Fld& f, const double o[3], con
       st[a] = 0;
     }
   }
-  const ff S1 = ff_of(t1 - t0);
+  const ff S1 = ff_of(tb - ta);
   const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+  const i32x4 R = field_rsrc(f);
+  const int bnx = f.bnx, bny = f.bny;
 
   float I[NB], cI[NB], tau[NB], ctau[NB];
 #pragma unroll
@@ -184,62 +228,73 @@ __device__ void march_uniform(const Geo& g, const Fld& f, const double o[3], con
   int k0 = 0, k1 = 0, k2 = 0;
   ff ta0 = T0[0], ta1 = T0[1], ta2 = T0[2];
   ff tc = {0.0f, 0.0f};
-  int idx = cx + nx * (cy + ny * cz);
-  Optics<NB, FK> op;
-  load_optics<NB, FK>(f, idx, op);
-  for (int v = 0; v < nvis; ++v) {
-    ff tn;
-    int ax;
-    if (v == nvis - 1) {
-      tn = S1;
-      ax = 3;
-    } else {
-      ax = (ta0.hi <= ta1.hi) ? (ta0.hi <= ta2.hi ? 0 : 2) : (ta1.hi <= ta2.hi ? 1 : 2);
-      tn = ax == 0 ? ta0 : (ax == 1 ? ta1 : ta2);
-    }
-    const float ds = (tn.hi - tc.hi) + (tn.lo - tc.lo);
-    tc = tn;
-    // step the DDA and start the next cell's loads before integrating this one
-    if (ax == 0) {
-      ++k0;
-      ta0 = ff_axpy(k0, D[0], T0[0]);
-      cx = min(max(cx + st[0], 0), nx - 1);
-    } else if (ax == 1) {
-      ++k1;
-      ta1 = ff_axpy(k1, D[1], T0[1]);
-      cy = min(max(cy + st[1], 0), ny - 1);
-    } else if (ax == 2) {
-      ++k2;
-      ta2 = ff_axpy(k2, D[2], T0[2]);
-      cz = min(max(cz + st[2], 0), nz - 1);
-    }
-    const Optics<NB, FK> cur = op;
-    if (ax != 3) {
-      idx = cx + nx * (cy + ny * cz);
-      load_optics<NB, FK>(f, idx, op);
-    }
+  int idx = brick_index(cx, cy, cz, bnx, bny);
+  // Batches of KB cells: the DDA walks KB cells ahead (cell offsets and
+  // segment lengths), all their loads are issued together, then the cells
+  // are integrated in order; KB loads per lane are in flight at once.
+  for (int v0 = 0; v0 < nvis; v0 += KB) {
+    int off[KB];
+    float dsq[KB];
 #pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      const float dtau = cur.k[b] * ds;
-      const float T = __builtin_amdgcn_exp2f(-(tau[b] - ctau[b]) * LOG2E_F);
-      kadd(I[b], cI[b], T * (cur.j[b] * ds) * seg_weight(dtau));
-      kadd(tau[b], ctau[b], dtau);
+    for (int q = 0; q < KB; ++q) {
+      off[q] = idx;
+      ff tn;
+      int ax;
+      if (v0 + q >= nvis - 1) {  // the last cell ends at tb; past it ds = 0
+        tn = S1;
+        ax = 3;
+      } else {
+        ax = (ta0.hi <= ta1.hi) ? (ta0.hi <= ta2.hi ? 0 : 2) : (ta1.hi <= ta2.hi ? 1 : 2);
+        tn = ax == 0 ? ta0 : (ax == 1 ? ta1 : ta2);
+      }
+      dsq[q] = (tn.hi - tc.hi) + (tn.lo - tc.lo);
+      tc = tn;
+      if (ax == 0) {
+        ++k0;
+        ta0 = ff_axpy(k0, D[0], T0[0]);
+        cx = min(max(cx + st[0], 0), nx - 1);
+      } else if (ax == 1) {
+        ++k1;
+        ta1 = ff_axpy(k1, D[1], T0[1]);
+        cy = min(max(cy + st[1], 0), ny - 1);
+      } else if (ax == 2) {
+        ++k2;
+        ta2 = ff_axpy(k2, D[2], T0[2]);
+        cz = min(max(cz + st[2], 0), nz - 1);
+      }
+      idx = brick_index(cx, cy, cz, bnx, bny);
     }
-    kadd(N, cN, cur.rho * ds);
-    if constexpr (RANGE) {
-      rmin = fminf(rmin, cur.rho);
-      rmax = fmaxf(rmax, cur.rho);
+    Raw<FK> raw[KB];
+#pragma unroll
+    for (int q = 0; q < KB; ++q) raw[q] = load_raw<FK>(R, off[q]);
+#pragma unroll
+    for (int q = 0; q < KB; ++q) {
+      if (v0 + q >= nvis) break;
+      const float ds = dsq[q];
+      float jb[NB], kb[NB];
+      optics<NB, FK>(f, raw[q], jb, kb);
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const float dtau = kb[b] * ds;
+        const float T = __builtin_amdgcn_exp2f(-(tau[b] - ctau[b]) * LOG2E_F);
+        kadd(I[b], cI[b], T * (jb[b] * ds) * seg_weight(dtau));
+        kadd(tau[b], ctau[b], dtau);
+      }
+      kadd(N, cN, raw[q].rho * ds);
+      if constexpr (RANGE) {
+        rmin = fminf(rmin, raw[q].rho);
+        rmax = fmaxf(rmax, raw[q].rho);
+      }
     }
   }
 #pragma unroll
-  for (int b = 0; b < NB; ++b) r.I[b] = I[b] - cI[b];
+  for (int b = 0; b < NB; ++b) {
+    r.I[b] = I[b] - cI[b];
+    r.tau[b] = tau[b] - ctau[b];
+  }
   r.N = N - cN;
-  r.nvis = nvis;
-  r.hit = true;
-  if constexpr (RANGE) {
-    r.rmin = rmin;
-    r.rmax = rmax;
-  }
+  r.rmin = rmin;
+  r.rmax = rmax;
 }
 
 __device__ __forceinline__ void pixel_ray(const DevView& V, int N0, int L, uint32_t i, uint32_t j,
@@ -251,24 +306,171 @@ __device__ __forceinline__ void pixel_ray(const DevView& V, int N0, int L, uint3
   for (int a = 0; a < 3; ++a) o[a] = V.c[a] + au * V.eu[a] + av * V.ev[a];
 }
 
+template <int NB>
+struct RayRes {
+  float I[NB];
+  float N;
+  int nvis;
+  bool hit;
+  float rmin, rmax;
+};
+
+// LDS staging of the per-segment partials of one 64-ray tile:
+// [segment][field][lane], fields I[NB], tau[NB], N, rmin, rmax
+template <int NB>
+struct TileLds {
+  float v[MAX_SEG][2 * NB + 3][WAVE];
+  int nvis[WAVE];
+  int hit[WAVE];
+};
+
+// A block of S = 2^sh waves traces a tile of 64 rays (one per lane): wave
+// k marches the k-th of S equal parameter sub-intervals of every ray's
+// chord, so at each step the 64 lanes of a wave read the cells of 64
+// neighbouring rays at a similar depth.  The partials meet in LDS and wave 0
+// folds them in order,
+//   I = sum_k exp(-tau_0 - ... - tau_{k-1}) I_k,
+// which is exact for piecewise-constant cells.  The split depends only on
+// the ray and S (fixed per grid), so a ray's result does not depend on which
+// block or kernel traced it.  Every thread of the block calls this; the
+// result is valid in wave 0.
 template <int NB, int FK, bool RANGE>
-__device__ __forceinline__ void trace_pixel(const MarchArgs& A, uint32_t v, int L, uint32_t i, uint32_t j,
-                                            RayRes<NB>& r) {
-  const DevView& V = A.views[v];
-  double o[3];
-  pixel_ray(V, A.img.N0, L, i, j, o);
-  march_uniform<NB, FK, RANGE>(A.g, A.f, o, V.d, r);
+__device__ __forceinline__ void trace_tile(const MarchArgs& A, TileLds<NB>& T, bool live, uint32_t v, int L,
+                                           uint32_t i, uint32_t j, int sh, RayRes<NB>& r) {
+  const int S = 1 << sh, lane = threadIdx.x & (WAVE - 1), k = threadIdx.x / WAVE;
+  Seg<NB> sg;
+#pragma unroll
+  for (int b = 0; b < NB; ++b) sg.I[b] = sg.tau[b] = 0.0f;
+  sg.N = 0.0f;
+  sg.rmin = __builtin_huge_valf();
+  sg.rmax = -__builtin_huge_valf();
+  bool hit = false;
+  int nvis = 0;
+  if (live) {
+    const DevView& V = A.views[v];
+    double o[3], t0, t1;
+    pixel_ray(V, A.img.N0, L, i, j, o);
+    hit = slab(A.g, o, V.d, V.inv_d, t0, t1);
+    if (hit) {
+      if (k == 0) nvis = cells_between(A.g, o, V.d, t0, t1);  // before the march: frees t0, t1
+      const double len = t1 - t0, inv_s = 1.0 / (double)S;  // S a power of two: k/S exact
+      const double ta = k == 0 ? t0 : t0 + len * ((double)k * inv_s);
+      const double tb = k == S - 1 ? t1 : t0 + len * ((double)(k + 1) * inv_s);
+      march_interval<NB, FK, RANGE>(A.g, A.f, o, V.d, V.inv_d, ta, tb, sg);
+    }
+  }
+  __syncthreads();  // the previous tile's fold has read the staging area
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    T.v[k][b][lane] = sg.I[b];
+    T.v[k][NB + b][lane] = sg.tau[b];
+  }
+  T.v[k][2 * NB][lane] = sg.N;
+  if constexpr (RANGE) {
+    T.v[k][2 * NB + 1][lane] = sg.rmin;
+    T.v[k][2 * NB + 2][lane] = sg.rmax;
+  }
+  if (k == 0) {
+    T.nvis[lane] = nvis;
+    T.hit[lane] = hit;
+  }
+  __syncthreads();
+  if (k != 0) return;
+  float accI[NB], accT[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    accI[b] = T.v[0][b][lane];
+    accT[b] = T.v[0][NB + b][lane];
+  }
+  float accN = T.v[0][2 * NB][lane];
+  float mn = sg.rmin, mx = sg.rmax;
+  for (int q = 1; q < S; ++q) {
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      accI[b] += __builtin_amdgcn_exp2f(-accT[b] * LOG2E_F) * T.v[q][b][lane];
+      accT[b] += T.v[q][NB + b][lane];
+    }
+    accN += T.v[q][2 * NB][lane];
+    if constexpr (RANGE) {
+      mn = fminf(mn, T.v[q][2 * NB + 1][lane]);
+      mx = fmaxf(mx, T.v[q][2 * NB + 2][lane]);
+    }
+  }
+#pragma unroll
+  for (int b = 0; b < NB; ++b) r.I[b] = accI[b];
+  r.N = accN;
+  r.nvis = T.nvis[lane];
+  r.hit = T.hit[lane] != 0;
+  if constexpr (RANGE) {
+    r.rmin = r.hit ? mn : 0.0f;
+    r.rmax = r.hit ? mx : 0.0f;
+  }
 }
 
-__device__ __forceinline__ void wave_add(unsigned long long* p, unsigned long long x) {
-  // one atomic per wave
-  unsigned long long s = x;
+// Static, XCD-aware split of n tiles over the blocks of the grid.  Blocks
+// are dispatched round-robin over the 8 XCDs (block b on XCD b % 8); tiles
+// are dealt to the XCDs in chunks of TCHUNK consecutive tiles (neighbouring
+// pixels, whose rays read neighbouring cells, then share an L2), and each
+// XCD's blocks stride over its chunks.  No work counter: same-address
+// atomics from thousands of waves serialise.  The grid is a multiple of 8.
+constexpr long long TCHUNK = 4;
+struct Split {
+  long long k, step, n, x;
+  __device__ long long tile() const {  // k-th item of XCD x
+    return ((k / TCHUNK) * 8 + x) * TCHUNK + (k % TCHUNK);
+  }
+  __device__ bool ok() const { return tile() < n; }
+};
+__device__ __forceinline__ Split xcd_split(long long n) {
+  Split sp;
+  sp.x = blockIdx.x & 7;
+  sp.k = blockIdx.x >> 3;
+  sp.step = gridDim.x >> 3;
+  sp.n = n;
+  return sp;
+}
+// number of items of XCD x (upper bound on k), uniform per block
+__device__ __forceinline__ long long xcd_items(long long n) { return (n + 7) / 8 + TCHUNK; }
+
+// add the block's hit and visit counts (held by wave 0) into a spread slot
+__device__ __forceinline__ void block_stats(unsigned long long* ctr, unsigned long long hit,
+                                            unsigned long long vis) {
+  if (threadIdx.x >= WAVE) return;
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-  if ((threadIdx.x & 63) == 0 && s) atomicAdd(p, s);
+  for (int o = 32; o > 0; o >>= 1) {
+    hit += __shfl_xor(hit, o);
+    vis += __shfl_xor(vis, o);
+  }
+  if (threadIdx.x == 0) {
+    const int slot = blockIdx.x & (CTR_SLOTS - 1);
+    if (hit) atomicAdd(&ctr[CTR_HITS + slot], hit);
+    if (vis) atomicAdd(&ctr[CTR_VISITS + slot], vis);
+  }
 }
 
 // ------------------------------------------------------------ kernels
+// packed layout, written slot by slot (padding cells of odd sizes get 0)
+template <int FK>
+__global__ __launch_bounds__(256) void k_pack(Geo g, Fld f) {
+  const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+  const int64_t slots = 8ll * f.bnx * f.bny * f.bnz;
+  for (int64_t sl = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; sl < slots; sl += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = sl >> 3;
+    const int x = (int)(2 * (b % f.bnx)) + (int)(sl & 1);
+    const int y = (int)(2 * ((b / f.bnx) % f.bny)) + (int)((sl >> 1) & 1);
+    const int z = (int)(2 * (b / ((int64_t)f.bnx * f.bny))) + (int)((sl >> 2) & 1);
+    const bool in = x < nx && y < ny && z < nz;
+    const int64_t src = in ? x + (int64_t)nx * (y + (int64_t)ny * z) : 0;
+    if constexpr (FK == AIR_FIELD_RHO_J_KAPPA) {
+      float4 v = in ? make_float4(f.rho[src], f.emis[src], f.kappa[src], 0.0f) : make_float4(0.f, 0.f, 0.f, 0.f);
+      reinterpret_cast<float4*>(const_cast<void*>(f.packed))[sl] = v;
+    } else {
+      float2 v = in ? make_float2(f.rho[src], f.temp[src]) : make_float2(0.f, 0.f);
+      reinterpret_cast<float2*>(const_cast<void*>(f.packed))[sl] = v;
+    }
+  }
+}
+
 __global__ void k_init(MarchArgs A) {
   const int64_t V = A.img.V, S = A.img.S, n0sq = (int64_t)A.img.N0 * A.img.N0;
   const int64_t words = V * S / 4;
@@ -291,100 +493,113 @@ __global__ void k_init(MarchArgs A) {
       A.w.ctr[k] = k == CTR_CURSOR ? (unsigned long long)(V * n0sq) : 0ull;
 }
 
+// Queue march of level L: tiles of 64 consecutive entries, one tile per
+// block at a time (S waves per block).
 template <int NB, int FK>
-__global__ __launch_bounds__(256) void k_march_queue(MarchArgs A, int L) {
+__global__ __launch_bounds__(64 * MAX_SEG) void k_march_queue(MarchArgs A, int L) {
+  __shared__ TileLds<NB> T;
   unsigned long long* ctr = A.w.ctr;
   const unsigned long long qs = ctr[CTR_LSTART + L];
   // appends past the capacity are dropped (and flagged), never read
   const unsigned long long qe = min(ctr[CTR_CURSOR], (unsigned long long)A.w.qcap);
   if (blockIdx.x == 0 && threadIdx.x == 0) ctr[CTR_LSTART + L + 1] = qe;
-  const unsigned long long ntiles = (qe - qs + WAVE - 1) / WAVE;
-  const int lane = threadIdx.x & (WAVE - 1);
-  const int64_t S = A.img.S;
-  for (;;) {
-    unsigned long long t = 0;
-    if (lane == 0) t = atomicAdd(&ctr[CTR_TILE + L], 1ull);
-    t = __shfl(t, 0);
-    if (t >= ntiles) break;
-    const unsigned long long e = qs + t * WAVE + lane;
-    unsigned long long hit = 0, vis = 0;
-    if (e < qe) {
-      uint32_t v, lev, key;
+  const int lane = threadIdx.x & (WAVE - 1), sh = A.g.seg_shift;
+  const int64_t SV = A.img.S, VS = (int64_t)A.img.V * SV;
+  const bool range = L == 0 && A.w.rmin != nullptr;  // uniform: level 0 holds only level-0 nodes
+  unsigned long long hit = 0, vis = 0;
+  const long long ntiles = (long long)((qe - qs + WAVE - 1) / WAVE);
+  Split sp = xcd_split(ntiles);
+  const long long kend = xcd_items(ntiles);
+  for (; sp.k < kend; sp.k += sp.step) {
+    if (!sp.ok()) continue;  // uniform per block
+    const unsigned long long e = qs + (unsigned long long)sp.tile() * WAVE + lane;
+    const bool live = e < qe;
+    uint32_t v = 0, lev = 0, key = 0, i = 0, j = 0;
+    if (live) {
       qdecode(A.w.queue[e], v, lev, key);
-      uint32_t i, j;
       coords_of(key, (int)lev, A.img.N0, i, j);
-      RayRes<NB> r;
-      if (lev == 0 && A.w.rmin) {
-        trace_pixel<NB, FK, true>(A, v, (int)lev, i, j, r);
-        A.w.rmin[(int64_t)v * A.img.N0 * A.img.N0 + key] = r.rmin;
-        A.w.rmax[(int64_t)v * A.img.N0 * A.img.N0 + key] = r.rmax;
-      } else {
-        trace_pixel<NB, FK, false>(A, v, (int)lev, i, j, r);
-      }
-      const int64_t pos = (int64_t)v * S + A.img.off[lev] + key;
-      const int64_t VS = (int64_t)A.img.V * S;
+    }
+    RayRes<NB> r;
+    if (range)
+      trace_tile<NB, FK, true>(A, T, live, v, (int)lev, i, j, sh, r);
+    else
+      trace_tile<NB, FK, false>(A, T, live, v, (int)lev, i, j, sh, r);
+    if (threadIdx.x < WAVE && live) {
+      const int64_t pos = (int64_t)v * SV + A.img.off[lev] + key;
 #pragma unroll
       for (int b = 0; b < NB; ++b)
         if (b < A.f.nb) A.w.valI[b * VS + pos] = r.I[b];
       A.w.valN[pos] = r.N;
       A.w.visits[pos] = r.nvis;
       A.w.state[pos] = A.w.state[pos] | ST_TRACED;
-      hit = r.hit;
-      vis = (unsigned long long)r.nvis;
+      if (range) {
+        A.w.rmin[(int64_t)v * A.img.N0 * A.img.N0 + key] = r.rmin;
+        A.w.rmax[(int64_t)v * A.img.N0 * A.img.N0 + key] = r.rmax;
+      }
+      hit += r.hit;
+      vis += (unsigned long long)r.nvis;
     }
-    wave_add(&ctr[CTR_HITS], hit);
-    wave_add(&ctr[CTR_VISITS], vis);
   }
+  block_stats(ctr, hit, vis);
 }
 
 // fixed raster: entry e = view * R^2 + key, key in forest-Morton order
 template <int NB, int FK>
-__global__ __launch_bounds__(256) void k_march_fixed(MarchArgs A, int L, float* images) {
-  unsigned long long* ctr = A.w.ctr;
+__global__ __launch_bounds__(64 * MAX_SEG) void k_march_fixed(MarchArgs A, int L, float* images) {
+  __shared__ TileLds<NB> T;
   const int64_t R = (int64_t)A.img.N0 << L, R2 = R * R;
   const unsigned long long total = (unsigned long long)A.img.V * R2;
-  const unsigned long long ntiles = (total + WAVE - 1) / WAVE;
-  const int lane = threadIdx.x & (WAVE - 1);
-  for (;;) {
-    unsigned long long t = 0;
-    if (lane == 0) t = atomicAdd(&ctr[CTR_TILE], 1ull);
-    t = __shfl(t, 0);
-    if (t >= ntiles) break;
-    const unsigned long long e = t * WAVE + lane;
-    unsigned long long hit = 0, vis = 0;
-    if (e < total) {
-      const uint32_t v = (uint32_t)(e / R2), key = (uint32_t)(e % R2);
-      uint32_t i, j;
+  const int lane = threadIdx.x & (WAVE - 1), sh = A.g.seg_shift;
+  unsigned long long hit = 0, vis = 0;
+  const long long ntiles = (long long)((total + WAVE - 1) / WAVE);
+  Split sp = xcd_split(ntiles);
+  const long long kend = xcd_items(ntiles);
+  for (; sp.k < kend; sp.k += sp.step) {
+    if (!sp.ok()) continue;
+    const unsigned long long e = (unsigned long long)sp.tile() * WAVE + lane;
+    const bool live = e < total;
+    uint32_t v = 0, key = 0, i = 0, j = 0;
+    if (live) {
+      v = (uint32_t)(e / R2);
+      key = (uint32_t)(e % R2);
       coords_of(key, L, A.img.N0, i, j);
-      RayRes<NB> r;
-      trace_pixel<NB, FK, false>(A, v, L, i, j, r);
+    }
+    RayRes<NB> r;
+    trace_tile<NB, FK, false>(A, T, live, v, L, i, j, sh, r);
+    if (threadIdx.x < WAVE && live) {
       if (images) {
-        float* img = images + (int64_t)v * (NB + 1) * R2 + (int64_t)j * R + i;
+        float* img = images + (int64_t)v * (A.f.nb + 1) * R2 + (int64_t)j * R + i;
 #pragma unroll
         for (int b = 0; b < NB; ++b)
           if (b < A.f.nb) img[b * R2] = r.I[b];
         img[A.f.nb * R2] = r.N;
       }
-      hit = r.hit;
-      vis = (unsigned long long)r.nvis;
+      hit += r.hit;
+      vis += (unsigned long long)r.nvis;
     }
-    wave_add(&ctr[CTR_HITS], hit);
-    wave_add(&ctr[CTR_VISITS], vis);
   }
+  block_stats(A.w.ctr, hit, vis);
 }
 
 template <int NB, int FK>
-__global__ __launch_bounds__(256) void k_trace_pixels(MarchArgs A, int64_t n, const int32_t* level,
-                                                      const int32_t* ix, const int32_t* iy, float* I,
-                                                      float* N, int32_t* visits) {
-  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+__global__ __launch_bounds__(64 * MAX_SEG) void k_trace_pixels(MarchArgs A, int64_t n, const int32_t* level,
+                                                               const int32_t* ix, const int32_t* iy, float* I,
+                                                               float* N, int32_t* visits) {
+  __shared__ TileLds<NB> T;
+  const int lane = threadIdx.x & (WAVE - 1), sh = A.g.seg_shift;
+  for (int64_t b0 = (int64_t)blockIdx.x * WAVE; b0 < n; b0 += (int64_t)gridDim.x * WAVE) {  // uniform per block
+    const int64_t k = b0 + lane;
+    const bool live = k < n;
     RayRes<NB> r;
-    trace_pixel<NB, FK, false>(A, 0, level[k], (uint32_t)ix[k], (uint32_t)iy[k], r);
+    trace_tile<NB, FK, false>(A, T, live, 0, live ? level[k] : 0, live ? (uint32_t)ix[k] : 0u,
+                              live ? (uint32_t)iy[k] : 0u, sh, r);
+    if (threadIdx.x < WAVE && live) {
 #pragma unroll
-    for (int b = 0; b < NB; ++b)
-      if (b < A.f.nb) I[b * n + k] = r.I[b];
-    if (N) N[k] = r.N;
-    if (visits) visits[k] = r.nvis;
+      for (int b = 0; b < NB; ++b)
+        if (b < A.f.nb) I[b * n + k] = r.I[b];
+      if (N) N[k] = r.N;
+      if (visits) visits[k] = r.nvis;
+    }
   }
 }
 
@@ -411,31 +626,42 @@ __global__ __launch_bounds__(256) void k_trace_pixels(MarchArgs A, int64_t n, co
     }                                                                            \
   } while (0)
 
+hipError_t launch_pack(const Geo& g, const Fld& f, void* packed, hipStream_t s) {
+  Fld F = f;
+  F.packed = packed;
+  if (f.kind == AIR_FIELD_RHO_J_KAPPA)
+    hipLaunchKernelGGL(k_pack<AIR_FIELD_RHO_J_KAPPA>, dim3(4096), dim3(256), 0, s, g, F);
+  else
+    hipLaunchKernelGGL(k_pack<AIR_FIELD_RHO_T>, dim3(4096), dim3(256), 0, s, g, F);
+  return hipGetLastError();
+}
+
 hipError_t launch_init(const MarchArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_init, dim3(2048), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
 hipError_t launch_march_queue(const MarchArgs& a, int L, int grid_blocks, hipStream_t s) {
-  AIR_DISPATCH(a.f.nb, a.f.kind,
-               hipLaunchKernelGGL((k_march_queue<NB_, FK_>), dim3(grid_blocks), dim3(256), 0, s, a, L));
+  const dim3 blk(WAVE << a.g.seg_shift);
+  AIR_DISPATCH(a.f.nb, a.f.kind, hipLaunchKernelGGL((k_march_queue<NB_, FK_>), dim3(grid_blocks), blk, 0, s, a, L));
   return hipGetLastError();
 }
 
 hipError_t launch_march_fixed(const MarchArgs& a, int level, float* images, int grid_blocks, hipStream_t s) {
+  const dim3 blk(WAVE << a.g.seg_shift);
   AIR_DISPATCH(a.f.nb, a.f.kind,
-               hipLaunchKernelGGL((k_march_fixed<NB_, FK_>), dim3(grid_blocks), dim3(256), 0, s, a, level,
-                                  images));
+               hipLaunchKernelGGL((k_march_fixed<NB_, FK_>), dim3(grid_blocks), blk, 0, s, a, level, images));
   return hipGetLastError();
 }
 
 hipError_t launch_trace_pixels(const MarchArgs& a, int64_t n, const int32_t* level, const int32_t* ix,
                                const int32_t* iy, float* I, float* N, int32_t* visits, hipStream_t s) {
-  int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
+  int blocks = (int)std::min<int64_t>((n + WAVE - 1) / WAVE, 4096);
   if (blocks < 1) blocks = 1;
+  const dim3 blk(WAVE << a.g.seg_shift);
   AIR_DISPATCH(a.f.nb, a.f.kind,
-               hipLaunchKernelGGL((k_trace_pixels<NB_, FK_>), dim3(blocks), dim3(256), 0, s, a, n, level, ix, iy,
-                                  I, N, visits));
+               hipLaunchKernelGGL((k_trace_pixels<NB_, FK_>), dim3(blocks), blk, 0, s, a, n, level, ix, iy, I, N,
+                                  visits));
   return hipGetLastError();
 }
 

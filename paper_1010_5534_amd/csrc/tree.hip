@@ -14,8 +14,8 @@ namespace air {
 
 namespace {
 
-constexpr int RB = 128;             // refine block size
-constexpr int STK = 2 * MAXL + 2;   // closure stack depth bound (2L + 1)
+constexpr int RB = 256;             // refine block size
+constexpr int STK = 2 * MAXL;       // closure stack depth bound: 2L + 1 with L <= MAXL - 2
 
 __device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
@@ -66,7 +66,10 @@ struct BandW {
 };
 
 __global__ __launch_bounds__(RB) void k_refine(MarchArgs A, int L, float xcI, float xcN, BandW W) {
-  __shared__ uint64_t stk[STK][RB];
+  __shared__ uint32_t stk_key[STK][RB];
+  __shared__ uint8_t stk_lev[STK][RB];
+  __shared__ unsigned wcnt[RB / WAVE];
+  __shared__ unsigned long long bbase;
   unsigned long long* ctr = A.w.ctr;
   const unsigned long long qs = ctr[CTR_LSTART + L], qe = ctr[CTR_LSTART + L + 1];
   const int N0 = A.img.N0, nb = A.f.nb;
@@ -118,15 +121,23 @@ __global__ __launch_bounds__(RB) void k_refine(MarchArgs A, int L, float xcI, fl
         atomicOr(reinterpret_cast<uint32_t*>(A.w.state + vb + A.img.off[L + 1] + 4ll * key),
                  0x01010101u * (AIR_NODE_EXIST | AIR_NODE_TESTED));
     }
-    // children of the flagged nodes of this wave: one queue reservation
+    // children of the block's flagged nodes: one queue reservation per block
     const uint64_t mask = __ballot(flag);
-    if (mask) {
-      const int leader = __builtin_ctzll(mask);
-      unsigned long long dst = 0;
-      if (lane == leader) dst = atomicAdd(&ctr[CTR_CURSOR], 4ull * (unsigned long long)__popcll(mask));
-      dst = __shfl(dst, leader);
+    const int w = tid / WAVE;
+    if (lane == 0) wcnt[w] = (unsigned)__popcll(mask);
+    __syncthreads();
+    if (tid == 0) {
+      unsigned tot = 0;
+      for (int q = 0; q < RB / WAVE; ++q) tot += wcnt[q];
+      bbase = tot ? atomicAdd(&ctr[CTR_CURSOR], 4ull * tot) : 0ull;
+    }
+    __syncthreads();
+    {
+      unsigned before = 0;
+      for (int q = 0; q < w; ++q) before += wcnt[q];
+      unsigned long long dst = bbase + 4ull * (before + lanes_below(mask));
+      __syncthreads();  // wcnt and bbase are rewritten by the next iteration
       if (flag) {
-        dst += 4ull * lanes_below(mask);
         if (dst + 4 <= qcap) {
 #pragma unroll
           for (uint32_t c = 0; c < 4; ++c) A.w.queue[dst + c] = qentry(v, L + 1, 4u * key + c);
@@ -145,7 +156,11 @@ __global__ __launch_bounds__(RB) void k_refine(MarchArgs A, int L, float xcI, fl
       auto request = [&](int l, uint32_t qi, uint32_t qj) {
         const uint32_t kq = key_of(qi, qj, l, N0);
         const uint32_t old = state_or(A.w.state, vb + A.img.off[l] + kq, AIR_NODE_REFINED);
-        if (!(old & AIR_NODE_REFINED)) stk[sp++][tid] = ((uint64_t)l << 32) | kq;
+        if (!(old & AIR_NODE_REFINED)) {
+          stk_key[sp][tid] = kq;
+          stk_lev[sp][tid] = (uint8_t)l;
+          ++sp;
+        }
       };
       // the parents of the 8 neighbours of (l, ni, nj), other than its own
       auto around = [&](int l, uint32_t ni, uint32_t nj) {
@@ -159,9 +174,9 @@ __global__ __launch_bounds__(RB) void k_refine(MarchArgs A, int L, float xcI, fl
       };
       around(L, i, j);
       while (sp > 0) {
-        const uint64_t t = stk[--sp][tid];
-        const int l = (int)(t >> 32);
-        const uint32_t kq = (uint32_t)t;
+        --sp;
+        const int l = stk_lev[sp][tid];
+        const uint32_t kq = stk_key[sp][tid];
         if (l >= 1) {
           uint32_t qi, qj;
           coords_of(kq, l, N0, qi, qj);
@@ -198,46 +213,58 @@ __device__ __forceinline__ unsigned long long block_sum_u64(unsigned long long x
   return t;
 }
 
-// per chunk of CHUNK positions: existing nodes; plus the tree counters
-__global__ __launch_bounds__(256) void k_count(MarchArgs A, unsigned long long* chunk_counts,
-                                               unsigned long long* vstat) {
-  __shared__ unsigned long long sh[4];
-  __shared__ unsigned long long lv[MAXL];
+// per chunk of CHUNK positions: existing nodes (for the scan) and the tree
+// counters, written per chunk; no global atomics
+__global__ __launch_bounds__(256) void k_count(MarchArgs A, unsigned long long* chunk_counts, unsigned* chunk_stats,
+                                               int64_t n_chunks) {
+  __shared__ unsigned sh[VS_N][4];
   const int64_t c = blockIdx.x;
-  const int64_t S = A.img.S;
-  const int64_t v = (c * CHUNK) / S;  // S is a multiple of CHUNK
-  if (threadIdx.x < MAXL) lv[threadIdx.x] = 0;
-  __syncthreads();
-  unsigned long long n = 0, leaves = 0, tested = 0, flagged = 0, bal = 0;
+  unsigned cnt[VS_N] = {0, 0, 0, 0, 0};
   for (int k = 0; k < CHUNK / 256; ++k) {
     const int64_t p = c * CHUNK + k * 256 + threadIdx.x;
     const uint8_t s = A.w.state[p];
     if (s & AIR_NODE_EXIST) {
-      ++n;
-      leaves += !(s & AIR_NODE_REFINED);
-      tested += (s & AIR_NODE_EVALUATED) != 0;
-      flagged += (s & AIR_NODE_FLAGGED) != 0;
-      bal += (s & AIR_NODE_BALANCE) != 0;
-      atomicAdd(&lv[level_of(A.img, p % S)], 1ull);
+      ++cnt[VS_NODES];
+      cnt[VS_LEAVES] += !(s & AIR_NODE_REFINED);
+      cnt[VS_TESTED] += (s & AIR_NODE_EVALUATED) != 0;
+      cnt[VS_FLAGGED] += (s & AIR_NODE_FLAGGED) != 0;
+      cnt[VS_BALANCE] += (s & AIR_NODE_BALANCE) != 0;
     }
   }
-  const unsigned long long tot = block_sum_u64(n, sh);
-  const unsigned long long tl = block_sum_u64(leaves, sh);
-  const unsigned long long tt = block_sum_u64(tested, sh);
-  const unsigned long long tf = block_sum_u64(flagged, sh);
-  const unsigned long long tb = block_sum_u64(bal, sh);
-  if (threadIdx.x == 0) {
-    chunk_counts[c] = tot;
-    unsigned long long* ctr = A.w.ctr;
-    if (tl) atomicAdd(&ctr[CTR_LEAVES], tl);
-    if (tl) atomicAdd(&vstat[v * (MAXL + 1) + MAXL], tl);
-    if (tt) atomicAdd(&ctr[CTR_TESTED], tt);
-    if (tf) atomicAdd(&ctr[CTR_FLAGGED], tf);
-    if (tb) atomicAdd(&ctr[CTR_BALANCE], tb);
+  const int w = threadIdx.x / WAVE;
+#pragma unroll
+  for (int q = 0; q < VS_N; ++q) {
+    unsigned x = cnt[q];
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+    if ((threadIdx.x & (WAVE - 1)) == 0) sh[q][w] = x;
   }
-  if (threadIdx.x < MAXL && lv[threadIdx.x]) {
-    atomicAdd(&A.w.ctr[CTR_NODES + threadIdx.x], lv[threadIdx.x]);
-    atomicAdd(&vstat[v * (MAXL + 1) + threadIdx.x], lv[threadIdx.x]);
+  __syncthreads();
+  if (threadIdx.x < VS_N) {
+    const unsigned t = sh[threadIdx.x][0] + sh[threadIdx.x][1] + sh[threadIdx.x][2] + sh[threadIdx.x][3];
+    chunk_stats[threadIdx.x * n_chunks + c] = t;
+    if (threadIdx.x == VS_NODES) chunk_counts[c] = t;
+  }
+}
+
+// per (view, level): sum the counters of its chunks (levels start on a
+// chunk), fixed order
+__global__ __launch_bounds__(256) void k_reduce_stats(MarchArgs A, const unsigned* chunk_stats, int64_t n_chunks,
+                                                      unsigned long long* vstat) {
+  __shared__ unsigned long long sh[256];
+  const int v = blockIdx.x / (A.img.Lmax + 1), L = blockIdx.x % (A.img.Lmax + 1);
+  const int64_t c0 = ((int64_t)v * A.img.S + A.img.off[L]) / CHUNK;
+  const int64_t c1 = ((int64_t)v * A.img.S + A.img.off[L + 1]) / CHUNK;
+  for (int q = 0; q < VS_N; ++q) {
+    unsigned long long x = 0;
+    for (int64_t c = c0 + threadIdx.x; c < c1; c += 256) x += chunk_stats[q * n_chunks + c];
+    sh[threadIdx.x] = x;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) vstat[((int64_t)v * MAXL + L) * VS_N + q] = sh[0];
+    __syncthreads();
   }
 }
 
@@ -383,14 +410,21 @@ __global__ __launch_bounds__(256) void k_flux_partial(MarchArgs A, const DevView
   }
 }
 
-// per (view, band): sum the view's chunk partials in order
-__global__ void k_flux_final(const double* partial, int64_t chunks_per_view, int V, int nb, double* flux) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= V * nb) return;
-  const int v = t / nb, b = t % nb;
-  double s = 0.0;
-  for (int64_t c = 0; c < chunks_per_view; ++c) s += partial[((int64_t)v * chunks_per_view + c) * nb + b];
-  flux[t] = s;
+// per (view, band): sum the view's chunk partials, fixed order (each thread
+// a fixed stride, then a fixed tree)
+__global__ __launch_bounds__(256) void k_flux_final(const double* partial, int64_t chunks_per_view, int nb,
+                                                    double* flux) {
+  __shared__ double sh[256];
+  const int v = blockIdx.x / nb, b = blockIdx.x % nb;
+  double x = 0.0;
+  for (int64_t c = threadIdx.x; c < chunks_per_view; c += 256) x += partial[((int64_t)v * chunks_per_view + c) * nb + b];
+  sh[threadIdx.x] = x;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) flux[blockIdx.x] = sh[0];
 }
 
 // fixed image flux: per (view, band, chunk of raster) partials
@@ -416,12 +450,18 @@ __global__ __launch_bounds__(256) void k_fixed_partial(const float* images, int 
   if (threadIdx.x == 0) partial[c] = sh[0];
 }
 
-__global__ void k_fixed_final(const double* partial, int64_t chunks_per_plane, int n_planes, double* flux) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n_planes) return;
-  double s = 0.0;
-  for (int64_t c = 0; c < chunks_per_plane; ++c) s += partial[(int64_t)t * chunks_per_plane + c];
-  flux[t] = s;
+__global__ __launch_bounds__(256) void k_fixed_final(const double* partial, int64_t chunks_per_plane,
+                                                     double* flux) {
+  __shared__ double sh[256];
+  double x = 0.0;
+  for (int64_t c = threadIdx.x; c < chunks_per_plane; c += 256) x += partial[(int64_t)blockIdx.x * chunks_per_plane + c];
+  sh[threadIdx.x] = x;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) flux[blockIdx.x] = sh[0];
 }
 
 }  // namespace
@@ -434,9 +474,11 @@ hipError_t launch_refine(const MarchArgs& a, int L, float xcI, float xcN, const 
   return hipGetLastError();
 }
 
-hipError_t launch_count(const MarchArgs& a, unsigned long long* chunk_counts, int64_t n_chunks,
-                        unsigned long long* vstat, hipStream_t s) {
-  hipLaunchKernelGGL(k_count, dim3((unsigned)n_chunks), dim3(256), 0, s, a, chunk_counts, vstat);
+hipError_t launch_count(const MarchArgs& a, unsigned long long* chunk_counts, unsigned* chunk_stats,
+                        int64_t n_chunks, unsigned long long* vstat, hipStream_t s) {
+  hipLaunchKernelGGL(k_count, dim3((unsigned)n_chunks), dim3(256), 0, s, a, chunk_counts, chunk_stats, n_chunks);
+  hipLaunchKernelGGL(k_reduce_stats, dim3((unsigned)(a.img.V * (a.img.Lmax + 1))), dim3(256), 0, s, a, chunk_stats,
+                     n_chunks, vstat);
   return hipGetLastError();
 }
 
@@ -464,9 +506,8 @@ hipError_t launch_assemble(const MarchArgs& a, float* images, hipStream_t s) {
 
 hipError_t launch_flux(const MarchArgs& a, double* partial, int64_t n_chunks, double* flux_dev, hipStream_t s) {
   hipLaunchKernelGGL(k_flux_partial, dim3((unsigned)n_chunks), dim3(256), 0, s, a, a.views, partial);
-  const int n = a.img.V * a.f.nb;
-  hipLaunchKernelGGL(k_flux_final, dim3((n + 63) / 64), dim3(64), 0, s, partial, n_chunks / a.img.V, a.img.V,
-                     a.f.nb, flux_dev);
+  hipLaunchKernelGGL(k_flux_final, dim3((unsigned)(a.img.V * a.f.nb)), dim3(256), 0, s, partial,
+                     n_chunks / a.img.V, a.f.nb, flux_dev);
   return hipGetLastError();
 }
 
@@ -475,7 +516,7 @@ hipError_t launch_fixed_flux(const float* images, int V, int nb, int64_t R, doub
   const int64_t R2 = R * R, cpp = (R2 + CHUNK - 1) / CHUNK;
   const int64_t n = (int64_t)V * nb * cpp;
   hipLaunchKernelGGL(k_fixed_partial, dim3((unsigned)n), dim3(256), 0, s, images, nb, R2, pix_area, cpp, partial);
-  hipLaunchKernelGGL(k_fixed_final, dim3((V * nb + 63) / 64), dim3(64), 0, s, partial, cpp, V * nb, flux_dev);
+  hipLaunchKernelGGL(k_fixed_final, dim3((unsigned)(V * nb)), dim3(256), 0, s, partial, cpp, flux_dev);
   return hipGetLastError();
 }
 

@@ -16,7 +16,7 @@ HEADER = os.path.join(ROOT, "include", "air.h")
 def declared_functions():
     src = open(HEADER).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"^\s*(?:air_status|void|const char\*)\s+(air_\w+)\s*\(", src, flags=re.M)))
+    return sorted(set(re.findall(r"^\s*(?:air_status|void|const char\*|int64_t)\s+(air_\w+)\s*\(", src, flags=re.M)))
 
 
 def test_header_declares_entry_points():
@@ -42,8 +42,8 @@ def test_struct_layouts_match_header():
 int main(void) {
   printf("%zu %zu %zu %zu %zu %zu\n", sizeof(air_grid), sizeof(air_field), sizeof(air_view),
          sizeof(air_params), sizeof(air_tree), sizeof(air_stats));
-  printf("%zu %zu %zu %zu\n", offsetof(air_grid, block_level), offsetof(air_field, band),
-         offsetof(air_tree, level), offsetof(air_tree, visits));
+  printf("%zu %zu %zu %zu %zu\n", offsetof(air_grid, block_level), offsetof(air_field, band),
+         offsetof(air_tree, level), offsetof(air_tree, visits), offsetof(air_field, packed));
   return 0;
 }
 '''
@@ -57,7 +57,24 @@ int main(void) {
     assert sizes[:6] == [C.sizeof(t) for t in (air.air_grid, air.air_field, air.air_view, air.air_params,
                                                  air.air_tree, air.air_stats)]
     assert sizes[6:] == [air.air_grid.block_level.offset, air.air_field.band.offset, air.air_tree.level.offset,
-                         air.air_tree.visits.offset]
+                         air.air_tree.visits.offset, air.air_field.packed.offset]
+
+
+def test_packed_bytes_without_device():
+    """air_field_packed_bytes needs no device: 2x2x2 bricks, 16 B or 8 B cells."""
+    import ctypes as C
+    from paper_1010_5534_amd import air
+    g = air.air_grid()
+    g.kind = 0
+    g.n[:] = [5, 8, 3]
+    g.hi[:] = [1.0, 1.0, 1.0]
+    f = air.air_field()
+    f.kind, f.n_bands, f.rho, f.emis, f.kappa = 0, 1, 16, 16, 16  # non-NULL, never dereferenced
+    assert air.lib().air_field_packed_bytes(C.addressof(g), C.addressof(f)) == 3 * 4 * 2 * 8 * 16
+    f.kind, f.temp, f.n_bands = 1, 16, 4
+    assert air.lib().air_field_packed_bytes(C.addressof(g), C.addressof(f)) == 3 * 4 * 2 * 8 * 8
+    f.n_bands = 9
+    assert air.lib().air_field_packed_bytes(C.addressof(g), C.addressof(f)) == air.AIR_EINVAL
 
 
 def test_null_context_is_rejected_without_device_work():

@@ -288,6 +288,49 @@ def test_capacity_error_reports_needed_size(ctx, gauss):
     assert trees[0].n_nodes == full[0].n_nodes > 100
 
 
+def _brick_order(a, n):
+    """numpy reference of the packed layout: 2x2x2 bricks, x fastest."""
+    nx, ny, nz = n
+    bx, by, bz = (nx + 1) // 2, (ny + 1) // 2, (nz + 1) // 2
+    pad = np.zeros((2 * bz, 2 * by, 2 * bx) + a.shape[3:], a.dtype)
+    pad[:nz, :ny, :nx] = a
+    pad = pad.reshape(bz, 2, by, 2, bx, 2, *a.shape[3:])      # z, cz, y, cy, x, cx
+    pad = pad.transpose(0, 2, 4, 1, 3, 5, *range(6, pad.ndim))  # brick z, y, x, then cz, cy, cx
+    return pad.reshape(bz * by * bx * 8, *a.shape[3:])
+
+
+def test_packed_layout_contents(ctx):
+    from paper_1010_5534_amd import air
+    g, f = inputs.winds2(seed=8, n=6)
+    f.rho = np.arange(216, dtype=np.float32).reshape(6, 6, 6)
+    g = inputs.Grid(inputs.GRID_UNIFORM, (6, 5, 3))
+    f = inputs.Field(0, np.arange(90, dtype=np.float32).reshape(3, 5, 6), 1000 + np.arange(90, dtype=np.float32).reshape(3, 5, 6),
+                     2000 + np.arange(90, dtype=np.float32).reshape(3, 5, 6))
+    sc = ctx.prepare(air.upload(g, f))
+    got = sc.tensors[-1].cpu().numpy().view(np.float32).reshape(-1, 4)
+    stacked = np.stack([f.rho, f.emis, f.kappa, np.zeros_like(f.rho)], axis=-1)
+    assert np.array_equal(got, _brick_order(stacked, g.n))
+
+
+def test_prepacked_field_equals_per_call_packing(ctx):
+    """A field packed once (air_field_pack) renders bit for bit like one the
+    library packs on every call."""
+    from paper_1010_5534_amd import air
+    g, f = inputs.winds2(seed=8, n=50)  # even and odd brick counts
+    views = inputs.winds2_views()
+    prm = air.params(10, 4, 0.4)
+    a = ctx.render(air.upload(g, f), views, prm)
+    b = ctx.render(ctx.prepare(air.upload(g, f)), views, prm)
+    for ta, tb in zip(a[0], b[0]):
+        assert torch.equal(ta.I, tb.I) and torch.equal(ta.state, tb.state)
+    assert torch.equal(a[1], b[1])
+    g2, f2 = inputs.winds2(seed=8, n=33, kind=inputs.FIELD_RHO_T, bands=inputs.default_bands(2))
+    s1, s2 = air.upload(g2, f2), ctx.prepare(air.upload(g2, f2))
+    i1, _, _ = ctx.render_fixed(s1, views, 8, 2)
+    i2, _, _ = ctx.render_fixed(s2, views, 8, 2)
+    assert torch.equal(i1, i2)
+
+
 def test_tree_links_consistent(ctx, gauss):
     from paper_1010_5534_amd import air
     g, f, scene = gauss
