@@ -1,9 +1,9 @@
 #!/usr/bin/env python3
 """Benchmark of adaptive image ray-tracing on one MI355X.
 
-Workload (the uniform colliding-winds case): 256^3 float32 field with two
-wind sources and a shocked shell (seed 0), j = rho^2 T^0.5, kappa =
-rho T^-1.5; 64x64 coarse image, 5 refinement levels (2048^2 effective),
+Workload (the uniform colliding-winds case): 256^3 float32 (rho, T) field
+with two wind sources and a shocked shell (seed 0), one band j = rho^2
+T^0.5, kappa = rho T^-1.5 evaluated per visit; 64x64 coarse image, 5 refinement levels (2048^2 effective),
 xi_crit = 0.5, three views (+z, +x, (1,1,1)/sqrt3).  One step = plain AIR of
 the three views in one call: march every level, refinement test, 2:1
 closure, compaction, canonical quadtree, raster assembly and float64 flux.
@@ -24,10 +24,10 @@ sys.path.insert(0, ROOT)
 METRIC = "rays/s & per-image time: learned AIR vs plain AIR vs fixed-res, 1 GPU"
 HBM_PEAK_GBS = 8000.0
 N0, LMAX, XI_CRIT, SEED, NGRID = 64, 5, 0.5, 0, 256
-# algorithmic bytes of the march: per (ray, cell) visit the three float32
-# field values; per ray its queue entry (8 B) and results (I, N, visits: 12 B,
-# state byte)
-BYTES_PER_VISIT = 12
+# algorithmic bytes of the march: per (ray, cell) visit the two float32 field
+# values (rho, T); per ray its queue entry (8 B) and results (I, N, visits:
+# 12 B, state byte)
+BYTES_PER_VISIT = 8
 BYTES_PER_RAY_QUEUE = 8 + 12 + 1
 BYTES_PER_RAY_FIXED = 8  # I and N written to the raster
 
@@ -71,6 +71,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-fixed", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="after the timed region, one 256 MiB device copy whose counters calibrate HBM bytes")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the adaptive render of one scene runs on one device; "
@@ -84,7 +86,7 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     log("generating winds2 field", NGRID)
-    g, f = inputs.winds2(SEED, NGRID)
+    g, f = inputs.winds2(SEED, NGRID, kind=inputs.FIELD_RHO_T, bands=np.array([[1.0, 1.5, 0.5]]))
     views = inputs.winds2_views()
     ctx = air.Context(0)
     scene = ctx.prepare(air.upload(g, f))
@@ -119,7 +121,7 @@ def main():
     res = dict(metric=METRIC, value=rays_p / wall_p, unit="rays/s", n_gpus=1, steps=args.steps,
                warmup=args.warmup, ms_per_step=wall_p * 1e3, higher_is_better=True, scaling="weak",
                vs_baseline=None, dtype="f32", data="synthetic",
-               config=dict(workload=f"winds2 {NGRID}^3 seed {SEED}, {N0}x{N0} coarse, {LMAX} levels "
+               config=dict(workload=f"winds2 {NGRID}^3 (rho, T) seed {SEED}, {N0}x{N0} coarse, {LMAX} levels "
                                     f"({N0 << LMAX}^2 effective), xi_crit {XI_CRIT}, 3 views (+z, +x, diag)",
                            views=3, coarse=N0, levels=LMAX, grid=NGRID))
     per_level = st_p["rays_per_level"][:LMAX + 1]
@@ -152,6 +154,12 @@ def main():
                                    flux_rel_err=[float((flux_f[k][0] - flux_p[k][0]) / flux_f[k][0])
                                                  for k in range(len(views))])
     res["learned_air"] = None
+
+    if args.copy_probe:
+        src = torch.empty(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
 
     if not args.no_cpu_baseline:
         log("oracle CPU baseline")
