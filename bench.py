@@ -94,7 +94,7 @@ def main():
     torch.cuda.synchronize()
 
     def plain():
-        return ctx.render(scene, views, prm)
+        return ctx.render(scene, views, prm, reuse=True)
 
     def fixed():
         return ctx.render_fixed(scene, views, N0, LMAX)

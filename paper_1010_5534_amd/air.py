@@ -204,6 +204,7 @@ class Context:
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible: the AIR library runs on the GPU only")
         self.device = device
+        self._cache = {}
         self._p = C.c_void_p()
         rc = lib().air_create(C.byref(self._p), device)
         if rc != AIR_OK:
@@ -262,24 +263,39 @@ class Context:
         return s, t
 
     def render(self, scene: DeviceScene, views: Sequence, prm: air_params, want_tree=True, want_image=True,
-               want_flux=True, capacity: Optional[int] = None):
-        """Plain AIR over the views.  Returns (trees, images, flux, stats)."""
+               want_flux=True, capacity: Optional[int] = None, reuse: bool = False):
+        """Plain AIR over the views.  Returns (trees, images, flux, stats).
+        reuse=True hands back the same output tensors on every call with the
+        same shapes (the next call overwrites them)."""
         torch = _torch()
         V, nb = len(views), scene.n_bands
         R = prm.coarse_n << prm.max_level
         bound = sum((prm.coarse_n << L) ** 2 for L in range(prm.max_level + 1))
         cap = min(bound, capacity or (1 << 21))
         vs = _views(views)
-        images = torch.empty((V, nb + 1, R, R), dtype=torch.float32, device=f"cuda:{self.device}") \
-            if want_image else None
+        ikey = ("img", V, nb, R)
+        if want_image and reuse and ikey in self._cache:
+            images = self._cache[ikey]
+        else:
+            images = torch.empty((V, nb + 1, R, R), dtype=torch.float32, device=f"cuda:{self.device}") \
+                if want_image else None
+            if want_image and reuse:
+                self._cache[ikey] = images
         flux = np.zeros((V, nb), dtype=np.float64) if want_flux else None
         st = air_stats()
         while True:
             trees = (air_tree * V)() if want_tree else None
             keep = []
             if want_tree:
+                tkey = ("tree", V, nb, cap)
+                if reuse and tkey in self._cache:
+                    pairs = self._cache[tkey]
+                else:
+                    pairs = [self._alloc_tree(cap, nb) for _ in range(V)]
+                    if reuse:
+                        self._cache[tkey] = pairs
                 for k in range(V):
-                    s, t = self._alloc_tree(cap, nb)
+                    s, t = pairs[k]
                     trees[k] = s
                     keep.append(t)
             rc = lib().air_render(self._p, C.addressof(scene.grid), C.addressof(scene.field), C.addressof(vs), V,

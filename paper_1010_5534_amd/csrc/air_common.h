@@ -11,7 +11,10 @@ namespace air {
 constexpr int MAXL = AIR_MAX_LEVELS;
 constexpr int MAXB = AIR_MAX_BANDS;
 constexpr int WAVE = 64;
-constexpr int MAX_SEG = 8;  // at most 8 waves (sub-intervals) per ray tile
+#ifndef AIR_MAX_SEG
+#define AIR_MAX_SEG 8
+#endif
+constexpr int MAX_SEG = AIR_MAX_SEG;  // at most this many waves (sub-intervals) per ray tile
 
 // node state bits beyond the public ones: set by the march once the node's
 // values are written (the refinement test reads only traced values)

@@ -23,7 +23,10 @@ namespace air {
 namespace {
 
 constexpr float LOG2E_F = 1.4426950408889634f;
-constexpr int KB = 4;  // cells per load batch in the march
+#ifndef AIR_KB
+#define AIR_KB 4
+#endif
+constexpr int KB = AIR_KB;  // cells per load batch in the march
 
 struct ff {
   float hi, lo;
@@ -56,21 +59,24 @@ __device__ __forceinline__ void kadd(float& s, float& c, float x) {
 }
 
 // (1 - e^-x)/x: Taylor series below 1/4 (truncation < 2e-9 relative),
-// direct form above (cancellation at most a factor 4.5)
+// direct form above (cancellation at most a factor 4.5); the direct form is
+// evaluated only when some lane of the wave needs it
 __device__ __forceinline__ float seg_weight(float x) {
-  if (x < 0.25f) {
-    float y = -x;
-    float p = 1.0f / 5040.0f;
-    p = __builtin_fmaf(p, y, 1.0f / 720.0f);
-    p = __builtin_fmaf(p, y, 1.0f / 120.0f);
-    p = __builtin_fmaf(p, y, 1.0f / 24.0f);
-    p = __builtin_fmaf(p, y, 1.0f / 6.0f);
-    p = __builtin_fmaf(p, y, 0.5f);
-    p = __builtin_fmaf(p, y, 1.0f);
-    return p;
+  const float y = -x;
+  float p = 1.0f / 5040.0f;
+  p = __builtin_fmaf(p, y, 1.0f / 720.0f);
+  p = __builtin_fmaf(p, y, 1.0f / 120.0f);
+  p = __builtin_fmaf(p, y, 1.0f / 24.0f);
+  p = __builtin_fmaf(p, y, 1.0f / 6.0f);
+  p = __builtin_fmaf(p, y, 0.5f);
+  p = __builtin_fmaf(p, y, 1.0f);
+  const bool big = x >= 0.25f;
+  if (__ballot(big)) {
+    const float e = __builtin_amdgcn_exp2f(-x * LOG2E_F);
+    const float g = (1.0f - e) * __builtin_amdgcn_rcpf(x);
+    p = big ? g : p;
   }
-  float e = __builtin_amdgcn_exp2f(-x * LOG2E_F);
-  return (1.0f - e) * __builtin_amdgcn_rcpf(x);
+  return p;
 }
 
 // raw cell data: (rho, j, kappa) or (rho, T)
@@ -190,12 +196,17 @@ __device__ __forceinline__ int cells_between(const Geo& g, const double o[3], co
 
 // March the sub-interval [ta, tb] of the ray x(t) = o + t d (d unit) through
 // the uniform grid: DDA from the cell just after ta to the cell just before
-// tb, optical depth from 0 at ta.
+// tb, optical depth from 0 at ta.  Crossing parameters are measured from ta
+// (a sub-interval is at most ~1/S of the chord, ~32 cells): the first
+// crossing of each axis and the per-axis spacing come from float64, and the
+// k-th crossing is the single-rounding t_a(k) = fma(k, dt_a, t_a(0)), so no
+// rounding accumulates and each segment length is a difference of two
+// freshly rounded values.
 template <int NB, int FK, bool RANGE>
 __device__ void march_interval(const Geo& g, const Fld& f, const double o[3], const double d[3],
                                const double inv_d[3], double ta, double tb, Seg<NB>& r) {
   int c[3], st[3], nvis = 1;
-  ff T0[3], D[3];
+  float T0[3], D[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     const int k0 = cell_at(g, o, d, a, ta, true), k1 = cell_at(g, o, d, a, tb, false);
@@ -203,17 +214,16 @@ __device__ void march_interval(const Geo& g, const Fld& f, const double o[3], co
     nvis += abs(k1 - k0);
     if (d[a] != 0.0) {
       const int m = d[a] > 0.0 ? k0 + 1 : k0;
-      const double tf = (g.lo[a] + (double)m * g.h[a] - o[a]) * inv_d[a] - ta;
-      T0[a] = ff_of(tf);
-      D[a] = ff_of(g.h[a] * fabs(inv_d[a]));
+      T0[a] = (float)((g.lo[a] + (double)m * g.h[a] - o[a]) * inv_d[a] - ta);
+      D[a] = (float)(g.h[a] * fabs(inv_d[a]));
       st[a] = d[a] > 0.0 ? 1 : -1;
     } else {
-      T0[a] = {__builtin_huge_valf(), 0.0f};
-      D[a] = {0.0f, 0.0f};
+      T0[a] = __builtin_huge_valf();
+      D[a] = 0.0f;
       st[a] = 0;
     }
   }
-  const ff S1 = ff_of(tb - ta);
+  const float S1 = (float)(tb - ta);
   const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
   const i32x4 R = field_rsrc(f);
   const int bnx = f.bnx, bny = f.bny;
@@ -225,68 +235,88 @@ __device__ void march_interval(const Geo& g, const Fld& f, const double o[3], co
   float rmin = __builtin_huge_valf(), rmax = -__builtin_huge_valf();
 
   int cx = c[0], cy = c[1], cz = c[2];
-  int k0 = 0, k1 = 0, k2 = 0;
-  ff ta0 = T0[0], ta1 = T0[1], ta2 = T0[2];
-  ff tc = {0.0f, 0.0f};
+  const int s0 = st[0], s1 = st[1], s2 = st[2];
+  const float T00 = T0[0], T01 = T0[1], T02 = T0[2], D0 = D[0], D1 = D[1], D2 = D[2];
+  float k0 = 0.0f, k1 = 0.0f, k2 = 0.0f;  // crossings done per axis (exact small integers)
+  float t0 = T00, t1 = T01, t2 = T02;
+  float tc = 0.0f;
   int idx = brick_index(cx, cy, cz, bnx, bny);
-  // Batches of KB cells: the DDA walks KB cells ahead (cell offsets and
-  // segment lengths), all their loads are issued together, then the cells
-  // are integrated in order; KB loads per lane are in flight at once.
-  for (int v0 = 0; v0 < nvis; v0 += KB) {
-    int off[KB];
-    float dsq[KB];
-#pragma unroll
-    for (int q = 0; q < KB; ++q) {
-      off[q] = idx;
-      ff tn;
-      int ax;
-      if (v0 + q >= nvis - 1) {  // the last cell ends at tb; past it ds = 0
-        tn = S1;
-        ax = 3;
-      } else {
-        ax = (ta0.hi <= ta1.hi) ? (ta0.hi <= ta2.hi ? 0 : 2) : (ta1.hi <= ta2.hi ? 1 : 2);
-        tn = ax == 0 ? ta0 : (ax == 1 ? ta1 : ta2);
-      }
-      dsq[q] = (tn.hi - tc.hi) + (tn.lo - tc.lo);
-      tc = tn;
-      if (ax == 0) {
-        ++k0;
-        ta0 = ff_axpy(k0, D[0], T0[0]);
-        cx = min(max(cx + st[0], 0), nx - 1);
-      } else if (ax == 1) {
-        ++k1;
-        ta1 = ff_axpy(k1, D[1], T0[1]);
-        cy = min(max(cy + st[1], 0), ny - 1);
-      } else if (ax == 2) {
-        ++k2;
-        ta2 = ff_axpy(k2, D[2], T0[2]);
-        cz = min(max(cz + st[2], 0), nz - 1);
-      }
-      idx = brick_index(cx, cy, cz, bnx, bny);
-    }
-    Raw<FK> raw[KB];
-#pragma unroll
-    for (int q = 0; q < KB; ++q) raw[q] = load_raw<FK>(R, off[q]);
-#pragma unroll
-    for (int q = 0; q < KB; ++q) {
-      if (v0 + q >= nvis) break;
-      const float ds = dsq[q];
-      float jb[NB], kb[NB];
-      optics<NB, FK>(f, raw[q], jb, kb);
-#pragma unroll
-      for (int b = 0; b < NB; ++b) {
-        const float dtau = kb[b] * ds;
-        const float T = __builtin_amdgcn_exp2f(-(tau[b] - ctau[b]) * LOG2E_F);
-        kadd(I[b], cI[b], T * (jb[b] * ds) * seg_weight(dtau));
-        kadd(tau[b], ctau[b], dtau);
-      }
-      kadd(N, cN, raw[q].rho * ds);
-      if constexpr (RANGE) {
-        rmin = fminf(rmin, raw[q].rho);
-        rmax = fmaxf(rmax, raw[q].rho);
-      }
-    }
+
+  // One DDA step per cell of a batch of KB (the cell's record offset and
+  // segment length; past the last cell ds = 0 and the cell repeats), then
+  // the batch's loads.  Written as macros over named arrays so that every
+  // index is static and the batches stay in registers.
+#define AIR_DDA_BATCH(V0, OFF, DS, RAW)                                   \
+  _Pragma("unroll") for (int q = 0; q < KB; ++q) {                        \
+    OFF[q] = idx;                                                         \
+    float tn;                                                             \
+    int ax = 3;                                                           \
+    if ((V0) + q >= nvis - 1) {                                           \
+      tn = S1;                                                            \
+    } else {                                                              \
+      tn = fminf(fminf(t0, t1), t2);                                      \
+      ax = tn == t0 ? 0 : (tn == t1 ? 1 : 2);                             \
+    }                                                                     \
+    DS[q] = tn - tc;                                                      \
+    tc = tn;                                                              \
+    if (ax == 0) {                                                        \
+      k0 += 1.0f;                                                         \
+      t0 = __builtin_fmaf(k0, D0, T00);                                   \
+      cx = min(max(cx + s0, 0), nx - 1);                                  \
+    } else if (ax == 1) {                                                 \
+      k1 += 1.0f;                                                         \
+      t1 = __builtin_fmaf(k1, D1, T01);                                   \
+      cy = min(max(cy + s1, 0), ny - 1);                                  \
+    } else if (ax == 2) {                                                 \
+      k2 += 1.0f;                                                         \
+      t2 = __builtin_fmaf(k2, D2, T02);                                   \
+      cz = min(max(cz + s2, 0), nz - 1);                                  \
+    }                                                                     \
+    idx = brick_index(cx, cy, cz, bnx, bny);                              \
+  }                                                                       \
+  _Pragma("unroll") for (int q = 0; q < KB; ++q) RAW[q] = load_raw<FK>(R, OFF[q]);
+
+#define AIR_INTEGRATE(V0, DS, RAW)                                        \
+  _Pragma("unroll") for (int q = 0; q < KB; ++q) {                        \
+    if ((V0) + q < nvis) {                                                \
+      const float ds = DS[q];                                             \
+      float jb[NB], kb[NB];                                               \
+      optics<NB, FK>(f, RAW[q], jb, kb);                                  \
+      _Pragma("unroll") for (int b = 0; b < NB; ++b) {                    \
+        const float dtau = kb[b] * ds;                                    \
+        const float T = __builtin_amdgcn_exp2f(-(tau[b] - ctau[b]) * LOG2E_F); \
+        kadd(I[b], cI[b], T * (jb[b] * ds) * seg_weight(dtau));           \
+        kadd(tau[b], ctau[b], dtau);                                      \
+      }                                                                   \
+      kadd(N, cN, RAW[q].rho * ds);                                       \
+      if constexpr (RANGE) {                                              \
+        rmin = fminf(rmin, RAW[q].rho);                                   \
+        rmax = fmaxf(rmax, RAW[q].rho);                                   \
+      }                                                                   \
+    }                                                                     \
   }
+
+  // two batches in flight: walk and load batch n+1, then integrate batch n
+  int offA[KB], offB[KB];
+  float dsA[KB], dsB[KB];
+  Raw<FK> rawA[KB], rawB[KB];
+  AIR_DDA_BATCH(0, offA, dsA, rawA)
+  for (int v0 = 0;;) {
+    if (v0 + KB < nvis) {
+      AIR_DDA_BATCH(v0 + KB, offB, dsB, rawB)
+    }
+    AIR_INTEGRATE(v0, dsA, rawA)
+    v0 += KB;
+    if (v0 >= nvis) break;
+    if (v0 + KB < nvis) {
+      AIR_DDA_BATCH(v0 + KB, offA, dsA, rawA)
+    }
+    AIR_INTEGRATE(v0, dsB, rawB)
+    v0 += KB;
+    if (v0 >= nvis) break;
+  }
+#undef AIR_DDA_BATCH
+#undef AIR_INTEGRATE
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
     r.I[b] = I[b] - cI[b];
@@ -471,26 +501,27 @@ __global__ __launch_bounds__(256) void k_pack(Geo g, Fld f) {
   }
 }
 
+// zero the state maps (grid.y = view) with the base image marked existing and
+// tested, seed the queue with the base pixels, clear the counters
 __global__ void k_init(MarchArgs A) {
-  const int64_t V = A.img.V, S = A.img.S, n0sq = (int64_t)A.img.N0 * A.img.N0;
-  const int64_t words = V * S / 4;
-  uint32_t* st = reinterpret_cast<uint32_t*>(A.w.state);
+  const int64_t S = A.img.S, n0sq = (int64_t)A.img.N0 * A.img.N0;
+  const int v = blockIdx.y;
+  uint32_t* st = reinterpret_cast<uint32_t*>(A.w.state + (int64_t)v * S);
   const uint32_t base_bits = AIR_NODE_EXIST | AIR_NODE_TESTED;
-  for (int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; w < words;
-       w += (int64_t)gridDim.x * blockDim.x) {
-    int64_t local = (4 * w) % S;  // level 0 occupies [0, N0^2) of every view
+  for (int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; w < S / 4; w += (int64_t)gridDim.x * blockDim.x) {
     uint32_t word = 0;
+    if (4 * w < n0sq) {  // level 0 occupies [0, N0^2) of the view
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
-      if (local + b < n0sq) word |= base_bits << (8 * b);
+      for (int b = 0; b < 4; ++b)
+        if (4 * w + b < n0sq) word |= base_bits << (8 * b);
+    }
     st[w] = word;
   }
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < V * n0sq;
-       e += (int64_t)gridDim.x * blockDim.x)
-    A.w.queue[e] = qentry((uint32_t)(e / n0sq), 0, (uint32_t)(e % n0sq));
-  if (blockIdx.x == 0)
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n0sq; e += (int64_t)gridDim.x * blockDim.x)
+    A.w.queue[(int64_t)v * n0sq + e] = qentry((uint32_t)v, 0, (uint32_t)e);
+  if (blockIdx.x == 0 && blockIdx.y == 0)
     for (int k = threadIdx.x; k < CTR_COUNT; k += blockDim.x)
-      A.w.ctr[k] = k == CTR_CURSOR ? (unsigned long long)(V * n0sq) : 0ull;
+      A.w.ctr[k] = k == CTR_CURSOR ? (unsigned long long)(A.img.V * n0sq) : 0ull;
 }
 
 // Queue march of level L: tiles of 64 consecutive entries, one tile per
@@ -637,7 +668,8 @@ hipError_t launch_pack(const Geo& g, const Fld& f, void* packed, hipStream_t s) 
 }
 
 hipError_t launch_init(const MarchArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_init, dim3(2048), dim3(256), 0, s, a);
+  const int64_t per_view = std::max<int64_t>(1, std::min<int64_t>(2048, (a.img.S / 4 + 255) / 256));
+  hipLaunchKernelGGL(k_init, dim3((unsigned)per_view, (unsigned)a.img.V), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

@@ -202,6 +202,21 @@ __device__ __forceinline__ int level_of(const Img& img, int64_t local) {
   return L;
 }
 
+// a counting chunk lies in one (view, level): its view, level and first key
+struct ChunkPos {
+  int v, L;
+  int64_t key0;
+};
+__device__ __forceinline__ ChunkPos chunk_pos(const Img& img, int64_t c) {
+  ChunkPos r;
+  const int64_t p = c * CHUNK;
+  r.v = (int)(p / img.S);
+  const int64_t local = p - (int64_t)r.v * img.S;
+  r.L = level_of(img, local);
+  r.key0 = local - img.off[r.L];
+  return r;
+}
+
 __device__ __forceinline__ unsigned long long block_sum_u64(unsigned long long x, unsigned long long* sh) {
   for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
   const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
@@ -319,19 +334,22 @@ __global__ __launch_bounds__(256) void k_emit(MarchArgs A, const unsigned long l
   }
 }
 
+// one block per chunk; empty chunks return at once
 __global__ __launch_bounds__(256) void k_write_tree(MarchArgs A, const unsigned long long* chunk_off,
                                                     const int32_t* id_map, const TreeOut* outs) {
+  const int64_t c = blockIdx.x;
+  if (chunk_off[c + 1] == chunk_off[c]) return;
+  const ChunkPos cp = chunk_pos(A.img, c);
   const int64_t S = A.img.S, VS = (int64_t)A.img.V * S, cpv = S / CHUNK;
-  const int N0 = A.img.N0, nb = A.f.nb;
-  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < VS; p += (int64_t)gridDim.x * blockDim.x) {
+  const int N0 = A.img.N0, nb = A.f.nb, L = cp.L;
+  const TreeOut& T = outs[cp.v];
+  const int64_t base = (int64_t)chunk_off[cp.v * cpv];
+  const int64_t vb = (int64_t)cp.v * S;
+  for (int k = threadIdx.x; k < CHUNK; k += 256) {
+    const int64_t p = c * CHUNK + k;
     const uint8_t s = A.w.state[p];
     if (!(s & AIR_NODE_EXIST)) continue;
-    const int v = (int)(p / S);
-    const int64_t local = p - (int64_t)v * S;
-    const int L = level_of(A.img, local);
-    const uint32_t key = (uint32_t)(local - A.img.off[L]);
-    const TreeOut& T = outs[v];
-    const int64_t base = (int64_t)chunk_off[v * cpv];
+    const uint32_t key = (uint32_t)(cp.key0 + k);
     const int64_t id = (int64_t)id_map[p] - base;
     if (id >= T.capacity) continue;
     uint32_t i, j;
@@ -339,12 +357,9 @@ __global__ __launch_bounds__(256) void k_write_tree(MarchArgs A, const unsigned 
     if (T.level) T.level[id] = (int8_t)L;
     if (T.ix) T.ix[id] = (int32_t)i;
     if (T.iy) T.iy[id] = (int32_t)j;
-    if (T.parent)
-      T.parent[id] = L == 0 ? -1 : (int32_t)(id_map[(int64_t)v * S + A.img.off[L - 1] + (key >> 2)] - base);
+    if (T.parent) T.parent[id] = L == 0 ? -1 : (int32_t)(id_map[vb + A.img.off[L - 1] + (key >> 2)] - base);
     if (T.first_child)
-      T.first_child[id] = (s & AIR_NODE_REFINED)
-                              ? (int32_t)(id_map[(int64_t)v * S + A.img.off[L + 1] + 4ll * key] - base)
-                              : -1;
+      T.first_child[id] = (s & AIR_NODE_REFINED) ? (int32_t)(id_map[vb + A.img.off[L + 1] + 4ll * key] - base) : -1;
     if (T.state) T.state[id] = s & (uint8_t)~ST_TRACED;
     if (T.I)
       for (int b = 0; b < nb; ++b) T.I[b * T.capacity + id] = A.w.valI[b * VS + p];
@@ -356,48 +371,45 @@ __global__ __launch_bounds__(256) void k_write_tree(MarchArgs A, const unsigned 
   }
 }
 
-// raster of the leaves: each finest pixel descends from its coarse pixel
+// raster of the leaves: each finest pixel descends from its coarse pixel;
+// grid (pixels / 256, views)
 __global__ __launch_bounds__(256) void k_assemble(MarchArgs A, float* images) {
   const int N0 = A.img.N0, Lm = A.img.Lmax, nb = A.f.nb;
-  const int64_t R = (int64_t)N0 << Lm, R2 = R * R, S = A.img.S, VS = (int64_t)A.img.V * S;
-  const int64_t total = (int64_t)A.img.V * R2;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-    const int v = (int)(e / R2);
-    const int64_t r = e - (int64_t)v * R2;
-    const uint32_t i = (uint32_t)(r % R), j = (uint32_t)(r / R);
-    const int64_t vb = (int64_t)v * S;
-    uint32_t key = (j >> Lm) * (uint32_t)N0 + (i >> Lm);
-    int L = 0;
-    int64_t p = vb + key;
-    while (L < Lm && (A.w.state[p] & AIR_NODE_REFINED)) {
-      ++L;
-      const int sh = Lm - L;
-      key = 4u * key + (((i >> sh) & 1u) | (((j >> sh) & 1u) << 1));
-      p = vb + A.img.off[L] + key;
-    }
-    float* img = images + (int64_t)v * (nb + 1) * R2 + r;
-    for (int b = 0; b < nb; ++b) img[b * R2] = A.w.valI[b * VS + p];
-    img[nb * R2] = A.w.valN[p];
+  const uint32_t R = (uint32_t)N0 << Lm;
+  const int64_t R2 = (int64_t)R * R, VS = (int64_t)A.img.V * A.img.S;
+  const int v = blockIdx.y;
+  const int64_t vb = (int64_t)v * A.img.S;
+  const uint32_t e = blockIdx.x * 256u + threadIdx.x;
+  if ((int64_t)e >= R2) return;
+  const uint32_t i = e % R, j = e / R;
+  uint32_t key = (j >> Lm) * (uint32_t)N0 + (i >> Lm);
+  int L = 0;
+  int64_t p = vb + key;
+  while (L < Lm && (A.w.state[p] & AIR_NODE_REFINED)) {
+    ++L;
+    const int sh = Lm - L;
+    key = 4u * key + (((i >> sh) & 1u) | (((j >> sh) & 1u) << 1));
+    p = vb + A.img.off[L] + key;
   }
+  float* img = images + (int64_t)v * (nb + 1) * R2 + e;
+  for (int b = 0; b < nb; ++b) img[b * R2] = A.w.valI[b * VS + p];
+  img[nb * R2] = A.w.valN[p];
 }
 
 // flux partials per chunk and band: sum over leaves of (pixel area) I_b,
 // float64, fixed reduction order
 __global__ __launch_bounds__(256) void k_flux_partial(MarchArgs A, const DevView* views, double* partial) {
   __shared__ double sh[256];
-  const int64_t c = blockIdx.x, S = A.img.S, VS = (int64_t)A.img.V * S;
+  const int64_t c = blockIdx.x, VS = (int64_t)A.img.V * A.img.S;
   const int nb = A.f.nb;
+  const ChunkPos cp = chunk_pos(A.img, c);
+  const double px = views[cp.v].width / (double)((int64_t)A.img.N0 << cp.L), area = px * px;
   for (int b = 0; b < nb; ++b) {
     double s = 0.0;
     for (int k = 0; k < CHUNK / 256; ++k) {
       const int64_t p = c * CHUNK + k * 256 + threadIdx.x;
       const uint8_t st = A.w.state[p];
-      if ((st & AIR_NODE_EXIST) && !(st & AIR_NODE_REFINED)) {
-        const int v = (int)(p / S);
-        const int L = level_of(A.img, p - (int64_t)v * S);
-        const double px = views[v].width / (double)((int64_t)A.img.N0 << L);
-        s += px * px * (double)A.w.valI[b * VS + p];
-      }
+      if ((st & AIR_NODE_EXIST) && !(st & AIR_NODE_REFINED)) s += area * (double)A.w.valI[b * VS + p];
     }
     sh[threadIdx.x] = s;
     __syncthreads();
@@ -495,12 +507,14 @@ hipError_t launch_emit(const MarchArgs& a, const unsigned long long* chunk_offse
 
 hipError_t launch_write_tree(const MarchArgs& a, const unsigned long long* chunk_offsets, const int32_t* id_map,
                              const TreeOut* outs, hipStream_t s) {
-  hipLaunchKernelGGL(k_write_tree, dim3(4096), dim3(256), 0, s, a, chunk_offsets, id_map, outs);
+  const int64_t n_chunks = (int64_t)a.img.V * a.img.S / CHUNK;
+  hipLaunchKernelGGL(k_write_tree, dim3((unsigned)n_chunks), dim3(256), 0, s, a, chunk_offsets, id_map, outs);
   return hipGetLastError();
 }
 
 hipError_t launch_assemble(const MarchArgs& a, float* images, hipStream_t s) {
-  hipLaunchKernelGGL(k_assemble, dim3(8192), dim3(256), 0, s, a, images);
+  const int64_t R = (int64_t)a.img.N0 << a.img.Lmax;
+  hipLaunchKernelGGL(k_assemble, dim3((unsigned)((R * R + 255) / 256), (unsigned)a.img.V), dim3(256), 0, s, a, images);
   return hipGetLastError();
 }
 
