@@ -73,13 +73,21 @@ typedef struct {
   int32_t n[3];     /* uniform: cells per axis.  AMR: base blocks per axis */
   double lo[3];     /* box corner; the box is [lo, hi) with half-open cells */
   double hi[3];
-  int32_t bs;        /* AMR: cells per block edge (power of two, <= 32) */
-  int32_t max_level; /* AMR: deepest block level (ratio-2 refinement) */
+  int32_t bs;        /* AMR: cells per block edge (power of two, 2..32) */
+  int32_t max_level; /* AMR: deepest block level (ratio-2 refinement), 0..20 */
   int32_t n_blocks;  /* AMR: number of blocks; base blocks first, x fastest */
   const int32_t* block_level; /* device [n_blocks] */
   const int32_t* block_coord; /* device [n_blocks][3]: block coordinate at its own level */
   const int32_t* block_child; /* device [n_blocks]: first of 8 children (offset cx+2cy+4cz) or -1 */
 } air_grid;
+/* Every call that takes a block-AMR grid first reads the three tables back
+ * on its stream (a blocking copy of 20 bytes per block) and returns EINVAL
+ * unless they describe one hierarchy: base block b at level 0 with
+ * coordinate (b % n0, b / n0 % n1, b / (n0 n1)); every other block the child
+ * of exactly one earlier block; children stored consecutively after their
+ * parent, one level deeper, at coordinate 2 * parent + offset bits; no
+ * children at max_level; finest cells per axis (n * bs << max_level) and
+ * total cells (n_blocks * bs^3) below 2^30. */
 
 /* Cell data (device, float32). */
 typedef struct {
@@ -161,12 +169,13 @@ int64_t air_field_packed_bytes(const air_grid* grid, const air_field* field);
  * Write the march layout of `field` into `packed` (device, `bytes` >=
  * air_field_packed_bytes): the cells are grouped in 2x2x2 bricks (brick
  * index x fastest over ceil(n/2) bricks per axis; cell inside the brick
- * x&1 | (y&1)<<1 | (z&1)<<2) and each cell's values are adjacent, 16 B
+ * x&1 | (y&1)<<1 | (z&1)<<2; on a block-AMR grid the same inside each
+ * block, blocks in table order) and each cell's values are adjacent, 16 B
  * (rho, j, kappa, 0) for RHO_J_KAPPA or 8 B (rho, T) for RHO_T, so one brick
  * of a one-band field is one 128-byte cache line and a visit is one load.
  * Pass the buffer as field->packed to later calls; it holds a copy, so it
  * must be packed again after the arrays change.  Errors: EINVAL (sizes,
- * NULL pointers), ENOTSUP (block-AMR grids, packed size >= 4 GiB).
+ * NULL pointers, block tables), ENOTSUP (packed size >= 4 GiB).
  */
 air_status air_field_pack(air_ctx* ctx, const air_grid* grid, const air_field* field, void* packed,
                           int64_t bytes, void* stream);

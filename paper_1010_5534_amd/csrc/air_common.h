@@ -35,7 +35,13 @@ struct Geo {
   double h[3];    // uniform cell size; AMR: base block size
   double inv_h[3];
   int seg_shift;  // rays are traced by 2^seg_shift lanes (equal parameter sub-intervals)
-  int bs, max_level, n_blocks;
+  // block AMR: n = base blocks per axis, h = base cell size, bs = 2^bs_shift
+  // cells per block edge, levels 0..max_level; the finest spacing hf and
+  // cells per axis nf; max_blocks bounds the blocks one lane may visit
+  int bs, bs_shift, max_level, n_blocks;
+  int nf[3];
+  double hf[3], inv_hf[3];
+  int max_blocks;
   const int* bchild;
   const int* bcoord;
   const int* blevel;
@@ -87,6 +93,7 @@ struct Work {
   int* visits;      // [V*S]
   float* rmin;      // [V*N0*N0] level-0 density range (feature maps), may be null
   float* rmax;
+  int* lmax0;       // [V*N0*N0] level-0 finest grid level crossed (with rmin)
   uint64_t* queue;  // work queue entries
   uint64_t qcap;
   unsigned long long* ctr;  // [CTR_COUNT]
@@ -146,6 +153,7 @@ struct MarchArgs {
 
 hipError_t launch_init(const MarchArgs& a, hipStream_t s);
 hipError_t launch_pack(const Geo& g, const Fld& f, void* packed, hipStream_t s);
+hipError_t launch_pack_amr(const Geo& g, const Fld& f, void* packed, hipStream_t s);
 // bytes per packed cell
 inline int packed_cell_bytes(int field_kind) { return field_kind == AIR_FIELD_RHO_J_KAPPA ? 16 : 8; }
 

@@ -97,14 +97,67 @@ air_status check_grid(air_ctx* c, const air_grid* g) {
   if (!g) return fail(c, AIR_EINVAL, "grid is NULL");
   if (g->kind != AIR_GRID_UNIFORM && g->kind != AIR_GRID_BLOCK_AMR)
     return fail(c, AIR_EINVAL, "grid kind %d unknown", g->kind);
-  if (g->kind == AIR_GRID_BLOCK_AMR) return fail(c, AIR_ENOTSUP, "block-AMR grids are not supported by this call");
   for (int a = 0; a < 3; ++a) {
     if (g->n[a] < 1 || g->n[a] > (1 << 20)) return fail(c, AIR_EINVAL, "grid n[%d] = %d out of range", a, g->n[a]);
     if (!std::isfinite(g->lo[a]) || !std::isfinite(g->hi[a]) || !(g->hi[a] > g->lo[a]))
       return fail(c, AIR_EINVAL, "grid box on axis %d is empty or not finite", a);
   }
-  if ((int64_t)g->n[0] * g->n[1] * g->n[2] >= ((int64_t)1 << 30))
+  if (g->kind == AIR_GRID_UNIFORM) {
+    if ((int64_t)g->n[0] * g->n[1] * g->n[2] >= ((int64_t)1 << 30))
+      return fail(c, AIR_EINVAL, "grid has 2^30 cells or more (field arrays must stay below 4 GiB)");
+    return AIR_OK;
+  }
+  if (g->bs < 2 || g->bs > 32 || (g->bs & (g->bs - 1)))
+    return fail(c, AIR_EINVAL, "block size %d is not a power of two in 2..32", g->bs);
+  if (g->max_level < 0 || g->max_level > 20) return fail(c, AIR_EINVAL, "max_level %d out of range 0..20", g->max_level);
+  for (int a = 0; a < 3; ++a)
+    if (((int64_t)g->n[a] * g->bs << g->max_level) >= ((int64_t)1 << 30))
+      return fail(c, AIR_EINVAL, "finest cells on axis %d reach 2^30", a);
+  const int64_t base = (int64_t)g->n[0] * g->n[1] * g->n[2];
+  if (g->n_blocks < base) return fail(c, AIR_EINVAL, "n_blocks %d below the %lld base blocks", g->n_blocks, (long long)base);
+  if ((int64_t)g->n_blocks * g->bs * g->bs * g->bs >= ((int64_t)1 << 30))
     return fail(c, AIR_EINVAL, "grid has 2^30 cells or more (field arrays must stay below 4 GiB)");
+  if (!g->block_level || !g->block_coord || !g->block_child) return fail(c, AIR_EINVAL, "block tables are NULL");
+  return AIR_OK;
+}
+
+// The block tables are device data: read them back (on the caller's stream,
+// so pending writes land first) and check that they describe one hierarchy,
+// so the march's descent stays inside the tables.
+air_status check_blocks(air_ctx* c, const air_grid* g, hipStream_t s) {
+  if (g->kind != AIR_GRID_BLOCK_AMR) return AIR_OK;
+  const int nb = g->n_blocks;
+  std::vector<int32_t> lev(nb), crd(3 * (size_t)nb), chd(nb);
+  HIPCHK(c, hipMemcpyAsync(lev.data(), g->block_level, 4 * (size_t)nb, hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipMemcpyAsync(crd.data(), g->block_coord, 12 * (size_t)nb, hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipMemcpyAsync(chd.data(), g->block_child, 4 * (size_t)nb, hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  const int64_t base = (int64_t)g->n[0] * g->n[1] * g->n[2];
+  std::vector<uint8_t> owned(nb, 0);
+  for (int64_t b = 0; b < nb; ++b) {
+    if (b < base) {
+      const int64_t want[3] = {b % g->n[0], (b / g->n[0]) % g->n[1], b / ((int64_t)g->n[0] * g->n[1])};
+      if (lev[b] != 0 || crd[3 * b] != want[0] || crd[3 * b + 1] != want[1] || crd[3 * b + 2] != want[2])
+        return fail(c, AIR_EINVAL, "base block %lld must have level 0 and coordinate (%lld, %lld, %lld)",
+                    (long long)b, (long long)want[0], (long long)want[1], (long long)want[2]);
+    } else if (!owned[b]) {
+      return fail(c, AIR_EINVAL, "block %lld is nobody's child (children follow their parent)", (long long)b);
+    }
+    const int ch = chd[b];
+    if (ch < 0) continue;
+    if (lev[b] >= g->max_level) return fail(c, AIR_EINVAL, "block %lld at level %d has children", (long long)b, lev[b]);
+    if (ch <= b || (int64_t)ch + 8 > nb)
+      return fail(c, AIR_EINVAL, "block %lld: children %d..%d not after it inside the table", (long long)b, ch, ch + 7);
+    for (int k = 0; k < 8; ++k) {
+      const int64_t q = ch + k;
+      if (owned[q]) return fail(c, AIR_EINVAL, "block %lld has two parents", (long long)q);
+      owned[q] = 1;
+      if (lev[q] != lev[b] + 1) return fail(c, AIR_EINVAL, "block %lld: level is not its parent's + 1", (long long)q);
+      for (int a = 0; a < 3; ++a)
+        if (crd[3 * q + a] != 2 * crd[3 * b + a] + ((k >> a) & 1))
+          return fail(c, AIR_EINVAL, "block %lld: coordinate does not follow child offset %d", (long long)q, k);
+    }
+  }
   return AIR_OK;
 }
 
@@ -153,19 +206,54 @@ air_status make_view(air_ctx* c, const air_view* v, DevView& out) {
 void fill_geo(const air_grid* g, Geo& G) {
   std::memset(&G, 0, sizeof G);
   G.kind = g->kind;
+  const bool amr = g->kind == AIR_GRID_BLOCK_AMR;
+  const int cells_per_n = amr ? g->bs : 1;
   for (int a = 0; a < 3; ++a) {
     G.n[a] = g->n[a];
     G.lo[a] = g->lo[a];
     G.hi[a] = g->hi[a];
-    G.h[a] = (g->hi[a] - g->lo[a]) / (double)g->n[a];
-    G.inv_h[a] = (double)g->n[a] / (g->hi[a] - g->lo[a]);
+    G.h[a] = (g->hi[a] - g->lo[a]) / ((double)g->n[a] * cells_per_n);
+    G.inv_h[a] = ((double)g->n[a] * cells_per_n) / (g->hi[a] - g->lo[a]);
   }
-  // lanes per ray: about 32 cells of the longest axis per lane, 1..16 lanes;
-  // fixed by the grid alone so every path traces a ray identically
-  int nmax = std::max(g->n[0], std::max(g->n[1], g->n[2]));
+  // lanes per ray: about 32 cells of the longest axis per lane, up to
+  // MAX_SEG; fixed by the grid alone so every path traces a ray identically.
+  // A block-AMR grid counts its base cells twice when it has refined blocks.
+  int nmax = std::max(g->n[0], std::max(g->n[1], g->n[2])) * cells_per_n;
+  if (amr && g->max_level > 0) nmax *= 2;
   int sh = 0;
   while ((1 << sh) < MAX_SEG && (32 << sh) < nmax) ++sh;
   G.seg_shift = sh;
+  if (!amr) return;
+  G.bs = g->bs;
+  while ((1 << G.bs_shift) < g->bs) ++G.bs_shift;
+  G.max_level = g->max_level;
+  G.n_blocks = g->n_blocks;
+  int64_t blocks_fine = 0;
+  for (int a = 0; a < 3; ++a) {
+    G.nf[a] = (g->n[a] * g->bs) << g->max_level;
+    G.hf[a] = (g->hi[a] - g->lo[a]) / (double)G.nf[a];
+    G.inv_hf[a] = (double)G.nf[a] / (g->hi[a] - g->lo[a]);
+    blocks_fine += (int64_t)g->n[a] << g->max_level;
+  }
+  // a ray meets at most one block per finest block plane crossed, plus the
+  // steps over block corners
+  G.max_blocks = (int)std::min<int64_t>(2 * blocks_fine + 64, 1 << 30);
+  G.bchild = g->block_child;
+  G.bcoord = g->block_coord;
+  G.blevel = g->block_level;
+}
+
+int64_t cells_of(const air_grid* g) {
+  if (g->kind == AIR_GRID_BLOCK_AMR) return (int64_t)g->n_blocks * g->bs * g->bs * g->bs;
+  return (int64_t)g->n[0] * g->n[1] * g->n[2];
+}
+
+// both layouts are whole 2x2x2 bricks: the uniform grid rounds each axis up
+// to even, a block of bs^3 cells (bs even) is bs^3/8 bricks
+int64_t packed_bytes_of(const air_grid* g, const air_field* f) {
+  if (g->kind == AIR_GRID_BLOCK_AMR) return cells_of(g) * packed_cell_bytes(f->kind);
+  const int64_t bricks = (int64_t)((g->n[0] + 1) / 2) * ((g->n[1] + 1) / 2) * ((g->n[2] + 1) / 2);
+  return 8 * bricks * packed_cell_bytes(f->kind);
 }
 
 void fill_fld(const air_field* f, const air_grid* g, Fld& F) {
@@ -177,10 +265,12 @@ void fill_fld(const air_field* f, const air_grid* g, Fld& F) {
   F.kappa = f->kappa;
   F.temp = f->temp;
   F.packed = f->packed;
-  F.bnx = (g->n[0] + 1) / 2;
-  F.bny = (g->n[1] + 1) / 2;
-  F.bnz = (g->n[2] + 1) / 2;
-  F.packed_bytes = (uint32_t)(8ll * F.bnx * F.bny * F.bnz * packed_cell_bytes(f->kind));
+  if (g->kind == AIR_GRID_UNIFORM) {
+    F.bnx = (g->n[0] + 1) / 2;
+    F.bny = (g->n[1] + 1) / 2;
+    F.bnz = (g->n[2] + 1) / 2;
+  }
+  F.packed_bytes = (uint32_t)packed_bytes_of(g, f);
   for (int b = 0; b < F.nb && f->kind == AIR_FIELD_RHO_T; ++b) {
     F.k0[b] = (float)f->band[b][0];
     F.s[b] = (float)f->band[b][1];
@@ -188,9 +278,8 @@ void fill_fld(const air_field* f, const air_grid* g, Fld& F) {
   }
 }
 
-int64_t packed_bytes_of(const air_grid* g, const air_field* f) {
-  const int64_t bricks = (int64_t)((g->n[0] + 1) / 2) * ((g->n[1] + 1) / 2) * ((g->n[2] + 1) / 2);
-  return 8 * bricks * packed_cell_bytes(f->kind);
+hipError_t pack_any(const Geo& g, const Fld& f, void* packed, hipStream_t s) {
+  return g.kind == AIR_GRID_BLOCK_AMR ? launch_pack_amr(g, f, packed, s) : launch_pack(g, f, packed, s);
 }
 
 // point the march at a packed layout: the caller's, or one written now
@@ -201,7 +290,7 @@ air_status ensure_packed(air_ctx* c, const air_grid* g, const air_field* f, Marc
   air_status st = ensure(c, c->pack, (size_t)need);
   if (st) return st;
   A.f.packed = c->pack.p;
-  HIPCHK(c, launch_pack(A.g, A.f, c->pack.p, s));
+  HIPCHK(c, pack_any(A.g, A.f, c->pack.p, s));
   return AIR_OK;
 }
 
@@ -308,6 +397,7 @@ air_status air_render(air_ctx* c, const air_grid* grid, const air_field* field, 
     if (trees[k].capacity < 0) return fail(c, AIR_EINVAL, "tree %d capacity < 0", k);
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, AIR_EDEVICE, "hipSetDevice failed");
   hipStream_t s = (hipStream_t)stream;
+  if ((st = check_blocks(c, grid, s))) return st;
 
   MarchArgs A;
   std::memset(&A, 0, sizeof A);
@@ -474,6 +564,7 @@ air_status air_render_fixed(air_ctx* c, const air_grid* grid, const air_field* f
   if (flux && !images) return fail(c, AIR_EINVAL, "flux needs the image buffer");
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, AIR_EDEVICE, "hipSetDevice failed");
   hipStream_t s = (hipStream_t)stream;
+  if ((st = check_blocks(c, grid, s))) return st;
   MarchArgs A;
   std::memset(&A, 0, sizeof A);
   fill_geo(grid, A.g);
@@ -546,6 +637,7 @@ air_status air_trace_pixels(air_ctx* c, const air_grid* grid, const air_field* f
   if (n == 0) return AIR_OK;
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, AIR_EDEVICE, "hipSetDevice failed");
   hipStream_t s = (hipStream_t)stream;
+  if ((st = check_blocks(c, grid, s))) return st;
   MarchArgs A;
   std::memset(&A, 0, sizeof A);
   fill_geo(grid, A.g);
@@ -578,11 +670,12 @@ air_status air_field_pack(air_ctx* c, const air_grid* grid, const air_field* fie
   if (!packed || bytes < need) return fail(c, AIR_EINVAL, "packed buffer of %lld bytes, %lld needed", (long long)bytes, (long long)need);
   if (need >= ((int64_t)1 << 32)) return fail(c, AIR_ENOTSUP, "packed field of %lld bytes exceeds 4 GiB", (long long)need);
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, AIR_EDEVICE, "hipSetDevice failed");
+  if ((st = check_blocks(c, grid, (hipStream_t)stream))) return st;
   MarchArgs A;
   std::memset(&A, 0, sizeof A);
   fill_geo(grid, A.g);
   fill_fld(field, grid, A.f);
-  HIPCHK(c, launch_pack(A.g, A.f, packed, (hipStream_t)stream));
+  HIPCHK(c, pack_any(A.g, A.f, packed, (hipStream_t)stream));
   return AIR_OK;
 }
 

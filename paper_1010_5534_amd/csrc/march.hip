@@ -150,6 +150,7 @@ struct Seg {
   float I[NB], tau[NB];
   float N;
   float rmin, rmax;
+  int nvis, lmax;  // block AMR: cells walked and finest level met
 };
 
 // entry / exit of the grid box, float64; false if the ray misses
@@ -193,6 +194,90 @@ __device__ __forceinline__ int cells_between(const Geo& g, const double o[3], co
   for (int a = 0; a < 3; ++a) n += abs(cell_at(g, o, d, a, tb, false) - cell_at(g, o, d, a, ta, true));
   return n;
 }
+
+// The cell walk shared by the uniform and block-AMR marches, written as
+// macros over named arrays so that every index is static and the batches
+// stay in registers.  They expect in scope: the walk state idx, cx, cy, cz,
+// t0, t1, t2, k0, k1, k2, tc; the per-axis constants T00..T02, D0..D2,
+// s0..s2, the clamp bounds nx, ny, nz, the end S1 and cell count nvis; the
+// accumulators I, cI, tau, ctau, N, cN, rmin, rmax; the resource R, the
+// field f; and AIR_CELL_INDEX() giving the packed record of (cx, cy, cz).
+// AIR_DDA_BATCH takes one DDA step per cell of a batch of KB (the cell's
+// record offset and segment length; past the last cell ds = 0 and the cell
+// repeats), then issues the batch's loads.
+#define AIR_DDA_BATCH(V0, OFF, DS, RAW)                                   \
+  _Pragma("unroll") for (int q = 0; q < KB; ++q) {                        \
+    OFF[q] = idx;                                                         \
+    float tn;                                                             \
+    int ax = 3;                                                           \
+    if ((V0) + q >= nvis - 1) {                                           \
+      tn = S1;                                                            \
+    } else {                                                              \
+      tn = fminf(fminf(t0, t1), t2);                                      \
+      ax = tn == t0 ? 0 : (tn == t1 ? 1 : 2);                             \
+    }                                                                     \
+    DS[q] = tn - tc;                                                      \
+    tc = tn;                                                              \
+    if (ax == 0) {                                                        \
+      k0 += 1.0f;                                                         \
+      t0 = __builtin_fmaf(k0, D0, T00);                                   \
+      cx = min(max(cx + s0, 0), nx - 1);                                  \
+    } else if (ax == 1) {                                                 \
+      k1 += 1.0f;                                                         \
+      t1 = __builtin_fmaf(k1, D1, T01);                                   \
+      cy = min(max(cy + s1, 0), ny - 1);                                  \
+    } else if (ax == 2) {                                                 \
+      k2 += 1.0f;                                                         \
+      t2 = __builtin_fmaf(k2, D2, T02);                                   \
+      cz = min(max(cz + s2, 0), nz - 1);                                  \
+    }                                                                     \
+    idx = AIR_CELL_INDEX();                                              \
+  }                                                                       \
+  _Pragma("unroll") for (int q = 0; q < KB; ++q) RAW[q] = load_raw<FK>(R, OFF[q]);
+
+#define AIR_INTEGRATE(V0, DS, RAW)                                        \
+  _Pragma("unroll") for (int q = 0; q < KB; ++q) {                        \
+    if ((V0) + q < nvis) {                                                \
+      const float ds = DS[q];                                             \
+      float jb[NB], kb[NB];                                               \
+      optics<NB, FK>(f, RAW[q], jb, kb);                                  \
+      _Pragma("unroll") for (int b = 0; b < NB; ++b) {                    \
+        const float dtau = kb[b] * ds;                                    \
+        const float T = __builtin_amdgcn_exp2f(-(tau[b] - ctau[b]) * LOG2E_F); \
+        kadd(I[b], cI[b], T * (jb[b] * ds) * seg_weight(dtau));           \
+        kadd(tau[b], ctau[b], dtau);                                      \
+      }                                                                   \
+      kadd(N, cN, RAW[q].rho * ds);                                       \
+      if constexpr (RANGE) {                                              \
+        rmin = fminf(rmin, RAW[q].rho);                                   \
+        rmax = fmaxf(rmax, RAW[q].rho);                                   \
+      }                                                                   \
+    }                                                                     \
+  }
+
+// the whole cell walk, two batches in flight: walk and load batch n+1, then
+// integrate batch n
+#define AIR_MARCH_CELLS()                                                 \
+  {                                                                       \
+    int offA[KB], offB[KB];                                               \
+    float dsA[KB], dsB[KB];                                               \
+    Raw<FK> rawA[KB], rawB[KB];                                           \
+    AIR_DDA_BATCH(0, offA, dsA, rawA)                                     \
+    for (int v0 = 0;;) {                                                  \
+      if (v0 + KB < nvis) {                                               \
+        AIR_DDA_BATCH(v0 + KB, offB, dsB, rawB)                           \
+      }                                                                   \
+      AIR_INTEGRATE(v0, dsA, rawA)                                        \
+      v0 += KB;                                                           \
+      if (v0 >= nvis) break;                                              \
+      if (v0 + KB < nvis) {                                               \
+        AIR_DDA_BATCH(v0 + KB, offA, dsA, rawA)                           \
+      }                                                                   \
+      AIR_INTEGRATE(v0, dsB, rawB)                                        \
+      v0 += KB;                                                           \
+      if (v0 >= nvis) break;                                              \
+    }                                                                     \
+  }
 
 // March the sub-interval [ta, tb] of the ray x(t) = o + t d (d unit) through
 // the uniform grid: DDA from the cell just after ta to the cell just before
@@ -240,83 +325,10 @@ __device__ void march_interval(const Geo& g, const Fld& f, const double o[3], co
   float k0 = 0.0f, k1 = 0.0f, k2 = 0.0f;  // crossings done per axis (exact small integers)
   float t0 = T00, t1 = T01, t2 = T02;
   float tc = 0.0f;
-  int idx = brick_index(cx, cy, cz, bnx, bny);
-
-  // One DDA step per cell of a batch of KB (the cell's record offset and
-  // segment length; past the last cell ds = 0 and the cell repeats), then
-  // the batch's loads.  Written as macros over named arrays so that every
-  // index is static and the batches stay in registers.
-#define AIR_DDA_BATCH(V0, OFF, DS, RAW)                                   \
-  _Pragma("unroll") for (int q = 0; q < KB; ++q) {                        \
-    OFF[q] = idx;                                                         \
-    float tn;                                                             \
-    int ax = 3;                                                           \
-    if ((V0) + q >= nvis - 1) {                                           \
-      tn = S1;                                                            \
-    } else {                                                              \
-      tn = fminf(fminf(t0, t1), t2);                                      \
-      ax = tn == t0 ? 0 : (tn == t1 ? 1 : 2);                             \
-    }                                                                     \
-    DS[q] = tn - tc;                                                      \
-    tc = tn;                                                              \
-    if (ax == 0) {                                                        \
-      k0 += 1.0f;                                                         \
-      t0 = __builtin_fmaf(k0, D0, T00);                                   \
-      cx = min(max(cx + s0, 0), nx - 1);                                  \
-    } else if (ax == 1) {                                                 \
-      k1 += 1.0f;                                                         \
-      t1 = __builtin_fmaf(k1, D1, T01);                                   \
-      cy = min(max(cy + s1, 0), ny - 1);                                  \
-    } else if (ax == 2) {                                                 \
-      k2 += 1.0f;                                                         \
-      t2 = __builtin_fmaf(k2, D2, T02);                                   \
-      cz = min(max(cz + s2, 0), nz - 1);                                  \
-    }                                                                     \
-    idx = brick_index(cx, cy, cz, bnx, bny);                              \
-  }                                                                       \
-  _Pragma("unroll") for (int q = 0; q < KB; ++q) RAW[q] = load_raw<FK>(R, OFF[q]);
-
-#define AIR_INTEGRATE(V0, DS, RAW)                                        \
-  _Pragma("unroll") for (int q = 0; q < KB; ++q) {                        \
-    if ((V0) + q < nvis) {                                                \
-      const float ds = DS[q];                                             \
-      float jb[NB], kb[NB];                                               \
-      optics<NB, FK>(f, RAW[q], jb, kb);                                  \
-      _Pragma("unroll") for (int b = 0; b < NB; ++b) {                    \
-        const float dtau = kb[b] * ds;                                    \
-        const float T = __builtin_amdgcn_exp2f(-(tau[b] - ctau[b]) * LOG2E_F); \
-        kadd(I[b], cI[b], T * (jb[b] * ds) * seg_weight(dtau));           \
-        kadd(tau[b], ctau[b], dtau);                                      \
-      }                                                                   \
-      kadd(N, cN, RAW[q].rho * ds);                                       \
-      if constexpr (RANGE) {                                              \
-        rmin = fminf(rmin, RAW[q].rho);                                   \
-        rmax = fmaxf(rmax, RAW[q].rho);                                   \
-      }                                                                   \
-    }                                                                     \
-  }
-
-  // two batches in flight: walk and load batch n+1, then integrate batch n
-  int offA[KB], offB[KB];
-  float dsA[KB], dsB[KB];
-  Raw<FK> rawA[KB], rawB[KB];
-  AIR_DDA_BATCH(0, offA, dsA, rawA)
-  for (int v0 = 0;;) {
-    if (v0 + KB < nvis) {
-      AIR_DDA_BATCH(v0 + KB, offB, dsB, rawB)
-    }
-    AIR_INTEGRATE(v0, dsA, rawA)
-    v0 += KB;
-    if (v0 >= nvis) break;
-    if (v0 + KB < nvis) {
-      AIR_DDA_BATCH(v0 + KB, offA, dsA, rawA)
-    }
-    AIR_INTEGRATE(v0, dsB, rawB)
-    v0 += KB;
-    if (v0 >= nvis) break;
-  }
-#undef AIR_DDA_BATCH
-#undef AIR_INTEGRATE
+#define AIR_CELL_INDEX() brick_index(cx, cy, cz, bnx, bny)
+  int idx = AIR_CELL_INDEX();
+  AIR_MARCH_CELLS()
+#undef AIR_CELL_INDEX
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
     r.I[b] = I[b] - cI[b];
@@ -325,6 +337,120 @@ __device__ void march_interval(const Geo& g, const Fld& f, const double o[3], co
   r.N = N - cN;
   r.rmin = rmin;
   r.rmax = rmax;
+}
+
+
+// finest-level cell of axis a just after (after = true) or just before t
+__device__ __forceinline__ int fine_at(const Geo& g, const double o[3], const double d[3], int a, double t,
+                                       bool after) {
+  const double u = (o[a] + t * d[a] - g.lo[a]) * g.inv_hf[a];
+  int k;
+  if (d[a] > 0.0)
+    k = after ? (int)floor(u) : (int)ceil(u) - 1;
+  else if (d[a] < 0.0)
+    k = after ? (int)ceil(u) - 1 : (int)floor(u);
+  else
+    k = (int)floor(u);
+  return min(max(k, 0), g.nf[a] - 1);
+}
+
+// March [ta, tb] through a block-AMR grid: locate the leaf block just after
+// the current parameter (integer fine coordinates, descent through the child
+// table), walk its cells at its level's spacing up to the block exit, and
+// continue from there.  Crossing parameters restart at every block entry.
+// At most g.max_blocks blocks are visited, so every lane terminates; a block
+// entered exactly at its exit (a rounding corner) is stepped over by one ulp.
+template <int NB, int FK, bool RANGE>
+__device__ void march_amr_interval(const Geo& g, const Fld& f, const double o[3], const double d[3],
+                                   const double inv_d[3], double ta, double tb, Seg<NB>& r) {
+  const i32x4 R = field_rsrc(f);
+  const int bs = g.bs, lbs = g.bs_shift, mL = g.max_level, hb = bs >> 1;
+  const int nx = bs, ny = bs, nz = bs;
+  float I[NB], cI[NB], tau[NB], ctau[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) I[b] = cI[b] = tau[b] = ctau[b] = 0.0f;
+  float N = 0.0f, cN = 0.0f;
+  float rmin = __builtin_huge_valf(), rmax = -__builtin_huge_valf();
+  int nvis_total = 0, lmax = -1;
+  double t = ta;
+  for (int it = 0; it < g.max_blocks && t < tb; ++it) {
+    int F[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) F[a] = fine_at(g, o, d, a, t, true);
+    int b = (((F[2] >> mL) >> lbs) * g.n[1] + ((F[1] >> mL) >> lbs)) * g.n[0] + ((F[0] >> mL) >> lbs);
+    int l = 0;
+    for (int ch = g.bchild[b]; ch >= 0 && l < mL; ch = g.bchild[b]) {
+      ++l;
+      int off = 0;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) off |= (((F[a] >> (mL - l)) >> lbs) - 2 * g.bcoord[3 * b + a]) << a;
+      b = min(ch + off, g.n_blocks - 1);  // the host checked the tables; this only bounds the reads
+    }
+    int bc[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) bc[a] = g.bcoord[3 * b + a];
+    const double scale = 1.0 / (double)(1 << l);
+    double t_exit = __builtin_huge_val();
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const double hl = g.h[a] * scale;
+      if (d[a] > 0.0)
+        t_exit = fmin(t_exit, (g.lo[a] + (double)((bc[a] + 1) * bs) * hl - o[a]) * inv_d[a]);
+      else if (d[a] < 0.0)
+        t_exit = fmin(t_exit, (g.lo[a] + (double)(bc[a] * bs) * hl - o[a]) * inv_d[a]);
+    }
+    const double t_end = fmin(t_exit, tb);
+    if (!(t_end > t)) {  // entered at its exit: step over the corner
+      t = nextafter(t, __builtin_huge_val());
+      continue;
+    }
+    // cells of the block between t and t_end, and the DDA constants
+    int c[3], st[3], nvis = 1;
+    float T0[3], D[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const int k0 = min(max((F[a] >> (mL - l)) - bs * bc[a], 0), bs - 1);
+      const int k1 = min(max((fine_at(g, o, d, a, t_end, false) >> (mL - l)) - bs * bc[a], 0), bs - 1);
+      c[a] = k0;
+      nvis += abs(k1 - k0);
+      const double hl = g.h[a] * scale;
+      if (d[a] != 0.0) {
+        const int m = bs * bc[a] + k0 + (d[a] > 0.0 ? 1 : 0);
+        T0[a] = (float)((g.lo[a] + (double)m * hl - o[a]) * inv_d[a] - t);
+        D[a] = (float)(hl * fabs(inv_d[a]));
+        st[a] = d[a] > 0.0 ? 1 : -1;
+      } else {
+        T0[a] = __builtin_huge_valf();
+        D[a] = 0.0f;
+        st[a] = 0;
+      }
+    }
+    const float S1 = (float)(t_end - t);
+    int cx = c[0], cy = c[1], cz = c[2];
+    const int s0 = st[0], s1 = st[1], s2 = st[2];
+    const float T00 = T0[0], T01 = T0[1], T02 = T0[2], D0 = D[0], D1 = D[1], D2 = D[2];
+    float k0 = 0.0f, k1 = 0.0f, k2 = 0.0f;
+    float t0 = T00, t1 = T01, t2 = T02;
+    float tc = 0.0f;
+    const int bbase = b * (bs * bs * bs);
+#define AIR_CELL_INDEX() (bbase + brick_index(cx, cy, cz, hb, hb))
+    int idx = AIR_CELL_INDEX();
+    AIR_MARCH_CELLS()
+#undef AIR_CELL_INDEX
+    nvis_total += nvis;
+    lmax = max(lmax, l);
+    t = t_end;
+  }
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    r.I[b] = I[b] - cI[b];
+    r.tau[b] = tau[b] - ctau[b];
+  }
+  r.N = N - cN;
+  r.rmin = rmin;
+  r.rmax = rmax;
+  r.nvis = nvis_total;
+  r.lmax = lmax;
 }
 
 __device__ __forceinline__ void pixel_ray(const DevView& V, int N0, int L, uint32_t i, uint32_t j,
@@ -341,6 +467,7 @@ struct RayRes {
   float I[NB];
   float N;
   int nvis;
+  int lmax;  // finest grid level crossed, -1 for a miss
   bool hit;
   float rmin, rmax;
 };
@@ -350,6 +477,7 @@ struct RayRes {
 template <int NB>
 struct TileLds {
   float v[MAX_SEG][2 * NB + 3][WAVE];
+  int cnt[MAX_SEG][2][WAVE];  // cells walked, finest level (block AMR)
   int nvis[WAVE];
   int hit[WAVE];
 };
@@ -364,7 +492,7 @@ struct TileLds {
 // the ray and S (fixed per grid), so a ray's result does not depend on which
 // block or kernel traced it.  Every thread of the block calls this; the
 // result is valid in wave 0.
-template <int NB, int FK, bool RANGE>
+template <int NB, int FK, int GK, bool RANGE>
 __device__ __forceinline__ void trace_tile(const MarchArgs& A, TileLds<NB>& T, bool live, uint32_t v, int L,
                                            uint32_t i, uint32_t j, int sh, RayRes<NB>& r) {
   const int S = 1 << sh, lane = threadIdx.x & (WAVE - 1), k = threadIdx.x / WAVE;
@@ -374,6 +502,8 @@ __device__ __forceinline__ void trace_tile(const MarchArgs& A, TileLds<NB>& T, b
   sg.N = 0.0f;
   sg.rmin = __builtin_huge_valf();
   sg.rmax = -__builtin_huge_valf();
+  sg.nvis = 0;
+  sg.lmax = -1;
   bool hit = false;
   int nvis = 0;
   if (live) {
@@ -382,11 +512,14 @@ __device__ __forceinline__ void trace_tile(const MarchArgs& A, TileLds<NB>& T, b
     pixel_ray(V, A.img.N0, L, i, j, o);
     hit = slab(A.g, o, V.d, V.inv_d, t0, t1);
     if (hit) {
-      if (k == 0) nvis = cells_between(A.g, o, V.d, t0, t1);  // before the march: frees t0, t1
+      if (GK == AIR_GRID_UNIFORM && k == 0) nvis = cells_between(A.g, o, V.d, t0, t1);  // frees t0, t1 early
       const double len = t1 - t0, inv_s = 1.0 / (double)S;  // S a power of two: k/S exact
       const double ta = k == 0 ? t0 : t0 + len * ((double)k * inv_s);
       const double tb = k == S - 1 ? t1 : t0 + len * ((double)(k + 1) * inv_s);
-      march_interval<NB, FK, RANGE>(A.g, A.f, o, V.d, V.inv_d, ta, tb, sg);
+      if constexpr (GK == AIR_GRID_UNIFORM)
+        march_interval<NB, FK, RANGE>(A.g, A.f, o, V.d, V.inv_d, ta, tb, sg);
+      else
+        march_amr_interval<NB, FK, RANGE>(A.g, A.f, o, V.d, V.inv_d, ta, tb, sg);
     }
   }
   __syncthreads();  // the previous tile's fold has read the staging area
@@ -399,6 +532,10 @@ __device__ __forceinline__ void trace_tile(const MarchArgs& A, TileLds<NB>& T, b
   if constexpr (RANGE) {
     T.v[k][2 * NB + 1][lane] = sg.rmin;
     T.v[k][2 * NB + 2][lane] = sg.rmax;
+  }
+  if constexpr (GK == AIR_GRID_BLOCK_AMR) {
+    T.cnt[k][0][lane] = sg.nvis;
+    T.cnt[k][1][lane] = sg.lmax;
   }
   if (k == 0) {
     T.nvis[lane] = nvis;
@@ -414,6 +551,7 @@ __device__ __forceinline__ void trace_tile(const MarchArgs& A, TileLds<NB>& T, b
   }
   float accN = T.v[0][2 * NB][lane];
   float mn = sg.rmin, mx = sg.rmax;
+  int cells = sg.nvis, lm = sg.lmax;
   for (int q = 1; q < S; ++q) {
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
@@ -425,12 +563,23 @@ __device__ __forceinline__ void trace_tile(const MarchArgs& A, TileLds<NB>& T, b
       mn = fminf(mn, T.v[q][2 * NB + 1][lane]);
       mx = fmaxf(mx, T.v[q][2 * NB + 2][lane]);
     }
+    if constexpr (GK == AIR_GRID_BLOCK_AMR) {
+      cells += T.cnt[q][0][lane];
+      lm = max(lm, T.cnt[q][1][lane]);
+    }
   }
 #pragma unroll
   for (int b = 0; b < NB; ++b) r.I[b] = accI[b];
   r.N = accN;
-  r.nvis = T.nvis[lane];
   r.hit = T.hit[lane] != 0;
+  if constexpr (GK == AIR_GRID_BLOCK_AMR) {
+    // a cell cut by a sub-interval boundary counts once per part
+    r.nvis = cells;
+    r.lmax = r.hit ? lm : -1;
+  } else {
+    r.nvis = T.nvis[lane];
+    r.lmax = r.hit ? 0 : -1;
+  }
   if constexpr (RANGE) {
     r.rmin = r.hit ? mn : 0.0f;
     r.rmax = r.hit ? mx : 0.0f;
@@ -501,6 +650,23 @@ __global__ __launch_bounds__(256) void k_pack(Geo g, Fld f) {
   }
 }
 
+// block-AMR packed layout: inside each block of bs^3 cells, 2x2x2 bricks
+template <int FK>
+__global__ __launch_bounds__(256) void k_pack_amr(Geo g, Fld f) {
+  const int bs = g.bs, hb = bs >> 1;
+  const int64_t cells = (int64_t)g.n_blocks * bs * bs * bs;
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < cells; q += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = q / ((int64_t)bs * bs * bs);
+    const int loc = (int)(q - b * bs * bs * bs);
+    const int x = loc % bs, y = (loc / bs) % bs, z = loc / (bs * bs);
+    const int64_t dst = b * bs * bs * bs + brick_index(x, y, z, hb, hb);
+    if constexpr (FK == AIR_FIELD_RHO_J_KAPPA)
+      reinterpret_cast<float4*>(const_cast<void*>(f.packed))[dst] = make_float4(f.rho[q], f.emis[q], f.kappa[q], 0.0f);
+    else
+      reinterpret_cast<float2*>(const_cast<void*>(f.packed))[dst] = make_float2(f.rho[q], f.temp[q]);
+  }
+}
+
 // zero the state maps (grid.y = view) with the base image marked existing and
 // tested, seed the queue with the base pixels, clear the counters
 __global__ void k_init(MarchArgs A) {
@@ -526,7 +692,7 @@ __global__ void k_init(MarchArgs A) {
 
 // Queue march of level L: tiles of 64 consecutive entries, one tile per
 // block at a time (S waves per block).
-template <int NB, int FK>
+template <int NB, int FK, int GK>
 __global__ __launch_bounds__(64 * MAX_SEG) void k_march_queue(MarchArgs A, int L) {
   __shared__ TileLds<NB> T;
   unsigned long long* ctr = A.w.ctr;
@@ -552,9 +718,9 @@ __global__ __launch_bounds__(64 * MAX_SEG) void k_march_queue(MarchArgs A, int L
     }
     RayRes<NB> r;
     if (range)
-      trace_tile<NB, FK, true>(A, T, live, v, (int)lev, i, j, sh, r);
+      trace_tile<NB, FK, GK, true>(A, T, live, v, (int)lev, i, j, sh, r);
     else
-      trace_tile<NB, FK, false>(A, T, live, v, (int)lev, i, j, sh, r);
+      trace_tile<NB, FK, GK, false>(A, T, live, v, (int)lev, i, j, sh, r);
     if (threadIdx.x < WAVE && live) {
       const int64_t pos = (int64_t)v * SV + A.img.off[lev] + key;
 #pragma unroll
@@ -564,8 +730,10 @@ __global__ __launch_bounds__(64 * MAX_SEG) void k_march_queue(MarchArgs A, int L
       A.w.visits[pos] = r.nvis;
       A.w.state[pos] = A.w.state[pos] | ST_TRACED;
       if (range) {
-        A.w.rmin[(int64_t)v * A.img.N0 * A.img.N0 + key] = r.rmin;
-        A.w.rmax[(int64_t)v * A.img.N0 * A.img.N0 + key] = r.rmax;
+        const int64_t q0 = (int64_t)v * A.img.N0 * A.img.N0 + key;
+        A.w.rmin[q0] = r.rmin;
+        A.w.rmax[q0] = r.rmax;
+        A.w.lmax0[q0] = r.lmax;
       }
       hit += r.hit;
       vis += (unsigned long long)r.nvis;
@@ -575,7 +743,7 @@ __global__ __launch_bounds__(64 * MAX_SEG) void k_march_queue(MarchArgs A, int L
 }
 
 // fixed raster: entry e = view * R^2 + key, key in forest-Morton order
-template <int NB, int FK>
+template <int NB, int FK, int GK>
 __global__ __launch_bounds__(64 * MAX_SEG) void k_march_fixed(MarchArgs A, int L, float* images) {
   __shared__ TileLds<NB> T;
   const int64_t R = (int64_t)A.img.N0 << L, R2 = R * R;
@@ -596,7 +764,7 @@ __global__ __launch_bounds__(64 * MAX_SEG) void k_march_fixed(MarchArgs A, int L
       coords_of(key, L, A.img.N0, i, j);
     }
     RayRes<NB> r;
-    trace_tile<NB, FK, false>(A, T, live, v, L, i, j, sh, r);
+    trace_tile<NB, FK, GK, false>(A, T, live, v, L, i, j, sh, r);
     if (threadIdx.x < WAVE && live) {
       if (images) {
         float* img = images + (int64_t)v * (A.f.nb + 1) * R2 + (int64_t)j * R + i;
@@ -612,7 +780,7 @@ __global__ __launch_bounds__(64 * MAX_SEG) void k_march_fixed(MarchArgs A, int L
   block_stats(A.w.ctr, hit, vis);
 }
 
-template <int NB, int FK>
+template <int NB, int FK, int GK>
 __global__ __launch_bounds__(64 * MAX_SEG) void k_trace_pixels(MarchArgs A, int64_t n, const int32_t* level,
                                                                const int32_t* ix, const int32_t* iy, float* I,
                                                                float* N, int32_t* visits) {
@@ -622,8 +790,8 @@ __global__ __launch_bounds__(64 * MAX_SEG) void k_trace_pixels(MarchArgs A, int6
     const int64_t k = b0 + lane;
     const bool live = k < n;
     RayRes<NB> r;
-    trace_tile<NB, FK, false>(A, T, live, 0, live ? level[k] : 0, live ? (uint32_t)ix[k] : 0u,
-                              live ? (uint32_t)iy[k] : 0u, sh, r);
+    trace_tile<NB, FK, GK, false>(A, T, live, 0, live ? level[k] : 0, live ? (uint32_t)ix[k] : 0u,
+                                  live ? (uint32_t)iy[k] : 0u, sh, r);
     if (threadIdx.x < WAVE && live) {
 #pragma unroll
       for (int b = 0; b < NB; ++b)
@@ -637,25 +805,42 @@ __global__ __launch_bounds__(64 * MAX_SEG) void k_trace_pixels(MarchArgs A, int6
 }  // namespace
 
 // ----------------------------------------------------------- dispatch
-#define AIR_DISPATCH(NBV, FKV, CALL)                                             \
+#define AIR_DISPATCH_NB(NBV, FKV, GKV, ...)                                      \
   do {                                                                           \
     if (FKV == AIR_FIELD_RHO_J_KAPPA) {                                          \
-      constexpr int NB_ = 1, FK_ = AIR_FIELD_RHO_J_KAPPA;                        \
-      CALL;                                                                      \
+      constexpr int NB_ = 1, FK_ = AIR_FIELD_RHO_J_KAPPA, GK_ = GKV;             \
+      __VA_ARGS__;                                                               \
     } else if (NBV == 1) {                                                       \
-      constexpr int NB_ = 1, FK_ = AIR_FIELD_RHO_T;                              \
-      CALL;                                                                      \
+      constexpr int NB_ = 1, FK_ = AIR_FIELD_RHO_T, GK_ = GKV;                   \
+      __VA_ARGS__;                                                               \
     } else if (NBV == 2) {                                                       \
-      constexpr int NB_ = 2, FK_ = AIR_FIELD_RHO_T;                              \
-      CALL;                                                                      \
+      constexpr int NB_ = 2, FK_ = AIR_FIELD_RHO_T, GK_ = GKV;                   \
+      __VA_ARGS__;                                                               \
     } else if (NBV <= 4) {                                                       \
-      constexpr int NB_ = 4, FK_ = AIR_FIELD_RHO_T;                              \
-      CALL;                                                                      \
+      constexpr int NB_ = 4, FK_ = AIR_FIELD_RHO_T, GK_ = GKV;                   \
+      __VA_ARGS__;                                                               \
     } else {                                                                     \
-      constexpr int NB_ = 8, FK_ = AIR_FIELD_RHO_T;                              \
-      CALL;                                                                      \
+      constexpr int NB_ = 8, FK_ = AIR_FIELD_RHO_T, GK_ = GKV;                   \
+      __VA_ARGS__;                                                               \
     }                                                                            \
   } while (0)
+#define AIR_DISPATCH(A_, ...)                                                    \
+  do {                                                                           \
+    if ((A_).g.kind == AIR_GRID_BLOCK_AMR)                                       \
+      AIR_DISPATCH_NB((A_).f.nb, (A_).f.kind, AIR_GRID_BLOCK_AMR, __VA_ARGS__);   \
+    else                                                                         \
+      AIR_DISPATCH_NB((A_).f.nb, (A_).f.kind, AIR_GRID_UNIFORM, __VA_ARGS__);     \
+  } while (0)
+
+hipError_t launch_pack_amr(const Geo& g, const Fld& f, void* packed, hipStream_t s) {
+  Fld F = f;
+  F.packed = packed;
+  if (f.kind == AIR_FIELD_RHO_J_KAPPA)
+    hipLaunchKernelGGL(k_pack_amr<AIR_FIELD_RHO_J_KAPPA>, dim3(4096), dim3(256), 0, s, g, F);
+  else
+    hipLaunchKernelGGL(k_pack_amr<AIR_FIELD_RHO_T>, dim3(4096), dim3(256), 0, s, g, F);
+  return hipGetLastError();
+}
 
 hipError_t launch_pack(const Geo& g, const Fld& f, void* packed, hipStream_t s) {
   Fld F = f;
@@ -675,14 +860,13 @@ hipError_t launch_init(const MarchArgs& a, hipStream_t s) {
 
 hipError_t launch_march_queue(const MarchArgs& a, int L, int grid_blocks, hipStream_t s) {
   const dim3 blk(WAVE << a.g.seg_shift);
-  AIR_DISPATCH(a.f.nb, a.f.kind, hipLaunchKernelGGL((k_march_queue<NB_, FK_>), dim3(grid_blocks), blk, 0, s, a, L));
+  AIR_DISPATCH(a, hipLaunchKernelGGL((k_march_queue<NB_, FK_, GK_>), dim3(grid_blocks), blk, 0, s, a, L));
   return hipGetLastError();
 }
 
 hipError_t launch_march_fixed(const MarchArgs& a, int level, float* images, int grid_blocks, hipStream_t s) {
   const dim3 blk(WAVE << a.g.seg_shift);
-  AIR_DISPATCH(a.f.nb, a.f.kind,
-               hipLaunchKernelGGL((k_march_fixed<NB_, FK_>), dim3(grid_blocks), blk, 0, s, a, level, images));
+  AIR_DISPATCH(a, hipLaunchKernelGGL((k_march_fixed<NB_, FK_, GK_>), dim3(grid_blocks), blk, 0, s, a, level, images));
   return hipGetLastError();
 }
 
@@ -691,9 +875,8 @@ hipError_t launch_trace_pixels(const MarchArgs& a, int64_t n, const int32_t* lev
   int blocks = (int)std::min<int64_t>((n + WAVE - 1) / WAVE, 4096);
   if (blocks < 1) blocks = 1;
   const dim3 blk(WAVE << a.g.seg_shift);
-  AIR_DISPATCH(a.f.nb, a.f.kind,
-               hipLaunchKernelGGL((k_trace_pixels<NB_, FK_>), dim3(blocks), blk, 0, s, a, n, level, ix, iy, I, N,
-                                  visits));
+  AIR_DISPATCH(a, hipLaunchKernelGGL((k_trace_pixels<NB_, FK_, GK_>), dim3(blocks), blk, 0, s, a, n, level, ix, iy, I,
+                                      N, visits));
   return hipGetLastError();
 }
 

@@ -1,0 +1,174 @@
+"""GPU parity on block-AMR grids (section 3 uses a block-structured AMR
+simulation): the HIP block march, through the C ABI, against the FP64
+oracle's point-location march on the same seeded hierarchies."""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle
+import parity
+from paper_1010_5534_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1010_5534_amd import air
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = air.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def amr_small():
+    """Two-wind field on 8^3 base blocks of 8^3 cells, two refined levels."""
+    from paper_1010_5534_amd import air
+    g, f = inputs.amr_winds(seed=0, base_cells=64, bs=8, max_level=2, frac=(0.15, 0.04),
+                            kind=inputs.FIELD_RHO_J_KAPPA)
+    return g, f, air.upload(g, f)
+
+
+def test_amr_hierarchy_is_refined(amr_small):
+    g, f, _ = amr_small
+    levels = np.bincount(g.block_level, minlength=3)
+    assert levels[1] > 0 and levels[2] > 0
+
+
+@pytest.mark.parametrize("direction", [(0, 0, 1), (1, 0, 0), (1, 1, 1), (0.3, -0.8, 0.52), (-1, -0.2, 0.1)])
+def test_amr_fixed_matches_oracle(ctx, amr_small, direction):
+    g, f, scene = amr_small
+    v = inputs.view_for(direction)
+    say(f"fixed amr_winds 64/8 L2 dir={direction} N0=16 L=3")
+    img, flux, st = ctx.render_fixed(scene, [v], 16, 3)
+    ref = oracle.render_fixed(g, f, v, 16, 3)
+    gi = img[0].cpu().numpy().astype(np.float64)
+    assert parity.rel_err(gi[0], ref["I"][0]).max() <= 1e-5
+    assert parity.rel_err(gi[1], ref["N"]).max() <= 1e-5
+    assert np.array_equal(gi[0] == 0, ref["I"][0] == 0)
+
+
+@pytest.mark.parametrize("xc", [0.3, 0.6])
+def test_amr_tree_parity(ctx, amr_small, xc):
+    from paper_1010_5534_amd import air
+    g, f, scene = amr_small
+    v = inputs.view_for((1, 1, 1))
+    say(f"air amr_winds 64/8 L2 N0=16 Lmax=4 xi_crit={xc}")
+    trees, img, flux, st = ctx.render(scene, [v], air.params(16, 4, xc))
+    t = oracle.air(g, f, v, 16, 4, xc)
+    rep = parity.compare(parity.gpu_dense(trees[0], 16, 4, 1), t, xc)
+    say({k: (x if not isinstance(x, list) else len(x)) for k, x in rep.items()})
+    parity.assert_parity(rep)
+    if rep["flips"] == 0:
+        assert trees[0].n_nodes == t.nodes
+        assert flux[0][0] == pytest.approx(oracle.leaf_flux(t, v.width, t.flat_I[0]), rel=1e-5)
+
+
+def test_amr_multiband_views_batch(ctx):
+    """Several (rho, T) bands and views in one call, each view bitwise equal
+    to its own call."""
+    from paper_1010_5534_amd import air
+    g, f = inputs.amr_winds(seed=2, base_cells=32, bs=4, max_level=2, frac=(0.2, 0.05),
+                            bands=inputs.default_bands(4))
+    scene = ctx.prepare(air.upload(g, f))
+    views = inputs.isotropic_views(3, seed=5)
+    prm = air.params(8, 3, 0.5, band_weight=[1.0, 0.5, 0.25, 0.125])
+    trees, img, flux, _ = ctx.render(scene, views, prm)
+    for k, v in enumerate(views):
+        say(f"air amr_winds 32/4 4 bands view {k}")
+        t = oracle.air(g, f, v, 8, 3, 0.5, band_w=[1.0, 0.5, 0.25, 0.125])
+        rep = parity.compare(parity.gpu_dense(trees[k], 8, 3, 4), t, 0.5, band_w=[1.0, 0.5, 0.25, 0.125])
+        parity.assert_parity(rep)
+        t1, i1, f1, _ = ctx.render(scene, [v], prm)
+        assert torch.equal(t1[0].I, trees[k].I) and torch.equal(i1[0], img[k])
+
+
+def test_uniform_as_amr_matches_uniform(ctx):
+    """A one-level hierarchy holding a uniform grid's data renders like the
+    uniform grid (the two marches split a ray differently, so to the value
+    tolerance, not bitwise)."""
+    from paper_1010_5534_amd import air
+    g, f = inputs.winds2(seed=1, n=64)
+    ga, fa = inputs.uniform_as_amr(g, f, bs=8)
+    v = inputs.view_for((0.3, -0.8, 0.52))
+    iu, _, _ = ctx.render_fixed(air.upload(g, f), [v], 16, 3)
+    ia, _, _ = ctx.render_fixed(air.upload(ga, fa), [v], 16, 3)
+    a, b = ia[0].cpu().numpy(), iu[0].cpu().numpy()
+    assert parity.rel_err(a[0], b[0]).max() <= 2e-5
+    assert parity.rel_err(a[1], b[1]).max() <= 2e-5
+
+
+def test_amr_trace_pixels_matches_oracle(ctx, amr_small):
+    g, f, scene = amr_small
+    v = inputs.view_for((0.2, 0.9, -0.4))
+    rng = np.random.default_rng(7)
+    L = rng.integers(0, 6, 2000)
+    R = 16 << L
+    i = (rng.uniform(size=2000) * R).astype(np.int64)
+    j = (rng.uniform(size=2000) * R).astype(np.int64)
+    I, N, vis = ctx.trace_pixels(scene, v, 16, L, i, j)
+    ref = oracle.trace_pixels(g, f, v, 16, L, i, j)
+    assert parity.rel_err(I[0].cpu().numpy(), ref["I"][0]).max() <= 1e-5
+    assert parity.rel_err(N.cpu().numpy(), ref["N"]).max() <= 1e-5
+
+
+def _amr_brick_order(a, bs):
+    """numpy reference of the block-AMR packed layout: within each block of
+    bs^3 cells, 2x2x2 bricks, x fastest."""
+    nb = a.shape[0] // bs ** 3
+    h = bs // 2
+    x = a.reshape(nb, h, 2, h, 2, h, 2, *a.shape[1:])       # b, z, cz, y, cy, x, cx
+    x = x.transpose(0, 1, 3, 5, 2, 4, 6, *range(7, x.ndim))  # b, bz, by, bx, cz, cy, cx
+    return x.reshape(nb * bs ** 3, *a.shape[1:])
+
+
+def test_amr_packed_layout_contents(ctx):
+    from paper_1010_5534_amd import air
+    g = inputs.amr_from_predicate(1, 4, 1, lambda l, blo, sz: l == 0)
+    n = g.n_cells
+    f = inputs.Field(1, np.arange(n, dtype=np.float32), temp=1000 + np.arange(n, dtype=np.float32),
+                     bands=inputs.default_bands(1))
+    sc = ctx.prepare(air.upload(g, f))
+    got = sc.tensors[-1].cpu().numpy().view(np.float32).reshape(-1, 2)
+    assert np.array_equal(got, _amr_brick_order(np.stack([f.rho, f.temp], axis=-1), 4))
+
+
+def _bad_tables():
+    base = inputs.amr_from_predicate(2, 4, 1, lambda l, blo, sz: l == 0 and blo == (0.0, 0.0, 0.0))
+    out = []
+    g = inputs.Grid(**{**base.__dict__, "block_coord": base.block_coord.copy()})
+    g.block_coord[9] = (5, 0, 0)  # child coordinate off its parent
+    out.append(("child coordinate", g))
+    g = inputs.Grid(**{**base.__dict__, "block_child": base.block_child.copy()})
+    g.block_child[0] = base.n_blocks - 4  # children run past the table
+    out.append(("children past the end", g))
+    g = inputs.Grid(**{**base.__dict__, "block_level": base.block_level.copy()})
+    g.block_level[3] = 1  # base block not at level 0
+    out.append(("base level", g))
+    g = inputs.Grid(**{**base.__dict__, "max_level": 0})  # children below the deepest level
+    out.append(("max level", g))
+    g = inputs.Grid(**{**base.__dict__, "bs": 6})  # not a power of two
+    out.append(("block size", g))
+    return out
+
+
+@pytest.mark.parametrize("case", range(5))
+def test_amr_table_errors(ctx, case):
+    from paper_1010_5534_amd import air
+    name, g = _bad_tables()[case]
+    f = inputs.Field(0, np.ones(g.n_blocks * 64, np.float32), np.ones(g.n_blocks * 64, np.float32),
+                     np.ones(g.n_blocks * 64, np.float32))
+    say(f"bad block table: {name}")
+    with pytest.raises(air.AirError) as e:
+        ctx.render_fixed(air.upload(g, f), [inputs.view_for((0, 0, 1))], 8, 1)
+    assert e.value.code == air.AIR_EINVAL

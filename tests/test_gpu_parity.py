@@ -261,13 +261,6 @@ def test_argument_errors(ctx, gauss):
     prm.flags = 1
     with pytest.raises(air.AirError):
         ctx.render(scene, [v], prm, want_tree=False, want_image=False, want_flux=False)
-    # a block-AMR grid through the uniform path is refused before any launch
-    ga = inputs.amr_from_predicate(2, 4, 1, lambda *a: False)
-    fa = inputs.Field(0, np.ones(ga.n_cells, np.float32), np.ones(ga.n_cells, np.float32),
-                      np.ones(ga.n_cells, np.float32))
-    with pytest.raises(air.AirError) as e:
-        ctx.render(air.upload(ga, fa), [v], air.params(8, 2), want_tree=False, want_image=False, want_flux=False)
-    assert e.value.code == air.AIR_ENOTSUP
 
 
 def test_capacity_error_reports_needed_size(ctx, gauss):
