@@ -161,8 +161,8 @@ typedef struct {
 
 typedef struct air_ctx air_ctx;
 
-/* Bytes of the march layout of a field on a uniform grid, or a negative
- * air_status for invalid arguments. */
+/* Bytes of the march layout of a field, or a negative air_status for
+ * invalid arguments. */
 int64_t air_field_packed_bytes(const air_grid* grid, const air_field* field);
 
 /*
@@ -233,6 +233,104 @@ air_status air_trace_pixels(air_ctx* ctx, const air_grid* grid, const air_field*
                             const air_view* view, int32_t coarse_n, int64_t n, const int32_t* level,
                             const int32_t* ix, const int32_t* iy, float* I, float* N, int32_t* visits,
                             void* stream);
+
+/* ------------------------------------------------------------------------
+ * Learned depth proposal.  A small network (four 3x3 convolutions,
+ * 4 -> 32 -> 32 -> 32 -> 6 channels, zero padding, ReLU after the first
+ * three) reads four maps of the coarse trace and predicts, per coarse pixel,
+ * the deepest level of its final tree (classes 0..5).  air_render_learned
+ * traces every node down to a depth chosen from that prediction in one
+ * speculative march, then runs the level loop of air_render, which traces
+ * only the nodes the speculation did not cover.  Its outputs are bit for bit
+ * those of air_render; only the time differs.
+ * ---------------------------------------------------------------------- */
+#define AIR_CNN_FEATURES 4
+#define AIR_CNN_CLASSES 6
+#define AIR_CNN_PARAMS 21414 /* for each layer: weights [cout][3][3][cin], then bias [cout] */
+
+typedef struct air_cnn air_cnn;
+
+/* A network on the context's device, parameters zero, feature mean 0 and
+ * scale 1.  Destroy it before its context. */
+air_status air_cnn_create(air_ctx* ctx, air_cnn** out);
+void air_cnn_destroy(air_cnn* net);
+/* Host parameters [AIR_CNN_PARAMS] (float32 master copy) and the feature
+ * standardisation (x - mean) / scale applied to the raw maps (scale > 0).
+ * Resets the optimiser state. */
+air_status air_cnn_set(air_ctx* ctx, air_cnn* net, const float* params, const float* feat_mean,
+                       const float* feat_scale);
+/* Copy the parameters and the standardisation back to the host (any may be
+ * NULL); synchronises the context's device. */
+air_status air_cnn_get(air_ctx* ctx, const air_cnn* net, float* params, float* feat_mean, float* feat_scale);
+
+/*
+ * Raw input maps of the coarse trace, device [n_views][coarse_n][coarse_n][4]
+ * in raster order (row j = pixel index along e_v): log10(I_w + 1e-30) with
+ * I_w = sum_b band_weight[b] I_b (host [n_bands]), log10(N + 1e-30), the
+ * finest grid level the ray crosses (-1 for a miss), and
+ * log10(rho_max / rho_min) over the cells it crosses (0 for a miss or a zero
+ * density).
+ */
+air_status air_features(air_ctx* ctx, const air_grid* grid, const air_field* field, const air_view* views,
+                        int32_t n_views, int32_t coarse_n, const float* band_weight, float* features,
+                        void* stream);
+
+/*
+ * Forward pass on n_maps raw maps (device [n_maps][h][w][4], standardised
+ * with the network's mean and scale, then rounded to bfloat16) into logits
+ * (device [n_maps][h][w][8] float32, classes 0..5 in the first six).
+ * Weights and activations are bfloat16, accumulation float32.
+ */
+air_status air_cnn_forward(air_ctx* ctx, air_cnn* net, const float* features, int32_t n_maps, int32_t h,
+                           int32_t w, float* logits, void* stream);
+
+/*
+ * Loss and gradient of one batch: class-weighted softmax cross-entropy,
+ * sum_p cw[t_p] (-log softmax(z_p)[t_p]) / sum_p cw[t_p], with labels device
+ * [n_maps][h][w] (values outside 0..5 are clamped) and class_weight host
+ * [6].  loss: host, may be NULL (then the call does not wait).  The
+ * gradient is kept in the network for air_cnn_adam and copied to grad
+ * (device [AIR_CNN_PARAMS] float32) when grad is not NULL.
+ */
+air_status air_cnn_loss_grad(air_ctx* ctx, air_cnn* net, const float* features, const int32_t* labels,
+                             int32_t n_maps, int32_t h, int32_t w, const float* class_weight, double* loss,
+                             float* grad, void* stream);
+
+/* One Adam step (bias-corrected) with the network's last gradient. */
+air_status air_cnn_adam(air_ctx* ctx, air_cnn* net, float lr, float beta1, float beta2, float eps, void* stream);
+
+/* Training labels: the deepest level of a finished tree (from air_render)
+ * inside each coarse pixel, device int32 [coarse_n][coarse_n] raster order. */
+air_status air_tree_depth(air_ctx* ctx, const air_tree* tree, int32_t coarse_n, int32_t* depth, void* stream);
+
+/* Cost model of the depth choice: per coarse pixel, the depth d in
+ * 0..min(max_depth, params.max_level) minimising
+ * c_ray * (4 + 16 + ... + 4^d) + c_sweep * P(deeper than d). */
+typedef struct {
+  float c_ray;
+  float c_sweep;
+  int32_t max_depth;
+  uint32_t flags; /* reserved, must be 0 */
+} air_learn_params;
+
+typedef struct {
+  int64_t spec_rays;                    /* rays traced by the speculative march */
+  int64_t wasted;                       /* speculative rays that are no tree node */
+  int64_t missing;                      /* tree nodes below level 0 the level loop traced */
+  int64_t depth_hist[AIR_MAX_LEVELS];   /* coarse pixels per chosen depth */
+  double ms_features; /* device time: feature maps + network + depth choice + work list */
+  double ms_spec;     /* device time of the speculative march */
+} air_learn_stats;
+
+/*
+ * air_render with the learned proposal (arguments as air_render, plus the
+ * network, its cost model and optional counters).  Trees, images and fluxes
+ * equal air_render's bit for bit.
+ */
+air_status air_render_learned(air_ctx* ctx, const air_grid* grid, const air_field* field, const air_view* views,
+                              int32_t n_views, const air_params* params, const air_cnn* net,
+                              const air_learn_params* learn, air_tree* trees, float* images, double* flux,
+                              air_stats* stats, air_learn_stats* learn_stats, void* stream);
 
 #ifdef __cplusplus
 }

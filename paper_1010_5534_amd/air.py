@@ -20,7 +20,10 @@ FIELD_RHO_J_KAPPA, FIELD_RHO_T = 0, 1
 NODE_EXIST, NODE_TESTED, NODE_FLAGGED, NODE_BALANCE, NODE_REFINED, NODE_EVALUATED = 1, 2, 4, 8, 16, 32
 
 EXPORTS = ("air_create", "air_destroy", "air_last_error", "air_render", "air_render_fixed", "air_trace_pixels",
-           "air_field_packed_bytes", "air_field_pack")
+           "air_field_packed_bytes", "air_field_pack", "air_cnn_create", "air_cnn_destroy", "air_cnn_set",
+           "air_cnn_get", "air_features", "air_cnn_forward", "air_cnn_loss_grad", "air_cnn_adam", "air_tree_depth",
+           "air_render_learned")
+CNN_FEATURES, CNN_CLASSES, CNN_PARAMS = 4, 6, 21414
 
 
 class AirError(RuntimeError):
@@ -64,6 +67,15 @@ class air_stats(C.Structure):
                 ("ms_total", C.c_double), ("ms_march", C.c_double), ("ms_test", C.c_double)]
 
 
+class air_learn_params(C.Structure):
+    _fields_ = [("c_ray", C.c_float), ("c_sweep", C.c_float), ("max_depth", C.c_int32), ("flags", C.c_uint32)]
+
+
+class air_learn_stats(C.Structure):
+    _fields_ = [("spec_rays", C.c_int64), ("wasted", C.c_int64), ("missing", C.c_int64),
+                ("depth_hist", C.c_int64 * MAX_LEVELS), ("ms_features", C.c_double), ("ms_spec", C.c_double)]
+
+
 _lib = None
 
 
@@ -91,6 +103,21 @@ def lib():
         L.air_field_packed_bytes.restype = C.c_int64
         L.air_field_pack.argtypes = [vp, vp, vp, vp, C.c_int64, vp]
         L.air_field_pack.restype = C.c_int32
+        i32 = C.c_int32
+        L.air_cnn_create.argtypes = [vp, C.POINTER(vp)]
+        L.air_cnn_destroy.argtypes = [vp]
+        L.air_cnn_destroy.restype = None
+        L.air_cnn_set.argtypes = [vp, vp, vp, vp, vp]
+        L.air_cnn_get.argtypes = [vp, vp, vp, vp, vp]
+        L.air_features.argtypes = [vp, vp, vp, vp, i32, i32, vp, vp, vp]
+        L.air_cnn_forward.argtypes = [vp, vp, vp, i32, i32, i32, vp, vp]
+        L.air_cnn_loss_grad.argtypes = [vp, vp, vp, vp, i32, i32, i32, vp, vp, vp, vp]
+        L.air_cnn_adam.argtypes = [vp, vp, C.c_float, C.c_float, C.c_float, C.c_float, vp]
+        L.air_tree_depth.argtypes = [vp, vp, i32, vp, vp]
+        L.air_render_learned.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        for name in ("air_cnn_create", "air_cnn_set", "air_cnn_get", "air_features", "air_cnn_forward",
+                     "air_cnn_loss_grad", "air_cnn_adam", "air_tree_depth", "air_render_learned"):
+            getattr(L, name).restype = C.c_int32
         _lib = L
     return _lib
 
@@ -267,6 +294,21 @@ class Context:
         """Plain AIR over the views.  Returns (trees, images, flux, stats).
         reuse=True hands back the same output tensors on every call with the
         same shapes (the next call overwrites them)."""
+        return self._render(scene, views, prm, want_tree, want_image, want_flux, capacity, reuse, None, None)
+
+    def render_learned(self, scene: DeviceScene, views: Sequence, prm: air_params, net: "Network",
+                       c_ray: float, c_sweep: float, max_depth: int = 5, want_tree=True, want_image=True,
+                       want_flux=True, capacity: Optional[int] = None, reuse: bool = False):
+        """AIR with the learned depth proposal (air_render_learned).  Returns
+        (trees, images, flux, stats, learn_stats); outputs equal render()'s."""
+        lp = air_learn_params()
+        lp.c_ray, lp.c_sweep, lp.max_depth, lp.flags = c_ray, c_sweep, max_depth, 0
+        ls = air_learn_stats()
+        out = self._render(scene, views, prm, want_tree, want_image, want_flux, capacity, reuse, (net, lp), ls)
+        return out + (dict(spec_rays=ls.spec_rays, wasted=ls.wasted, missing=ls.missing,
+                           depth_hist=list(ls.depth_hist)[:6], ms_features=ls.ms_features, ms_spec=ls.ms_spec),)
+
+    def _render(self, scene, views, prm, want_tree, want_image, want_flux, capacity, reuse, learned, ls):
         torch = _torch()
         V, nb = len(views), scene.n_bands
         R = prm.coarse_n << prm.max_level
@@ -298,10 +340,15 @@ class Context:
                     s, t = pairs[k]
                     trees[k] = s
                     keep.append(t)
-            rc = lib().air_render(self._p, C.addressof(scene.grid), C.addressof(scene.field), C.addressof(vs), V,
-                                  C.addressof(prm), C.addressof(trees) if want_tree else None,
-                                  images.data_ptr() if want_image else None,
-                                  flux.ctypes.data if want_flux else None, C.addressof(st), self._stream())
+            targs = (C.addressof(trees) if want_tree else None, images.data_ptr() if want_image else None,
+                     flux.ctypes.data if want_flux else None, C.addressof(st))
+            if learned is None:
+                rc = lib().air_render(self._p, C.addressof(scene.grid), C.addressof(scene.field), C.addressof(vs),
+                                      V, C.addressof(prm), *targs, self._stream())
+            else:
+                rc = lib().air_render_learned(self._p, C.addressof(scene.grid), C.addressof(scene.field),
+                                              C.addressof(vs), V, C.addressof(prm), learned[0]._p,
+                                              C.addressof(learned[1]), *targs, C.addressof(ls), self._stream())
             if rc == AIR_ECAPACITY and want_tree:
                 cap = max(trees[k].n_nodes for k in range(V))
                 continue
@@ -348,3 +395,88 @@ class Context:
                                     N.data_ptr(), vis.data_ptr(), self._stream())
         self._check(rc)
         return I, N, vis
+
+    # ---------------------------------------------------- learned proposal
+    def features(self, scene: DeviceScene, views: Sequence, coarse_n: int, band_weight=None):
+        """Raw coarse feature maps [V, N0, N0, 4] (air_features)."""
+        torch = _torch()
+        V = len(views)
+        w = np.ones(scene.n_bands, np.float32) if band_weight is None else np.asarray(band_weight, np.float32)
+        out = torch.empty((V, coarse_n, coarse_n, CNN_FEATURES), dtype=torch.float32, device=f"cuda:{self.device}")
+        vs = _views(views)
+        self._check(lib().air_features(self._p, C.addressof(scene.grid), C.addressof(scene.field), C.addressof(vs),
+                                       V, coarse_n, w.ctypes.data, out.data_ptr(), self._stream()))
+        return out
+
+    def tree_depth(self, tree: Tree, coarse_n: int):
+        """Depth label per coarse pixel [N0, N0] int32 (air_tree_depth)."""
+        torch = _torch()
+        t = air_tree()
+        t.capacity = tree.n_nodes
+        t.n_nodes = tree.n_nodes
+        t.level, t.ix, t.iy = tree.level.data_ptr(), tree.ix.data_ptr(), tree.iy.data_ptr()
+        out = torch.empty((coarse_n, coarse_n), dtype=torch.int32, device=f"cuda:{self.device}")
+        self._check(lib().air_tree_depth(self._p, C.addressof(t), coarse_n, out.data_ptr(), self._stream()))
+        return out
+
+
+class Network:
+    """The depth-proposal network (air_cnn) of a context."""
+
+    def __init__(self, ctx: Context, params=None, mean=None, scale=None):
+        self.ctx = ctx
+        self._p = C.c_void_p()
+        ctx._check(lib().air_cnn_create(ctx._p, C.byref(self._p)))
+        if params is not None:
+            self.set(params, mean, scale)
+
+    def close(self):
+        if self._p:
+            lib().air_cnn_destroy(self._p)
+            self._p = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set(self, params, mean=None, scale=None):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        assert p.shape == (CNN_PARAMS,)
+        m = np.zeros(CNN_FEATURES, np.float32) if mean is None else np.ascontiguousarray(mean, np.float32)
+        s = np.ones(CNN_FEATURES, np.float32) if scale is None else np.ascontiguousarray(scale, np.float32)
+        self.ctx._check(lib().air_cnn_set(self.ctx._p, self._p, p.ctypes.data, m.ctypes.data, s.ctypes.data))
+
+    def get(self):
+        p = np.zeros(CNN_PARAMS, np.float32)
+        m = np.zeros(CNN_FEATURES, np.float32)
+        s = np.zeros(CNN_FEATURES, np.float32)
+        self.ctx._check(lib().air_cnn_get(self.ctx._p, self._p, p.ctypes.data, m.ctypes.data, s.ctypes.data))
+        return p, m, s
+
+    def forward(self, feat):
+        """feat: float32 device [n, h, w, 4] -> logits [n, h, w, 8]."""
+        torch = _torch()
+        feat = feat.contiguous()
+        n, h, w, _ = feat.shape
+        z = torch.empty((n, h, w, 8), dtype=torch.float32, device=feat.device)
+        self.ctx._check(lib().air_cnn_forward(self.ctx._p, self._p, feat.data_ptr(), n, h, w, z.data_ptr(),
+                                              self.ctx._stream()))
+        return z
+
+    def loss_grad(self, feat, labels, class_weight, want_loss=True, want_grad=False):
+        torch = _torch()
+        feat = feat.contiguous()
+        labels = labels.to(torch.int32).contiguous()
+        n, h, w, _ = feat.shape
+        cw = np.ascontiguousarray(class_weight, np.float32)
+        loss = C.c_double(0.0)
+        g = torch.empty(CNN_PARAMS, dtype=torch.float32, device=feat.device) if want_grad else None
+        self.ctx._check(lib().air_cnn_loss_grad(self.ctx._p, self._p, feat.data_ptr(), labels.data_ptr(), n, h, w,
+                                                cw.ctypes.data, C.byref(loss) if want_loss else None,
+                                                g.data_ptr() if want_grad else None, self.ctx._stream()))
+        return (loss.value if want_loss else None), g
+
+    def adam(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        self.ctx._check(lib().air_cnn_adam(self.ctx._p, self._p, lr, beta1, beta2, eps, self.ctx._stream()))

@@ -19,6 +19,13 @@ constexpr int MAX_SEG = AIR_MAX_SEG;  // at most this many waves (sub-intervals)
 // node state bits beyond the public ones: set by the march once the node's
 // values are written (the refinement test reads only traced values)
 constexpr uint8_t ST_TRACED = 64u;
+// set by the speculative march of the learned proposal: the node's values
+// are already in the maps (it may never become a tree node)
+constexpr uint8_t ST_SPEC = 128u;
+
+// learned proposal: depth classes 0..5 and the float32 logit row stride
+constexpr int DEPTH_CLASSES = 6;
+constexpr int LOGIT_STRIDE = 8;
 
 // view, precomputed on the host in double precision
 struct DevView {
@@ -82,7 +89,10 @@ enum : int {
 };
 constexpr int CTR_SLOTS = 64;
 // per (view, level) record of the tree counters, filled by the reduce pass
-enum : int { VS_NODES = 0, VS_LEAVES, VS_TESTED, VS_FLAGGED, VS_BALANCE, VS_N };
+// per (view, level) counts; SPEC = speculatively traced positions, WASTED =
+// those that are no tree node, MISSING = tree nodes below level 0 traced by
+// the level loop instead
+enum : int { VS_NODES = 0, VS_LEAVES, VS_TESTED, VS_FLAGGED, VS_BALANCE, VS_SPEC, VS_WASTED, VS_MISSING, VS_N };
 
 struct Work {
   uint8_t* state;   // [V*S]
@@ -96,6 +106,7 @@ struct Work {
   int* lmax0;       // [V*N0*N0] level-0 finest grid level crossed (with rmin)
   uint64_t* queue;  // work queue entries
   uint64_t qcap;
+  int skip_spec;    // learned mode: the level march skips nodes with ST_SPEC
   unsigned long long* ctr;  // [CTR_COUNT]
 };
 
@@ -162,6 +173,19 @@ __host__ __device__ inline int brick_index(int x, int y, int z, int bnx, int bny
   return ((((z >> 1) * bny + (y >> 1)) * bnx + (x >> 1)) << 3) | (x & 1) | ((y & 1) << 1) | ((z & 1) << 2);
 }
 hipError_t launch_march_queue(const MarchArgs& a, int L, int grid_blocks, hipStream_t s);
+// speculative march of the learned proposal: the n = *count entries of spec
+hipError_t launch_march_spec(const MarchArgs& a, const uint64_t* spec, const unsigned long long* count,
+                             int grid_blocks, hipStream_t s);
+struct LearnW {
+  float w[MAXB];
+};
+hipError_t launch_features(const MarchArgs& a, const LearnW& w, float* feat, hipStream_t s);
+hipError_t launch_decide(const float* logits, int64_t total, int dmax, float c_ray, float c_sweep, uint8_t* depth,
+                         unsigned long long* counts, hipStream_t s);
+hipError_t launch_spec_emit(const uint8_t* depth, const unsigned long long* offsets, int64_t total, int64_t n0sq,
+                            uint64_t* spec, hipStream_t s);
+hipError_t launch_tree_depth(const int8_t* level, const int32_t* ix, const int32_t* iy, int64_t n, int N0,
+                             int* depth, hipStream_t s);
 hipError_t launch_refine(const MarchArgs& a, int L, float xcI, float xcN, const float* w, int grid_blocks,
                          hipStream_t s);
 hipError_t launch_march_fixed(const MarchArgs& a, int level, float* images, int grid_blocks, hipStream_t s);

@@ -14,12 +14,18 @@
 #include <vector>
 
 #include "air_common.h"
+#include "cnn.h"
 
 using namespace air;
 
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+};
+
+struct air_cnn {
+  int device = 0;
+  air::cnn::Net net;
 };
 
 struct air_ctx {
@@ -29,6 +35,9 @@ struct air_ctx {
   std::string err;
   DevBuf state, valI, valN, xiI, xiN, visits, rmin, rmax, queue, ctr, chunk, cstat, vstat, idmap, partial, flux,
       views, touts, pack;
+  // learned proposal: coarse maps, network activations and gradients, depth
+  // choice and speculative work list
+  DevBuf lmax0, feat, cx0, ca1, ca2, ca3, cz, cdz, cda, cdb, cwpart, closs_part, closs, depth8, scount, spec;
   unsigned long long* host_ctr = nullptr;  // pinned
   double* host_flux = nullptr;             // pinned
   unsigned long long* host_vstat = nullptr;
@@ -38,7 +47,8 @@ struct air_ctx {
   size_t stage_n = 0;
   // timing events: [0] start, [1] end, then a pair around every march and
   // every test launch
-  static constexpr int NEV = 2 + 4 * AIR_MAX_LEVELS;
+  static constexpr int EV_FEAT0 = 2 + 4 * AIR_MAX_LEVELS, EV_SPEC0 = EV_FEAT0 + 1, EV_SPEC1 = EV_FEAT0 + 2;
+  static constexpr int NEV = EV_FEAT0 + 3;
   hipEvent_t ev[NEV] = {};
 };
 
@@ -317,6 +327,281 @@ int march_blocks(const air_ctx* c, int seg_shift) {
   return std::max(8, (c->num_cus * per_cu + 7) / 8 * 8);
 }
 
+
+// network workspace for P pixels (the training buffers too when asked)
+air_status ensure_cnn_work(air_ctx* c, int64_t P, bool training) {
+  air_status st;
+  if ((st = ensure(c, c->cx0, 2 * cnn::XC * P))) return st;
+  if ((st = ensure(c, c->ca1, 2 * cnn::HID * P))) return st;
+  if ((st = ensure(c, c->ca2, 2 * cnn::HID * P))) return st;
+  if ((st = ensure(c, c->ca3, 2 * cnn::HID * P))) return st;
+  if ((st = ensure(c, c->cz, 4 * cnn::ZC * P))) return st;
+  if (!training) return AIR_OK;
+  if ((st = ensure(c, c->cdz, 2 * cnn::ZC * P))) return st;
+  if ((st = ensure(c, c->cda, 2 * cnn::HID * P))) return st;
+  if ((st = ensure(c, c->cdb, 2 * cnn::HID * P))) return st;
+  if ((st = ensure(c, c->cwpart, 4 * cnn::wgrad_partial_floats()))) return st;
+  if ((st = ensure(c, c->closs_part, 8 * cnn::loss_partial_doubles()))) return st;
+  return ensure(c, c->closs, 16);
+}
+
+// device buffers and march arguments of one render of V views to Lm levels
+air_status setup_render(air_ctx* c, const air_grid* grid, const air_field* field, const air_view* views, int V,
+                        int N0, int Lm, bool range, hipStream_t s, MarchArgs& A, int64_t& n_chunks) {
+  std::memset(&A, 0, sizeof A);
+  fill_geo(grid, A.g);
+  if (c->seg_shift_override >= 0) A.g.seg_shift = c->seg_shift_override;
+  fill_fld(field, grid, A.f);
+  const int nb = A.f.nb;
+  A.img.N0 = N0;
+  A.img.Lmax = Lm;
+  A.img.V = V;
+  // every level starts on a counting chunk, so a chunk belongs to one
+  // (view, level)
+  int64_t off = 0;
+  for (int L = 0; L <= Lm; ++L) {
+    A.img.off[L] = off;
+    off = round_up(off + ((int64_t)N0 * N0 << (2 * L)), CHUNK);
+  }
+  for (int L = Lm + 1; L <= MAXL; ++L) A.img.off[L] = off;
+  const int64_t S = off;
+  A.img.S = S;
+  const int64_t VS = (int64_t)V * S;
+  n_chunks = VS / CHUNK;
+  air_status st;
+  if ((st = ensure(c, c->state, VS))) return st;
+  if ((st = ensure(c, c->valI, 4 * VS * nb))) return st;
+  if ((st = ensure(c, c->valN, 4 * VS))) return st;
+  if ((st = ensure(c, c->xiI, 4 * VS))) return st;
+  if ((st = ensure(c, c->xiN, 4 * VS))) return st;
+  if ((st = ensure(c, c->visits, 4 * VS))) return st;
+  if ((st = ensure(c, c->queue, 8 * VS))) return st;
+  if ((st = ensure(c, c->ctr, 8 * CTR_COUNT))) return st;
+  if ((st = ensure(c, c->chunk, 8 * (n_chunks + 1)))) return st;
+  if ((st = ensure(c, c->cstat, 4 * VS_N * n_chunks))) return st;
+  if ((st = ensure(c, c->vstat, 8 * (size_t)V * MAXL * VS_N))) return st;
+  if ((st = ensure(c, c->partial, 8 * n_chunks * nb))) return st;
+  if ((st = ensure(c, c->flux, 8 * V * nb))) return st;
+  A.w.state = (uint8_t*)c->state.p;
+  A.w.valI = (float*)c->valI.p;
+  A.w.valN = (float*)c->valN.p;
+  A.w.xiI = (float*)c->xiI.p;
+  A.w.xiN = (float*)c->xiN.p;
+  A.w.visits = (int*)c->visits.p;
+  A.w.queue = (uint64_t*)c->queue.p;
+  A.w.qcap = (uint64_t)VS;
+  A.w.ctr = (unsigned long long*)c->ctr.p;
+  if (range) {
+    const int64_t n0 = (int64_t)V * N0 * N0;
+    if ((st = ensure(c, c->rmin, 4 * n0))) return st;
+    if ((st = ensure(c, c->rmax, 4 * n0))) return st;
+    if ((st = ensure(c, c->lmax0, 4 * n0))) return st;
+    A.w.rmin = (float*)c->rmin.p;
+    A.w.rmax = (float*)c->rmax.p;
+    A.w.lmax0 = (int*)c->lmax0.p;
+  }
+  if ((st = upload_views(c, views, V, s, &A.views))) return st;
+  return ensure_packed(c, grid, field, A, s);
+}
+
+air_status check_render_args(air_ctx* c, const air_grid* grid, const air_field* field, const air_view* views,
+                             int n_views, const air_params* prm) {
+  air_status st;
+  if ((st = check_grid(c, grid))) return st;
+  if ((st = check_field(c, field))) return st;
+  if (!views || n_views < 1 || n_views > AIR_MAX_VIEWS)
+    return fail(c, AIR_EINVAL, "n_views %d out of range 1..%d", n_views, AIR_MAX_VIEWS);
+  if (!prm) return fail(c, AIR_EINVAL, "params is NULL");
+  const int N0 = prm->coarse_n, Lm = prm->max_level;
+  if (N0 < 1 || N0 > 65536) return fail(c, AIR_EINVAL, "coarse_n %d out of range", N0);
+  if (Lm < 0 || Lm >= AIR_MAX_LEVELS) return fail(c, AIR_EINVAL, "max_level %d out of range 0..%d", Lm, AIR_MAX_LEVELS - 1);
+  if ((double)N0 * N0 * std::pow(4.0, Lm) > 4294967295.0)
+    return fail(c, AIR_EINVAL, "coarse_n^2 * 4^max_level exceeds 2^32 pixels per view");
+  if (!std::isfinite(prm->xi_crit_I) || !std::isfinite(prm->xi_crit_N) || prm->xi_crit_I < 0 || prm->xi_crit_N < 0)
+    return fail(c, AIR_EINVAL, "xi_crit must be finite and >= 0");
+  if (prm->flags != 0) return fail(c, AIR_EINVAL, "params.flags must be 0");
+  return AIR_OK;
+}
+
+// the learned steps after the coarse march: feature maps, network, depth
+// choice, work list, speculative march
+air_status learned_steps(air_ctx* c, const MarchArgs& A, const air_cnn* net, const air_learn_params* lp,
+                         const float* w, hipStream_t s) {
+  const int V = A.img.V, N0 = A.img.N0;
+  const int64_t total = (int64_t)V * N0 * N0, VS = (int64_t)V * A.img.S;
+  air_status st;
+  if ((st = ensure(c, c->feat, 16 * total))) return st;
+  if ((st = ensure_cnn_work(c, total, false))) return st;
+  if ((st = ensure(c, c->depth8, total))) return st;
+  if ((st = ensure(c, c->scount, 8 * (total + 1)))) return st;
+  if ((st = ensure(c, c->spec, 8 * VS))) return st;
+  LearnW W;
+  for (int b = 0; b < MAXB; ++b) W.w[b] = w[b];
+  HIPCHK(c, hipEventRecord(c->ev[air_ctx::EV_FEAT0], s));
+  HIPCHK(c, launch_features(A, W, (float*)c->feat.p, s));
+  HIPCHK(c, cnn::input_maps((const float*)c->feat.p, total, net->net.mean, net->net.stdv, (uint16_t*)c->cx0.p, s));
+  HIPCHK(c, cnn::conv_forward(0, net->net, (const uint16_t*)c->cx0.p, V, N0, N0, c->ca1.p, s));
+  HIPCHK(c, cnn::conv_forward(1, net->net, (const uint16_t*)c->ca1.p, V, N0, N0, c->ca2.p, s));
+  HIPCHK(c, cnn::conv_forward(2, net->net, (const uint16_t*)c->ca2.p, V, N0, N0, c->ca3.p, s));
+  HIPCHK(c, cnn::conv_forward(3, net->net, (const uint16_t*)c->ca3.p, V, N0, N0, c->cz.p, s));
+  const int dmax = std::min(lp->max_depth, std::min(A.img.Lmax, DEPTH_CLASSES - 1));
+  unsigned long long* cnt = (unsigned long long*)c->scount.p;
+  HIPCHK(c, launch_decide((const float*)c->cz.p, total, dmax, lp->c_ray, lp->c_sweep, (uint8_t*)c->depth8.p, cnt, s));
+  HIPCHK(c, launch_scan(cnt, total, s));
+  HIPCHK(c, launch_spec_emit((const uint8_t*)c->depth8.p, cnt, total, (int64_t)N0 * N0, (uint64_t*)c->spec.p, s));
+  HIPCHK(c, hipEventRecord(c->ev[air_ctx::EV_SPEC0], s));
+  HIPCHK(c, launch_march_spec(A, (const uint64_t*)c->spec.p, cnt + total, march_blocks(c, A.g.seg_shift), s));
+  HIPCHK(c, hipEventRecord(c->ev[air_ctx::EV_SPEC1], s));
+  return AIR_OK;
+}
+
+air_status render_core(air_ctx* c, const air_grid* grid, const air_field* field, const air_view* views,
+                       int32_t n_views, const air_params* prm, const air_cnn* net, const air_learn_params* lp,
+                       air_tree* trees, float* images, double* flux, air_stats* stats, air_learn_stats* ls,
+                       void* stream) {
+  if (!c) return AIR_EINVAL;
+  c->err.clear();
+  air_status st;
+  if ((st = check_render_args(c, grid, field, views, n_views, prm))) return st;
+  for (int k = 0; trees && k < n_views; ++k)
+    if (trees[k].capacity < 0) return fail(c, AIR_EINVAL, "tree %d capacity < 0", k);
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, AIR_EDEVICE, "hipSetDevice failed");
+  hipStream_t s = (hipStream_t)stream;
+  if ((st = check_blocks(c, grid, s))) return st;
+  const bool learned = net != nullptr;
+  const int N0 = prm->coarse_n, Lm = prm->max_level, V = n_views;
+  MarchArgs A;
+  int64_t n_chunks = 0;
+  if ((st = setup_render(c, grid, field, views, V, N0, Lm, learned, s, A, n_chunks))) return st;
+  const int nb = A.f.nb;
+  A.w.skip_spec = learned ? 1 : 0;
+  float w[MAXB];
+  for (int b = 0; b < MAXB; ++b) w[b] = b < nb ? prm->band_weight[b] : 0.0f;
+
+  // the level loop: trace the queue of new nodes, then test, close and
+  // compact; the queue bounds live in device counters, so no host round trip
+  hipEvent_t* ev = c->ev;
+  HIPCHK(c, hipEventRecord(ev[0], s));
+  HIPCHK(c, launch_init(A, s));
+  for (int L = 0; L <= Lm; ++L) {
+    HIPCHK(c, hipEventRecord(ev[2 + 4 * L], s));
+    HIPCHK(c, launch_march_queue(A, L, march_blocks(c, A.g.seg_shift), s));
+    HIPCHK(c, hipEventRecord(ev[3 + 4 * L], s));
+    if (learned && L == 0) {
+      if ((st = learned_steps(c, A, net, lp, w, s))) return st;
+      HIPCHK(c, hipEventRecord(ev[3 + 4 * L], s));  // the test timing starts after the learned steps
+    }
+    if (L < Lm) HIPCHK(c, launch_refine(A, L, prm->xi_crit_I, prm->xi_crit_N, w, c->num_cus * 4, s));
+    HIPCHK(c, hipEventRecord(ev[4 + 4 * L], s));
+  }
+  unsigned long long* chunk = (unsigned long long*)c->chunk.p;
+  unsigned long long* vstat = (unsigned long long*)c->vstat.p;
+  HIPCHK(c, launch_count(A, chunk, (unsigned*)c->cstat.p, n_chunks, vstat, s));
+  if (trees) {
+    if ((st = ensure(c, c->idmap, 4 * (size_t)V * A.img.S))) return st;
+    if ((st = ensure(c, c->touts, sizeof(TreeOut) * V))) return st;
+    HIPCHK(c, launch_scan(chunk, n_chunks, s));
+    HIPCHK(c, launch_emit(A, chunk, n_chunks, (int32_t*)c->idmap.p, s));
+    std::vector<TreeOut> to(V);
+    for (int k = 0; k < V; ++k) {
+      const air_tree& t = trees[k];
+      to[k] = TreeOut{t.level, t.ix, t.iy, t.parent, t.first_child, t.state, t.I, t.N, t.xi_I, t.xi_N,
+                      t.visits, t.capacity};
+    }
+    // the views' staging copy above must land before the buffer is reused
+    HIPCHK(c, hipStreamSynchronize(s));
+    if ((st = ensure_host(c, &c->stage, &c->stage_n, sizeof(TreeOut) * V))) return st;
+    std::memcpy(c->stage, to.data(), sizeof(TreeOut) * V);
+    HIPCHK(c, hipMemcpyAsync(c->touts.p, c->stage, sizeof(TreeOut) * V, hipMemcpyHostToDevice, s));
+    HIPCHK(c, launch_write_tree(A, chunk, (const int32_t*)c->idmap.p, (const TreeOut*)c->touts.p, s));
+  }
+  if (images) HIPCHK(c, launch_assemble(A, images, s));
+  if (flux) HIPCHK(c, launch_flux(A, (double*)c->partial.p, n_chunks, (double*)c->flux.p, s));
+
+  HIPCHK(c, hipEventRecord(ev[1], s));
+  // one wait: counters, per-view counts, fluxes
+  const size_t vstat_bytes = 8 * (size_t)V * MAXL * VS_N;
+  if ((st = ensure_host(c, (void**)&c->host_vstat, &c->host_vstat_n, vstat_bytes))) return st;
+  HIPCHK(c, hipMemcpyAsync(c->host_ctr, A.w.ctr, 8 * CTR_COUNT, hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipMemcpyAsync(c->host_vstat, vstat, vstat_bytes, hipMemcpyDeviceToHost, s));
+  if (flux) {
+    if ((st = ensure_host(c, (void**)&c->host_flux, &c->host_flux_n, 8 * V * nb))) return st;
+    HIPCHK(c, hipMemcpyAsync(c->host_flux, c->flux.p, 8 * V * nb, hipMemcpyDeviceToHost, s));
+  }
+  std::vector<uint8_t> depth_h;
+  if (learned && ls) {
+    depth_h.resize((size_t)V * N0 * N0);
+    HIPCHK(c, hipMemcpyAsync(depth_h.data(), c->depth8.p, depth_h.size(), hipMemcpyDeviceToHost, s));
+  }
+  HIPCHK(c, hipStreamSynchronize(s));
+  const unsigned long long* hc = c->host_ctr;
+  if (hc[CTR_OVERFLOW]) return fail(c, AIR_EDEVICE, "internal work queue overflow");
+  if (flux) std::memcpy(flux, c->host_flux, 8 * V * nb);
+  if (stats) {
+    std::memset(stats, 0, sizeof *stats);
+    for (int k = 0; k < CTR_SLOTS; ++k) {
+      stats->hits += (int64_t)hc[CTR_HITS + k];
+      stats->visits += (int64_t)hc[CTR_VISITS + k];
+    }
+    for (int v = 0; v < V; ++v)
+      for (int L = 0; L <= Lm; ++L) {
+        const unsigned long long* r = c->host_vstat + ((size_t)v * MAXL + L) * VS_N;
+        stats->rays_per_level[L] += (int64_t)r[VS_NODES];
+        stats->leaves += (int64_t)r[VS_LEAVES];
+        stats->tested += (int64_t)r[VS_TESTED];
+        stats->flagged += (int64_t)r[VS_FLAGGED];
+        stats->balance += (int64_t)r[VS_BALANCE];
+      }
+    for (int L = 0; L <= Lm; ++L) {
+      stats->rays += stats->rays_per_level[L];
+      if (stats->rays_per_level[L]) stats->depth = L;
+    }
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, ev[0], ev[1]) == hipSuccess) stats->ms_total = ms;
+    for (int L = 0; L <= Lm; ++L) {
+      if (hipEventElapsedTime(&ms, ev[2 + 4 * L], ev[3 + 4 * L]) == hipSuccess) stats->ms_march += ms;
+      if (hipEventElapsedTime(&ms, ev[3 + 4 * L], ev[4 + 4 * L]) == hipSuccess) stats->ms_test += ms;
+    }
+    stats->march_launches = Lm + 1;
+    if (learned) {
+      if (hipEventElapsedTime(&ms, ev[air_ctx::EV_SPEC0], ev[air_ctx::EV_SPEC1]) == hipSuccess) stats->ms_march += ms;
+      stats->march_launches += 1;
+    }
+  }
+  if (learned && ls) {
+    std::memset(ls, 0, sizeof *ls);
+    for (int v = 0; v < V; ++v)
+      for (int L = 0; L <= Lm; ++L) {
+        const unsigned long long* r = c->host_vstat + ((size_t)v * MAXL + L) * VS_N;
+        ls->spec_rays += (int64_t)r[VS_SPEC];
+        ls->wasted += (int64_t)r[VS_WASTED];
+        ls->missing += (int64_t)r[VS_MISSING];
+      }
+    for (uint8_t d : depth_h) ls->depth_hist[d] += 1;
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, ev[air_ctx::EV_FEAT0], ev[air_ctx::EV_SPEC0]) == hipSuccess) ls->ms_features = ms;
+    if (hipEventElapsedTime(&ms, ev[air_ctx::EV_SPEC0], ev[air_ctx::EV_SPEC1]) == hipSuccess) ls->ms_spec = ms;
+  }
+  air_status res = AIR_OK;
+  for (int k = 0; trees && k < V; ++k) {
+    int64_t n = 0, leaves = 0;
+    for (int L = 0; L < MAXL; ++L) {
+      const unsigned long long* r = c->host_vstat + ((size_t)k * MAXL + L) * VS_N;
+      trees[k].n_per_level[L] = L <= Lm ? (int64_t)r[VS_NODES] : 0;
+      if (L <= Lm) {
+        n += (int64_t)r[VS_NODES];
+        leaves += (int64_t)r[VS_LEAVES];
+      }
+    }
+    trees[k].n_nodes = n;
+    trees[k].n_leaves = leaves;
+    if (n > trees[k].capacity)
+      res = fail(c, AIR_ECAPACITY, "tree %d needs %lld nodes, capacity %lld", k, (long long)n,
+                 (long long)trees[k].capacity);
+  }
+  return res;
+}
+
 }  // namespace
 
 extern "C" {
@@ -361,7 +646,9 @@ void air_destroy(air_ctx* c) {
   (void)hipSetDevice(c->device);
   for (DevBuf* b : {&c->state, &c->valI, &c->valN, &c->xiI, &c->xiN, &c->visits, &c->rmin, &c->rmax, &c->queue,
                     &c->ctr, &c->chunk, &c->cstat, &c->vstat, &c->idmap, &c->partial, &c->flux, &c->views,
-                    &c->touts, &c->pack})
+                    &c->touts, &c->pack, &c->lmax0, &c->feat, &c->cx0, &c->ca1, &c->ca2, &c->ca3, &c->cz,
+                    &c->cdz, &c->cda, &c->cdb, &c->cwpart, &c->closs_part, &c->closs, &c->depth8, &c->scount,
+                    &c->spec})
     if (b->p) (void)hipFree(b->p);
   if (c->host_ctr) (void)hipHostFree(c->host_ctr);
   if (c->host_flux) (void)hipHostFree(c->host_flux);
@@ -377,174 +664,23 @@ const char* air_last_error(const air_ctx* c) { return c ? c->err.c_str() : "cont
 air_status air_render(air_ctx* c, const air_grid* grid, const air_field* field, const air_view* views,
                       int32_t n_views, const air_params* prm, air_tree* trees, float* images, double* flux,
                       air_stats* stats, void* stream) {
+  return render_core(c, grid, field, views, n_views, prm, nullptr, nullptr, trees, images, flux, stats, nullptr,
+                     stream);
+}
+
+air_status air_render_learned(air_ctx* c, const air_grid* grid, const air_field* field, const air_view* views,
+                              int32_t n_views, const air_params* prm, const air_cnn* net,
+                              const air_learn_params* learn, air_tree* trees, float* images, double* flux,
+                              air_stats* stats, air_learn_stats* learn_stats, void* stream) {
   if (!c) return AIR_EINVAL;
   c->err.clear();
-  air_status st;
-  if ((st = check_grid(c, grid))) return st;
-  if ((st = check_field(c, field))) return st;
-  if (!views || n_views < 1 || n_views > AIR_MAX_VIEWS)
-    return fail(c, AIR_EINVAL, "n_views %d out of range 1..%d", n_views, AIR_MAX_VIEWS);
-  if (!prm) return fail(c, AIR_EINVAL, "params is NULL");
-  const int N0 = prm->coarse_n, Lm = prm->max_level;
-  if (N0 < 1 || N0 > 65536) return fail(c, AIR_EINVAL, "coarse_n %d out of range", N0);
-  if (Lm < 0 || Lm >= AIR_MAX_LEVELS) return fail(c, AIR_EINVAL, "max_level %d out of range 0..%d", Lm, AIR_MAX_LEVELS - 1);
-  if ((double)N0 * N0 * std::pow(4.0, Lm) > 4294967295.0)
-    return fail(c, AIR_EINVAL, "coarse_n^2 * 4^max_level exceeds 2^32 pixels per view");
-  if (!std::isfinite(prm->xi_crit_I) || !std::isfinite(prm->xi_crit_N) || prm->xi_crit_I < 0 || prm->xi_crit_N < 0)
-    return fail(c, AIR_EINVAL, "xi_crit must be finite and >= 0");
-  if (prm->flags != 0) return fail(c, AIR_EINVAL, "params.flags must be 0");
-  for (int k = 0; trees && k < n_views; ++k)
-    if (trees[k].capacity < 0) return fail(c, AIR_EINVAL, "tree %d capacity < 0", k);
-  if (hipSetDevice(c->device) != hipSuccess) return fail(c, AIR_EDEVICE, "hipSetDevice failed");
-  hipStream_t s = (hipStream_t)stream;
-  if ((st = check_blocks(c, grid, s))) return st;
-
-  MarchArgs A;
-  std::memset(&A, 0, sizeof A);
-  fill_geo(grid, A.g);
-  if (c->seg_shift_override >= 0) A.g.seg_shift = c->seg_shift_override;
-  fill_fld(field, grid, A.f);
-  const int nb = A.f.nb, V = n_views;
-  A.img.N0 = N0;
-  A.img.Lmax = Lm;
-  A.img.V = V;
-  // every level starts on a counting chunk, so a chunk belongs to one
-  // (view, level)
-  int64_t off = 0;
-  for (int L = 0; L <= Lm; ++L) {
-    A.img.off[L] = off;
-    off = round_up(off + ((int64_t)N0 * N0 << (2 * L)), CHUNK);
-  }
-  for (int L = Lm + 1; L <= MAXL; ++L) A.img.off[L] = off;
-  const int64_t S = off;
-  A.img.S = S;
-  const int64_t VS = (int64_t)V * S;
-  const int64_t n_chunks = VS / CHUNK;
-  if ((st = ensure(c, c->state, VS))) return st;
-  if ((st = ensure(c, c->valI, 4 * VS * nb))) return st;
-  if ((st = ensure(c, c->valN, 4 * VS))) return st;
-  if ((st = ensure(c, c->xiI, 4 * VS))) return st;
-  if ((st = ensure(c, c->xiN, 4 * VS))) return st;
-  if ((st = ensure(c, c->visits, 4 * VS))) return st;
-  if ((st = ensure(c, c->queue, 8 * VS))) return st;
-  if ((st = ensure(c, c->ctr, 8 * CTR_COUNT))) return st;
-  if ((st = ensure(c, c->chunk, 8 * (n_chunks + 1)))) return st;
-  if ((st = ensure(c, c->cstat, 4 * VS_N * n_chunks))) return st;
-  if ((st = ensure(c, c->vstat, 8 * (size_t)V * MAXL * VS_N))) return st;
-  if ((st = ensure(c, c->partial, 8 * n_chunks * nb))) return st;
-  if ((st = ensure(c, c->flux, 8 * V * nb))) return st;
-  if (trees) {
-    if ((st = ensure(c, c->idmap, 4 * VS))) return st;
-    if ((st = ensure(c, c->touts, sizeof(TreeOut) * V))) return st;
-  }
-  A.w.state = (uint8_t*)c->state.p;
-  A.w.valI = (float*)c->valI.p;
-  A.w.valN = (float*)c->valN.p;
-  A.w.xiI = (float*)c->xiI.p;
-  A.w.xiN = (float*)c->xiN.p;
-  A.w.visits = (int*)c->visits.p;
-  A.w.queue = (uint64_t*)c->queue.p;
-  A.w.qcap = (uint64_t)VS;
-  A.w.ctr = (unsigned long long*)c->ctr.p;
-  if ((st = upload_views(c, views, V, s, &A.views))) return st;
-  if ((st = ensure_packed(c, grid, field, A, s))) return st;
-
-  float w[MAXB];
-  for (int b = 0; b < MAXB; ++b) w[b] = b < nb ? prm->band_weight[b] : 0.0f;
-
-  // the level loop: trace the queue of new nodes, then test, close and
-  // compact; the queue bounds live in device counters, so no host round trip
-  hipEvent_t* ev = c->ev;
-  HIPCHK(c, hipEventRecord(ev[0], s));
-  HIPCHK(c, launch_init(A, s));
-  for (int L = 0; L <= Lm; ++L) {
-    HIPCHK(c, hipEventRecord(ev[2 + 4 * L], s));
-    HIPCHK(c, launch_march_queue(A, L, march_blocks(c, A.g.seg_shift), s));
-    HIPCHK(c, hipEventRecord(ev[3 + 4 * L], s));
-    if (L < Lm) HIPCHK(c, launch_refine(A, L, prm->xi_crit_I, prm->xi_crit_N, w, c->num_cus * 4, s));
-    HIPCHK(c, hipEventRecord(ev[4 + 4 * L], s));
-  }
-  unsigned long long* chunk = (unsigned long long*)c->chunk.p;
-  unsigned long long* vstat = (unsigned long long*)c->vstat.p;
-  HIPCHK(c, launch_count(A, chunk, (unsigned*)c->cstat.p, n_chunks, vstat, s));
-  if (trees) {
-    HIPCHK(c, launch_scan(chunk, n_chunks, s));
-    HIPCHK(c, launch_emit(A, chunk, n_chunks, (int32_t*)c->idmap.p, s));
-    std::vector<TreeOut> to(V);
-    for (int k = 0; k < V; ++k) {
-      const air_tree& t = trees[k];
-      to[k] = TreeOut{t.level, t.ix, t.iy, t.parent, t.first_child, t.state, t.I, t.N, t.xi_I, t.xi_N,
-                      t.visits, t.capacity};
-    }
-    // the views' staging copy above must land before the buffer is reused
-    HIPCHK(c, hipStreamSynchronize(s));
-    if ((st = ensure_host(c, &c->stage, &c->stage_n, sizeof(TreeOut) * V))) return st;
-    std::memcpy(c->stage, to.data(), sizeof(TreeOut) * V);
-    HIPCHK(c, hipMemcpyAsync(c->touts.p, c->stage, sizeof(TreeOut) * V, hipMemcpyHostToDevice, s));
-    HIPCHK(c, launch_write_tree(A, chunk, (const int32_t*)c->idmap.p, (const TreeOut*)c->touts.p, s));
-  }
-  if (images) HIPCHK(c, launch_assemble(A, images, s));
-  if (flux) HIPCHK(c, launch_flux(A, (double*)c->partial.p, n_chunks, (double*)c->flux.p, s));
-
-  HIPCHK(c, hipEventRecord(ev[1], s));
-  // one wait: counters, per-view counts, fluxes
-  const size_t vstat_bytes = 8 * (size_t)V * MAXL * VS_N;
-  if ((st = ensure_host(c, (void**)&c->host_vstat, &c->host_vstat_n, vstat_bytes))) return st;
-  HIPCHK(c, hipMemcpyAsync(c->host_ctr, A.w.ctr, 8 * CTR_COUNT, hipMemcpyDeviceToHost, s));
-  HIPCHK(c, hipMemcpyAsync(c->host_vstat, vstat, vstat_bytes, hipMemcpyDeviceToHost, s));
-  if (flux) {
-    if ((st = ensure_host(c, (void**)&c->host_flux, &c->host_flux_n, 8 * V * nb))) return st;
-    HIPCHK(c, hipMemcpyAsync(c->host_flux, c->flux.p, 8 * V * nb, hipMemcpyDeviceToHost, s));
-  }
-  HIPCHK(c, hipStreamSynchronize(s));
-  const unsigned long long* hc = c->host_ctr;
-  if (hc[CTR_OVERFLOW]) return fail(c, AIR_EDEVICE, "internal work queue overflow");
-  if (flux) std::memcpy(flux, c->host_flux, 8 * V * nb);
-  if (stats) {
-    std::memset(stats, 0, sizeof *stats);
-    for (int k = 0; k < CTR_SLOTS; ++k) {
-      stats->hits += (int64_t)hc[CTR_HITS + k];
-      stats->visits += (int64_t)hc[CTR_VISITS + k];
-    }
-    for (int v = 0; v < V; ++v)
-      for (int L = 0; L <= Lm; ++L) {
-        const unsigned long long* r = c->host_vstat + ((size_t)v * MAXL + L) * VS_N;
-        stats->rays_per_level[L] += (int64_t)r[VS_NODES];
-        stats->leaves += (int64_t)r[VS_LEAVES];
-        stats->tested += (int64_t)r[VS_TESTED];
-        stats->flagged += (int64_t)r[VS_FLAGGED];
-        stats->balance += (int64_t)r[VS_BALANCE];
-      }
-    for (int L = 0; L <= Lm; ++L) {
-      stats->rays += stats->rays_per_level[L];
-      if (stats->rays_per_level[L]) stats->depth = L;
-    }
-    float ms = 0.0f;
-    if (hipEventElapsedTime(&ms, ev[0], ev[1]) == hipSuccess) stats->ms_total = ms;
-    for (int L = 0; L <= Lm; ++L) {
-      if (hipEventElapsedTime(&ms, ev[2 + 4 * L], ev[3 + 4 * L]) == hipSuccess) stats->ms_march += ms;
-      if (hipEventElapsedTime(&ms, ev[3 + 4 * L], ev[4 + 4 * L]) == hipSuccess) stats->ms_test += ms;
-    }
-    stats->march_launches = Lm + 1;
-  }
-  air_status res = AIR_OK;
-  for (int k = 0; trees && k < V; ++k) {
-    int64_t n = 0, leaves = 0;
-    for (int L = 0; L < MAXL; ++L) {
-      const unsigned long long* r = c->host_vstat + ((size_t)k * MAXL + L) * VS_N;
-      trees[k].n_per_level[L] = L <= Lm ? (int64_t)r[VS_NODES] : 0;
-      if (L <= Lm) {
-        n += (int64_t)r[VS_NODES];
-        leaves += (int64_t)r[VS_LEAVES];
-      }
-    }
-    trees[k].n_nodes = n;
-    trees[k].n_leaves = leaves;
-    if (n > trees[k].capacity)
-      res = fail(c, AIR_ECAPACITY, "tree %d needs %lld nodes, capacity %lld", k, (long long)n,
-                 (long long)trees[k].capacity);
-  }
-  return res;
+  if (!net || !learn) return fail(c, AIR_EINVAL, "network or learn parameters NULL");
+  if (net->device != c->device) return fail(c, AIR_EINVAL, "network and context are on different devices");
+  if (!std::isfinite(learn->c_ray) || !std::isfinite(learn->c_sweep) || learn->c_ray < 0 || learn->c_sweep < 0)
+    return fail(c, AIR_EINVAL, "c_ray and c_sweep must be finite and >= 0");
+  if (learn->max_depth < 0 || learn->flags != 0) return fail(c, AIR_EINVAL, "max_depth < 0 or flags != 0");
+  return render_core(c, grid, field, views, n_views, prm, net, learn, trees, images, flux, stats, learn_stats,
+                     stream);
 }
 
 air_status air_render_fixed(air_ctx* c, const air_grid* grid, const air_field* field, const air_view* views,
@@ -676,6 +812,220 @@ air_status air_field_pack(air_ctx* c, const air_grid* grid, const air_field* fie
   fill_geo(grid, A.g);
   fill_fld(field, grid, A.f);
   HIPCHK(c, pack_any(A.g, A.f, packed, (hipStream_t)stream));
+  return AIR_OK;
+}
+
+// ------------------------------------------------------------ learned proposal
+air_status air_cnn_create(air_ctx* c, air_cnn** out) {
+  if (!c || !out) return AIR_EINVAL;
+  c->err.clear();
+  *out = nullptr;
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, AIR_EDEVICE, "hipSetDevice failed");
+  air_cnn* n = new air_cnn;
+  n->device = c->device;
+  cnn::Net& N = n->net;
+  const size_t P = AIR_CNN_PARAMS;
+  bool ok = hipMalloc(&N.theta, 4 * P) == hipSuccess && hipMalloc(&N.m, 4 * P) == hipSuccess &&
+            hipMalloc(&N.v, 4 * P) == hipSuccess && hipMalloc(&N.grad, 4 * P) == hipSuccess;
+  const int csi[cnn::LAYERS] = {cnn::XC, cnn::HID, cnn::HID, cnn::HID};
+  const int cso[cnn::LAYERS] = {cnn::HID, cnn::HID, cnn::HID, cnn::ZC};
+  const int rows[cnn::LAYERS] = {cnn::HID, cnn::HID, cnn::HID, 16};
+  for (int l = 0; ok && l < cnn::LAYERS; ++l) {
+    ok = hipMalloc(&N.wf[l], 2 * (size_t)rows[l] * cnn::KPAD(csi[l])) == hipSuccess;
+    if (ok && l > 0) ok = hipMalloc(&N.wt[l], 2 * (size_t)cnn::HID * cnn::KPAD(cso[l])) == hipSuccess;
+  }
+  if (ok)
+    ok = hipMemset(N.theta, 0, 4 * P) == hipSuccess && hipMemset(N.m, 0, 4 * P) == hipSuccess &&
+         hipMemset(N.v, 0, 4 * P) == hipSuccess && hipMemset(N.grad, 0, 4 * P) == hipSuccess &&
+         cnn::prep_weights(N, nullptr) == hipSuccess && hipDeviceSynchronize() == hipSuccess;
+  if (!ok) {
+    (void)hipGetLastError();
+    air_cnn_destroy(n);
+    return fail(c, AIR_ENOMEM, "network allocation failed");
+  }
+  *out = n;
+  return AIR_OK;
+}
+
+void air_cnn_destroy(air_cnn* n) {
+  if (!n) return;
+  (void)hipSetDevice(n->device);
+  cnn::Net& N = n->net;
+  for (float* p : {N.theta, N.m, N.v, N.grad})
+    if (p) (void)hipFree(p);
+  for (int l = 0; l < cnn::LAYERS; ++l) {
+    if (N.wf[l]) (void)hipFree(N.wf[l]);
+    if (N.wt[l]) (void)hipFree(N.wt[l]);
+  }
+  delete n;
+}
+
+air_status air_cnn_set(air_ctx* c, air_cnn* n, const float* params, const float* mean, const float* scale) {
+  if (!c || !n) return AIR_EINVAL;
+  c->err.clear();
+  if (n->device != c->device) return fail(c, AIR_EINVAL, "network and context are on different devices");
+  if (!params || !mean || !scale) return fail(c, AIR_EINVAL, "params, mean or scale is NULL");
+  for (int k = 0; k < cnn::FEAT; ++k)
+    if (!std::isfinite(mean[k]) || !std::isfinite(scale[k]) || !(scale[k] > 0))
+      return fail(c, AIR_EINVAL, "feature mean must be finite and scale > 0");
+  for (int k = 0; k < AIR_CNN_PARAMS; ++k)
+    if (!std::isfinite(params[k])) return fail(c, AIR_EINVAL, "parameter %d not finite", k);
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, AIR_EDEVICE, "hipSetDevice failed");
+  cnn::Net& N = n->net;
+  const size_t P = AIR_CNN_PARAMS;
+  HIPCHK(c, hipMemcpy(N.theta, params, 4 * P, hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemset(N.m, 0, 4 * P));
+  HIPCHK(c, hipMemset(N.v, 0, 4 * P));
+  HIPCHK(c, hipMemset(N.grad, 0, 4 * P));
+  for (int k = 0; k < cnn::FEAT; ++k) {
+    N.mean[k] = mean[k];
+    N.stdv[k] = scale[k];
+  }
+  N.step = 0;
+  HIPCHK(c, cnn::prep_weights(N, nullptr));
+  HIPCHK(c, hipDeviceSynchronize());
+  return AIR_OK;
+}
+
+air_status air_cnn_get(air_ctx* c, const air_cnn* n, float* params, float* mean, float* scale) {
+  if (!c || !n) return AIR_EINVAL;
+  c->err.clear();
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, AIR_EDEVICE, "hipSetDevice failed");
+  if (params) {
+    HIPCHK(c, hipDeviceSynchronize());
+    HIPCHK(c, hipMemcpy(params, n->net.theta, 4 * (size_t)AIR_CNN_PARAMS, hipMemcpyDeviceToHost));
+  }
+  for (int k = 0; k < cnn::FEAT; ++k) {
+    if (mean) mean[k] = n->net.mean[k];
+    if (scale) scale[k] = n->net.stdv[k];
+  }
+  return AIR_OK;
+}
+
+namespace {
+air_status check_maps(air_ctx* c, const air_cnn* n, const float* feat, int32_t n_maps, int32_t h, int32_t w) {
+  if (!n) return fail(c, AIR_EINVAL, "network is NULL");
+  if (n->device != c->device) return fail(c, AIR_EINVAL, "network and context are on different devices");
+  if (!feat) return fail(c, AIR_EINVAL, "features NULL");
+  if (n_maps < 1 || h < 1 || w < 1 || (int64_t)n_maps * h * w >= ((int64_t)1 << 31) / 64)
+    return fail(c, AIR_EINVAL, "map count or size out of range");
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, AIR_EDEVICE, "hipSetDevice failed");
+  return AIR_OK;
+}
+
+air_status cnn_forward_all(air_ctx* c, const air_cnn* n, const float* feat, int n_maps, int h, int w, float* z,
+                           hipStream_t s) {
+  const int64_t P = (int64_t)n_maps * h * w;
+  const cnn::Net& N = n->net;
+  HIPCHK(c, cnn::input_maps(feat, P, N.mean, N.stdv, (uint16_t*)c->cx0.p, s));
+  HIPCHK(c, cnn::conv_forward(0, N, (const uint16_t*)c->cx0.p, n_maps, h, w, c->ca1.p, s));
+  HIPCHK(c, cnn::conv_forward(1, N, (const uint16_t*)c->ca1.p, n_maps, h, w, c->ca2.p, s));
+  HIPCHK(c, cnn::conv_forward(2, N, (const uint16_t*)c->ca2.p, n_maps, h, w, c->ca3.p, s));
+  HIPCHK(c, cnn::conv_forward(3, N, (const uint16_t*)c->ca3.p, n_maps, h, w, z, s));
+  return AIR_OK;
+}
+}  // namespace
+
+air_status air_cnn_forward(air_ctx* c, air_cnn* n, const float* feat, int32_t n_maps, int32_t h, int32_t w,
+                           float* logits, void* stream) {
+  if (!c) return AIR_EINVAL;
+  c->err.clear();
+  air_status st;
+  if ((st = check_maps(c, n, feat, n_maps, h, w))) return st;
+  if (!logits) return fail(c, AIR_EINVAL, "logits NULL");
+  if ((st = ensure_cnn_work(c, (int64_t)n_maps * h * w, false))) return st;
+  return cnn_forward_all(c, n, feat, n_maps, h, w, logits, (hipStream_t)stream);
+}
+
+air_status air_cnn_loss_grad(air_ctx* c, air_cnn* n, const float* feat, const int32_t* labels, int32_t n_maps,
+                             int32_t h, int32_t w, const float* class_weight, double* loss, float* grad,
+                             void* stream) {
+  if (!c) return AIR_EINVAL;
+  c->err.clear();
+  air_status st;
+  if ((st = check_maps(c, n, feat, n_maps, h, w))) return st;
+  if (!labels || !class_weight) return fail(c, AIR_EINVAL, "labels or class weights NULL");
+  for (int k = 0; k < cnn::CLASSES; ++k)
+    if (!std::isfinite(class_weight[k]) || class_weight[k] < 0) return fail(c, AIR_EINVAL, "class weight %d invalid", k);
+  const int64_t P = (int64_t)n_maps * h * w;
+  if ((st = ensure_cnn_work(c, P, true))) return st;
+  hipStream_t s = (hipStream_t)stream;
+  cnn::Net& N = n->net;
+  if ((st = cnn_forward_all(c, n, feat, n_maps, h, w, (float*)c->cz.p, s))) return st;
+  HIPCHK(c, cnn::loss_and_dz((const float*)c->cz.p, labels, P, class_weight, (double*)c->closs_part.p,
+                             (double*)c->closs.p, (uint16_t*)c->cdz.p, s));
+  float* wp = (float*)c->cwpart.p;
+  const uint16_t* cdz = (const uint16_t*)c->cdz.p;
+  uint16_t* da = (uint16_t*)c->cda.p;
+  uint16_t* db = (uint16_t*)c->cdb.p;
+  // back through layers 3..0: weight gradient from (dy, input), then the
+  // input gradient masked by the input's ReLU
+  HIPCHK(c, cnn::conv_weight_grad(3, N, cdz, (const uint16_t*)c->ca3.p, n_maps, h, w, wp, s));
+  HIPCHK(c, cnn::conv_input_grad(3, N, cdz, (const uint16_t*)c->ca3.p, n_maps, h, w, da, s));
+  HIPCHK(c, cnn::conv_weight_grad(2, N, da, (const uint16_t*)c->ca2.p, n_maps, h, w, wp, s));
+  HIPCHK(c, cnn::conv_input_grad(2, N, da, (const uint16_t*)c->ca2.p, n_maps, h, w, db, s));
+  HIPCHK(c, cnn::conv_weight_grad(1, N, db, (const uint16_t*)c->ca1.p, n_maps, h, w, wp, s));
+  HIPCHK(c, cnn::conv_input_grad(1, N, db, (const uint16_t*)c->ca1.p, n_maps, h, w, da, s));
+  HIPCHK(c, cnn::conv_weight_grad(0, N, da, (const uint16_t*)c->cx0.p, n_maps, h, w, wp, s));
+  if (grad) HIPCHK(c, hipMemcpyAsync(grad, N.grad, 4 * (size_t)AIR_CNN_PARAMS, hipMemcpyDeviceToDevice, s));
+  if (loss) {
+    double host[2];
+    HIPCHK(c, hipMemcpyAsync(host, c->closs.p, 16, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    *loss = host[1];
+  }
+  return AIR_OK;
+}
+
+air_status air_cnn_adam(air_ctx* c, air_cnn* n, float lr, float beta1, float beta2, float eps, void* stream) {
+  if (!c) return AIR_EINVAL;
+  c->err.clear();
+  if (!n) return fail(c, AIR_EINVAL, "network is NULL");
+  if (!(lr >= 0) || !(beta1 >= 0 && beta1 < 1) || !(beta2 >= 0 && beta2 < 1) || !(eps > 0))
+    return fail(c, AIR_EINVAL, "Adam hyper-parameters out of range");
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, AIR_EDEVICE, "hipSetDevice failed");
+  hipStream_t s = (hipStream_t)stream;
+  HIPCHK(c, cnn::adam(n->net, AIR_CNN_PARAMS, lr, beta1, beta2, eps, s));
+  HIPCHK(c, cnn::prep_weights(n->net, s));
+  return AIR_OK;
+}
+
+air_status air_features(air_ctx* c, const air_grid* grid, const air_field* field, const air_view* views,
+                        int32_t n_views, int32_t coarse_n, const float* band_weight, float* features, void* stream) {
+  if (!c) return AIR_EINVAL;
+  c->err.clear();
+  air_params prm;
+  std::memset(&prm, 0, sizeof prm);
+  prm.coarse_n = coarse_n;
+  air_status st;
+  if ((st = check_render_args(c, grid, field, views, n_views, &prm))) return st;
+  if (!band_weight || !features) return fail(c, AIR_EINVAL, "band weights or features NULL");
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, AIR_EDEVICE, "hipSetDevice failed");
+  hipStream_t s = (hipStream_t)stream;
+  if ((st = check_blocks(c, grid, s))) return st;
+  MarchArgs A;
+  int64_t n_chunks = 0;
+  if ((st = setup_render(c, grid, field, views, n_views, coarse_n, 0, true, s, A, n_chunks))) return st;
+  LearnW W;
+  for (int b = 0; b < MAXB; ++b) W.w[b] = b < A.f.nb ? band_weight[b] : 0.0f;
+  HIPCHK(c, launch_init(A, s));
+  HIPCHK(c, launch_march_queue(A, 0, march_blocks(c, A.g.seg_shift), s));
+  HIPCHK(c, launch_features(A, W, features, s));
+  return AIR_OK;
+}
+
+air_status air_tree_depth(air_ctx* c, const air_tree* tree, int32_t coarse_n, int32_t* depth, void* stream) {
+  if (!c) return AIR_EINVAL;
+  c->err.clear();
+  if (!tree || !depth || coarse_n < 1) return fail(c, AIR_EINVAL, "tree, depth or coarse_n invalid");
+  if (tree->n_nodes < 0 || tree->n_nodes > tree->capacity) return fail(c, AIR_EINVAL, "tree n_nodes out of range");
+  if (tree->n_nodes > 0 && (!tree->level || !tree->ix || !tree->iy))
+    return fail(c, AIR_EINVAL, "tree level/ix/iy NULL");
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, AIR_EDEVICE, "hipSetDevice failed");
+  hipStream_t s = (hipStream_t)stream;
+  HIPCHK(c, hipMemsetAsync(depth, 0, 4 * (size_t)coarse_n * coarse_n, s));
+  if (tree->n_nodes > 0)
+    HIPCHK(c, launch_tree_depth(tree->level, tree->ix, tree->iy, tree->n_nodes, coarse_n, depth, s));
   return AIR_OK;
 }
 

@@ -1,0 +1,474 @@
+// Depth-proposal network on gfx950: 3x3 convolutions as implicit GEMMs on
+// the bf16 matrix cores (v_mfma_f32_16x16x32_bf16, float32 accumulation),
+// its backward pass, the weighted cross-entropy and Adam.
+//
+// Tensors are NHWC: pixel p = (map * h + y) * w + x, channels contiguous.
+// Activations and back-propagated gradients are bf16 (round to nearest
+// even), logits float32.  A convolution
+//   y[p, o] = bias[o] + sum_{ky, kx, c} x[p shifted by (ky-1, kx-1), c] W[o, ky, kx, c]
+// is the product D = A B with A = W as a [rows][K] matrix (K = 9 taps x
+// stored input channels, padded to 32) and B[k][p] = the shifted input; one
+// wave computes a 16-pixel column block for every output row, holding all of
+// A in registers, and each lane gathers its pixel's 8 consecutive channels
+// of one tap with a single 16-byte load.  The input gradient is the same
+// product with the flipped, transposed weights; the weight gradient stages a
+// 32-pixel chunk of both operands transposed in LDS and reduces over pixels
+// into per-block partials that one more kernel sums in a fixed order.
+#include <algorithm>
+#include <cmath>
+
+#include "cnn.h"
+
+namespace air {
+namespace cnn {
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x4 __attribute__((ext_vector_type(4)));
+
+constexpr int WAVE = 64;
+constexpr uint16_t BF16_ONE = 0x3f80;
+
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0;  // NaN stays NaN
+  u += 0x7fffu + ((u >> 16) & 1u);                     // nearest, ties to even
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+__device__ __forceinline__ bool bf_pos(uint16_t h) { return !(h & 0x8000u) && (h & 0x7fffu); }
+
+__device__ __forceinline__ f32x4 mfma(const u16x8& a, const u16x8& b, const f32x4& c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c, 0,
+                                                 0, 0);
+}
+
+// stored channels of each layer's input and output, and the rows of its
+// forward matrix
+constexpr int CS_IN[LAYERS] = {XC, HID, HID, HID};
+constexpr int CS_OUT[LAYERS] = {HID, HID, HID, ZC};
+constexpr int ROWS[LAYERS] = {HID, HID, HID, 16};
+
+struct Prep {
+  const float* theta;
+  uint16_t* wf[LAYERS];
+  uint16_t* wt[LAYERS];
+  int woff[LAYERS];
+};
+
+// bf16 operand matrices from the float32 parameters
+__global__ __launch_bounds__(256) void k_prep(Prep P) {
+  const int l = blockIdx.y;
+  const int cin = CIN[l], cout = COUT[l], csi = CS_IN[l], cso = CS_OUT[l];
+  const float* w = P.theta + P.woff[l];
+  // forward: wf[r][k], k = tap * csi + c
+  const int kpf = KPAD(csi), nf = ROWS[l] * kpf;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nf; e += gridDim.x * blockDim.x) {
+    const int r = e / kpf, k = e % kpf, tap = k / csi, c = k % csi;
+    float val = 0.0f;
+    if (r < cout && k < 9 * csi && c < cin) val = w[(r * 9 + tap) * cin + c];
+    P.wf[l][e] = f2bf(val);
+  }
+  if (l == 0) return;
+  // input gradient: wt[c][k], k = tap' * cso + o, tap' = (2 - ky) * 3 + (2 - kx)
+  const int kpt = KPAD(cso), nt = HID * kpt;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nt; e += gridDim.x * blockDim.x) {
+    const int c = e / kpt, k = e % kpt, tp = k / cso, o = k % cso;
+    float val = 0.0f;
+    if (k < 9 * cso && o < cout && c < cin) {
+      const int ky = 2 - tp / 3, kx = 2 - tp % 3;
+      val = w[(o * 9 + ky * 3 + kx) * cin + c];
+    }
+    P.wt[l][e] = f2bf(val);
+  }
+}
+
+struct Norm {
+  float mean[FEAT], inv_std[FEAT];
+};
+
+// standardised bf16 input maps, channels 4..7 zero
+__global__ __launch_bounds__(256) void k_input(const float* feat, int64_t P, Norm nm, uint16_t* x) {
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < P; p += (int64_t)gridDim.x * blockDim.x) {
+    u16x8 o = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int c = 0; c < FEAT; ++c) o[c] = f2bf((feat[p * FEAT + c] - nm.mean[c]) * nm.inv_std[c]);
+    *reinterpret_cast<u16x8*>(x + p * XC) = o;
+  }
+}
+
+enum { MODE_HIDDEN = 0, MODE_LOGITS = 1, MODE_MASK = 2 };
+
+// D[rows][pixels] = A[rows][K] B[K][pixels]; CS = stored input channels,
+// CSO = stored output channels, NBIAS = real output channels (bias length)
+template <int CS, int RW, int CSO, int MODE>
+__global__ __launch_bounds__(256) void k_conv(const uint16_t* __restrict__ wmat, const float* __restrict__ bias,
+                                              int nbias, const uint16_t* __restrict__ x,
+                                              const uint16_t* __restrict__ act, int n, int h, int w,
+                                              void* __restrict__ out) {
+  constexpr int K = 9 * CS, KP = (K + 31) / 32 * 32, KS = KP / 32, MB = RW / 16;
+  const int lane = threadIdx.x & (WAVE - 1), g = lane >> 4, c16 = lane & 15;
+  u16x8 a[MB][KS];
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
+      a[mb][ks] = *reinterpret_cast<const u16x8*>(wmat + (mb * 16 + c16) * KP + ks * 32 + 8 * g);
+  const int64_t P = (int64_t)n * h * w, tiles = (P + 15) / 16;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / WAVE;
+  for (int64_t t = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE; t < tiles; t += nwaves) {
+    const int64_t p = t * 16 + c16;
+    const bool ok = p < P;
+    int xx = 0, y = 0;
+    int64_t b = 0;
+    if (ok) {
+      xx = (int)(p % w);
+      y = (int)((p / w) % h);
+      b = p / ((int64_t)w * h);
+    }
+    f32x4 acc[MB];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) acc[mb] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int k0 = ks * 32 + 8 * g;
+      u16x8 bv = {0, 0, 0, 0, 0, 0, 0, 0};
+      if (ok && k0 < K) {
+        const int tap = k0 / CS, c0 = k0 % CS;
+        const int yy = y + tap / 3 - 1, xs = xx + tap % 3 - 1;
+        if (yy >= 0 && yy < h && xs >= 0 && xs < w)
+          bv = *reinterpret_cast<const u16x8*>(x + ((b * h + yy) * w + xs) * CS + c0);
+      }
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) acc[mb] = mfma(a[mb][ks], bv, acc[mb]);
+    }
+    if (!ok) continue;
+    // lane holds rows mb*16 + 4g + i of pixel p
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+      const int r0 = mb * 16 + 4 * g;
+      if (r0 >= CSO) continue;
+      if constexpr (MODE == MODE_LOGITS) {
+        float4 o;
+        o.x = acc[mb][0] + (r0 + 0 < nbias ? bias[r0 + 0] : 0.0f);
+        o.y = acc[mb][1] + (r0 + 1 < nbias ? bias[r0 + 1] : 0.0f);
+        o.z = acc[mb][2] + (r0 + 2 < nbias ? bias[r0 + 2] : 0.0f);
+        o.w = acc[mb][3] + (r0 + 3 < nbias ? bias[r0 + 3] : 0.0f);
+        *reinterpret_cast<float4*>(static_cast<float*>(out) + p * CSO + r0) = o;
+      } else {
+        u16x4 o;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          float v = acc[mb][i];
+          if constexpr (MODE == MODE_HIDDEN) {
+            v = fmaxf(v + (r0 + i < nbias ? bias[r0 + i] : 0.0f), 0.0f);
+          } else {
+            v = bf_pos(act[p * CSO + r0 + i]) ? v : 0.0f;
+          }
+          o[i] = f2bf(v);
+        }
+        *reinterpret_cast<u16x4*>(static_cast<uint16_t*>(out) + p * CSO + r0) = o;
+      }
+    }
+  }
+}
+
+// weight gradient: G[o][n] = sum_p dy[p, o] X[p, n], n = tap * CS + c, plus
+// the bias column n = 9 CS of ones.  CS = stored input channels, DC = stored
+// dy channels, RW = padded rows.
+constexpr int WG_BLOCKS = 256;
+constexpr int WG_MAX_FLOATS = HID * ((9 * HID + 1 + 15) / 16 * 16);
+
+template <int CS, int DC, int RW>
+__global__ __launch_bounds__(256) void k_wgrad(const uint16_t* __restrict__ dy, const uint16_t* __restrict__ x,
+                                               int n, int h, int w, float* __restrict__ partial) {
+  constexpr int N = 9 * CS + 1, NBK = (N + 15) / 16, NP = NBK * 16, MB = RW / 16, TILES = MB * NBK;
+  constexpr int PER = (TILES + 3) / 4;
+  __shared__ __attribute__((aligned(16))) uint16_t dyT[RW][32];
+  __shared__ __attribute__((aligned(16))) uint16_t xs[9 * CS][32];
+  const int tid = threadIdx.x, wv = tid / WAVE, lane = tid & (WAVE - 1), g = lane >> 4, c16 = lane & 15;
+  f32x4 acc[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) acc[q] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  const int64_t P = (int64_t)n * h * w, chunks = (P + 31) / 32;
+  for (int64_t ch = blockIdx.x; ch < chunks; ch += gridDim.x) {
+    __syncthreads();  // the previous chunk's operands are consumed
+    for (int e = tid; e < RW * 32; e += 256) {
+      const int r = e % RW, px = e / RW;
+      const int64_t p = ch * 32 + px;
+      dyT[r][px] = (p < P && r < DC) ? dy[p * DC + r] : (uint16_t)0;
+    }
+    for (int e = tid; e < 9 * CS * 32; e += 256) {
+      const int c = e % CS, rest = e / CS, px = rest % 32, tap = rest / 32;
+      const int64_t p = ch * 32 + px;
+      uint16_t val = 0;
+      if (p < P) {
+        const int xx = (int)(p % w), y = (int)((p / w) % h);
+        const int64_t b = p / ((int64_t)w * h);
+        const int yy = y + tap / 3 - 1, xq = xx + tap % 3 - 1;
+        if (yy >= 0 && yy < h && xq >= 0 && xq < w) val = x[((b * h + yy) * w + xq) * CS + c];
+      }
+      xs[tap * CS + c][px] = val;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int tile = wv + 4 * q;
+      if (tile >= TILES) break;  // uniform per wave
+      const int mb = tile / NBK, nb = tile % NBK;
+      const u16x8 av = *reinterpret_cast<const u16x8*>(&dyT[mb * 16 + c16][8 * g]);
+      const int col = nb * 16 + c16;
+      u16x8 bv = {0, 0, 0, 0, 0, 0, 0, 0};
+      if (col < 9 * CS) {
+        bv = *reinterpret_cast<const u16x8*>(&xs[col][8 * g]);
+      } else if (col == 9 * CS) {
+        const int64_t p0 = ch * 32 + 8 * g;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) bv[e] = p0 + e < P ? BF16_ONE : (uint16_t)0;
+      }
+      acc[q] = mfma(av, bv, acc[q]);
+    }
+  }
+  float* out = partial + (int64_t)blockIdx.x * RW * NP;
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int tile = wv + 4 * q;
+    if (tile >= TILES) break;
+    const int mb = tile / NBK, nb = tile % NBK;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) out[(mb * 16 + 4 * g + i) * NP + nb * 16 + c16] = acc[q][i];
+  }
+}
+
+// sum the per-block partials in block order into the flat gradient
+__global__ __launch_bounds__(256) void k_wgrad_reduce(const float* partial, int nblocks, int rw, int np, int cs,
+                                                      int cin, int cout, float* gw, float* gb) {
+  const int total = cout * (9 * cs + 1);
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
+    const int o = e / (9 * cs + 1), col = e % (9 * cs + 1);
+    if (col < 9 * cs && col % cs >= cin) continue;  // padding channel
+    float s = 0.0f;
+    for (int b = 0; b < nblocks; ++b) s += partial[(int64_t)b * rw * np + o * np + col];
+    if (col == 9 * cs)
+      gb[o] = s;
+    else
+      gw[(o * 9 + col / cs) * cin + col % cs] = s;
+  }
+}
+
+struct ClassW {
+  float w[CLASSES];
+};
+constexpr int LOSS_BLOCKS = 256;
+
+__device__ __forceinline__ int label_at(const int32_t* labels, int64_t p) {
+  return min(max((int)labels[p], 0), CLASSES - 1);
+}
+
+__device__ __forceinline__ double block_sum_f64(double v, double* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// per block: sum of class weights and of weighted negative log-likelihoods
+__global__ __launch_bounds__(256) void k_loss_partial(const float* z, const int32_t* labels, int64_t P, ClassW cw,
+                                                      double* partial) {
+  __shared__ double sh[256];
+  double sw = 0.0, sl = 0.0;
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < P; p += (int64_t)gridDim.x * blockDim.x) {
+    const float* zp = z + p * ZC;
+    const int t = label_at(labels, p);
+    float m = zp[0];
+    for (int c = 1; c < CLASSES; ++c) m = fmaxf(m, zp[c]);
+    double se = 0.0;
+    for (int c = 0; c < CLASSES; ++c) se += exp((double)zp[c] - (double)m);
+    const double wt = cw.w[t];
+    sw += wt;
+    sl += wt * ((double)m + log(se) - (double)zp[t]);
+  }
+  sw = block_sum_f64(sw, sh);
+  sl = block_sum_f64(sl, sh);
+  if (threadIdx.x == 0) {
+    partial[2 * blockIdx.x] = sw;
+    partial[2 * blockIdx.x + 1] = sl;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_loss_final(const double* partial, int nblocks, double* out) {
+  __shared__ double sh[256];
+  double sw = 0.0, sl = 0.0;
+  for (int b = threadIdx.x; b < nblocks; b += 256) {
+    sw += partial[2 * b];
+    sl += partial[2 * b + 1];
+  }
+  sw = block_sum_f64(sw, sh);
+  sl = block_sum_f64(sl, sh);
+  if (threadIdx.x == 0) {
+    out[0] = sw;
+    out[1] = sw > 0.0 ? sl / sw : 0.0;
+  }
+}
+
+// dz = (softmax(z) - onehot) w_t / sum w, bf16, channels 6 and 7 zero
+__global__ __launch_bounds__(256) void k_dz(const float* z, const int32_t* labels, int64_t P, ClassW cw,
+                                            const double* out, uint16_t* dz) {
+  const double sw = out[0];
+  const float inv = sw > 0.0 ? (float)(1.0 / sw) : 0.0f;
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < P; p += (int64_t)gridDim.x * blockDim.x) {
+    const float* zp = z + p * ZC;
+    const int t = label_at(labels, p);
+    float m = zp[0];
+    for (int c = 1; c < CLASSES; ++c) m = fmaxf(m, zp[c]);
+    float e[CLASSES], se = 0.0f;
+    for (int c = 0; c < CLASSES; ++c) {
+      e[c] = expf(zp[c] - m);
+      se += e[c];
+    }
+    const float scale = cw.w[t] * inv;
+    u16x8 o = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int c = 0; c < CLASSES; ++c) o[c] = f2bf((e[c] / se - (c == t ? 1.0f : 0.0f)) * scale);
+    *reinterpret_cast<u16x8*>(dz + p * ZC) = o;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_adam(float* theta, float* m, float* v, const float* g, int P, float lr,
+                                              float b1, float b2, float eps, float c1, float c2) {
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < P; k += gridDim.x * blockDim.x) {
+    const float gk = g[k];
+    const float mk = b1 * m[k] + (1.0f - b1) * gk;
+    const float vk = b2 * v[k] + (1.0f - b2) * gk * gk;
+    m[k] = mk;
+    v[k] = vk;
+    theta[k] -= lr * (mk * c1) / (sqrtf(vk * c2) + eps);
+  }
+}
+
+int conv_blocks(int64_t P) {
+  const int64_t tiles = (P + 15) / 16, waves = 4;  // 4 waves per block
+  return (int)std::min<int64_t>(std::max<int64_t>((tiles + waves - 1) / waves, 1), 2048);
+}
+
+}  // namespace
+
+hipError_t prep_weights(const Net& net, hipStream_t s) {
+  Prep P;
+  P.theta = net.theta;
+  const Offsets o = offsets();
+  for (int l = 0; l < LAYERS; ++l) {
+    P.wf[l] = net.wf[l];
+    P.wt[l] = net.wt[l];
+    P.woff[l] = o.w[l];
+  }
+  hipLaunchKernelGGL(k_prep, dim3(16, LAYERS), dim3(256), 0, s, P);
+  return hipGetLastError();
+}
+
+hipError_t input_maps(const float* feat, int64_t P, const float* mean, const float* stdv, uint16_t* x,
+                      hipStream_t s) {
+  Norm nm;
+  for (int c = 0; c < FEAT; ++c) {
+    nm.mean[c] = mean[c];
+    nm.inv_std[c] = 1.0f / stdv[c];
+  }
+  const int blocks = (int)std::min<int64_t>((P + 255) / 256 + 1, 4096);
+  hipLaunchKernelGGL(k_input, dim3(blocks), dim3(256), 0, s, feat, P, nm, x);
+  return hipGetLastError();
+}
+
+hipError_t conv_forward(int l, const Net& net, const uint16_t* x, int n, int h, int w, void* y, hipStream_t s) {
+  const Offsets o = offsets();
+  const float* bias = net.theta + o.b[l];
+  const int blocks = conv_blocks((int64_t)n * h * w);
+  switch (l) {
+    case 0:
+      hipLaunchKernelGGL((k_conv<XC, HID, HID, MODE_HIDDEN>), dim3(blocks), dim3(256), 0, s, net.wf[0], bias, HID, x,
+                         nullptr, n, h, w, y);
+      break;
+    case 1:
+    case 2:
+      hipLaunchKernelGGL((k_conv<HID, HID, HID, MODE_HIDDEN>), dim3(blocks), dim3(256), 0, s, net.wf[l], bias, HID,
+                         x, nullptr, n, h, w, y);
+      break;
+    default:
+      hipLaunchKernelGGL((k_conv<HID, 16, ZC, MODE_LOGITS>), dim3(blocks), dim3(256), 0, s, net.wf[3], bias, CLASSES,
+                         x, nullptr, n, h, w, y);
+  }
+  return hipGetLastError();
+}
+
+hipError_t conv_input_grad(int l, const Net& net, const uint16_t* dy, const uint16_t* act, int n, int h, int w,
+                           uint16_t* dx, hipStream_t s) {
+  const int blocks = conv_blocks((int64_t)n * h * w);
+  if (l == 3)
+    hipLaunchKernelGGL((k_conv<ZC, HID, HID, MODE_MASK>), dim3(blocks), dim3(256), 0, s, net.wt[3], nullptr, 0, dy,
+                       act, n, h, w, dx);
+  else
+    hipLaunchKernelGGL((k_conv<HID, HID, HID, MODE_MASK>), dim3(blocks), dim3(256), 0, s, net.wt[l], nullptr, 0, dy,
+                       act, n, h, w, dx);
+  return hipGetLastError();
+}
+
+size_t wgrad_partial_floats() { return (size_t)WG_BLOCKS * WG_MAX_FLOATS; }
+
+hipError_t conv_weight_grad(int l, const Net& net, const uint16_t* dy, const uint16_t* x, int n, int h, int w,
+                            float* partial, hipStream_t s) {
+  const int64_t P = (int64_t)n * h * w;
+  const int blocks = (int)std::min<int64_t>(std::max<int64_t>((P + 31) / 32, 1), WG_BLOCKS);
+  const Offsets o = offsets();
+  int cs, rw;
+  if (l == 0) {
+    hipLaunchKernelGGL((k_wgrad<XC, HID, HID>), dim3(blocks), dim3(256), 0, s, dy, x, n, h, w, partial);
+    cs = XC;
+    rw = HID;
+  } else if (l < 3) {
+    hipLaunchKernelGGL((k_wgrad<HID, HID, HID>), dim3(blocks), dim3(256), 0, s, dy, x, n, h, w, partial);
+    cs = HID;
+    rw = HID;
+  } else {
+    hipLaunchKernelGGL((k_wgrad<HID, ZC, 16>), dim3(blocks), dim3(256), 0, s, dy, x, n, h, w, partial);
+    cs = HID;
+    rw = 16;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int np = (9 * cs + 1 + 15) / 16 * 16;
+  hipLaunchKernelGGL(k_wgrad_reduce, dim3(64), dim3(256), 0, s, partial, blocks, rw, np, cs, CIN[l], COUT[l],
+                     net.grad + o.w[l], net.grad + o.b[l]);
+  return hipGetLastError();
+}
+
+size_t loss_partial_doubles() { return 2 * LOSS_BLOCKS; }
+
+hipError_t loss_and_dz(const float* z, const int32_t* labels, int64_t P, const float* class_w, double* partial,
+                       double* out, uint16_t* dz, hipStream_t s) {
+  ClassW cw;
+  for (int c = 0; c < CLASSES; ++c) cw.w[c] = class_w[c];
+  hipLaunchKernelGGL(k_loss_partial, dim3(LOSS_BLOCKS), dim3(256), 0, s, z, labels, P, cw, partial);
+  hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, s, partial, LOSS_BLOCKS, out);
+  const int blocks = (int)std::min<int64_t>((P + 255) / 256 + 1, 4096);
+  hipLaunchKernelGGL(k_dz, dim3(blocks), dim3(256), 0, s, z, labels, P, cw, out, dz);
+  return hipGetLastError();
+}
+
+hipError_t adam(Net& net, int P, float lr, float beta1, float beta2, float eps, hipStream_t s) {
+  net.step += 1;
+  const float c1 = (float)(1.0 / (1.0 - std::pow((double)beta1, (double)net.step)));
+  const float c2 = (float)(1.0 / (1.0 - std::pow((double)beta2, (double)net.step)));
+  hipLaunchKernelGGL(k_adam, dim3((P + 255) / 256), dim3(256), 0, s, net.theta, net.m, net.v, net.grad, P, lr, beta1,
+                     beta2, eps, c1, c2);
+  net.dirty = true;
+  return hipGetLastError();
+}
+
+}  // namespace cnn
+}  // namespace air

@@ -712,16 +712,30 @@ __global__ __launch_bounds__(64 * MAX_SEG) void k_march_queue(MarchArgs A, int L
     const unsigned long long e = qs + (unsigned long long)sp.tile() * WAVE + lane;
     const bool live = e < qe;
     uint32_t v = 0, lev = 0, key = 0, i = 0, j = 0;
+    bool trace = live;
     if (live) {
       qdecode(A.w.queue[e], v, lev, key);
       coords_of(key, (int)lev, A.img.N0, i, j);
+      // learned mode: a speculatively traced node already holds its values
+      if (A.w.skip_spec) trace = !(A.w.state[(int64_t)v * SV + A.img.off[lev] + key] & ST_SPEC);
+    }
+    if (!__ballot(trace)) {  // the same 64 entries in every wave: uniform per block
+      if (threadIdx.x < WAVE && live) {
+        const int64_t pos = (int64_t)v * SV + A.img.off[lev] + key;
+        A.w.state[pos] = A.w.state[pos] | ST_TRACED;
+      }
+      continue;
     }
     RayRes<NB> r;
     if (range)
-      trace_tile<NB, FK, GK, true>(A, T, live, v, (int)lev, i, j, sh, r);
+      trace_tile<NB, FK, GK, true>(A, T, trace, v, (int)lev, i, j, sh, r);
     else
-      trace_tile<NB, FK, GK, false>(A, T, live, v, (int)lev, i, j, sh, r);
-    if (threadIdx.x < WAVE && live) {
+      trace_tile<NB, FK, GK, false>(A, T, trace, v, (int)lev, i, j, sh, r);
+    if (threadIdx.x < WAVE && live && !trace) {
+      const int64_t pos = (int64_t)v * SV + A.img.off[lev] + key;
+      A.w.state[pos] = A.w.state[pos] | ST_TRACED;
+    }
+    if (threadIdx.x < WAVE && trace) {
       const int64_t pos = (int64_t)v * SV + A.img.off[lev] + key;
 #pragma unroll
       for (int b = 0; b < NB; ++b)
@@ -740,6 +754,47 @@ __global__ __launch_bounds__(64 * MAX_SEG) void k_march_queue(MarchArgs A, int L
     }
   }
   block_stats(ctr, hit, vis);
+}
+
+// Speculative march of the learned proposal: the entries of spec, of any
+// level; values land in the level maps as in the level march, marked
+// ST_SPEC (not ST_TRACED: the refinement test of a level sees a node only
+// once the level loop has reached it).
+template <int NB, int FK, int GK>
+__global__ __launch_bounds__(64 * MAX_SEG) void k_march_spec(MarchArgs A, const uint64_t* spec,
+                                                             const unsigned long long* count) {
+  __shared__ TileLds<NB> T;
+  const unsigned long long n = *count;
+  const int lane = threadIdx.x & (WAVE - 1), sh = A.g.seg_shift;
+  const int64_t SV = A.img.S, VS = (int64_t)A.img.V * SV;
+  unsigned long long hit = 0, vis = 0;
+  const long long ntiles = (long long)((n + WAVE - 1) / WAVE);
+  Split sp = xcd_split(ntiles);
+  const long long kend = xcd_items(ntiles);
+  for (; sp.k < kend; sp.k += sp.step) {
+    if (!sp.ok()) continue;
+    const unsigned long long e = (unsigned long long)sp.tile() * WAVE + lane;
+    const bool live = e < n;
+    uint32_t v = 0, lev = 0, key = 0, i = 0, j = 0;
+    if (live) {
+      qdecode(spec[e], v, lev, key);
+      coords_of(key, (int)lev, A.img.N0, i, j);
+    }
+    RayRes<NB> r;
+    trace_tile<NB, FK, GK, false>(A, T, live, v, (int)lev, i, j, sh, r);
+    if (threadIdx.x < WAVE && live) {
+      const int64_t pos = (int64_t)v * SV + A.img.off[lev] + key;
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+        if (b < A.f.nb) A.w.valI[b * VS + pos] = r.I[b];
+      A.w.valN[pos] = r.N;
+      A.w.visits[pos] = r.nvis;
+      A.w.state[pos] = A.w.state[pos] | ST_SPEC;
+      hit += r.hit;
+      vis += (unsigned long long)r.nvis;
+    }
+  }
+  block_stats(A.w.ctr, hit, vis);
 }
 
 // fixed raster: entry e = view * R^2 + key, key in forest-Morton order
@@ -831,6 +886,13 @@ __global__ __launch_bounds__(64 * MAX_SEG) void k_trace_pixels(MarchArgs A, int6
     else                                                                         \
       AIR_DISPATCH_NB((A_).f.nb, (A_).f.kind, AIR_GRID_UNIFORM, __VA_ARGS__);     \
   } while (0)
+
+hipError_t launch_march_spec(const MarchArgs& a, const uint64_t* spec, const unsigned long long* count,
+                             int grid_blocks, hipStream_t s) {
+  const dim3 blk(WAVE << a.g.seg_shift);
+  AIR_DISPATCH(a, hipLaunchKernelGGL((k_march_spec<NB_, FK_, GK_>), dim3(grid_blocks), blk, 0, s, a, spec, count));
+  return hipGetLastError();
+}
 
 hipError_t launch_pack_amr(const Geo& g, const Fld& f, void* packed, hipStream_t s) {
   Fld F = f;

@@ -234,17 +234,25 @@ __global__ __launch_bounds__(256) void k_count(MarchArgs A, unsigned long long* 
                                                int64_t n_chunks) {
   __shared__ unsigned sh[VS_N][4];
   const int64_t c = blockIdx.x;
-  unsigned cnt[VS_N] = {0, 0, 0, 0, 0};
+  unsigned cnt[VS_N];
+#pragma unroll
+  for (int q = 0; q < VS_N; ++q) cnt[q] = 0;
+  const bool above0 = chunk_pos(A.img, c).L > 0;
   for (int k = 0; k < CHUNK / 256; ++k) {
     const int64_t p = c * CHUNK + k * 256 + threadIdx.x;
     const uint8_t s = A.w.state[p];
+    const bool spec = (s & ST_SPEC) != 0;
     if (s & AIR_NODE_EXIST) {
       ++cnt[VS_NODES];
       cnt[VS_LEAVES] += !(s & AIR_NODE_REFINED);
       cnt[VS_TESTED] += (s & AIR_NODE_EVALUATED) != 0;
       cnt[VS_FLAGGED] += (s & AIR_NODE_FLAGGED) != 0;
       cnt[VS_BALANCE] += (s & AIR_NODE_BALANCE) != 0;
+      cnt[VS_MISSING] += above0 && !spec;
+    } else {
+      cnt[VS_WASTED] += spec;
     }
+    cnt[VS_SPEC] += spec;
   }
   const int w = threadIdx.x / WAVE;
 #pragma unroll
@@ -360,7 +368,7 @@ __global__ __launch_bounds__(256) void k_write_tree(MarchArgs A, const unsigned 
     if (T.parent) T.parent[id] = L == 0 ? -1 : (int32_t)(id_map[vb + A.img.off[L - 1] + (key >> 2)] - base);
     if (T.first_child)
       T.first_child[id] = (s & AIR_NODE_REFINED) ? (int32_t)(id_map[vb + A.img.off[L + 1] + 4ll * key] - base) : -1;
-    if (T.state) T.state[id] = s & (uint8_t)~ST_TRACED;
+    if (T.state) T.state[id] = s & (uint8_t)~(ST_TRACED | ST_SPEC);
     if (T.I)
       for (int b = 0; b < nb; ++b) T.I[b * T.capacity + id] = A.w.valI[b * VS + p];
     if (T.N) T.N[id] = A.w.valN[p];

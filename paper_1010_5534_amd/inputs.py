@@ -433,3 +433,20 @@ def ring(base_blocks: int = 4, bs: int = 8, max_level: int = 4, beta: float = 2.
 def ring_view() -> View:
     """Face-on: looking along +x, up = +z, so (u, v) = (y, z) (Fig. 1 note)."""
     return View((1.0, 0.0, 0.0), (0.0, 0.0, 1.0), (0.0, 0.0, 0.0), 10.0)
+
+
+# ------------------------------------------------- depth-proposal network
+CNN_CHANNELS = (4, 32, 32, 32, 6)
+
+
+def cnn_init(seed: int) -> np.ndarray:
+    """Seeded He-normal initial parameters of the depth-proposal network,
+    float32, laid out per layer as weights [cout][3][3][cin] then bias
+    [cout] (biases zero)."""
+    rng = np.random.default_rng(50_000 + seed)
+    parts = []
+    for l in range(4):
+        cin, cout = CNN_CHANNELS[l], CNN_CHANNELS[l + 1]
+        parts.append(rng.normal(size=cout * 9 * cin) * math.sqrt(2.0 / (9 * cin)))
+        parts.append(np.zeros(cout))
+    return np.concatenate(parts).astype(np.float32)
