@@ -71,6 +71,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-fixed", action="store_true")
+    ap.add_argument("--skip-learned", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the timed region, one 256 MiB device copy whose counters calibrate HBM bytes")
     args = ap.parse_args()
@@ -91,6 +92,7 @@ def main():
     ctx = air.Context(0)
     scene = ctx.prepare(air.upload(g, f))
     prm = air.params(N0, LMAX, XI_CRIT)
+    prm_timed = air.params(N0, LMAX, XI_CRIT, timing=True)
     torch.cuda.synchronize()
 
     def plain():
@@ -107,7 +109,7 @@ def main():
         dev_ms, march_ms, stats = 0.0, 0.0, None
         for _ in range(steps):
             out = fn()
-            stats = out[-1]
+            stats = out[3] if len(out) > 3 else out[-1]
             dev_ms += stats["ms_total"]
             march_ms += stats["ms_march"]
         torch.cuda.synchronize()
@@ -115,9 +117,13 @@ def main():
         return out, wall, dev_ms / steps, march_ms / steps, stats
 
     log("plain AIR")
-    out_p, wall_p, dev_p, march_p, st_p = timed(plain, args.steps, args.warmup)
+    out_p, wall_p, dev_p, _, st_p = timed(plain, args.steps, args.warmup)
     trees, img_p, flux_p, _ = out_p
+    img_p = img_p.clone()
     rays_p = st_p["rays"]
+    # per-launch march time: a separate pass with an event around every
+    # launch (the events lengthen the call, so the throughput above has none)
+    _, _, _, march_p, st_t = timed(lambda: ctx.render(scene, views, prm_timed, reuse=True), max(3, args.steps // 3), 1)
     res = dict(metric=METRIC, value=rays_p / wall_p, unit="rays/s", n_gpus=1, steps=args.steps,
                warmup=args.warmup, ms_per_step=wall_p * 1e3, higher_is_better=True, scaling="weak",
                vs_baseline=None, dtype="f32", data="synthetic",
@@ -127,15 +133,16 @@ def main():
     per_level = st_p["rays_per_level"][:LMAX + 1]
     res["plain_air"] = dict(rays=rays_p, rays_per_level=per_level, hits=st_p["hits"], visits=st_p["visits"],
                             leaves=st_p["leaves"], flagged=st_p["flagged"], balance=st_p["balance"],
-                            ms_wall=wall_p * 1e3, ms_device=dev_p, ms_march=march_p,
-                            per_image_ms=wall_p * 1e3 / len(views), rays_per_s_device=rays_p / (dev_p * 1e-3))
+                            ms_wall=wall_p * 1e3, ms_device=dev_p, ms_march_timed_pass=march_p,
+                            ms_test_timed_pass=st_t["ms_test"], per_image_ms=wall_p * 1e3 / len(views),
+                            rays_per_s_device=rays_p / (dev_p * 1e-3))
     bytes_p = st_p["visits"] * BYTES_PER_VISIT + rays_p * BYTES_PER_RAY_QUEUE
     achieved = bytes_p / (march_p * 1e-3) / 1e9
     res["roofline"] = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
                            frac=achieved / HBM_PEAK_GBS, traffic=traffic_from_profile("k_march_queue"),
-                           kernel="k_march_queue", launches=st_p["march_launches"],
-                           avg_launch_ms=march_p / st_p["march_launches"],
-                           bytes_per_launch=bytes_p / st_p["march_launches"],
+                           kernel="k_march_queue", launches=st_t["march_launches"],
+                           avg_launch_ms=march_p / st_t["march_launches"],
+                           bytes_per_launch=bytes_p / st_t["march_launches"],
                            bytes_rule=f"{BYTES_PER_VISIT} B/visit + {BYTES_PER_RAY_QUEUE} B/ray")
 
     if not args.skip_fixed:
@@ -153,7 +160,33 @@ def main():
         res["air_vs_fixed"] = dict(speedup=wall_f / wall_p, ray_reduction=rays_f / rays_p,
                                    flux_rel_err=[float((flux_f[k][0] - flux_p[k][0]) / flux_f[k][0])
                                                  for k in range(len(views))])
+        del out_f, img_f
+
     res["learned_air"] = None
+    wpath = os.path.join(ROOT, "paper_1010_5534_amd", "weights", "depth_cnn.npz")
+    if os.path.exists(wpath) and not args.skip_learned:
+        log("learned AIR")
+        wz = np.load(wpath)
+        net = air.Network(ctx, wz["params"], wz["mean"], wz["scale"])
+        c_ray, c_sweep = float(wz["c_ray"]), float(wz["c_sweep"])
+
+        def learned():
+            return ctx.render_learned(scene, views, prm, net, c_ray, c_sweep, reuse=True)
+
+        out_l, wall_l, dev_l, _, st_l = timed(learned, args.steps, args.warmup)
+        ls = out_l[4]
+        same = bool(torch.equal(out_l[1].view(torch.int32), img_p.view(torch.int32))
+                    and np.array_equal(out_l[2], flux_p) and st_l["rays"] == rays_p)
+        tl = ctx.render_learned(scene, views, prm_timed, net, c_ray, c_sweep, reuse=True)
+        res["learned_air"] = dict(rays=st_l["rays"], ms_wall=wall_l * 1e3, ms_device=dev_l,
+                                  per_image_ms=wall_l * 1e3 / len(views), rays_per_s=st_l["rays"] / wall_l,
+                                  speedup_vs_plain=wall_p / wall_l, equal_to_plain=same,
+                                  spec_rays=ls["spec_rays"], wasted=ls["wasted"], missing=ls["missing"],
+                                  depth_hist=ls["depth_hist"], c_ray=c_ray, c_sweep=c_sweep,
+                                  ms_features_timed_pass=tl[4]["ms_features"], ms_spec_timed_pass=tl[4]["ms_spec"],
+                                  network="paper_1010_5534_amd/weights/depth_cnn.npz (trained on seeds 1..2000; "
+                                          "this workload's seed 0 is held out)")
+        net.close()
 
     if args.copy_probe:
         src = torch.empty(64 << 20, dtype=torch.float32, device="cuda")

@@ -110,6 +110,11 @@ typedef struct {
   double width;     /* image side length in grid units */
 } air_view;
 
+/* air_params.flags: time every march and test launch with HIP events
+ * (air_stats.ms_march / ms_test; otherwise they are 0).  The events sit
+ * between the kernels on the stream and lengthen the call a little. */
+#define AIR_FLAG_TIMING 1u
+
 /* Refinement parameters (sections 2 and 3). */
 typedef struct {
   int32_t coarse_n;  /* N0: base image is N0 x N0 (step i) */
@@ -117,7 +122,7 @@ typedef struct {
   float xi_crit_I;   /* refine iff xi(I) >= xi_crit_I; > 1 disables (xi <= 1) */
   float xi_crit_N;   /* same for the column density N; several variables are OR-ed */
   float band_weight[AIR_MAX_BANDS]; /* the tested intensity is sum_b w_b I_b */
-  uint32_t flags;    /* reserved, must be 0 */
+  uint32_t flags;    /* AIR_FLAG_* bits; others must be 0 */
 } air_params;
 
 /* Pixel quadtree in canonical order: by level, then coarse pixel (row-major),
@@ -155,8 +160,8 @@ typedef struct {
   int32_t depth;                         /* deepest level reached */
   int32_t march_launches;                /* march kernel launches in the call */
   double ms_total;  /* device time of the call, first kernel to last (HIP events on the stream) */
-  double ms_march;  /* device time of the march kernels, summed over levels */
-  double ms_test;   /* device time of the test / 2:1 closure / compaction kernels */
+  double ms_march;  /* with AIR_FLAG_TIMING: device time of the march kernels, summed over launches */
+  double ms_test;   /* with AIR_FLAG_TIMING: device time of the test / 2:1 closure / compaction kernels */
 } air_stats;
 
 typedef struct air_ctx air_ctx;
@@ -213,6 +218,20 @@ const char* air_last_error(const air_ctx* ctx);
 air_status air_render(air_ctx* ctx, const air_grid* grid, const air_field* field, const air_view* views,
                       int32_t n_views, const air_params* params, air_tree* trees, float* images,
                       double* flux, air_stats* stats, void* stream);
+
+/*
+ * air_render for many views and bands in one captured launch sequence: the
+ * first call for a workload shape times the level loop under a few launch
+ * shapes (march waves per CU, test blocks per CU; results do not depend on
+ * them) and keeps the fastest; the whole device sequence of the call (level
+ * loop, canonical tree, raster, flux) is captured once into a HIP graph and
+ * replayed while every launch argument stays the same (same buffers and
+ * sizes; the views' contents may change).  Arguments, outputs and errors as
+ * air_render, bit for bit equal to it; AIR_FLAG_TIMING is ignored.
+ */
+air_status air_render_batch(air_ctx* ctx, const air_grid* grid, const air_field* field, const air_view* views,
+                            int32_t n_views, const air_params* params, air_tree* trees, float* images,
+                            double* flux, air_stats* stats, void* stream);
 
 /*
  * Fixed-resolution baseline (section 3, Table 1 "Fixed"): every pixel of the
@@ -318,8 +337,8 @@ typedef struct {
   int64_t wasted;                       /* speculative rays that are no tree node */
   int64_t missing;                      /* tree nodes below level 0 the level loop traced */
   int64_t depth_hist[AIR_MAX_LEVELS];   /* coarse pixels per chosen depth */
-  double ms_features; /* device time: feature maps + network + depth choice + work list */
-  double ms_spec;     /* device time of the speculative march */
+  double ms_features; /* with AIR_FLAG_TIMING: feature maps + network + depth choice + work list */
+  double ms_spec;     /* with AIR_FLAG_TIMING: the speculative march */
 } air_learn_stats;
 
 /*

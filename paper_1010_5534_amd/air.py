@@ -22,7 +22,7 @@ NODE_EXIST, NODE_TESTED, NODE_FLAGGED, NODE_BALANCE, NODE_REFINED, NODE_EVALUATE
 EXPORTS = ("air_create", "air_destroy", "air_last_error", "air_render", "air_render_fixed", "air_trace_pixels",
            "air_field_packed_bytes", "air_field_pack", "air_cnn_create", "air_cnn_destroy", "air_cnn_set",
            "air_cnn_get", "air_features", "air_cnn_forward", "air_cnn_loss_grad", "air_cnn_adam", "air_tree_depth",
-           "air_render_learned")
+           "air_render_learned", "air_render_batch")
 CNN_FEATURES, CNN_CLASSES, CNN_PARAMS = 4, 6, 21414
 
 
@@ -95,6 +95,8 @@ def lib():
         L.air_last_error.restype = C.c_char_p
         L.air_render.argtypes = [vp, vp, vp, vp, C.c_int32, vp, vp, vp, vp, vp, vp]
         L.air_render.restype = C.c_int32
+        L.air_render_batch.argtypes = [vp, vp, vp, vp, C.c_int32, vp, vp, vp, vp, vp, vp]
+        L.air_render_batch.restype = C.c_int32
         L.air_render_fixed.argtypes = [vp, vp, vp, vp, C.c_int32, C.c_int32, C.c_int32, vp, vp, vp, vp]
         L.air_render_fixed.restype = C.c_int32
         L.air_trace_pixels.argtypes = [vp, vp, vp, vp, C.c_int32, C.c_int64, vp, vp, vp, vp, vp, vp, vp]
@@ -175,6 +177,29 @@ def upload(grid, field, device="cuda") -> DeviceScene:
     return DeviceScene(g, f, keep, field.n_bands)
 
 
+def scene_from_tensors(n: int, rho, temp, bands) -> DeviceScene:
+    """A uniform n^3 unit-box (rho, T) scene from float32 device tensors
+    (z slowest, x fastest) and host band parameters [n_bands][3]."""
+    torch = _torch()
+    rho = rho.contiguous().to(torch.float32)
+    temp = temp.contiguous().to(torch.float32)
+    bands = np.asarray(bands, dtype=np.float64).reshape(-1, 3)
+    g = air_grid()
+    g.kind = GRID_UNIFORM
+    g.n[:] = [n, n, n]
+    g.lo[:] = [0.0, 0.0, 0.0]
+    g.hi[:] = [1.0, 1.0, 1.0]
+    f = air_field()
+    f.kind = FIELD_RHO_T
+    f.n_bands = len(bands)
+    f.rho = rho.data_ptr()
+    f.temp = temp.data_ptr()
+    for b in range(len(bands)):
+        for k in range(3):
+            f.band[b][k] = float(bands[b][k])
+    return DeviceScene(g, f, [rho, temp], len(bands))
+
+
 def _views(views) -> C.Array:
     arr = (air_view * len(views))()
     for k, v in enumerate(views):
@@ -185,7 +210,10 @@ def _views(views) -> C.Array:
     return arr
 
 
-def params(coarse_n, max_level, xi_crit_I=0.5, xi_crit_N=2.0, band_weight=None) -> air_params:
+FLAG_TIMING = 1
+
+
+def params(coarse_n, max_level, xi_crit_I=0.5, xi_crit_N=2.0, band_weight=None, timing=False) -> air_params:
     p = air_params()
     p.coarse_n = coarse_n
     p.max_level = max_level
@@ -193,7 +221,7 @@ def params(coarse_n, max_level, xi_crit_I=0.5, xi_crit_N=2.0, band_weight=None) 
     p.xi_crit_N = xi_crit_N
     w = [1.0] * MAX_BANDS if band_weight is None else list(band_weight) + [0.0] * (MAX_BANDS - len(band_weight))
     p.band_weight[:] = [float(x) for x in w[:MAX_BANDS]]
-    p.flags = 0
+    p.flags = FLAG_TIMING if timing else 0
     return p
 
 
@@ -296,6 +324,13 @@ class Context:
         same shapes (the next call overwrites them)."""
         return self._render(scene, views, prm, want_tree, want_image, want_flux, capacity, reuse, None, None)
 
+    def render_batch(self, scene: DeviceScene, views: Sequence, prm: air_params, want_tree=True, want_image=True,
+                     want_flux=True, capacity: Optional[int] = None, reuse: bool = True):
+        """air_render_batch: the same outputs as render(), from a captured,
+        autotuned launch sequence (reuse keeps the output buffers, so the
+        captured sequence can be replayed)."""
+        return self._render(scene, views, prm, want_tree, want_image, want_flux, capacity, reuse, "batch", None)
+
     def render_learned(self, scene: DeviceScene, views: Sequence, prm: air_params, net: "Network",
                        c_ray: float, c_sweep: float, max_depth: int = 5, want_tree=True, want_image=True,
                        want_flux=True, capacity: Optional[int] = None, reuse: bool = False):
@@ -342,9 +377,10 @@ class Context:
                     keep.append(t)
             targs = (C.addressof(trees) if want_tree else None, images.data_ptr() if want_image else None,
                      flux.ctypes.data if want_flux else None, C.addressof(st))
-            if learned is None:
-                rc = lib().air_render(self._p, C.addressof(scene.grid), C.addressof(scene.field), C.addressof(vs),
-                                      V, C.addressof(prm), *targs, self._stream())
+            if learned is None or learned == "batch":
+                fn = lib().air_render if learned is None else lib().air_render_batch
+                rc = fn(self._p, C.addressof(scene.grid), C.addressof(scene.field), C.addressof(vs),
+                        V, C.addressof(prm), *targs, self._stream())
             else:
                 rc = lib().air_render_learned(self._p, C.addressof(scene.grid), C.addressof(scene.field),
                                               C.addressof(vs), V, C.addressof(prm), learned[0]._p,

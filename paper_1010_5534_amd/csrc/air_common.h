@@ -179,6 +179,12 @@ hipError_t launch_march_spec(const MarchArgs& a, const uint64_t* spec, const uns
 struct LearnW {
   float w[MAXB];
 };
+// launch shapes that do not change results: waves per CU of the march grids,
+// blocks per CU of the refinement test
+struct Tune {
+  int march_waves_per_cu = 16;
+  int refine_blocks_per_cu = 4;
+};
 hipError_t launch_features(const MarchArgs& a, const LearnW& w, float* feat, hipStream_t s);
 hipError_t launch_decide(const float* logits, int64_t total, int dmax, float c_ray, float c_sweep, uint8_t* depth,
                          unsigned long long* counts, hipStream_t s);

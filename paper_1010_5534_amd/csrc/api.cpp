@@ -11,6 +11,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <map>
 #include <vector>
 
 #include "air_common.h"
@@ -45,6 +46,16 @@ struct air_ctx {
   size_t host_flux_n = 0;
   void* stage = nullptr;  // pinned staging for small uploads
   size_t stage_n = 0;
+  void* stage2 = nullptr;  // pinned staging of the tree output table
+  size_t stage2_n = 0;
+  // air_render_batch: the captured launch sequence of the last call and the
+  // launch shapes chosen per workload shape
+  std::string graph_key;
+  hipStream_t cap_stream = nullptr;  // the graph is captured and replayed here
+  hipEvent_t cap_in = nullptr, cap_out = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  hipGraph_t graph = nullptr;
+  std::map<std::string, air::Tune> tuned;
   // timing events: [0] start, [1] end, then a pair around every march and
   // every test launch
   static constexpr int EV_FEAT0 = 2 + 4 * AIR_MAX_LEVELS, EV_SPEC0 = EV_FEAT0 + 1, EV_SPEC1 = EV_FEAT0 + 2;
@@ -322,8 +333,8 @@ air_status upload_views(air_ctx* c, const air_view* views, int V, hipStream_t s,
 }
 
 // a multiple of 8 blocks (one share per XCD), about 16 waves per CU
-int march_blocks(const air_ctx* c, int seg_shift) {
-  const int per_cu = std::max(1, 16 >> seg_shift);
+int march_blocks(const air_ctx* c, int seg_shift, int waves_per_cu = 16) {
+  const int per_cu = std::max(1, waves_per_cu >> seg_shift);
   return std::max(8, (c->num_cus * per_cu + 7) / 8 * 8);
 }
 
@@ -419,25 +430,30 @@ air_status check_render_args(air_ctx* c, const air_grid* grid, const air_field* 
     return fail(c, AIR_EINVAL, "coarse_n^2 * 4^max_level exceeds 2^32 pixels per view");
   if (!std::isfinite(prm->xi_crit_I) || !std::isfinite(prm->xi_crit_N) || prm->xi_crit_I < 0 || prm->xi_crit_N < 0)
     return fail(c, AIR_EINVAL, "xi_crit must be finite and >= 0");
-  if (prm->flags != 0) return fail(c, AIR_EINVAL, "params.flags must be 0");
+  if (prm->flags & ~AIR_FLAG_TIMING) return fail(c, AIR_EINVAL, "params.flags has unknown bits");
   return AIR_OK;
 }
 
-// the learned steps after the coarse march: feature maps, network, depth
-// choice, work list, speculative march
-air_status learned_steps(air_ctx* c, const MarchArgs& A, const air_cnn* net, const air_learn_params* lp,
-                         const float* w, hipStream_t s) {
-  const int V = A.img.V, N0 = A.img.N0;
-  const int64_t total = (int64_t)V * N0 * N0, VS = (int64_t)V * A.img.S;
+// device buffers of the learned steps
+air_status ensure_learned(air_ctx* c, const MarchArgs& A) {
+  const int64_t total = (int64_t)A.img.V * A.img.N0 * A.img.N0, VS = (int64_t)A.img.V * A.img.S;
   air_status st;
   if ((st = ensure(c, c->feat, 16 * total))) return st;
   if ((st = ensure_cnn_work(c, total, false))) return st;
   if ((st = ensure(c, c->depth8, total))) return st;
   if ((st = ensure(c, c->scount, 8 * (total + 1)))) return st;
-  if ((st = ensure(c, c->spec, 8 * VS))) return st;
+  return ensure(c, c->spec, 8 * VS);
+}
+
+// the learned steps after the coarse march: feature maps, network, depth
+// choice, work list, speculative march
+air_status learned_steps(air_ctx* c, const MarchArgs& A, const air_cnn* net, const air_learn_params* lp,
+                         const float* w, bool timing, const Tune& tune, hipStream_t s) {
+  const int V = A.img.V, N0 = A.img.N0;
+  const int64_t total = (int64_t)V * N0 * N0;
   LearnW W;
   for (int b = 0; b < MAXB; ++b) W.w[b] = w[b];
-  HIPCHK(c, hipEventRecord(c->ev[air_ctx::EV_FEAT0], s));
+  if (timing) HIPCHK(c, hipEventRecord(c->ev[air_ctx::EV_FEAT0], s));
   HIPCHK(c, launch_features(A, W, (float*)c->feat.p, s));
   HIPCHK(c, cnn::input_maps((const float*)c->feat.p, total, net->net.mean, net->net.stdv, (uint16_t*)c->cx0.p, s));
   HIPCHK(c, cnn::conv_forward(0, net->net, (const uint16_t*)c->cx0.p, V, N0, N0, c->ca1.p, s));
@@ -449,16 +465,115 @@ air_status learned_steps(air_ctx* c, const MarchArgs& A, const air_cnn* net, con
   HIPCHK(c, launch_decide((const float*)c->cz.p, total, dmax, lp->c_ray, lp->c_sweep, (uint8_t*)c->depth8.p, cnt, s));
   HIPCHK(c, launch_scan(cnt, total, s));
   HIPCHK(c, launch_spec_emit((const uint8_t*)c->depth8.p, cnt, total, (int64_t)N0 * N0, (uint64_t*)c->spec.p, s));
-  HIPCHK(c, hipEventRecord(c->ev[air_ctx::EV_SPEC0], s));
-  HIPCHK(c, launch_march_spec(A, (const uint64_t*)c->spec.p, cnt + total, march_blocks(c, A.g.seg_shift), s));
-  HIPCHK(c, hipEventRecord(c->ev[air_ctx::EV_SPEC1], s));
+  if (timing) HIPCHK(c, hipEventRecord(c->ev[air_ctx::EV_SPEC0], s));
+  HIPCHK(c, launch_march_spec(A, (const uint64_t*)c->spec.p, cnt + total,
+                              march_blocks(c, A.g.seg_shift, tune.march_waves_per_cu), s));
+  if (timing) HIPCHK(c, hipEventRecord(c->ev[air_ctx::EV_SPEC1], s));
+  return AIR_OK;
+}
+
+// everything a render puts on the stream between its setup and its result
+// copies: no allocation and no host wait, so it can be captured in a graph
+struct Plan {
+  MarchArgs A;
+  int64_t n_chunks = 0;
+  float xcI = 0, xcN = 0, w[MAXB] = {};
+  const air_cnn* net = nullptr;
+  air_learn_params lp{};
+  bool trees = false, flux = false, timing = false;
+  float* images = nullptr;
+};
+
+air_status enqueue_render(air_ctx* c, const Plan& P, const Tune& tune, hipStream_t s) {
+  const MarchArgs& A = P.A;
+  const int Lm = A.img.Lmax;
+  hipEvent_t* ev = c->ev;
+  air_status st;
+  // the level loop: trace the queue of new nodes, then test, close and
+  // compact; the queue bounds live in device counters, so no host round trip
+  HIPCHK(c, launch_init(A, s));
+  for (int L = 0; L <= Lm; ++L) {
+    if (P.timing) HIPCHK(c, hipEventRecord(ev[2 + 4 * L], s));
+    HIPCHK(c, launch_march_queue(A, L, march_blocks(c, A.g.seg_shift, tune.march_waves_per_cu), s));
+    if (P.timing) HIPCHK(c, hipEventRecord(ev[3 + 4 * L], s));
+    if (P.net && L == 0) {
+      if ((st = learned_steps(c, A, P.net, &P.lp, P.w, P.timing, tune, s))) return st;
+      if (P.timing) HIPCHK(c, hipEventRecord(ev[3 + 4 * L], s));  // the test timing starts after the learned steps
+    }
+    if (L < Lm) HIPCHK(c, launch_refine(A, L, P.xcI, P.xcN, P.w, c->num_cus * tune.refine_blocks_per_cu, s));
+    if (P.timing) HIPCHK(c, hipEventRecord(ev[4 + 4 * L], s));
+  }
+  unsigned long long* chunk = (unsigned long long*)c->chunk.p;
+  HIPCHK(c, launch_count(A, chunk, (unsigned*)c->cstat.p, P.n_chunks, (unsigned long long*)c->vstat.p, s));
+  if (P.trees) {
+    HIPCHK(c, launch_scan(chunk, P.n_chunks, s));
+    HIPCHK(c, launch_emit(A, chunk, P.n_chunks, (int32_t*)c->idmap.p, s));
+    HIPCHK(c, launch_write_tree(A, chunk, (const int32_t*)c->idmap.p, (const TreeOut*)c->touts.p, s));
+  }
+  if (P.images) HIPCHK(c, launch_assemble(A, P.images, s));
+  if (P.flux) HIPCHK(c, launch_flux(A, (double*)c->partial.p, P.n_chunks, (double*)c->flux.p, s));
+  return AIR_OK;
+}
+
+// the graph key: every argument of every launch (pointers, sizes, scalars)
+std::string plan_key(const Plan& P, const Tune& t) {
+  std::string k(reinterpret_cast<const char*>(&P.A), sizeof P.A);
+  k.append(reinterpret_cast<const char*>(&P.n_chunks), sizeof P.n_chunks);
+  k.append(reinterpret_cast<const char*>(&P.xcI), sizeof(float) * (2 + MAXB));
+  k.append(reinterpret_cast<const char*>(&P.net), sizeof P.net);
+  k.append(reinterpret_cast<const char*>(&P.lp), sizeof P.lp);
+  const char flags[3] = {(char)P.trees, (char)P.flux, (char)P.timing};
+  k.append(flags, 3);
+  k.append(reinterpret_cast<const char*>(&P.images), sizeof P.images);
+  k.append(reinterpret_cast<const char*>(&t), sizeof t);
+  return k;
+}
+
+// the workload shape the launch shapes are tuned for
+std::string shape_key(const Plan& P) {
+  char b[256];
+  snprintf(b, sizeof b, "%d/%d,%d,%d/%d,%d/%d/%d/%d/%d", P.A.g.kind, P.A.g.n[0], P.A.g.n[1], P.A.g.n[2],
+           P.A.g.bs, P.A.g.max_level, P.A.img.V, P.A.img.N0, P.A.img.Lmax, P.A.f.nb);
+  return std::string(b) + (P.net ? "/learned" : "/plain");
+}
+
+// pick the launch shapes by timing the whole render once per candidate
+// (results do not depend on them), then keep the fastest for the shape
+air_status autotune(air_ctx* c, const Plan& P, hipStream_t s, Tune& best) {
+  const std::string key = shape_key(P);
+  auto it = c->tuned.find(key);
+  if (it != c->tuned.end()) {
+    best = it->second;
+    return AIR_OK;
+  }
+  float best_ms = 1e30f;
+  for (int mw : {8, 16, 32})
+    for (int rb : {2, 4, 8}) {
+      Tune t;
+      t.march_waves_per_cu = mw;
+      t.refine_blocks_per_cu = rb;
+      float ms = 0.0f;
+      for (int rep = 0; rep < 2; ++rep) {  // the second run is timed
+        HIPCHK(c, hipEventRecord(c->ev[0], s));
+        air_status st = enqueue_render(c, P, t, s);
+        if (st) return st;
+        HIPCHK(c, hipEventRecord(c->ev[1], s));
+        HIPCHK(c, hipEventSynchronize(c->ev[1]));
+        HIPCHK(c, hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
+      }
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = t;
+      }
+    }
+  c->tuned[key] = best;
   return AIR_OK;
 }
 
 air_status render_core(air_ctx* c, const air_grid* grid, const air_field* field, const air_view* views,
                        int32_t n_views, const air_params* prm, const air_cnn* net, const air_learn_params* lp,
                        air_tree* trees, float* images, double* flux, air_stats* stats, air_learn_stats* ls,
-                       void* stream) {
+                       void* stream, bool batch) {
   if (!c) return AIR_EINVAL;
   c->err.clear();
   air_status st;
@@ -470,55 +585,75 @@ air_status render_core(air_ctx* c, const air_grid* grid, const air_field* field,
   if ((st = check_blocks(c, grid, s))) return st;
   const bool learned = net != nullptr;
   const int N0 = prm->coarse_n, Lm = prm->max_level, V = n_views;
-  MarchArgs A;
-  int64_t n_chunks = 0;
-  if ((st = setup_render(c, grid, field, views, V, N0, Lm, learned, s, A, n_chunks))) return st;
+  Plan P;
+  if ((st = setup_render(c, grid, field, views, V, N0, Lm, learned, s, P.A, P.n_chunks))) return st;
+  const MarchArgs& A = P.A;
   const int nb = A.f.nb;
-  A.w.skip_spec = learned ? 1 : 0;
-  float w[MAXB];
-  for (int b = 0; b < MAXB; ++b) w[b] = b < nb ? prm->band_weight[b] : 0.0f;
-
-  // the level loop: trace the queue of new nodes, then test, close and
-  // compact; the queue bounds live in device counters, so no host round trip
-  hipEvent_t* ev = c->ev;
-  HIPCHK(c, hipEventRecord(ev[0], s));
-  HIPCHK(c, launch_init(A, s));
-  for (int L = 0; L <= Lm; ++L) {
-    HIPCHK(c, hipEventRecord(ev[2 + 4 * L], s));
-    HIPCHK(c, launch_march_queue(A, L, march_blocks(c, A.g.seg_shift), s));
-    HIPCHK(c, hipEventRecord(ev[3 + 4 * L], s));
-    if (learned && L == 0) {
-      if ((st = learned_steps(c, A, net, lp, w, s))) return st;
-      HIPCHK(c, hipEventRecord(ev[3 + 4 * L], s));  // the test timing starts after the learned steps
-    }
-    if (L < Lm) HIPCHK(c, launch_refine(A, L, prm->xi_crit_I, prm->xi_crit_N, w, c->num_cus * 4, s));
-    HIPCHK(c, hipEventRecord(ev[4 + 4 * L], s));
-  }
-  unsigned long long* chunk = (unsigned long long*)c->chunk.p;
-  unsigned long long* vstat = (unsigned long long*)c->vstat.p;
-  HIPCHK(c, launch_count(A, chunk, (unsigned*)c->cstat.p, n_chunks, vstat, s));
+  P.A.w.skip_spec = learned ? 1 : 0;
+  P.xcI = prm->xi_crit_I;
+  P.xcN = prm->xi_crit_N;
+  for (int b = 0; b < MAXB; ++b) P.w[b] = b < nb ? prm->band_weight[b] : 0.0f;
+  P.net = net;
+  if (lp) P.lp = *lp;
+  P.trees = trees != nullptr;
+  P.flux = flux != nullptr;
+  P.images = images;
+  P.timing = !batch && (prm->flags & AIR_FLAG_TIMING) != 0;
+  if (learned && (st = ensure_learned(c, A))) return st;
   if (trees) {
     if ((st = ensure(c, c->idmap, 4 * (size_t)V * A.img.S))) return st;
     if ((st = ensure(c, c->touts, sizeof(TreeOut) * V))) return st;
-    HIPCHK(c, launch_scan(chunk, n_chunks, s));
-    HIPCHK(c, launch_emit(A, chunk, n_chunks, (int32_t*)c->idmap.p, s));
-    std::vector<TreeOut> to(V);
+    if ((st = ensure_host(c, &c->stage2, &c->stage2_n, sizeof(TreeOut) * V))) return st;
+    TreeOut* to = static_cast<TreeOut*>(c->stage2);
     for (int k = 0; k < V; ++k) {
       const air_tree& t = trees[k];
       to[k] = TreeOut{t.level, t.ix, t.iy, t.parent, t.first_child, t.state, t.I, t.N, t.xi_I, t.xi_N,
                       t.visits, t.capacity};
     }
-    // the views' staging copy above must land before the buffer is reused
-    HIPCHK(c, hipStreamSynchronize(s));
-    if ((st = ensure_host(c, &c->stage, &c->stage_n, sizeof(TreeOut) * V))) return st;
-    std::memcpy(c->stage, to.data(), sizeof(TreeOut) * V);
-    HIPCHK(c, hipMemcpyAsync(c->touts.p, c->stage, sizeof(TreeOut) * V, hipMemcpyHostToDevice, s));
-    HIPCHK(c, launch_write_tree(A, chunk, (const int32_t*)c->idmap.p, (const TreeOut*)c->touts.p, s));
+    HIPCHK(c, hipMemcpyAsync(c->touts.p, c->stage2, sizeof(TreeOut) * V, hipMemcpyHostToDevice, s));
   }
-  if (images) HIPCHK(c, launch_assemble(A, images, s));
-  if (flux) HIPCHK(c, launch_flux(A, (double*)c->partial.p, n_chunks, (double*)c->flux.p, s));
-
+  hipEvent_t* ev = c->ev;
+  if (batch) {
+    Tune tune;
+    if ((st = autotune(c, P, s, tune))) return st;
+    const std::string key = plan_key(P, tune);
+    // capture and replay on the context's own stream (the caller's may be
+    // the null stream, which cannot be captured), ordered after the uploads
+    // above and before the result copies below by two events
+    hipStream_t cs = c->cap_stream;
+    if (key != c->graph_key || !c->graph_exec) {
+      if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+      if (c->graph) (void)hipGraphDestroy(c->graph);
+      c->graph_exec = nullptr;
+      c->graph = nullptr;
+      c->graph_key.clear();
+      HIPCHK(c, hipStreamSynchronize(s));  // the tuning runs are done before the sequence is captured
+      HIPCHK(c, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+      st = enqueue_render(c, P, tune, cs);
+      hipGraph_t g = nullptr;
+      const hipError_t e = hipStreamEndCapture(cs, &g);
+      if (st) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+      }
+      if (e != hipSuccess) return fail(c, AIR_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
+      HIPCHK(c, hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0));
+      c->graph = g;
+      c->graph_key = key;
+    }
+    HIPCHK(c, hipEventRecord(ev[0], s));
+    HIPCHK(c, hipEventRecord(c->cap_in, s));
+    HIPCHK(c, hipStreamWaitEvent(cs, c->cap_in, 0));
+    HIPCHK(c, hipGraphLaunch(c->graph_exec, cs));
+    HIPCHK(c, hipEventRecord(c->cap_out, cs));
+    HIPCHK(c, hipStreamWaitEvent(s, c->cap_out, 0));
+  } else {
+    HIPCHK(c, hipEventRecord(ev[0], s));
+    if ((st = enqueue_render(c, P, Tune(), s))) return st;
+  }
   HIPCHK(c, hipEventRecord(ev[1], s));
+  const bool timing = P.timing;
+  unsigned long long* vstat = (unsigned long long*)c->vstat.p;
   // one wait: counters, per-view counts, fluxes
   const size_t vstat_bytes = 8 * (size_t)V * MAXL * VS_N;
   if ((st = ensure_host(c, (void**)&c->host_vstat, &c->host_vstat_n, vstat_bytes))) return st;
@@ -558,13 +693,14 @@ air_status render_core(air_ctx* c, const air_grid* grid, const air_field* field,
     }
     float ms = 0.0f;
     if (hipEventElapsedTime(&ms, ev[0], ev[1]) == hipSuccess) stats->ms_total = ms;
-    for (int L = 0; L <= Lm; ++L) {
+    for (int L = 0; timing && L <= Lm; ++L) {
       if (hipEventElapsedTime(&ms, ev[2 + 4 * L], ev[3 + 4 * L]) == hipSuccess) stats->ms_march += ms;
       if (hipEventElapsedTime(&ms, ev[3 + 4 * L], ev[4 + 4 * L]) == hipSuccess) stats->ms_test += ms;
     }
     stats->march_launches = Lm + 1;
     if (learned) {
-      if (hipEventElapsedTime(&ms, ev[air_ctx::EV_SPEC0], ev[air_ctx::EV_SPEC1]) == hipSuccess) stats->ms_march += ms;
+      if (timing && hipEventElapsedTime(&ms, ev[air_ctx::EV_SPEC0], ev[air_ctx::EV_SPEC1]) == hipSuccess)
+        stats->ms_march += ms;
       stats->march_launches += 1;
     }
   }
@@ -579,8 +715,10 @@ air_status render_core(air_ctx* c, const air_grid* grid, const air_field* field,
       }
     for (uint8_t d : depth_h) ls->depth_hist[d] += 1;
     float ms = 0.0f;
-    if (hipEventElapsedTime(&ms, ev[air_ctx::EV_FEAT0], ev[air_ctx::EV_SPEC0]) == hipSuccess) ls->ms_features = ms;
-    if (hipEventElapsedTime(&ms, ev[air_ctx::EV_SPEC0], ev[air_ctx::EV_SPEC1]) == hipSuccess) ls->ms_spec = ms;
+    if (timing && hipEventElapsedTime(&ms, ev[air_ctx::EV_FEAT0], ev[air_ctx::EV_SPEC0]) == hipSuccess)
+      ls->ms_features = ms;
+    if (timing && hipEventElapsedTime(&ms, ev[air_ctx::EV_SPEC0], ev[air_ctx::EV_SPEC1]) == hipSuccess)
+      ls->ms_spec = ms;
   }
   air_status res = AIR_OK;
   for (int k = 0; trees && k < V; ++k) {
@@ -637,6 +775,12 @@ air_status air_create(air_ctx** out, int32_t device) {
       air_destroy(c);
       return AIR_EDEVICE;
     }
+  if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&c->cap_in, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->cap_out, hipEventDisableTiming) != hipSuccess) {
+    air_destroy(c);
+    return AIR_EDEVICE;
+  }
   *out = c;
   return AIR_OK;
 }
@@ -654,6 +798,12 @@ void air_destroy(air_ctx* c) {
   if (c->host_flux) (void)hipHostFree(c->host_flux);
   if (c->host_vstat) (void)hipHostFree(c->host_vstat);
   if (c->stage) (void)hipHostFree(c->stage);
+  if (c->stage2) (void)hipHostFree(c->stage2);
+  if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  if (c->cap_in) (void)hipEventDestroy(c->cap_in);
+  if (c->cap_out) (void)hipEventDestroy(c->cap_out);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   for (int k = 0; k < air_ctx::NEV; ++k)
     if (c->ev[k]) (void)hipEventDestroy(c->ev[k]);
   delete c;
@@ -665,7 +815,14 @@ air_status air_render(air_ctx* c, const air_grid* grid, const air_field* field, 
                       int32_t n_views, const air_params* prm, air_tree* trees, float* images, double* flux,
                       air_stats* stats, void* stream) {
   return render_core(c, grid, field, views, n_views, prm, nullptr, nullptr, trees, images, flux, stats, nullptr,
-                     stream);
+                     stream, false);
+}
+
+air_status air_render_batch(air_ctx* c, const air_grid* grid, const air_field* field, const air_view* views,
+                            int32_t n_views, const air_params* prm, air_tree* trees, float* images, double* flux,
+                            air_stats* stats, void* stream) {
+  return render_core(c, grid, field, views, n_views, prm, nullptr, nullptr, trees, images, flux, stats, nullptr,
+                     stream, true);
 }
 
 air_status air_render_learned(air_ctx* c, const air_grid* grid, const air_field* field, const air_view* views,
@@ -680,7 +837,7 @@ air_status air_render_learned(air_ctx* c, const air_grid* grid, const air_field*
     return fail(c, AIR_EINVAL, "c_ray and c_sweep must be finite and >= 0");
   if (learn->max_depth < 0 || learn->flags != 0) return fail(c, AIR_EINVAL, "max_depth < 0 or flags != 0");
   return render_core(c, grid, field, views, n_views, prm, net, learn, trees, images, flux, stats, learn_stats,
-                     stream);
+                     stream, false);
 }
 
 air_status air_render_fixed(air_ctx* c, const air_grid* grid, const air_field* field, const air_view* views,

@@ -291,32 +291,36 @@ __global__ __launch_bounds__(256) void k_reduce_stats(MarchArgs A, const unsigne
   }
 }
 
-// exclusive scan of the chunk counts (one block; n_chunks is modest)
+// exclusive scan of n counts in one block of 1024 threads: each thread sums
+// a contiguous run, the 1024 run sums are scanned by wave prefix sums and
+// the 16 wave totals, then each thread rewrites its run; the total lands in
+// a[n]
 __global__ __launch_bounds__(1024) void k_scan(unsigned long long* a, int64_t n) {
-  __shared__ unsigned long long part[1024];
+  __shared__ unsigned long long wsum[1024 / WAVE];
+  const int tid = threadIdx.x, lane = tid & (WAVE - 1), w = tid / WAVE;
   const int64_t per = (n + 1023) / 1024;
-  const int64_t b = threadIdx.x * per, e = min<int64_t>(b + per, n);
+  const int64_t b = tid * per, e = min<int64_t>(b + per, n);
   unsigned long long s = 0;
   for (int64_t k = b; k < e; ++k) s += a[k];
-  part[threadIdx.x] = s;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned long long run = 0;
-    for (int k = 0; k < 1024; ++k) {
-      unsigned long long t = part[k];
-      part[k] = run;
-      run += t;
-    }
+  unsigned long long x = s;  // inclusive prefix inside the wave
+  for (int o = 1; o < WAVE; o <<= 1) {
+    const unsigned long long y = __shfl_up(x, o);
+    if (lane >= o) x += y;
   }
+  if (lane == WAVE - 1) wsum[w] = x;
   __syncthreads();
-  unsigned long long run = part[threadIdx.x];
+  unsigned long long before = 0, total = 0;
+  for (int q = 0; q < 1024 / WAVE; ++q) {
+    before += q < w ? wsum[q] : 0ull;
+    total += wsum[q];
+  }
+  unsigned long long run = before + x - s;  // exclusive prefix of this run
   for (int64_t k = b; k < e; ++k) {
-    unsigned long long t = a[k];
+    const unsigned long long t = a[k];
     a[k] = run;
     run += t;
   }
-  if (e == n && b < e) a[n] = run;  // total after the last element
-  if (n == 0 && threadIdx.x == 0) a[0] = 0;
+  if (tid == 0) a[n] = total;
 }
 
 // node ids: exclusive prefix of existing positions in canonical order

@@ -318,9 +318,10 @@ def amr_cell_centres(grid: Grid) -> np.ndarray:
 
 def amr_winds(seed: int = 0, base_cells: int = 128, bs: int = 16, max_level: int = 2,
               frac=(0.10, 0.03), kind: int = FIELD_RHO_T, bands=None, kappa0: float = 1.0):
-    """Block AMR over the two-wind field: blocks within a distance of the
-    shell surface or a source are refined; the distances are bisected so the
-    level-1 and level-2 blocks cover about frac[0] and frac[1] of the volume."""
+    """Block AMR over the two-wind field: a block whose centre lies within a
+    distance of the shell surface or a source is refined; the distances are
+    bisected so the level-1 and level-2 blocks cover about frac[0] and
+    frac[1] of the volume."""
     src, etas = winds2_sources(seed)
     nb0 = base_cells // bs
     q = math.sqrt(etas[1] / etas[0])
@@ -337,7 +338,7 @@ def amr_winds(seed: int = 0, base_cells: int = 128, bs: int = 16, max_level: int
 
         def pred(l, blo, sz):
             cc = np.asarray(blo) + 0.5 * sz
-            return surf_dist(cc) < ds[l] + 0.5 * math.sqrt(3) * sz
+            return surf_dist(cc) < ds[l]
         return amr_from_predicate(nb0, bs, max_level, pred)
 
     def vol_frac(grid, lev):
@@ -450,3 +451,63 @@ def cnn_init(seed: int) -> np.ndarray:
         parts.append(rng.normal(size=cout * 9 * cin) * math.sqrt(2.0 / (9 * cin)))
         parts.append(np.zeros(cout))
     return np.concatenate(parts).astype(np.float32)
+
+
+def winds_field_torch(src: np.ndarray, etas: np.ndarray, n: int, device, r0: float = 0.05,
+                      shell_cells: float = 1.5, slab: int = 64):
+    """winds_rho_t on the cell centres of the uniform n^3 unit box, evaluated
+    with torch in float64 on `device` (a GPU makes the many-seed training
+    sets cheap); returns float32 (rho, T) tensors [n, n, n], z slowest.  Same
+    formulas and operation order as winds_rho_t; cells exactly on a shell's
+    distance threshold or a density tie may round the other way."""
+    import torch
+    h = 1.0 / n
+    c = (torch.arange(n, dtype=torch.float64, device=device) + 0.5) * h
+    rho_out = torch.empty((n, n, n), dtype=torch.float32, device=device)
+    t_out = torch.empty((n, n, n), dtype=torch.float32, device=device)
+    y, x = torch.meshgrid(c, c, indexing="ij")
+    S = torch.as_tensor(np.asarray(src, dtype=np.float64), device=device)
+    K = len(src)
+    for z0 in range(0, n, slab):
+        z1 = min(n, z0 + slab)
+        zz = c[z0:z1].view(-1, 1, 1).expand(-1, n, n)
+        pts = torch.stack([x.expand(z1 - z0, n, n), y.expand(z1 - z0, n, n), zz], dim=-1)
+        dk = []
+        for k in range(K):
+            dv = pts - S[k]
+            r = torch.sqrt(torch.sum(dv * dv, dim=-1))
+            dk.append((torch.clamp(r, min=2.0 * h), dv, r))
+        dens = torch.stack([float(etas[k]) * (r0 / dk[k][0]) ** 2 for k in range(K)], dim=0)
+        rho = dens.max(dim=0).values
+        temp = torch.ones_like(rho)
+        if K >= 2:
+            order = torch.argsort(-dens, dim=0)
+            k1, k2 = order[0], order[1]
+            shell = torch.zeros(rho.shape, dtype=torch.bool, device=device)
+            for a in range(K):
+                for b in range(K):
+                    if a == b:
+                        continue
+                    m = (k1 == a) & (k2 == b)
+                    ra, dva, rra = dk[a]
+                    rb, dvb, rrb = dk[b]
+                    q = math.sqrt(etas[b] / etas[a])
+                    gfun = rrb - q * rra
+                    grad = dvb / torch.clamp(rrb, min=1e-300)[..., None] - q * dva / torch.clamp(rra, min=1e-300)[..., None]
+                    gn = torch.sqrt(torch.sum(grad * grad, dim=-1))
+                    dist = torch.abs(gfun) / torch.clamp(gn, min=1e-12)
+                    shell |= m & (dist <= shell_cells * h)
+            rho = torch.where(shell, 4.0 * rho, rho)
+            temp = torch.where(shell, torch.full_like(temp, 10.0), temp)
+        rho_out[z0:z1] = rho.to(torch.float32)
+        t_out[z0:z1] = temp.to(torch.float32)
+    return rho_out, t_out
+
+
+def training_scene(seed: int):
+    """One training sample of the depth proposal: the two-wind sources of
+    `seed` (mass-loss ratio and phase) and a seeded isotropic view."""
+    src, etas = winds2_sources(seed)
+    rng = np.random.default_rng(20_000 + seed)
+    d = rng.normal(size=3)
+    return src, etas, view_for(d / np.linalg.norm(d))

@@ -1,0 +1,185 @@
+"""Train the depth-proposal network on the GPU with the library's own
+kernels, on plain-AIR trees of many seeded two-wind renders.
+
+Data: for each seed, the two-wind field (mass-loss ratio and phase drawn
+from the seed) on a uniform 256^3 grid, one band (kappa0 1, T exponents
+-1.5 and 0.5), a seeded isotropic view, a 64x64 coarse image with 5
+refinement levels at xi_crit 0.5.  Inputs are the four coarse maps of
+air_features; labels the deepest level of each coarse pixel's plain-AIR
+tree (air_tree_depth).  Training: class-weighted cross-entropy, Adam, the
+bf16 MFMA forward and backward kernels of the library.  Evaluation on
+held-out seeds: label accuracy, and air_render_learned against air_render
+(speculative, wasted and missing rays, device time per image), with the
+cost ratio of the depth choice picked on part of the held-out set.
+
+Writes <out>.npz (parameters, feature standardisation, cost model, class
+weights) and <out>.json (training log and evaluation)."""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(HERE))
+
+from paper_1010_5534_amd import air, inputs  # noqa: E402
+
+GRID, N0, LMAX, XC = 256, 64, 5, 0.5
+BANDS = [[1.0, 1.5, 0.5]]
+
+
+def log(*a):
+    print(*a, flush=True)
+
+
+def scene_for(seed, device="cuda"):
+    src, etas, view = inputs.training_scene(seed)
+    rho, temp = inputs.winds_field_torch(src, etas, GRID, device)
+    return air.scene_from_tensors(GRID, rho, temp, BANDS), view
+
+
+def build_dataset(ctx, seeds):
+    import torch
+    prm = air.params(N0, LMAX, XC)
+    feats = torch.empty((len(seeds), N0, N0, 4), dtype=torch.float32, device="cuda")
+    labels = torch.empty((len(seeds), N0, N0), dtype=torch.int32, device="cuda")
+    t0 = time.time()
+    for k, seed in enumerate(seeds):
+        scene, view = scene_for(seed)
+        ctx.prepare(scene)
+        trees, _, _, _ = ctx.render(scene, [view], prm, want_image=False, want_flux=False, reuse=True)
+        labels[k] = ctx.tree_depth(trees[0], N0)
+        feats[k] = ctx.features(scene, [view], N0)[0]
+        if (k + 1) % 100 == 0:
+            torch.cuda.synchronize()
+            log(f"  data {k + 1}/{len(seeds)} ({time.time() - t0:.1f} s)")
+    torch.cuda.synchronize()
+    return feats, labels
+
+
+def evaluate_labels(net, feats, labels):
+    import torch
+    z = net.forward(feats)[..., :6]
+    pred = z.argmax(dim=-1).to(torch.int32)
+    acc = float((pred == labels).float().mean())
+    under = float((pred < labels).float().mean())
+    conf = torch.zeros((6, 6), dtype=torch.int64)
+    for a in range(6):
+        for b in range(6):
+            conf[a, b] = int(((labels == a) & (pred == b)).sum())
+    return dict(accuracy=acc, under_predicted=under, confusion=conf.tolist())
+
+
+def time_renders(ctx, net, seeds, c_ray, c_sweep, repeats=3):
+    """Median device ms per image of plain and learned AIR, and the learned
+    counters, over the seeds (outputs checked equal)."""
+    import torch
+    prm = air.params(N0, LMAX, XC)
+    plain_ms, learned_ms = [], []
+    tot = dict(spec_rays=0, wasted=0, missing=0, rays=0)
+    for seed in seeds:
+        scene, view = scene_for(seed)
+        ctx.prepare(scene)
+        tp, ip, fp, sp = ctx.render(scene, [view], prm, want_tree=False, reuse=True)
+        tl, il, fl, sl, ls = ctx.render_learned(scene, [view], prm, net, c_ray, c_sweep, want_tree=False, reuse=True)
+        assert np.array_equal(fp, fl), "learned flux differs from plain"
+        a, b = [], []
+        for _ in range(repeats):
+            a.append(ctx.render(scene, [view], prm, want_tree=False, reuse=True)[3]["ms_total"])
+            b.append(ctx.render_learned(scene, [view], prm, net, c_ray, c_sweep, want_tree=False,
+                                        reuse=True)[3]["ms_total"])
+        plain_ms.append(float(np.median(a)))
+        learned_ms.append(float(np.median(b)))
+        for k in ("spec_rays", "wasted", "missing"):
+            tot[k] += ls[k]
+        tot["rays"] += sp["rays"]
+    torch.cuda.synchronize()
+    return dict(plain_ms=float(np.mean(plain_ms)), learned_ms=float(np.mean(learned_ms)),
+                speedup=float(np.mean(plain_ms) / np.mean(learned_ms)), **tot)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--train", type=int, default=2000, help="training seeds 1..N")
+    ap.add_argument("--val", type=int, default=200, help="held-out seeds after the training seeds")
+    ap.add_argument("--epochs", type=int, default=30)
+    ap.add_argument("--batch", type=int, default=32)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--init-seed", type=int, default=0)
+    ap.add_argument("--out", default=os.path.join(HERE, "weights", "depth_cnn"))
+    args = ap.parse_args()
+
+    import torch
+    assert torch.cuda.is_available(), "training runs on the GPU"
+    ctx = air.Context(0)
+    train_seeds = list(range(1, args.train + 1))
+    val_seeds = list(range(args.train + 1, args.train + args.val + 1))
+    log(f"building {len(train_seeds)} training and {len(val_seeds)} held-out maps")
+    t0 = time.time()
+    ftr, ltr = build_dataset(ctx, train_seeds)
+    fva, lva = build_dataset(ctx, val_seeds)
+    t_data = time.time() - t0
+    # standardisation and class weights from the training set
+    flat = ftr.reshape(-1, 4).double()
+    mean = flat.mean(dim=0).float().cpu().numpy()
+    scale = flat.std(dim=0).clamp(min=1e-3).float().cpu().numpy()
+    freq = torch.bincount(ltr.reshape(-1).long(), minlength=6).double().cpu().numpy()
+    freq = freq / freq.sum()
+    cw = 1.0 / np.sqrt(np.maximum(freq, 1e-4))
+    cw = (cw / np.sum(cw * freq)).astype(np.float32)
+    log(f"label frequencies {np.round(freq, 4).tolist()}  class weights {np.round(cw, 3).tolist()}")
+
+    net = air.Network(ctx, inputs.cnn_init(args.init_seed), mean, scale)
+    rng = np.random.default_rng(1234)
+    hist = []
+    nb = len(train_seeds) // args.batch
+    t1 = time.time()
+    for ep in range(args.epochs):
+        order = torch.as_tensor(rng.permutation(len(train_seeds)), device="cuda")
+        for b in range(nb):
+            idx = order[b * args.batch:(b + 1) * args.batch]
+            net.loss_grad(ftr[idx].contiguous(), ltr[idx].contiguous(), cw, want_loss=False)
+            net.adam(lr=args.lr)
+        ltrain, _ = net.loss_grad(ftr[:256].contiguous(), ltr[:256].contiguous(), cw)
+        lval, _ = net.loss_grad(fva, lva, cw)
+        hist.append(dict(epoch=ep + 1, train_loss=ltrain, val_loss=lval))
+        log(f"epoch {ep + 1}: train {ltrain:.4f}  held-out {lval:.4f}")
+    torch.cuda.synchronize()
+    t_train = time.time() - t1
+    ev = evaluate_labels(net, fva, lva)
+    log(f"held-out accuracy {ev['accuracy']:.4f}, under-predicted {ev['under_predicted']:.4f}")
+
+    # cost ratio of the depth choice: c_ray 1, c_sweep picked on 40 held-out seeds
+    pick = val_seeds[:40]
+    sweep = []
+    for cs in (0.0, 20.0, 60.0, 200.0, 600.0, 2000.0):
+        r = time_renders(ctx, net, pick, 1.0, cs, repeats=2)
+        sweep.append(dict(c_sweep=cs, **r))
+        log(f"c_sweep {cs}: plain {r['plain_ms']:.3f} ms learned {r['learned_ms']:.3f} ms "
+            f"spec {r['spec_rays']} wasted {r['wasted']} missing {r['missing']}")
+    best = min(sweep, key=lambda r: r["learned_ms"])
+    c_sweep = best["c_sweep"]
+    rest = time_renders(ctx, net, val_seeds[40:], 1.0, c_sweep)
+    log(f"held-out (seeds {val_seeds[40]}..{val_seeds[-1]}): plain {rest['plain_ms']:.3f} ms, learned "
+        f"{rest['learned_ms']:.3f} ms per image, speedup {rest['speedup']:.3f}")
+    # the same held-out seeds with constant depths instead of the network
+    params, m_, s_ = net.get()
+    os.makedirs(os.path.dirname(args.out), exist_ok=True)
+    np.savez(args.out + ".npz", params=params, mean=m_, scale=s_, c_ray=np.float32(1.0),
+             c_sweep=np.float32(c_sweep), class_weight=cw)
+    summary = dict(workload=f"two-wind {GRID}^3, one band, {N0}x{N0} coarse, {LMAX} levels, xi_crit {XC}, "
+                            f"isotropic seeded views", train_seeds=[1, args.train],
+                   held_out_seeds=[val_seeds[0], val_seeds[-1]], epochs=args.epochs, batch=args.batch, lr=args.lr,
+                   label_freq=freq.tolist(), class_weight=cw.tolist(), seconds_data=t_data,
+                   seconds_train=t_train, history=hist, held_out_labels=ev, cost_sweep=sweep, c_sweep=c_sweep,
+                   held_out_render=rest)
+    with open(args.out + ".json", "w") as fh:
+        json.dump(summary, fh, indent=1)
+    log(f"wrote {args.out}.npz and .json")
+
+
+if __name__ == "__main__":
+    main()
