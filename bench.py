@@ -64,6 +64,39 @@ def cpu_baseline(g, f, views):
                 seconds=dt)
 
 
+def batched_amr(ctx, air, inputs, np, torch, args):
+    """Block AMR (128^3 base in 16^3 blocks, levels 0-2 over about 10% and 3%
+    of the volume), 64 isotropic views x 8 bands, 128x128 coarse, 3 levels,
+    in one air_render_batch call."""
+    log("batched AMR: 64 views x 8 bands")
+    g, f = inputs.amr_winds(seed=0, base_cells=128, bs=16, max_level=2, bands=inputs.default_bands(8))
+    scene = ctx.prepare(air.upload(g, f))
+    views = inputs.isotropic_views(64, seed=3)
+    prm = air.params(128, 3, 0.5)
+    for _ in range(2):
+        ctx.render_batch(scene, views, prm, want_image=False)
+    torch.cuda.synchronize()
+    steps = max(2, args.steps // 3)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out = ctx.render_batch(scene, views, prm, want_image=False)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    st = out[3]
+    t1 = time.perf_counter()
+    ref = ctx.render(scene, views, prm, want_image=False, reuse=True)
+    torch.cuda.synchronize()
+    wall_eager = time.perf_counter() - t1
+    same = bool(np.array_equal(ref[2], out[2]) and ref[3]["rays"] == st["rays"])
+    visits = st["visits"]
+    return dict(workload="block AMR 128^3 base, 16^3 blocks, levels 0-2 (seed 0), (rho, T) 8 bands, 64 views, "
+                         "128x128 coarse, 3 levels, xi_crit 0.5",
+                blocks=g.n_blocks, cells=g.n_cells, rays=st["rays"], hits=st["hits"], visits=visits,
+                ms_wall=wall * 1e3, per_image_ms=wall * 1e3 / len(views), rays_per_s=st["rays"] / wall,
+                band_visits_per_s=8 * visits / wall, ms_wall_eager_render=wall_eager * 1e3,
+                equal_to_render=same)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -72,6 +105,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-fixed", action="store_true")
     ap.add_argument("--skip-learned", action="store_true")
+    ap.add_argument("--skip-amr", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the timed region, one 256 MiB device copy whose counters calibrate HBM bytes")
     args = ap.parse_args()
@@ -162,6 +196,14 @@ def main():
                                                  for k in range(len(views))])
         del out_f, img_f
 
+    # the same plain AIR through the captured, autotuned launch sequence
+    log("plain AIR, captured batch")
+    out_b, wall_b, dev_b, _, st_b = timed(lambda: ctx.render_batch(scene, views, prm), args.steps, args.warmup)
+    same_b = bool(torch.equal(out_b[1].view(torch.int32), img_p.view(torch.int32)) and np.array_equal(out_b[2], flux_p))
+    res["plain_air_batch"] = dict(ms_wall=wall_b * 1e3, ms_device=dev_b, per_image_ms=wall_b * 1e3 / len(views),
+                                  rays_per_s=st_b["rays"] / wall_b, equal_to_plain=same_b)
+    del out_b
+
     res["learned_air"] = None
     wpath = os.path.join(ROOT, "paper_1010_5534_amd", "weights", "depth_cnn.npz")
     if os.path.exists(wpath) and not args.skip_learned:
@@ -187,6 +229,9 @@ def main():
                                   network="paper_1010_5534_amd/weights/depth_cnn.npz (trained on seeds 1..2000; "
                                           "this workload's seed 0 is held out)")
         net.close()
+
+    if not args.skip_amr:
+        res["batched_amr"] = batched_amr(ctx, air, inputs, np, torch, args)
 
     if args.copy_probe:
         src = torch.empty(64 << 20, dtype=torch.float32, device="cuda")
