@@ -3,7 +3,7 @@
 
 Workload (the uniform colliding-winds case): 256^3 float32 (rho, T) field
 with two wind sources and a shocked shell (seed 0), one band j = rho^2
-T^0.5, kappa = rho T^-1.5 evaluated per visit; 64x64 coarse image, 5 refinement levels (2048^2 effective),
+T^0.5, kappa = rho T^-1.5 (evaluated once per cell when the field is packed); 64x64 coarse image, 5 refinement levels (2048^2 effective),
 xi_crit = 0.5, three views (+z, +x, (1,1,1)/sqrt3).  One step = plain AIR of
 the three views in one call: march every level, refinement test, 2:1
 closure, compaction, canonical quadtree, raster assembly and float64 flux.
@@ -24,10 +24,11 @@ sys.path.insert(0, ROOT)
 METRIC = "rays/s & per-image time: learned AIR vs plain AIR vs fixed-res, 1 GPU"
 HBM_PEAK_GBS = 8000.0
 N0, LMAX, XI_CRIT, SEED, NGRID = 64, 5, 0.5, 0, 256
-# algorithmic bytes of the march: per (ray, cell) visit the two float32 field
-# values (rho, T); per ray its queue entry (8 B) and results (I, N, visits:
-# 12 B, state byte)
-BYTES_PER_VISIT = 8
+# algorithmic bytes of the march: per (ray, cell) visit the three float32
+# values the one-band integration reads (rho, j, kappa: the packed record
+# evaluates j and kappa from (rho, T) once per field); per ray its queue entry
+# (8 B) and results (I, N, visits: 12 B, state byte)
+BYTES_PER_VISIT = 12
 BYTES_PER_RAY_QUEUE = 8 + 12 + 1
 BYTES_PER_RAY_FIXED = 8  # I and N written to the raster
 

@@ -166,7 +166,11 @@ hipError_t launch_init(const MarchArgs& a, hipStream_t s);
 hipError_t launch_pack(const Geo& g, const Fld& f, void* packed, hipStream_t s);
 hipError_t launch_pack_amr(const Geo& g, const Fld& f, void* packed, hipStream_t s);
 // bytes per packed cell
-inline int packed_cell_bytes(int field_kind) { return field_kind == AIR_FIELD_RHO_J_KAPPA ? 16 : 8; }
+// bytes of one packed cell record: (rho, j, kappa, 0) for RHO_J_KAPPA and for
+// one-band RHO_T (j, kappa evaluated once when packing), (rho, T) otherwise
+inline int packed_cell_bytes(int field_kind, int n_bands) {
+  return (field_kind == AIR_FIELD_RHO_J_KAPPA || n_bands == 1) ? 16 : 8;
+}
 
 // packed index of cell (x, y, z): 2x2x2 bricks, x fastest
 __host__ __device__ inline int brick_index(int x, int y, int z, int bnx, int bny) {
@@ -203,7 +207,7 @@ hipError_t launch_count(const MarchArgs& a, unsigned long long* chunk_counts, un
                         int64_t n_chunks, unsigned long long* vstat, hipStream_t s);
 hipError_t launch_scan(unsigned long long* chunk_counts, int64_t n_chunks, hipStream_t s);
 hipError_t launch_emit(const MarchArgs& a, const unsigned long long* chunk_offsets, int64_t n_chunks,
-                       int32_t* id_map, hipStream_t s);
+                       int32_t* id_map, uint64_t* node_pos, hipStream_t s);
 struct TreeOut {
   int8_t* level;
   int32_t* ix;
@@ -219,7 +223,7 @@ struct TreeOut {
   int64_t capacity;
 };
 hipError_t launch_write_tree(const MarchArgs& a, const unsigned long long* chunk_offsets, const int32_t* id_map,
-                             const TreeOut* outs, hipStream_t s);
+                             const uint64_t* node_pos, const TreeOut* outs, int grid_blocks, hipStream_t s);
 hipError_t launch_assemble(const MarchArgs& a, float* images, hipStream_t s);
 hipError_t launch_flux(const MarchArgs& a, double* partial, int64_t n_chunks, double* flux_dev,
                        hipStream_t s);

@@ -38,7 +38,7 @@ struct air_ctx {
       views, touts, pack;
   // learned proposal: coarse maps, network activations and gradients, depth
   // choice and speculative work list
-  DevBuf lmax0, feat, cx0, ca1, ca2, ca3, cz, cdz, cda, cdb, cwpart, closs_part, closs, depth8, scount, spec;
+  DevBuf nodepos, lmax0, feat, cx0, ca1, ca2, ca3, cz, cdz, cda, cdb, cwpart, closs_part, closs, depth8, scount, spec;
   unsigned long long* host_ctr = nullptr;  // pinned
   double* host_flux = nullptr;             // pinned
   unsigned long long* host_vstat = nullptr;
@@ -272,9 +272,9 @@ int64_t cells_of(const air_grid* g) {
 // both layouts are whole 2x2x2 bricks: the uniform grid rounds each axis up
 // to even, a block of bs^3 cells (bs even) is bs^3/8 bricks
 int64_t packed_bytes_of(const air_grid* g, const air_field* f) {
-  if (g->kind == AIR_GRID_BLOCK_AMR) return cells_of(g) * packed_cell_bytes(f->kind);
+  if (g->kind == AIR_GRID_BLOCK_AMR) return cells_of(g) * packed_cell_bytes(f->kind, f->n_bands);
   const int64_t bricks = (int64_t)((g->n[0] + 1) / 2) * ((g->n[1] + 1) / 2) * ((g->n[2] + 1) / 2);
-  return 8 * bricks * packed_cell_bytes(f->kind);
+  return 8 * bricks * packed_cell_bytes(f->kind, f->n_bands);
 }
 
 void fill_fld(const air_field* f, const air_grid* g, Fld& F) {
@@ -507,8 +507,9 @@ air_status enqueue_render(air_ctx* c, const Plan& P, const Tune& tune, hipStream
   HIPCHK(c, launch_count(A, chunk, (unsigned*)c->cstat.p, P.n_chunks, (unsigned long long*)c->vstat.p, s));
   if (P.trees) {
     HIPCHK(c, launch_scan(chunk, P.n_chunks, s));
-    HIPCHK(c, launch_emit(A, chunk, P.n_chunks, (int32_t*)c->idmap.p, s));
-    HIPCHK(c, launch_write_tree(A, chunk, (const int32_t*)c->idmap.p, (const TreeOut*)c->touts.p, s));
+    HIPCHK(c, launch_emit(A, chunk, P.n_chunks, (int32_t*)c->idmap.p, (uint64_t*)c->nodepos.p, s));
+    HIPCHK(c, launch_write_tree(A, chunk, (const int32_t*)c->idmap.p, (const uint64_t*)c->nodepos.p,
+                                (const TreeOut*)c->touts.p, c->num_cus * 8, s));
   }
   if (P.images) HIPCHK(c, launch_assemble(A, P.images, s));
   if (P.flux) HIPCHK(c, launch_flux(A, (double*)c->partial.p, P.n_chunks, (double*)c->flux.p, s));
@@ -602,6 +603,7 @@ air_status render_core(air_ctx* c, const air_grid* grid, const air_field* field,
   if (learned && (st = ensure_learned(c, A))) return st;
   if (trees) {
     if ((st = ensure(c, c->idmap, 4 * (size_t)V * A.img.S))) return st;
+    if ((st = ensure(c, c->nodepos, 8 * (size_t)V * A.img.S))) return st;
     if ((st = ensure(c, c->touts, sizeof(TreeOut) * V))) return st;
     if ((st = ensure_host(c, &c->stage2, &c->stage2_n, sizeof(TreeOut) * V))) return st;
     TreeOut* to = static_cast<TreeOut*>(c->stage2);
@@ -790,7 +792,7 @@ void air_destroy(air_ctx* c) {
   (void)hipSetDevice(c->device);
   for (DevBuf* b : {&c->state, &c->valI, &c->valN, &c->xiI, &c->xiN, &c->visits, &c->rmin, &c->rmax, &c->queue,
                     &c->ctr, &c->chunk, &c->cstat, &c->vstat, &c->idmap, &c->partial, &c->flux, &c->views,
-                    &c->touts, &c->pack, &c->lmax0, &c->feat, &c->cx0, &c->ca1, &c->ca2, &c->ca3, &c->cz,
+                    &c->touts, &c->pack, &c->nodepos, &c->lmax0, &c->feat, &c->cx0, &c->ca1, &c->ca2, &c->ca3, &c->cz,
                     &c->cdz, &c->cda, &c->cdb, &c->cwpart, &c->closs_part, &c->closs, &c->depth8, &c->scount,
                     &c->spec})
     if (b->p) (void)hipFree(b->p);

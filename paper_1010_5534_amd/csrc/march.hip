@@ -85,8 +85,10 @@ struct Raw {
   float rho, a, b;
 };
 
-// The packed field (air_field_pack): one 16-byte (rho, j, kappa, 0) or
-// 8-byte (rho, T) record per cell in 2x2x2 bricks.  Loads go through a
+// The packed field (air_field_pack): one 16-byte (rho, j, kappa, 0) record
+// per cell (one-band (rho, T) fields get their j, kappa evaluated once when
+// packing: three transcendentals fewer per visit) or 8-byte (rho, T) for
+// several bands, in 2x2x2 bricks.  Loads go through a
 // buffer resource: a 32-bit byte offset, and 0 past num_records, so an index
 // can never leave the array.  The loads are bound to the LLVM buffer-load
 // intrinsics directly (the vector-returning clang builtins shrink to one
@@ -235,24 +237,41 @@ __device__ __forceinline__ int cells_between(const Geo& g, const double o[3], co
   }                                                                       \
   _Pragma("unroll") for (int q = 0; q < KB; ++q) RAW[q] = load_raw<FK>(R, OFF[q]);
 
+// One batch of up to KB cells: plain float32 sums inside the batch (at most
+// KB terms), one Kahan step per batch into the running I, tau, N.  The
+// transmission of each cell uses the compensated optical depth at the batch
+// start plus the batch's partial sum.
 #define AIR_INTEGRATE(V0, DS, RAW)                                        \
-  _Pragma("unroll") for (int q = 0; q < KB; ++q) {                        \
-    if ((V0) + q < nvis) {                                                \
-      const float ds = DS[q];                                             \
-      float jb[NB], kb[NB];                                               \
-      optics<NB, FK>(f, RAW[q], jb, kb);                                  \
-      _Pragma("unroll") for (int b = 0; b < NB; ++b) {                    \
-        const float dtau = kb[b] * ds;                                    \
-        const float T = __builtin_amdgcn_exp2f(-(tau[b] - ctau[b]) * LOG2E_F); \
-        kadd(I[b], cI[b], T * (jb[b] * ds) * seg_weight(dtau));           \
-        kadd(tau[b], ctau[b], dtau);                                      \
-      }                                                                   \
-      kadd(N, cN, RAW[q].rho * ds);                                       \
-      if constexpr (RANGE) {                                              \
-        rmin = fminf(rmin, RAW[q].rho);                                   \
-        rmax = fmaxf(rmax, RAW[q].rho);                                   \
+  {                                                                       \
+    float bI[NB], bT[NB], t0b[NB], bN = 0.0f;                             \
+    _Pragma("unroll") for (int b = 0; b < NB; ++b) {                      \
+      bI[b] = 0.0f;                                                       \
+      bT[b] = 0.0f;                                                       \
+      t0b[b] = tau[b] - ctau[b];                                          \
+    }                                                                     \
+    _Pragma("unroll") for (int q = 0; q < KB; ++q) {                      \
+      if ((V0) + q < nvis) {                                              \
+        const float ds = DS[q];                                           \
+        float jb[NB], kb[NB];                                             \
+        optics<NB, FK>(f, RAW[q], jb, kb);                                \
+        _Pragma("unroll") for (int b = 0; b < NB; ++b) {                  \
+          const float dtau = kb[b] * ds;                                  \
+          const float T = __builtin_amdgcn_exp2f(-(t0b[b] + bT[b]) * LOG2E_F); \
+          bI[b] += T * (jb[b] * ds) * seg_weight(dtau);                   \
+          bT[b] += dtau;                                                  \
+        }                                                                 \
+        bN += RAW[q].rho * ds;                                            \
+        if constexpr (RANGE) {                                            \
+          rmin = fminf(rmin, RAW[q].rho);                                 \
+          rmax = fmaxf(rmax, RAW[q].rho);                                 \
+        }                                                                 \
       }                                                                   \
     }                                                                     \
+    _Pragma("unroll") for (int b = 0; b < NB; ++b) {                      \
+      kadd(I[b], cI[b], bI[b]);                                           \
+      kadd(tau[b], ctau[b], bT[b]);                                       \
+    }                                                                     \
+    kadd(N, cN, bN);                                                      \
   }
 
 // the whole cell walk, two batches in flight: walk and load batch n+1, then
@@ -628,8 +647,36 @@ __device__ __forceinline__ void block_stats(unsigned long long* ctr, unsigned lo
 }
 
 // ------------------------------------------------------------ kernels
+// packing modes: copy (rho, j, kappa); evaluate one band's (j, kappa) from
+// (rho, T) with the march's own optics; copy (rho, T)
+enum { PACK_RJK = 0, PACK_RT_TO_RJK = 1, PACK_RT = 2 };
+
+template <int PM>
+__device__ __forceinline__ void pack_cell(const Fld& f, int64_t src, bool in, int64_t dst) {
+  if constexpr (PM == PACK_RT) {
+    const float2 v = in ? make_float2(f.rho[src], f.temp[src]) : make_float2(0.f, 0.f);
+    reinterpret_cast<float2*>(const_cast<void*>(f.packed))[dst] = v;
+  } else {
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (in) {
+      if constexpr (PM == PACK_RJK) {
+        v = make_float4(f.rho[src], f.emis[src], f.kappa[src], 0.0f);
+      } else {
+        Raw<AIR_FIELD_RHO_T> r;
+        r.rho = f.rho[src];
+        r.a = f.temp[src];
+        r.b = 0.0f;
+        float j[1], k[1];
+        optics<1, AIR_FIELD_RHO_T>(f, r, j, k);
+        v = make_float4(r.rho, j[0], k[0], 0.0f);
+      }
+    }
+    reinterpret_cast<float4*>(const_cast<void*>(f.packed))[dst] = v;
+  }
+}
+
 // packed layout, written slot by slot (padding cells of odd sizes get 0)
-template <int FK>
+template <int PM>
 __global__ __launch_bounds__(256) void k_pack(Geo g, Fld f) {
   const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
   const int64_t slots = 8ll * f.bnx * f.bny * f.bnz;
@@ -640,18 +687,12 @@ __global__ __launch_bounds__(256) void k_pack(Geo g, Fld f) {
     const int z = (int)(2 * (b / ((int64_t)f.bnx * f.bny))) + (int)((sl >> 2) & 1);
     const bool in = x < nx && y < ny && z < nz;
     const int64_t src = in ? x + (int64_t)nx * (y + (int64_t)ny * z) : 0;
-    if constexpr (FK == AIR_FIELD_RHO_J_KAPPA) {
-      float4 v = in ? make_float4(f.rho[src], f.emis[src], f.kappa[src], 0.0f) : make_float4(0.f, 0.f, 0.f, 0.f);
-      reinterpret_cast<float4*>(const_cast<void*>(f.packed))[sl] = v;
-    } else {
-      float2 v = in ? make_float2(f.rho[src], f.temp[src]) : make_float2(0.f, 0.f);
-      reinterpret_cast<float2*>(const_cast<void*>(f.packed))[sl] = v;
-    }
+    pack_cell<PM>(f, src, in, sl);
   }
 }
 
 // block-AMR packed layout: inside each block of bs^3 cells, 2x2x2 bricks
-template <int FK>
+template <int PM>
 __global__ __launch_bounds__(256) void k_pack_amr(Geo g, Fld f) {
   const int bs = g.bs, hb = bs >> 1;
   const int64_t cells = (int64_t)g.n_blocks * bs * bs * bs;
@@ -659,11 +700,7 @@ __global__ __launch_bounds__(256) void k_pack_amr(Geo g, Fld f) {
     const int64_t b = q / ((int64_t)bs * bs * bs);
     const int loc = (int)(q - b * bs * bs * bs);
     const int x = loc % bs, y = (loc / bs) % bs, z = loc / (bs * bs);
-    const int64_t dst = b * bs * bs * bs + brick_index(x, y, z, hb, hb);
-    if constexpr (FK == AIR_FIELD_RHO_J_KAPPA)
-      reinterpret_cast<float4*>(const_cast<void*>(f.packed))[dst] = make_float4(f.rho[q], f.emis[q], f.kappa[q], 0.0f);
-    else
-      reinterpret_cast<float2*>(const_cast<void*>(f.packed))[dst] = make_float2(f.rho[q], f.temp[q]);
+    pack_cell<PM>(f, q, true, b * bs * bs * bs + brick_index(x, y, z, hb, hb));
   }
 }
 
@@ -862,11 +899,8 @@ __global__ __launch_bounds__(64 * MAX_SEG) void k_trace_pixels(MarchArgs A, int6
 // ----------------------------------------------------------- dispatch
 #define AIR_DISPATCH_NB(NBV, FKV, GKV, ...)                                      \
   do {                                                                           \
-    if (FKV == AIR_FIELD_RHO_J_KAPPA) {                                          \
+    if (FKV == AIR_FIELD_RHO_J_KAPPA || NBV == 1) {                              \
       constexpr int NB_ = 1, FK_ = AIR_FIELD_RHO_J_KAPPA, GK_ = GKV;             \
-      __VA_ARGS__;                                                               \
-    } else if (NBV == 1) {                                                       \
-      constexpr int NB_ = 1, FK_ = AIR_FIELD_RHO_T, GK_ = GKV;                   \
       __VA_ARGS__;                                                               \
     } else if (NBV == 2) {                                                       \
       constexpr int NB_ = 2, FK_ = AIR_FIELD_RHO_T, GK_ = GKV;                   \
@@ -894,23 +928,30 @@ hipError_t launch_march_spec(const MarchArgs& a, const uint64_t* spec, const uns
   return hipGetLastError();
 }
 
+int pack_mode(const Fld& f) {
+  if (f.kind == AIR_FIELD_RHO_J_KAPPA) return PACK_RJK;
+  return f.nb == 1 ? PACK_RT_TO_RJK : PACK_RT;
+}
+
 hipError_t launch_pack_amr(const Geo& g, const Fld& f, void* packed, hipStream_t s) {
   Fld F = f;
   F.packed = packed;
-  if (f.kind == AIR_FIELD_RHO_J_KAPPA)
-    hipLaunchKernelGGL(k_pack_amr<AIR_FIELD_RHO_J_KAPPA>, dim3(4096), dim3(256), 0, s, g, F);
-  else
-    hipLaunchKernelGGL(k_pack_amr<AIR_FIELD_RHO_T>, dim3(4096), dim3(256), 0, s, g, F);
+  switch (pack_mode(f)) {
+    case PACK_RJK: hipLaunchKernelGGL(k_pack_amr<PACK_RJK>, dim3(4096), dim3(256), 0, s, g, F); break;
+    case PACK_RT_TO_RJK: hipLaunchKernelGGL(k_pack_amr<PACK_RT_TO_RJK>, dim3(4096), dim3(256), 0, s, g, F); break;
+    default: hipLaunchKernelGGL(k_pack_amr<PACK_RT>, dim3(4096), dim3(256), 0, s, g, F);
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_pack(const Geo& g, const Fld& f, void* packed, hipStream_t s) {
   Fld F = f;
   F.packed = packed;
-  if (f.kind == AIR_FIELD_RHO_J_KAPPA)
-    hipLaunchKernelGGL(k_pack<AIR_FIELD_RHO_J_KAPPA>, dim3(4096), dim3(256), 0, s, g, F);
-  else
-    hipLaunchKernelGGL(k_pack<AIR_FIELD_RHO_T>, dim3(4096), dim3(256), 0, s, g, F);
+  switch (pack_mode(f)) {
+    case PACK_RJK: hipLaunchKernelGGL(k_pack<PACK_RJK>, dim3(4096), dim3(256), 0, s, g, F); break;
+    case PACK_RT_TO_RJK: hipLaunchKernelGGL(k_pack<PACK_RT_TO_RJK>, dim3(4096), dim3(256), 0, s, g, F); break;
+    default: hipLaunchKernelGGL(k_pack<PACK_RT>, dim3(4096), dim3(256), 0, s, g, F);
+  }
   return hipGetLastError();
 }
 

@@ -229,7 +229,19 @@ __device__ __forceinline__ unsigned long long block_sum_u64(unsigned long long x
 }
 
 // per chunk of CHUNK positions: existing nodes (for the scan) and the tree
-// counters, written per chunk; no global atomics
+// counters, written per chunk; no global atomics.  Each thread reads its 16
+// consecutive state bytes with one load.
+constexpr int PPT = CHUNK / 256;  // positions per thread
+static_assert(PPT == 16, "one 16-byte state load per thread");
+
+__device__ __forceinline__ uint4 state16(const uint8_t* st, int64_t p) {
+  return *reinterpret_cast<const uint4*>(st + p);
+}
+__device__ __forceinline__ uint8_t byte_of(const uint4& q, int k) {
+  const uint32_t w = k < 4 ? q.x : k < 8 ? q.y : k < 12 ? q.z : q.w;
+  return (uint8_t)(w >> (8 * (k & 3)));
+}
+
 __global__ __launch_bounds__(256) void k_count(MarchArgs A, unsigned long long* chunk_counts, unsigned* chunk_stats,
                                                int64_t n_chunks) {
   __shared__ unsigned sh[VS_N][4];
@@ -238,9 +250,10 @@ __global__ __launch_bounds__(256) void k_count(MarchArgs A, unsigned long long* 
 #pragma unroll
   for (int q = 0; q < VS_N; ++q) cnt[q] = 0;
   const bool above0 = chunk_pos(A.img, c).L > 0;
-  for (int k = 0; k < CHUNK / 256; ++k) {
-    const int64_t p = c * CHUNK + k * 256 + threadIdx.x;
-    const uint8_t s = A.w.state[p];
+  const uint4 q4 = state16(A.w.state, c * CHUNK + threadIdx.x * PPT);
+#pragma unroll
+  for (int k = 0; k < PPT; ++k) {
+    const uint8_t s = byte_of(q4, k);
     const bool spec = (s & ST_SPEC) != 0;
     if (s & AIR_NODE_EXIST) {
       ++cnt[VS_NODES];
@@ -270,25 +283,30 @@ __global__ __launch_bounds__(256) void k_count(MarchArgs A, unsigned long long* 
 }
 
 // per (view, level): sum the counters of its chunks (levels start on a
-// chunk), fixed order
+// chunk) in one pass, fixed order
 __global__ __launch_bounds__(256) void k_reduce_stats(MarchArgs A, const unsigned* chunk_stats, int64_t n_chunks,
                                                       unsigned long long* vstat) {
-  __shared__ unsigned long long sh[256];
+  __shared__ unsigned long long sh[VS_N][4];
   const int v = blockIdx.x / (A.img.Lmax + 1), L = blockIdx.x % (A.img.Lmax + 1);
   const int64_t c0 = ((int64_t)v * A.img.S + A.img.off[L]) / CHUNK;
   const int64_t c1 = ((int64_t)v * A.img.S + A.img.off[L + 1]) / CHUNK;
+  unsigned long long x[VS_N];
+#pragma unroll
+  for (int q = 0; q < VS_N; ++q) x[q] = 0;
+  for (int64_t c = c0 + threadIdx.x; c < c1; c += 256)
+#pragma unroll
+    for (int q = 0; q < VS_N; ++q) x[q] += chunk_stats[q * n_chunks + c];
+  const int w = threadIdx.x / WAVE;
+#pragma unroll
   for (int q = 0; q < VS_N; ++q) {
-    unsigned long long x = 0;
-    for (int64_t c = c0 + threadIdx.x; c < c1; c += 256) x += chunk_stats[q * n_chunks + c];
-    sh[threadIdx.x] = x;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-      if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) vstat[((int64_t)v * MAXL + L) * VS_N + q] = sh[0];
-    __syncthreads();
+    unsigned long long y = x[q];
+    for (int o = 32; o > 0; o >>= 1) y += __shfl_xor(y, o);
+    if ((threadIdx.x & (WAVE - 1)) == 0) sh[q][w] = y;
   }
+  __syncthreads();
+  if (threadIdx.x < VS_N)
+    vstat[((int64_t)v * MAXL + L) * VS_N + threadIdx.x] =
+        sh[threadIdx.x][0] + sh[threadIdx.x][1] + sh[threadIdx.x][2] + sh[threadIdx.x][3];
 }
 
 // exclusive scan of n counts in one block of 1024 threads: each thread sums
@@ -323,47 +341,60 @@ __global__ __launch_bounds__(1024) void k_scan(unsigned long long* a, int64_t n)
   if (tid == 0) a[n] = total;
 }
 
-// node ids: exclusive prefix of existing positions in canonical order
-__global__ __launch_bounds__(256) void k_emit(MarchArgs A, const unsigned long long* chunk_off, int32_t* id_map) {
-  __shared__ unsigned long long sh[4];
-  const int64_t c = blockIdx.x;
-  unsigned long long run = chunk_off[c];
-  for (int k = 0; k < CHUNK / 256; ++k) {
-    const int64_t p = c * CHUNK + k * 256 + threadIdx.x;
-    const bool ex = (A.w.state[p] & AIR_NODE_EXIST) != 0;
-    const uint64_t m = __ballot(ex);
-    const int w = threadIdx.x >> 6;
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0) sh[w] = __popcll(m);
-    __syncthreads();
-    unsigned long long before = 0, tot = 0;
-    for (int q = 0; q < 4; ++q) {
-      if (q < w) before += sh[q];
-      tot += sh[q];
-    }
-    if (ex) id_map[p] = (int32_t)(run + before + lanes_below(m));
-    run += tot;
-  }
-}
-
-// one block per chunk; empty chunks return at once
-__global__ __launch_bounds__(256) void k_write_tree(MarchArgs A, const unsigned long long* chunk_off,
-                                                    const int32_t* id_map, const TreeOut* outs) {
+// node ids: exclusive prefix of existing positions in canonical order; also
+// the compact list of the nodes' positions (node_pos[id])
+__global__ __launch_bounds__(256) void k_emit(MarchArgs A, const unsigned long long* chunk_off, int32_t* id_map,
+                                              uint64_t* node_pos) {
+  __shared__ unsigned wsum[4];
   const int64_t c = blockIdx.x;
   if (chunk_off[c + 1] == chunk_off[c]) return;
-  const ChunkPos cp = chunk_pos(A.img, c);
+  const int64_t p0 = c * CHUNK + threadIdx.x * PPT;
+  const uint4 q4 = state16(A.w.state, p0);
+  unsigned mine = 0;
+#pragma unroll
+  for (int k = 0; k < PPT; ++k) mine += (byte_of(q4, k) & AIR_NODE_EXIST) ? 1u : 0u;
+  const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+  unsigned x = mine;  // inclusive prefix in the wave
+  for (int o = 1; o < WAVE; o <<= 1) {
+    const unsigned y = __shfl_up(x, o);
+    if (lane >= o) x += y;
+  }
+  if (lane == WAVE - 1) wsum[w] = x;
+  __syncthreads();
+  unsigned before = x - mine;
+  for (int q = 0; q < w; ++q) before += wsum[q];
+  unsigned long long id = chunk_off[c] + before;
+#pragma unroll
+  for (int k = 0; k < PPT; ++k)
+    if (byte_of(q4, k) & AIR_NODE_EXIST) {
+      id_map[p0 + k] = (int32_t)id;
+      node_pos[id] = (uint64_t)(p0 + k);
+      ++id;
+    }
+}
+
+// one thread per node (grid-stride up to the total the scan left in
+// chunk_off[n_chunks]): ids are consecutive, so every output array is
+// written contiguously
+__global__ __launch_bounds__(256) void k_write_tree(MarchArgs A, const unsigned long long* chunk_off, int64_t n_chunks,
+                                                    const int32_t* id_map, const uint64_t* node_pos,
+                                                    const TreeOut* outs) {
+  const unsigned long long total = chunk_off[n_chunks];
   const int64_t S = A.img.S, VS = (int64_t)A.img.V * S, cpv = S / CHUNK;
-  const int N0 = A.img.N0, nb = A.f.nb, L = cp.L;
-  const TreeOut& T = outs[cp.v];
-  const int64_t base = (int64_t)chunk_off[cp.v * cpv];
-  const int64_t vb = (int64_t)cp.v * S;
-  for (int k = threadIdx.x; k < CHUNK; k += 256) {
-    const int64_t p = c * CHUNK + k;
-    const uint8_t s = A.w.state[p];
-    if (!(s & AIR_NODE_EXIST)) continue;
-    const uint32_t key = (uint32_t)(cp.key0 + k);
-    const int64_t id = (int64_t)id_map[p] - base;
+  const int N0 = A.img.N0, nb = A.f.nb;
+  for (unsigned long long g = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x; g < total;
+       g += (unsigned long long)gridDim.x * blockDim.x) {
+    const int64_t p = (int64_t)node_pos[g];
+    const int v = (int)(p / S);
+    const int64_t local = p - (int64_t)v * S;
+    const int L = level_of(A.img, local);
+    const uint32_t key = (uint32_t)(local - A.img.off[L]);
+    const TreeOut& T = outs[v];
+    const int64_t base = (int64_t)chunk_off[v * cpv];
+    const int64_t id = (int64_t)g - base;
     if (id >= T.capacity) continue;
+    const int64_t vb = (int64_t)v * S;
+    const uint8_t s = A.w.state[p];
     uint32_t i, j;
     coords_of(key, L, N0, i, j);
     if (T.level) T.level[id] = (int8_t)L;
@@ -383,17 +414,11 @@ __global__ __launch_bounds__(256) void k_write_tree(MarchArgs A, const unsigned 
   }
 }
 
-// raster of the leaves: each finest pixel descends from its coarse pixel;
-// grid (pixels / 256, views)
-__global__ __launch_bounds__(256) void k_assemble(MarchArgs A, float* images) {
-  const int N0 = A.img.N0, Lm = A.img.Lmax, nb = A.f.nb;
-  const uint32_t R = (uint32_t)N0 << Lm;
-  const int64_t R2 = (int64_t)R * R, VS = (int64_t)A.img.V * A.img.S;
-  const int v = blockIdx.y;
-  const int64_t vb = (int64_t)v * A.img.S;
-  const uint32_t e = blockIdx.x * 256u + threadIdx.x;
-  if ((int64_t)e >= R2) return;
-  const uint32_t i = e % R, j = e / R;
+// raster of the leaves: each finest pixel descends from its coarse pixel to
+// the leaf holding it; a thread paints QX consecutive pixels of a row (16-byte
+// stores per plane when QX = 4); grid (pixels / QX / 256, views)
+__device__ __forceinline__ int64_t leaf_pos(const MarchArgs& A, int64_t vb, uint32_t i, uint32_t j) {
+  const int N0 = A.img.N0, Lm = A.img.Lmax;
   uint32_t key = (j >> Lm) * (uint32_t)N0 + (i >> Lm);
   int L = 0;
   int64_t p = vb + key;
@@ -403,35 +428,70 @@ __global__ __launch_bounds__(256) void k_assemble(MarchArgs A, float* images) {
     key = 4u * key + (((i >> sh) & 1u) | (((j >> sh) & 1u) << 1));
     p = vb + A.img.off[L] + key;
   }
+  return p;
+}
+
+template <int QX>
+__global__ __launch_bounds__(256) void k_assemble(MarchArgs A, float* images) {
+  const int N0 = A.img.N0, Lm = A.img.Lmax, nb = A.f.nb;
+  const uint32_t R = (uint32_t)N0 << Lm;
+  const int64_t R2 = (int64_t)R * R, VS = (int64_t)A.img.V * A.img.S;
+  const int v = blockIdx.y;
+  const int64_t vb = (int64_t)v * A.img.S;
+  const int64_t e = ((int64_t)blockIdx.x * 256 + threadIdx.x) * QX;
+  if (e >= R2) return;
+  const uint32_t i = (uint32_t)(e % R), j = (uint32_t)(e / R);
+  int64_t p[QX];
+#pragma unroll
+  for (int q = 0; q < QX; ++q) p[q] = leaf_pos(A, vb, i + q, j);
   float* img = images + (int64_t)v * (nb + 1) * R2 + e;
-  for (int b = 0; b < nb; ++b) img[b * R2] = A.w.valI[b * VS + p];
-  img[nb * R2] = A.w.valN[p];
+  for (int b = 0; b <= nb; ++b) {
+    const float* src = b < nb ? A.w.valI + b * VS : A.w.valN;
+    if constexpr (QX == 4) {
+      float4 o;
+      o.x = src[p[0]];
+      o.y = src[p[1]];
+      o.z = src[p[2]];
+      o.w = src[p[3]];
+      *reinterpret_cast<float4*>(img + b * R2) = o;
+    } else {
+      img[b * R2] = src[p[0]];
+    }
+  }
 }
 
 // flux partials per chunk and band: sum over leaves of (pixel area) I_b,
-// float64, fixed reduction order
+// float64, fixed reduction order; one pass over the chunk's states for all
+// bands
+__device__ __forceinline__ double wave_sum_f64(double x) {
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+  return x;
+}
+
 __global__ __launch_bounds__(256) void k_flux_partial(MarchArgs A, const DevView* views, double* partial) {
-  __shared__ double sh[256];
+  __shared__ double sh[MAXB][4];
   const int64_t c = blockIdx.x, VS = (int64_t)A.img.V * A.img.S;
   const int nb = A.f.nb;
   const ChunkPos cp = chunk_pos(A.img, c);
   const double px = views[cp.v].width / (double)((int64_t)A.img.N0 << cp.L), area = px * px;
-  for (int b = 0; b < nb; ++b) {
-    double s = 0.0;
-    for (int k = 0; k < CHUNK / 256; ++k) {
-      const int64_t p = c * CHUNK + k * 256 + threadIdx.x;
-      const uint8_t st = A.w.state[p];
-      if ((st & AIR_NODE_EXIST) && !(st & AIR_NODE_REFINED)) s += area * (double)A.w.valI[b * VS + p];
-    }
-    sh[threadIdx.x] = s;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-      if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) partial[c * nb + b] = sh[0];
-    __syncthreads();
+  const int64_t p0 = c * CHUNK + threadIdx.x * PPT;
+  const uint4 q4 = state16(A.w.state, p0);
+  double s[MAXB];
+#pragma unroll
+  for (int b = 0; b < MAXB; ++b) s[b] = 0.0;
+#pragma unroll
+  for (int k = 0; k < PPT; ++k) {
+    const uint8_t st = byte_of(q4, k);
+    if ((st & AIR_NODE_EXIST) && !(st & AIR_NODE_REFINED))
+      for (int b = 0; b < nb; ++b) s[b] += area * (double)A.w.valI[b * VS + p0 + k];
   }
+  const int w = threadIdx.x / WAVE;
+  for (int b = 0; b < nb; ++b) {
+    const double x = wave_sum_f64(s[b]);
+    if ((threadIdx.x & (WAVE - 1)) == 0) sh[b][w] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x < nb) partial[c * nb + threadIdx.x] = ((sh[threadIdx.x][0] + sh[threadIdx.x][1]) + sh[threadIdx.x][2]) + sh[threadIdx.x][3];
 }
 
 // per (view, band): sum the view's chunk partials, fixed order (each thread
@@ -512,21 +572,28 @@ hipError_t launch_scan(unsigned long long* chunk_counts, int64_t n_chunks, hipSt
 }
 
 hipError_t launch_emit(const MarchArgs& a, const unsigned long long* chunk_offsets, int64_t n_chunks,
-                       int32_t* id_map, hipStream_t s) {
-  hipLaunchKernelGGL(k_emit, dim3((unsigned)n_chunks), dim3(256), 0, s, a, chunk_offsets, id_map);
+                       int32_t* id_map, uint64_t* node_pos, hipStream_t s) {
+  hipLaunchKernelGGL(k_emit, dim3((unsigned)n_chunks), dim3(256), 0, s, a, chunk_offsets, id_map, node_pos);
   return hipGetLastError();
 }
 
 hipError_t launch_write_tree(const MarchArgs& a, const unsigned long long* chunk_offsets, const int32_t* id_map,
-                             const TreeOut* outs, hipStream_t s) {
+                             const uint64_t* node_pos, const TreeOut* outs, int grid_blocks, hipStream_t s) {
   const int64_t n_chunks = (int64_t)a.img.V * a.img.S / CHUNK;
-  hipLaunchKernelGGL(k_write_tree, dim3((unsigned)n_chunks), dim3(256), 0, s, a, chunk_offsets, id_map, outs);
+  hipLaunchKernelGGL(k_write_tree, dim3(grid_blocks), dim3(256), 0, s, a, chunk_offsets, n_chunks, id_map, node_pos,
+                     outs);
   return hipGetLastError();
 }
 
 hipError_t launch_assemble(const MarchArgs& a, float* images, hipStream_t s) {
   const int64_t R = (int64_t)a.img.N0 << a.img.Lmax;
-  hipLaunchKernelGGL(k_assemble, dim3((unsigned)((R * R + 255) / 256), (unsigned)a.img.V), dim3(256), 0, s, a, images);
+  // rows of a multiple of 4 pixels, 16-byte aligned planes: four pixels per thread
+  if (R % 4 == 0 && ((uintptr_t)images & 15) == 0)
+    hipLaunchKernelGGL(k_assemble<4>, dim3((unsigned)((R * R / 4 + 255) / 256), (unsigned)a.img.V), dim3(256), 0, s,
+                       a, images);
+  else
+    hipLaunchKernelGGL(k_assemble<1>, dim3((unsigned)((R * R + 255) / 256), (unsigned)a.img.V), dim3(256), 0, s, a,
+                       images);
   return hipGetLastError();
 }
 

@@ -73,6 +73,8 @@ def test_packed_bytes_without_device():
     assert air.lib().air_field_packed_bytes(C.addressof(g), C.addressof(f)) == 3 * 4 * 2 * 8 * 16
     f.kind, f.temp, f.n_bands = 1, 16, 4
     assert air.lib().air_field_packed_bytes(C.addressof(g), C.addressof(f)) == 3 * 4 * 2 * 8 * 8
+    f.n_bands = 1  # one band: (rho, j, kappa) evaluated once when packing
+    assert air.lib().air_field_packed_bytes(C.addressof(g), C.addressof(f)) == 3 * 4 * 2 * 8 * 16
     f.n_bands = 9
     assert air.lib().air_field_packed_bytes(C.addressof(g), C.addressof(f)) == air.AIR_EINVAL
 

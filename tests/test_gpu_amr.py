@@ -137,10 +137,29 @@ def test_amr_packed_layout_contents(ctx):
     g = inputs.amr_from_predicate(1, 4, 1, lambda l, blo, sz: l == 0)
     n = g.n_cells
     f = inputs.Field(1, np.arange(n, dtype=np.float32), temp=1000 + np.arange(n, dtype=np.float32),
-                     bands=inputs.default_bands(1))
+                     bands=inputs.default_bands(2))
     sc = ctx.prepare(air.upload(g, f))
     got = sc.tensors[-1].cpu().numpy().view(np.float32).reshape(-1, 2)
     assert np.array_equal(got, _amr_brick_order(np.stack([f.rho, f.temp], axis=-1), 4))
+
+
+def test_one_band_rho_t_packs_coefficients(ctx):
+    """A one-band (rho, T) field is packed as (rho, j, kappa, 0) records,
+    j = rho^2 T^q and kappa = k0 rho T^-s evaluated once."""
+    from paper_1010_5534_amd import air
+    g = inputs.amr_from_predicate(1, 4, 1, lambda l, blo, sz: l == 0)
+    n = g.n_cells
+    rng = np.random.default_rng(3)
+    rho = rng.uniform(0.1, 2.0, n).astype(np.float32)
+    T = rng.uniform(0.5, 10.0, n).astype(np.float32)
+    band = np.array([[0.7, 1.5, 0.5]])
+    f = inputs.Field(1, rho, temp=T, bands=band)
+    got = ctx.prepare(air.upload(g, f)).tensors[-1].cpu().numpy().view(np.float32).reshape(-1, 4)
+    r64, t64 = rho.astype(np.float64), T.astype(np.float64)
+    ref = np.stack([r64, r64 * r64 * t64 ** 0.5, 0.7 * r64 * t64 ** -1.5, np.zeros(n)], axis=-1)
+    ref = _amr_brick_order(ref, 4)
+    assert np.array_equal(got[:, 0], ref[:, 0].astype(np.float32)) and np.all(got[:, 3] == 0)
+    assert np.allclose(got[:, 1:3], ref[:, 1:3], rtol=2e-6, atol=0)
 
 
 def _bad_tables():
