@@ -231,24 +231,25 @@ def stats_dict(s: air_stats) -> dict:
                 march_launches=s.march_launches, ms_total=s.ms_total, ms_march=s.ms_march, ms_test=s.ms_test)
 
 
-@dataclasses.dataclass
 class Tree:
-    """Pixel quadtree of one view (device tensors, canonical order)."""
+    """Pixel quadtree of one view (device tensors, canonical order).  The
+    node arrays (level, ix, iy, parent, first_child, state, I [bands, n],
+    N, xi_I, xi_N, visits) are views of the output buffers, cut to n_nodes
+    when first read."""
 
-    n_nodes: int
-    n_per_level: list
-    n_leaves: int
-    level: object
-    ix: object
-    iy: object
-    parent: object
-    first_child: object
-    state: object
-    I: object
-    N: object
-    xi_I: object
-    xi_N: object
-    visits: object
+    ARRAYS = ("level", "ix", "iy", "parent", "first_child", "state", "I", "N", "xi_I", "xi_N", "visits")
+
+    def __init__(self, n_nodes: int, n_per_level: list, n_leaves: int, buffers: dict):
+        self.n_nodes = n_nodes
+        self.n_per_level = n_per_level
+        self.n_leaves = n_leaves
+        self._buf = buffers
+
+    def __getattr__(self, name):
+        if name in Tree.ARRAYS:
+            b = self.__dict__["_buf"][name]
+            return b[:, :self.n_nodes] if name == "I" else b[:self.n_nodes]
+        raise AttributeError(name)
 
 
 class Context:
@@ -395,8 +396,7 @@ class Context:
             for k in range(V):
                 n = trees[k].n_nodes
                 t = keep[k]
-                out.append(Tree(n, list(trees[k].n_per_level), trees[k].n_leaves,
-                                **{name: (t[name][:, :n] if name == "I" else t[name][:n]) for name in t}))
+                out.append(Tree(n, list(trees[k].n_per_level), trees[k].n_leaves, t))
         return out, images, flux, stats_dict(st)
 
     def render_fixed(self, scene: DeviceScene, views: Sequence, coarse_n: int, level: int, want_image=True,

@@ -33,6 +33,7 @@ struct air_ctx {
   int device = 0;
   int num_cus = 256;
   int seg_shift_override = -1;  // AIR_SEG_SHIFT: tuning knob for the lanes per ray
+  Tune eager;                   // launch shapes of air_render (AIR_MARCH_WAVES: march waves per CU)
   std::string err;
   DevBuf state, valI, valN, xiI, xiN, visits, rmin, rmax, queue, ctr, chunk, cstat, vstat, idmap, partial, flux,
       views, touts, pack;
@@ -651,7 +652,7 @@ air_status render_core(air_ctx* c, const air_grid* grid, const air_field* field,
     HIPCHK(c, hipStreamWaitEvent(s, c->cap_out, 0));
   } else {
     HIPCHK(c, hipEventRecord(ev[0], s));
-    if ((st = enqueue_render(c, P, Tune(), s))) return st;
+    if ((st = enqueue_render(c, P, c->eager, s))) return st;
   }
   HIPCHK(c, hipEventRecord(ev[1], s));
   const bool timing = P.timing;
@@ -763,6 +764,10 @@ air_status air_create(air_ctx** out, int32_t device) {
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
     c->num_cus = prop.multiProcessorCount;
+  if (const char* e = std::getenv("AIR_MARCH_WAVES")) {
+    const int v = std::atoi(e);
+    if (v >= 1 && v <= 64) c->eager.march_waves_per_cu = v;
+  }
   if (const char* e = std::getenv("AIR_SEG_SHIFT")) {
     const int v = std::atoi(e);
     if (v >= 0 && (1 << v) <= MAX_SEG) c->seg_shift_override = v;

@@ -58,10 +58,11 @@ __device__ __forceinline__ void kadd(float& s, float& c, float x) {
   s = t;
 }
 
-// (1 - e^-x)/x: Taylor series below 1/4 (truncation < 2e-9 relative),
-// direct form above (cancellation at most a factor 4.5); the direct form is
-// evaluated only when some lane of the wave needs it
-__device__ __forceinline__ float seg_weight(float x) {
+// (1 - e^-x)/x for 0 <= x < 1/4 by its Taylor series (truncation < 2e-9
+// relative); thicker cells use the transmission difference instead (see
+// AIR_INTEGRATE)
+constexpr float THICK = 0.25f;
+__device__ __forceinline__ float seg_weight_series(float x) {
   const float y = -x;
   float p = 1.0f / 5040.0f;
   p = __builtin_fmaf(p, y, 1.0f / 720.0f);
@@ -70,12 +71,6 @@ __device__ __forceinline__ float seg_weight(float x) {
   p = __builtin_fmaf(p, y, 1.0f / 6.0f);
   p = __builtin_fmaf(p, y, 0.5f);
   p = __builtin_fmaf(p, y, 1.0f);
-  const bool big = x >= 0.25f;
-  if (__ballot(big)) {
-    const float e = __builtin_amdgcn_exp2f(-x * LOG2E_F);
-    const float g = (1.0f - e) * __builtin_amdgcn_rcpf(x);
-    p = big ? g : p;
-  }
   return p;
 }
 
@@ -97,6 +92,7 @@ typedef int i32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 __device__ f32x4 buffer_load_f32x4(i32x4 rsrc, int voffset, int soffset, int aux) __asm("llvm.amdgcn.raw.buffer.load.v4f32");
+
 __device__ f32x2 buffer_load_f32x2(i32x4 rsrc, int voffset, int soffset, int aux) __asm("llvm.amdgcn.raw.buffer.load.v2f32");
 
 constexpr int RSRC_WORD3 = 0x00020000;  // raw 32-bit buffer on gfx9-class GPUs
@@ -238,16 +234,20 @@ __device__ __forceinline__ int cells_between(const Geo& g, const double o[3], co
   _Pragma("unroll") for (int q = 0; q < KB; ++q) RAW[q] = load_raw<FK>(R, OFF[q]);
 
 // One batch of up to KB cells: plain float32 sums inside the batch (at most
-// KB terms), one Kahan step per batch into the running I, tau, N.  The
-// transmission of each cell uses the compensated optical depth at the batch
-// start plus the batch's partial sum.
+// KB terms), one Kahan step per batch into the running I, tau, N.  Each
+// cell's exit transmission Ta = exp(-tau) comes from the compensated optical
+// depth at the batch start plus the batch's partial sum and is the next
+// cell's entry transmission Tb, so a cell costs one exp.  A cell adds
+// Tb j ds (1 - e^-x)/x, x = kappa ds: by the series for x < 1/4, else as
+// (Tb - Ta) j / kappa (cancellation at most a factor 4.5 there).
 #define AIR_INTEGRATE(V0, DS, RAW)                                        \
   {                                                                       \
-    float bI[NB], bT[NB], t0b[NB], bN = 0.0f;                             \
+    float bI[NB], bT[NB], t0b[NB], Tb[NB], bN = 0.0f;                     \
     _Pragma("unroll") for (int b = 0; b < NB; ++b) {                      \
       bI[b] = 0.0f;                                                       \
       bT[b] = 0.0f;                                                       \
       t0b[b] = tau[b] - ctau[b];                                          \
+      Tb[b] = __builtin_amdgcn_exp2f(-t0b[b] * LOG2E_F);                  \
     }                                                                     \
     _Pragma("unroll") for (int q = 0; q < KB; ++q) {                      \
       if ((V0) + q < nvis) {                                              \
@@ -256,9 +256,12 @@ __device__ __forceinline__ int cells_between(const Geo& g, const double o[3], co
         optics<NB, FK>(f, RAW[q], jb, kb);                                \
         _Pragma("unroll") for (int b = 0; b < NB; ++b) {                  \
           const float dtau = kb[b] * ds;                                  \
-          const float T = __builtin_amdgcn_exp2f(-(t0b[b] + bT[b]) * LOG2E_F); \
-          bI[b] += T * (jb[b] * ds) * seg_weight(dtau);                   \
           bT[b] += dtau;                                                  \
+          const float Ta = __builtin_amdgcn_exp2f(-(t0b[b] + bT[b]) * LOG2E_F); \
+          const float thin = Tb[b] * (jb[b] * ds) * seg_weight_series(dtau); \
+          const float thick = (Tb[b] - Ta) * jb[b] * __builtin_amdgcn_rcpf(kb[b]); \
+          bI[b] += dtau < THICK ? thin : thick;                           \
+          Tb[b] = Ta;                                                     \
         }                                                                 \
         bN += RAW[q].rho * ds;                                            \
         if constexpr (RANGE) {                                            \
@@ -275,7 +278,9 @@ __device__ __forceinline__ int cells_between(const Geo& g, const double o[3], co
   }
 
 // the whole cell walk, two batches in flight: walk and load batch n+1, then
-// integrate batch n
+// integrate batch n.  The next batch is issued unconditionally (past the
+// last cell the walk stays on it), so every iteration has the same loads in
+// flight and the waits count only the older batch.
 #define AIR_MARCH_CELLS()                                                 \
   {                                                                       \
     int offA[KB], offB[KB];                                               \
@@ -283,15 +288,19 @@ __device__ __forceinline__ int cells_between(const Geo& g, const double o[3], co
     Raw<FK> rawA[KB], rawB[KB];                                           \
     AIR_DDA_BATCH(0, offA, dsA, rawA)                                     \
     for (int v0 = 0;;) {                                                  \
-      if (v0 + KB < nvis) {                                               \
-        AIR_DDA_BATCH(v0 + KB, offB, dsB, rawB)                           \
-      }                                                                   \
+      AIR_DDA_BATCH(v0 + KB, offB, dsB, rawB)                             \
       AIR_INTEGRATE(v0, dsA, rawA)                                        \
       v0 += KB;                                                           \
       if (v0 >= nvis) break;                                              \
-      if (v0 + KB < nvis) {                                               \
-        AIR_DDA_BATCH(v0 + KB, offA, dsA, rawA)                           \
-      }                                                                   \
+      AIR_DDA_BATCH(v0 + KB, offA, dsA, rawA)                             \
+      AIR_INTEGRATE(v0, dsB, rawB)                                        \
+      v0 += KB;                                                           \
+      if (v0 >= nvis) break;                                              \
+      AIR_DDA_BATCH(v0 + KB, offB, dsB, rawB)                             \
+      AIR_INTEGRATE(v0, dsA, rawA)                                        \
+      v0 += KB;                                                           \
+      if (v0 >= nvis) break;                                              \
+      AIR_DDA_BATCH(v0 + KB, offA, dsA, rawA)                             \
       AIR_INTEGRATE(v0, dsB, rawB)                                        \
       v0 += KB;                                                           \
       if (v0 >= nvis) break;                                              \
