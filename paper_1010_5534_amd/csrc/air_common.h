@@ -190,8 +190,12 @@ struct Tune {
   int refine_blocks_per_cu = 4;
 };
 hipError_t launch_features(const MarchArgs& a, const LearnW& w, float* feat, hipStream_t s);
-hipError_t launch_decide(const float* logits, int64_t total, int dmax, float c_ray, float c_sweep, uint8_t* depth,
-                         unsigned long long* counts, hipStream_t s);
+// the same maps standardised ((x - mean) * inv_std) and rounded to bf16
+// straight into the network's input rows [V*N0*N0][8]
+struct FeatNorm {
+  float mean[4], inv_std[4];
+};
+hipError_t launch_features_bf16(const MarchArgs& a, const LearnW& w, const FeatNorm& nm, uint16_t* x0, hipStream_t s);
 hipError_t launch_spec_emit(const uint8_t* depth, const unsigned long long* offsets, int64_t total, int64_t n0sq,
                             uint64_t* spec, hipStream_t s);
 hipError_t launch_tree_depth(const int8_t* level, const int32_t* ix, const int32_t* iy, int64_t n, int N0,

@@ -455,15 +455,17 @@ air_status learned_steps(air_ctx* c, const MarchArgs& A, const air_cnn* net, con
   LearnW W;
   for (int b = 0; b < MAXB; ++b) W.w[b] = w[b];
   if (timing) HIPCHK(c, hipEventRecord(c->ev[air_ctx::EV_FEAT0], s));
-  HIPCHK(c, launch_features(A, W, (float*)c->feat.p, s));
-  HIPCHK(c, cnn::input_maps((const float*)c->feat.p, total, net->net.mean, net->net.stdv, (uint16_t*)c->cx0.p, s));
-  HIPCHK(c, cnn::conv_forward(0, net->net, (const uint16_t*)c->cx0.p, V, N0, N0, c->ca1.p, s));
-  HIPCHK(c, cnn::conv_forward(1, net->net, (const uint16_t*)c->ca1.p, V, N0, N0, c->ca2.p, s));
-  HIPCHK(c, cnn::conv_forward(2, net->net, (const uint16_t*)c->ca2.p, V, N0, N0, c->ca3.p, s));
-  HIPCHK(c, cnn::conv_forward(3, net->net, (const uint16_t*)c->ca3.p, V, N0, N0, c->cz.p, s));
+  FeatNorm nm;
+  for (int k = 0; k < 4; ++k) {
+    nm.mean[k] = net->net.mean[k];
+    nm.inv_std[k] = 1.0f / net->net.stdv[k];
+  }
+  HIPCHK(c, launch_features_bf16(A, W, nm, (uint16_t*)c->cx0.p, s));
   const int dmax = std::min(lp->max_depth, std::min(A.img.Lmax, DEPTH_CLASSES - 1));
   unsigned long long* cnt = (unsigned long long*)c->scount.p;
-  HIPCHK(c, launch_decide((const float*)c->cz.p, total, dmax, lp->c_ray, lp->c_sweep, (uint8_t*)c->depth8.p, cnt, s));
+  // the four layers and the depth choice in one launch
+  HIPCHK(c, cnn::infer_depth(net->net, (const uint16_t*)c->cx0.p, V, N0, N0, dmax, lp->c_ray, lp->c_sweep,
+                             (uint8_t*)c->depth8.p, cnt, s));
   HIPCHK(c, launch_scan(cnt, total, s));
   HIPCHK(c, launch_spec_emit((const uint8_t*)c->depth8.p, cnt, total, (int64_t)N0 * N0, (uint64_t*)c->spec.p, s));
   if (timing) HIPCHK(c, hipEventRecord(c->ev[air_ctx::EV_SPEC0], s));
@@ -523,6 +525,10 @@ std::string plan_key(const Plan& P, const Tune& t) {
   k.append(reinterpret_cast<const char*>(&P.n_chunks), sizeof P.n_chunks);
   k.append(reinterpret_cast<const char*>(&P.xcI), sizeof(float) * (2 + MAXB));
   k.append(reinterpret_cast<const char*>(&P.net), sizeof P.net);
+  if (P.net) {  // the standardisation is a kernel argument of the captured sequence
+    k.append(reinterpret_cast<const char*>(P.net->net.mean), sizeof P.net->net.mean);
+    k.append(reinterpret_cast<const char*>(P.net->net.stdv), sizeof P.net->net.stdv);
+  }
   k.append(reinterpret_cast<const char*>(&P.lp), sizeof P.lp);
   const char flags[3] = {(char)P.trees, (char)P.flux, (char)P.timing};
   k.append(flags, 3);

@@ -26,7 +26,7 @@ constexpr int KPAD(int cin_stored) { return (9 * cin_stored + 31) / 32 * 32; }
 struct Offsets {
   int w[LAYERS], b[LAYERS], total;
 };
-inline Offsets offsets() {
+__host__ __device__ inline Offsets offsets() {
   Offsets o{};
   int p = 0;
   for (int l = 0; l < LAYERS; ++l) {
@@ -52,6 +52,42 @@ struct Net {
   bool dirty = true;  // bf16 operands need rebuilding from theta
 };
 
+// rays of levels 1..d below one coarse pixel
+__host__ __device__ inline unsigned long long subtree_rays(int d) {
+  unsigned long long s = 0, q = 1;
+  for (int l = 1; l <= d; ++l) {
+    q *= 4;
+    s += q;
+  }
+  return s;
+}
+
+// cost-aware depth choice from one pixel's six logits: argmin over d <= dmax
+// of c_ray * rays(1..d) + c_sweep * P(depth > d), P the softmax; ties go to
+// the shallower depth
+__device__ inline int depth_choice(const float* z, int dmax, float c_ray, float c_sweep) {
+  float m = z[0];
+  for (int c = 1; c < CLASSES; ++c) m = fmaxf(m, z[c]);
+  float p[CLASSES], se = 0.0f;
+  for (int c = 0; c < CLASSES; ++c) {
+    p[c] = expf(z[c] - m);
+    se += p[c];
+  }
+  for (int c = 0; c < CLASSES; ++c) p[c] = p[c] / se;
+  int best = 0;
+  float best_cost = __builtin_huge_valf();
+  for (int d = 0; d <= dmax; ++d) {
+    float tail = 0.0f;
+    for (int c = d + 1; c < CLASSES; ++c) tail += p[c];
+    const float cost = c_ray * (float)subtree_rays(d) + c_sweep * tail;
+    if (cost < best_cost) {
+      best = d;
+      best_cost = cost;
+    }
+  }
+  return best;
+}
+
 // launchers; every pointer is device memory.  n = maps, h x w pixels each
 hipError_t prep_weights(const Net& net, hipStream_t s);
 hipError_t input_maps(const float* feat, int64_t P, const float* mean, const float* stdv, uint16_t* x, hipStream_t s);
@@ -73,6 +109,11 @@ hipError_t loss_and_dz(const float* z, const int32_t* labels, int64_t P, const f
                        double* out, uint16_t* dz, hipStream_t s);
 size_t loss_partial_doubles();
 hipError_t adam(Net& net, int P, float lr, float beta1, float beta2, float eps, hipStream_t s);
+// inference of all four layers on n maps of bf16 input rows x [n*h*w][8]
+// (16x16 output tiles, activations kept in LDS) followed by the depth choice:
+// depth[p] and its speculative ray count counts[p] per pixel
+hipError_t infer_depth(const Net& net, const uint16_t* x, int n, int h, int w, int dmax, float c_ray, float c_sweep,
+                       uint8_t* depth, unsigned long long* counts, hipStream_t s);
 
 }  // namespace cnn
 }  // namespace air

@@ -358,6 +358,107 @@ int conv_blocks(int64_t P) {
   return (int)std::min<int64_t>(std::max<int64_t>((tiles + waves - 1) / waves, 1), 2048);
 }
 
+// ---------------------------------------------------------------- inference
+// All four layers for one 16x16 output tile of one map: the input rows of a
+// 24x24 region (4-pixel halo) and each hidden layer's 22x22, 20x20, 18x18
+// region stay in LDS as bf16 NHWC; positions outside the image are zero, as
+// the layer-by-layer kernels' zero padding.  Every output pixel sees the
+// same MFMA sequence (same operands, same K order) as in k_conv, so the
+// logits are bit-identical to the layer-by-layer path.  The last layer's
+// logits go through LDS to the depth choice, one thread per pixel.
+constexpr int IT = 16;  // output tile edge
+
+template <int CS, int RW>
+__device__ __forceinline__ void fused_layer(const uint16_t* __restrict__ wmat, const float* __restrict__ bias,
+                                            int nbias, const uint16_t* in, int rin, uint16_t* out, float* zout,
+                                            int y0, int x0, int h, int w) {
+  constexpr int K = 9 * CS, KP = (K + 31) / 32 * 32, KS = KP / 32, MB = RW / 16;
+  const int lane = threadIdx.x & (WAVE - 1), g = lane >> 4, c16 = lane & 15, wv = threadIdx.x / WAVE;
+  const int rout = rin - 2, npx = rout * rout;
+  u16x8 a[MB][KS];
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
+      a[mb][ks] = *reinterpret_cast<const u16x8*>(wmat + (mb * 16 + c16) * KP + ks * 32 + 8 * g);
+  for (int t = wv; t * 16 < npx; t += 4) {
+    const int p = t * 16 + c16;
+    const bool ok = p < npx;
+    const int py = ok ? p / rout : 0, px = ok ? p % rout : 0;
+    f32x4 acc[MB];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) acc[mb] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int k0 = ks * 32 + 8 * g;
+      u16x8 bv = {0, 0, 0, 0, 0, 0, 0, 0};
+      if (ok && k0 < K) {
+        const int tap = k0 / CS, c0 = k0 % CS;
+        bv = *reinterpret_cast<const u16x8*>(in + ((py + tap / 3) * rin + (px + tap % 3)) * CS + c0);
+      }
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) acc[mb] = mfma(a[mb][ks], bv, acc[mb]);
+    }
+    if (!ok) continue;
+    // global position of this output pixel: region origin is tile origin
+    // minus the remaining halo
+    const int halo = (rout - IT) / 2;
+    const int gy = y0 - halo + py, gx = x0 - halo + px;
+    const bool inside = gy >= 0 && gy < h && gx >= 0 && gx < w;
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+      const int r0 = mb * 16 + 4 * g;
+      if (zout) {  // logits (last layer): channels 0..7 of the 16 rows
+        if (r0 < 8)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) zout[p * 8 + r0 + i] = acc[mb][i] + (r0 + i < nbias ? bias[r0 + i] : 0.0f);
+      } else {
+        u16x4 o;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          o[i] = inside ? f2bf(fmaxf(acc[mb][i] + (r0 + i < nbias ? bias[r0 + i] : 0.0f), 0.0f)) : (uint16_t)0;
+        *reinterpret_cast<u16x4*>(out + p * HID + r0) = o;
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_infer(Prep W, const float* theta, const uint16_t* x, int h, int w, int dmax,
+                                               float c_ray, float c_sweep, uint8_t* depth,
+                                               unsigned long long* counts) {
+  __shared__ __attribute__((aligned(16))) uint16_t bufA[20 * 20 * HID];  // input rows, then layer-1 output
+  __shared__ __attribute__((aligned(16))) uint16_t bufB[22 * 22 * HID];  // layer-0 output, then layer-2 output
+  __shared__ float z[IT * IT * 8];
+  const int tiles_x = (w + IT - 1) / IT, tiles_y = (h + IT - 1) / IT;
+  const int map = blockIdx.x / (tiles_x * tiles_y), tix = blockIdx.x % (tiles_x * tiles_y);
+  const int y0 = (tix / tiles_x) * IT, x0 = (tix % tiles_x) * IT;
+  const uint16_t* xm = x + (int64_t)map * h * w * XC;
+  // input rows of the 24x24 region (zero outside the image)
+  for (int e = threadIdx.x; e < 24 * 24; e += 256) {
+    const int gy = y0 - 4 + e / 24, gx = x0 - 4 + e % 24;
+    u16x8 v = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (gy >= 0 && gy < h && gx >= 0 && gx < w) v = *reinterpret_cast<const u16x8*>(xm + ((int64_t)gy * w + gx) * XC);
+    *reinterpret_cast<u16x8*>(bufA + e * XC) = v;
+  }
+  __syncthreads();
+  const Offsets o = offsets();
+  fused_layer<XC, HID>(W.wf[0], theta + o.b[0], HID, bufA, 24, bufB, nullptr, y0, x0, h, w);
+  __syncthreads();
+  fused_layer<HID, HID>(W.wf[1], theta + o.b[1], HID, bufB, 22, bufA, nullptr, y0, x0, h, w);
+  __syncthreads();
+  fused_layer<HID, HID>(W.wf[2], theta + o.b[2], HID, bufA, 20, bufB, nullptr, y0, x0, h, w);
+  __syncthreads();
+  fused_layer<HID, 16>(W.wf[3], theta + o.b[3], CLASSES, bufB, 18, nullptr, z, y0, x0, h, w);
+  __syncthreads();
+  const int py = threadIdx.x / IT, px = threadIdx.x % IT, gy = y0 + py, gx = x0 + px;
+  if (gy < h && gx < w) {
+    const int d = depth_choice(z + threadIdx.x * 8, dmax, c_ray, c_sweep);
+    const int64_t e = (int64_t)map * h * w + (int64_t)gy * w + gx;
+    depth[e] = (uint8_t)d;
+    counts[e] = subtree_rays(d);
+  }
+}
+
 }  // namespace
 
 hipError_t prep_weights(const Net& net, hipStream_t s) {
@@ -457,6 +558,20 @@ hipError_t loss_and_dz(const float* z, const int32_t* labels, int64_t P, const f
   hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, s, partial, LOSS_BLOCKS, out);
   const int blocks = (int)std::min<int64_t>((P + 255) / 256 + 1, 4096);
   hipLaunchKernelGGL(k_dz, dim3(blocks), dim3(256), 0, s, z, labels, P, cw, out, dz);
+  return hipGetLastError();
+}
+
+hipError_t infer_depth(const Net& net, const uint16_t* x, int n, int h, int w, int dmax, float c_ray, float c_sweep,
+                       uint8_t* depth, unsigned long long* counts, hipStream_t s) {
+  Prep P;
+  P.theta = net.theta;
+  for (int l = 0; l < LAYERS; ++l) {
+    P.wf[l] = net.wf[l];
+    P.wt[l] = net.wt[l];
+    P.woff[l] = 0;
+  }
+  const int tiles = ((w + IT - 1) / IT) * ((h + IT - 1) / IT) * n;
+  hipLaunchKernelGGL(k_infer, dim3(tiles), dim3(256), 0, s, P, net.theta, x, h, w, dmax, c_ray, c_sweep, depth, counts);
   return hipGetLastError();
 }
 

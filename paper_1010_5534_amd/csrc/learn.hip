@@ -1,19 +1,28 @@
 // Learned depth proposal around plain AIR: the coarse feature maps, the
-// cost-aware depth decision, the speculative work list and the depth labels
-// of finished trees.  The network itself is in cnn.hip; the speculative
-// march in march.hip.
+// speculative work list and the depth labels of finished trees.  The network
+// and the cost-aware depth choice are in cnn.hip; the speculative march in
+// march.hip.
 #include <algorithm>
 
 #include "air_common.h"
+#include "cnn.h"
 
 namespace air {
 
 namespace {
 
+__device__ __forceinline__ uint16_t to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0;
+  u += 0x7fffu + ((u >> 16) & 1u);  // nearest, ties to even
+  return (uint16_t)(u >> 16);
+}
+
 // raw features of each coarse pixel, raster order [V][N0][N0][4]:
 // log10(I_w + 1e-30), log10(N + 1e-30), finest grid level crossed (-1 for a
 // miss), log10(rho_max / rho_min) along the ray (0 for a miss or rho_min 0)
-__global__ __launch_bounds__(256) void k_features(MarchArgs A, LearnW W, float* feat) {
+template <bool BF16>
+__global__ __launch_bounds__(256) void k_features(MarchArgs A, LearnW W, float* feat, FeatNorm nm, uint16_t* x0) {
   const int N0 = A.img.N0, nb = A.f.nb;
   const int64_t n0sq = (int64_t)N0 * N0, total = (int64_t)A.img.V * n0sq, VS = (int64_t)A.img.V * A.img.S;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
@@ -29,45 +38,17 @@ __global__ __launch_bounds__(256) void k_features(MarchArgs A, LearnW W, float* 
     o.y = log10f(N + 1e-30f);
     o.z = (float)lm;
     o.w = (lm >= 0 && rmin > 0.0f) ? log10f(rmax / rmin) : 0.0f;
-    reinterpret_cast<float4*>(feat)[e] = o;
-  }
-}
-
-__device__ __forceinline__ unsigned long long subtree_rays(int d) {
-  unsigned long long s = 0, q = 1;
-  for (int l = 1; l <= d; ++l) {
-    q *= 4;
-    s += q;
-  }
-  return s;
-}
-
-// depth per coarse pixel: argmin_d c_ray * rays(1..d) + c_sweep * P(depth > d)
-__global__ __launch_bounds__(256) void k_decide(const float* z, int64_t total, int dmax, float c_ray, float c_sweep,
-                                                uint8_t* depth, unsigned long long* counts) {
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-    const float* zp = z + e * LOGIT_STRIDE;
-    float m = zp[0];
-    for (int c = 1; c < DEPTH_CLASSES; ++c) m = fmaxf(m, zp[c]);
-    float p[DEPTH_CLASSES], se = 0.0f;
-    for (int c = 0; c < DEPTH_CLASSES; ++c) {
-      p[c] = expf(zp[c] - m);
-      se += p[c];
+    if constexpr (BF16) {
+      // the network's input row: standardised, bfloat16, channels 4..7 zero
+      uint4 q;
+      q.x = (uint32_t)to_bf16((o.x - nm.mean[0]) * nm.inv_std[0]) | ((uint32_t)to_bf16((o.y - nm.mean[1]) * nm.inv_std[1]) << 16);
+      q.y = (uint32_t)to_bf16((o.z - nm.mean[2]) * nm.inv_std[2]) | ((uint32_t)to_bf16((o.w - nm.mean[3]) * nm.inv_std[3]) << 16);
+      q.z = 0u;
+      q.w = 0u;
+      reinterpret_cast<uint4*>(x0)[e] = q;
+    } else {
+      reinterpret_cast<float4*>(feat)[e] = o;
     }
-    for (int c = 0; c < DEPTH_CLASSES; ++c) p[c] = p[c] / se;
-    int best = 0;
-    float best_cost = __builtin_huge_valf();
-    for (int d = 0; d <= dmax; ++d) {
-      float tail = 0.0f;
-      for (int c = d + 1; c < DEPTH_CLASSES; ++c) tail += p[c];
-      const float cost = c_ray * (float)subtree_rays(d) + c_sweep * tail;
-      if (cost < best_cost) {
-        best = d;
-        best_cost = cost;
-      }
-    }
-    depth[e] = (uint8_t)best;
-    counts[e] = subtree_rays(best);
   }
 }
 
@@ -104,14 +85,14 @@ int grid_for(int64_t n) { return (int)std::min<int64_t>(std::max<int64_t>((n + 2
 }  // namespace
 
 hipError_t launch_features(const MarchArgs& a, const LearnW& w, float* feat, hipStream_t s) {
-  hipLaunchKernelGGL(k_features, dim3(grid_for((int64_t)a.img.V * a.img.N0 * a.img.N0)), dim3(256), 0, s, a, w, feat);
+  hipLaunchKernelGGL(k_features<false>, dim3(grid_for((int64_t)a.img.V * a.img.N0 * a.img.N0)), dim3(256), 0, s, a, w,
+                     feat, FeatNorm{}, nullptr);
   return hipGetLastError();
 }
 
-hipError_t launch_decide(const float* logits, int64_t total, int dmax, float c_ray, float c_sweep, uint8_t* depth,
-                         unsigned long long* counts, hipStream_t s) {
-  hipLaunchKernelGGL(k_decide, dim3(grid_for(total)), dim3(256), 0, s, logits, total, dmax, c_ray, c_sweep, depth,
-                     counts);
+hipError_t launch_features_bf16(const MarchArgs& a, const LearnW& w, const FeatNorm& nm, uint16_t* x0, hipStream_t s) {
+  hipLaunchKernelGGL(k_features<true>, dim3(grid_for((int64_t)a.img.V * a.img.N0 * a.img.N0)), dim3(256), 0, s, a, w,
+                     nullptr, nm, x0);
   return hipGetLastError();
 }
 

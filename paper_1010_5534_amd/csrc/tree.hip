@@ -310,16 +310,22 @@ __global__ __launch_bounds__(256) void k_reduce_stats(MarchArgs A, const unsigne
 }
 
 // exclusive scan of n counts in one block of 1024 threads: each thread sums
-// a contiguous run, the 1024 run sums are scanned by wave prefix sums and
-// the 16 wave totals, then each thread rewrites its run; the total lands in
-// a[n]
+// a contiguous run (16 independent loads at a time), the 1024 run sums are
+// scanned by wave prefix sums and the 16 wave totals, then each thread
+// rewrites its run; the total lands in a[n]
 __global__ __launch_bounds__(1024) void k_scan(unsigned long long* a, int64_t n) {
   __shared__ unsigned long long wsum[1024 / WAVE];
   const int tid = threadIdx.x, lane = tid & (WAVE - 1), w = tid / WAVE;
   const int64_t per = (n + 1023) / 1024;
   const int64_t b = tid * per, e = min<int64_t>(b + per, n);
   unsigned long long s = 0;
-  for (int64_t k = b; k < e; ++k) s += a[k];
+  for (int64_t k0 = b; k0 < e; k0 += 16) {
+    unsigned long long v[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) v[k] = k0 + k < e ? a[k0 + k] : 0ull;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) s += v[k];
+  }
   unsigned long long x = s;  // inclusive prefix inside the wave
   for (int o = 1; o < WAVE; o <<= 1) {
     const unsigned long long y = __shfl_up(x, o);
@@ -333,10 +339,16 @@ __global__ __launch_bounds__(1024) void k_scan(unsigned long long* a, int64_t n)
     total += wsum[q];
   }
   unsigned long long run = before + x - s;  // exclusive prefix of this run
-  for (int64_t k = b; k < e; ++k) {
-    const unsigned long long t = a[k];
-    a[k] = run;
-    run += t;
+  for (int64_t k0 = b; k0 < e; k0 += 16) {
+    unsigned long long v[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) v[k] = k0 + k < e ? a[k0 + k] : 0ull;
+#pragma unroll
+    for (int k = 0; k < 16; ++k)
+      if (k0 + k < e) {
+        a[k0 + k] = run;
+        run += v[k];
+      }
   }
   if (tid == 0) a[n] = total;
 }
