@@ -98,6 +98,51 @@ def batched_amr(ctx, air, inputs, np, torch, args):
                 equal_to_render=same)
 
 
+def large_scale(ctx, air, inputs, np, torch, args):
+    """Uniform 512^3 (rho, T) field with three wind sources and their pairwise
+    shells (seed 0), 4 bands, 16 isotropic views, 128x128 coarse, 6 levels
+    (8192^2 effective): plain AIR of all views in one call, trees and flux
+    (no raster), and the learned proposal beside it."""
+    log("large scale: 512^3, 16 views x 4 bands, 6 levels")
+    src, etas = inputs.winds3_sources(0)
+    rho, temp = inputs.winds_field_torch(src, etas, 512, "cuda")
+    scene = ctx.prepare(air.scene_from_tensors(512, rho, temp, inputs.default_bands(4)))
+    views = inputs.isotropic_views(16, seed=5)
+    prm = air.params(128, 6, 0.5, band_weight=[1.0, 1.0, 1.0, 1.0])
+    out = ctx.render(scene, views, prm, want_image=False, reuse=True)
+    torch.cuda.synchronize()
+    steps = 3
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out = ctx.render(scene, views, prm, want_image=False, reuse=True)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    st = out[3]
+    res = dict(workload="winds3 512^3 (rho, T) seed 0, 4 bands, 16 views, 128x128 coarse, 6 levels (8192^2), "
+                        "xi_crit 0.5", rays=st["rays"], hits=st["hits"], visits=st["visits"],
+               rays_per_level=st["rays_per_level"][:7], ms_wall=wall * 1e3, per_image_ms=wall * 1e3 / 16,
+               rays_per_s=st["rays"] / wall, band_visits_per_s=4 * st["visits"] / wall,
+               fixed_rays_equivalent=16 * 8192 * 8192)
+    wpath = os.path.join(ROOT, "paper_1010_5534_amd", "weights", "depth_cnn.npz")
+    if os.path.exists(wpath):
+        wz = np.load(wpath)
+        net = air.Network(ctx, wz["params"], wz["mean"], wz["scale"])
+        c_ray, c_sweep = float(wz["c_ray"]), float(wz["c_sweep"])
+        lo = ctx.render_learned(scene, views, prm, net, c_ray, c_sweep, want_image=False, reuse=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            lo = ctx.render_learned(scene, views, prm, net, c_ray, c_sweep, want_image=False, reuse=True)
+        torch.cuda.synchronize()
+        wl = (time.perf_counter() - t0) / steps
+        res["learned"] = dict(ms_wall=wl * 1e3, speedup_vs_plain=wall / wl,
+                              equal_to_plain=bool(np.array_equal(lo[2], out[2]) and lo[3]["rays"] == st["rays"]),
+                              spec_rays=lo[4]["spec_rays"], wasted=lo[4]["wasted"], missing=lo[4]["missing"])
+        net.close()
+    del scene, rho, temp
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -107,6 +152,7 @@ def main():
     ap.add_argument("--skip-fixed", action="store_true")
     ap.add_argument("--skip-learned", action="store_true")
     ap.add_argument("--skip-amr", action="store_true")
+    ap.add_argument("--skip-large", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the timed region, one 256 MiB device copy whose counters calibrate HBM bytes")
     args = ap.parse_args()
@@ -233,6 +279,8 @@ def main():
 
     if not args.skip_amr:
         res["batched_amr"] = batched_amr(ctx, air, inputs, np, torch, args)
+    if not args.skip_large:
+        res["large_scale"] = large_scale(ctx, air, inputs, np, torch, args)
 
     if args.copy_probe:
         src = torch.empty(64 << 20, dtype=torch.float32, device="cuda")

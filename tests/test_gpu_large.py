@@ -1,0 +1,140 @@
+"""The large-scale workload at full size: uniform 512^3 (rho, T) field with
+three wind sources and their pairwise shells, 128x128 coarse image, 6 levels
+(8192^2 effective), 16 views x 4 bands in one call, plain and learned.  The
+oracle checks a seeded 1% sample of every sampled view's nodes ray by ray;
+the trees are checked for the method's invariants (2:1 balance of adjacent
+leaves, tested children of flagged nodes, flags consistent with xi)."""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle
+import parity
+from paper_1010_5534_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+N0, LMAX, XC, N = 128, 6, 0.5, 512
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1010_5534_amd import air
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = air.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def large(ctx):
+    from paper_1010_5534_amd import air
+    src, etas = inputs.winds3_sources(0)
+    say("winds3 512^3 on the GPU")
+    rho, temp = inputs.winds_field_torch(src, etas, N, "cuda")
+    bands = inputs.default_bands(4)
+    scene = ctx.prepare(air.scene_from_tensors(N, rho, temp, bands))
+    views = inputs.isotropic_views(16, seed=5)
+    prm = air.params(N0, LMAX, XC, band_weight=[1.0, 1.0, 1.0, 1.0])
+    say("render 16 views x 4 bands")
+    out = ctx.render(scene, views, prm, want_image=False)
+    return scene, views, prm, out, rho, temp, bands
+
+
+def _host_field(rho, temp, bands):
+    g = inputs.Grid(inputs.GRID_UNIFORM, (N, N, N))
+    f = inputs.Field(inputs.FIELD_RHO_T, rho.cpu().numpy(), temp=temp.cpu().numpy(), bands=np.asarray(bands))
+    return g, f
+
+
+def test_large_sampled_rays_match_oracle(large):
+    scene, views, prm, out, rho, temp, bands = large
+    trees, _, _, st = out
+    say(f"rays {st['rays']} visits {st['visits']} per level {st['rays_per_level'][:LMAX + 1]}")
+    g, f = _host_field(rho, temp, bands)
+    rng = np.random.default_rng(12)
+    worst = 0.0
+    for k in (0, 7, 15):
+        t = trees[k]
+        n = t.n_nodes
+        pick = np.sort(rng.choice(n, size=max(1, n // 100), replace=False))
+        lv = t.level.cpu().numpy()[pick].astype(np.int32)
+        ix = t.ix.cpu().numpy()[pick]
+        iy = t.iy.cpu().numpy()[pick]
+        ref = oracle.trace_pixels(g, f, views[k], N0, lv, ix, iy)
+        I = t.I.cpu().numpy()[:, pick]
+        Nn = t.N.cpu().numpy()[pick]
+        e = max(parity.rel_err(I, ref["I"]).max(), parity.rel_err(Nn, ref["N"]).max())
+        say(f"view {k}: {len(pick)} sampled nodes of {n}, worst rel err {e:.2e}")
+        worst = max(worst, e)
+    assert worst <= 1e-5
+
+
+def test_large_tree_invariants(large):
+    scene, views, prm, out, rho, temp, bands = large
+    trees = out[0]
+    for k in (3, 11):
+        t = trees[k]
+        lv = t.level.cpu().numpy().astype(np.int64)
+        ix = t.ix.cpu().numpy().astype(np.int64)
+        iy = t.iy.cpu().numpy().astype(np.int64)
+        st = t.state.cpu().numpy()
+        xi = t.xi_I.cpu().numpy()
+        fc = t.first_child.cpu().numpy()
+        ev = (st & 32) > 0
+        fl = (st & 4) > 0
+        # flags follow xi on the evaluated nodes; xi in [0, 1]
+        assert np.array_equal(fl[ev], xi[ev] >= XC)
+        assert np.all((xi[ev] >= 0) & (xi[ev] <= 1))
+        # flagged nodes have four children, all tested
+        kids = fc[fl]
+        assert np.all(kids >= 0)
+        for c in range(4):
+            assert np.all((st[kids + c] & 2) > 0)
+        # 2:1: every leaf's 8 neighbours at its level exist or lie inside a
+        # leaf at most one level coarser (checked on the finest raster of a
+        # sampled window through leaf levels)
+        leaf = (st & 1 > 0) & ~((st & 16) > 0)
+        R = N0 << LMAX
+        win = 2048
+        y0 = x0 = R // 2 - win // 2
+        depth = np.full((win, win), -1, np.int8)
+        for L in range(LMAX + 1):
+            m = leaf & (lv == L)
+            s = 1 << (LMAX - L)
+            ii, jj = ix[m], iy[m]
+            keep = (jj * s + s > y0) & (jj * s < y0 + win) & (ii * s + s > x0) & (ii * s < x0 + win)
+            ii, jj = ii[keep], jj[keep]
+            for dy in range(s):
+                for dx in range(s):
+                    y, x = jj * s + dy - y0, ii * s + dx - x0
+                    ok = (y >= 0) & (y < win) & (x >= 0) & (x < win)
+                    depth[y[ok], x[ok]] = L
+        assert np.all(depth >= 0)  # the leaves tile the window
+        d = depth.astype(np.int16)
+        assert np.all(np.abs(np.diff(d, axis=0)) <= 1) and np.all(np.abs(np.diff(d, axis=1)) <= 1)
+        assert np.all(np.abs(d[1:, 1:] - d[:-1, :-1]) <= 1) and np.all(np.abs(d[1:, :-1] - d[:-1, 1:]) <= 1)
+
+
+def test_large_learned_equals_plain(ctx, large):
+    import os
+    from paper_1010_5534_amd import air
+    scene, views, prm, out, rho, temp, bands = large
+    w = np.load(os.path.join(os.path.dirname(air.__file__), "weights", "depth_cnn.npz"))
+    net = air.Network(ctx, w["params"], w["mean"], w["scale"])
+    lo = ctx.render_learned(scene, views, prm, net, 1.0, 200.0, want_image=False)
+    say(lo[4])
+    for a, b in zip(out[0], lo[0]):
+        assert a.n_nodes == b.n_nodes
+        assert torch.equal(a.I, b.I) and torch.equal(a.state, b.state)
+    assert np.array_equal(out[2], lo[2])
+    net.close()
