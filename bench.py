@@ -53,21 +53,49 @@ def traffic_from_profile(kernel):
 
 def cpu_baseline(g, f, views, min_seconds=10.0):
     """The FP64 oracle on the host cores: plain AIR of the same three views,
-    repeated until about min_seconds have passed."""
+    repeated until about min_seconds have passed.  Also returns the first
+    repetition's trees."""
     import oracle
     oracle.lib()
     t = time.perf_counter()
-    nodes, reps = 0, 0
+    nodes, reps, first = 0, 0, None
     while True:
-        for v in views:
-            nodes += oracle.air(g, f, v, N0, LMAX, XI_CRIT).nodes
+        trees = [oracle.air(g, f, v, N0, LMAX, XI_CRIT) for v in views]
+        nodes += sum(tr.nodes for tr in trees)
+        first = first or trees
         reps += 1
         dt = time.perf_counter() - t
         if dt >= min_seconds:
             break
     return dict(value=nodes / dt, unit="rays/s", cores=oracle.num_threads(), kind="oracle",
                 sample=f"full plain AIR of the 3 views, {reps} times ({nodes} rays) in {dt:.1f} s, FP64, OpenMP",
-                seconds=dt)
+                seconds=dt), first
+
+
+def oracle_error(gpu_trees, orc_trees, np):
+    """The timed plain-AIR trees (host copies) against the oracle's: node sets, and the
+    largest relative difference of I and N over every node (misses are exact
+    zeros on both sides)."""
+    worst_i = worst_n = 0.0
+    same = True
+    for tg, to in zip(gpu_trees, orc_trees):
+        lv, ix, iy = (tg[k].astype(np.int64) for k in ("level", "ix", "iy"))
+        I, Nn = tg["I"].astype(np.float64), tg["N"].astype(np.float64)
+        same = same and len(lv) == to.nodes
+        for L in range(LMAX + 1):
+            m = lv == L
+            ex = (to.state[L][iy[m], ix[m]] & 1) > 0
+            same = same and bool(ex.all()) and int(m.sum()) == int(((to.state[L] & 1) > 0).sum())
+            for a, b in ((I[:, m], to.I[L][:, iy[m], ix[m]]), (Nn[m], to.N[L][iy[m], ix[m]])):
+                den = np.abs(b)
+                with np.errstate(invalid="ignore", divide="ignore"):
+                    r = np.where(den > 0, np.abs(a - b) / den, np.where(a == 0, 0.0, np.inf))
+                e = float(r[..., ex].max()) if ex.any() else 0.0
+                if a.ndim == 2:
+                    worst_i = max(worst_i, e)
+                else:
+                    worst_n = max(worst_n, e)
+    return dict(trees_identical=same, max_rel_err_I=worst_i, max_rel_err_N=worst_n, tolerance=1e-5)
 
 
 def batched_amr(ctx, air, inputs, np, torch, args):
@@ -205,6 +233,7 @@ def main():
     log("plain AIR")
     out_p, wall_p, dev_p, _, st_p = timed(plain, args.steps, args.warmup)
     trees, img_p, flux_p, _ = out_p
+    trees_host = [{k: getattr(t, k).cpu().numpy() for k in ("level", "ix", "iy", "I", "N")} for t in trees]
     img_p = img_p.clone()
     rays_p = st_p["rays"]
     # per-launch march time: a separate pass with an event around every
@@ -295,8 +324,9 @@ def main():
 
     if not args.no_cpu_baseline:
         log("oracle CPU baseline")
-        cb = cpu_baseline(g, f, views)
+        cb, orc_trees = cpu_baseline(g, f, views)
         res["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
+        res["plain_air"]["vs_oracle"] = oracle_error(trees_host, orc_trees, np)
     else:
         res["cpu_baseline"] = None
     print(json.dumps(res), flush=True)

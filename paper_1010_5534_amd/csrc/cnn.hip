@@ -359,16 +359,17 @@ int conv_blocks(int64_t P) {
 }
 
 // ---------------------------------------------------------------- inference
-// All four layers for one 16x16 output tile of one map: the input rows of a
-// 24x24 region (4-pixel halo) and each hidden layer's 22x22, 20x20, 18x18
-// region stay in LDS as bf16 NHWC; positions outside the image are zero, as
-// the layer-by-layer kernels' zero padding.  Every output pixel sees the
-// same MFMA sequence (same operands, same K order) as in k_conv, so the
-// logits are bit-identical to the layer-by-layer path.  The last layer's
-// logits go through LDS to the depth choice, one thread per pixel.
-constexpr int IT = 16;  // output tile edge
-
-template <int CS, int RW>
+// All four layers for one IT x IT output tile of one map: the input rows of
+// an (IT+8)^2 region (4-pixel halo) and each hidden layer's (IT+6)^2,
+// (IT+4)^2, (IT+2)^2 region stay in LDS as bf16 NHWC; positions outside the
+// image are zero, as the layer-by-layer kernels' zero padding.  Every output
+// pixel sees the same MFMA sequence (same operands, same K order) as in
+// k_conv, so the logits are bit-identical to the layer-by-layer path and do
+// not depend on IT.  The last layer's logits go through LDS to the depth
+// choice, one thread per pixel.  IT = 16 for large maps; 8 when the 16x16
+// tiles would not give every compute unit a block (the four layers of a
+// tile run one after another, so small tiles shorten the launch).
+template <int IT, int CS, int RW>
 __device__ __forceinline__ void fused_layer(const uint16_t* __restrict__ wmat, const float* __restrict__ bias,
                                             int nbias, const uint16_t* in, int rin, uint16_t* out, float* zout,
                                             int y0, int x0, int h, int w) {
@@ -423,35 +424,38 @@ __device__ __forceinline__ void fused_layer(const uint16_t* __restrict__ wmat, c
   }
 }
 
+template <int IT>
 __global__ __launch_bounds__(256) void k_infer(Prep W, const float* theta, const uint16_t* x, int h, int w, int dmax,
                                                float c_ray, float c_sweep, uint8_t* depth,
                                                unsigned long long* counts) {
-  __shared__ __attribute__((aligned(16))) uint16_t bufA[20 * 20 * HID];  // input rows, then layer-1 output
-  __shared__ __attribute__((aligned(16))) uint16_t bufB[22 * 22 * HID];  // layer-0 output, then layer-2 output
+  constexpr int R0 = IT + 8, R1 = IT + 6, R2 = IT + 4, R3 = IT + 2;
+  constexpr int NA = R0 * R0 * XC > R2 * R2 * HID ? R0 * R0 * XC : R2 * R2 * HID;
+  __shared__ __attribute__((aligned(16))) uint16_t bufA[NA];             // input rows, then layer-1 output
+  __shared__ __attribute__((aligned(16))) uint16_t bufB[R1 * R1 * HID];  // layer-0 output, then layer-2 output
   __shared__ float z[IT * IT * 8];
   const int tiles_x = (w + IT - 1) / IT, tiles_y = (h + IT - 1) / IT;
   const int map = blockIdx.x / (tiles_x * tiles_y), tix = blockIdx.x % (tiles_x * tiles_y);
   const int y0 = (tix / tiles_x) * IT, x0 = (tix % tiles_x) * IT;
   const uint16_t* xm = x + (int64_t)map * h * w * XC;
-  // input rows of the 24x24 region (zero outside the image)
-  for (int e = threadIdx.x; e < 24 * 24; e += 256) {
-    const int gy = y0 - 4 + e / 24, gx = x0 - 4 + e % 24;
+  // input rows of the region (zero outside the image)
+  for (int e = threadIdx.x; e < R0 * R0; e += 256) {
+    const int gy = y0 - 4 + e / R0, gx = x0 - 4 + e % R0;
     u16x8 v = {0, 0, 0, 0, 0, 0, 0, 0};
     if (gy >= 0 && gy < h && gx >= 0 && gx < w) v = *reinterpret_cast<const u16x8*>(xm + ((int64_t)gy * w + gx) * XC);
     *reinterpret_cast<u16x8*>(bufA + e * XC) = v;
   }
   __syncthreads();
   const Offsets o = offsets();
-  fused_layer<XC, HID>(W.wf[0], theta + o.b[0], HID, bufA, 24, bufB, nullptr, y0, x0, h, w);
+  fused_layer<IT, XC, HID>(W.wf[0], theta + o.b[0], HID, bufA, R0, bufB, nullptr, y0, x0, h, w);
   __syncthreads();
-  fused_layer<HID, HID>(W.wf[1], theta + o.b[1], HID, bufB, 22, bufA, nullptr, y0, x0, h, w);
+  fused_layer<IT, HID, HID>(W.wf[1], theta + o.b[1], HID, bufB, R1, bufA, nullptr, y0, x0, h, w);
   __syncthreads();
-  fused_layer<HID, HID>(W.wf[2], theta + o.b[2], HID, bufA, 20, bufB, nullptr, y0, x0, h, w);
+  fused_layer<IT, HID, HID>(W.wf[2], theta + o.b[2], HID, bufA, R2, bufB, nullptr, y0, x0, h, w);
   __syncthreads();
-  fused_layer<HID, 16>(W.wf[3], theta + o.b[3], CLASSES, bufB, 18, nullptr, z, y0, x0, h, w);
+  fused_layer<IT, HID, 16>(W.wf[3], theta + o.b[3], CLASSES, bufB, R3, nullptr, z, y0, x0, h, w);
   __syncthreads();
   const int py = threadIdx.x / IT, px = threadIdx.x % IT, gy = y0 + py, gx = x0 + px;
-  if (gy < h && gx < w) {
+  if (threadIdx.x < IT * IT && gy < h && gx < w) {
     const int d = depth_choice(z + threadIdx.x * 8, dmax, c_ray, c_sweep);
     const int64_t e = (int64_t)map * h * w + (int64_t)gy * w + gx;
     depth[e] = (uint8_t)d;
@@ -570,8 +574,15 @@ hipError_t infer_depth(const Net& net, const uint16_t* x, int n, int h, int w, i
     P.wt[l] = net.wt[l];
     P.woff[l] = 0;
   }
-  const int tiles = ((w + IT - 1) / IT) * ((h + IT - 1) / IT) * n;
-  hipLaunchKernelGGL(k_infer, dim3(tiles), dim3(256), 0, s, P, net.theta, x, h, w, dmax, c_ray, c_sweep, depth, counts);
+  const int tiles16 = ((w + 15) / 16) * ((h + 15) / 16) * n;
+  if (tiles16 >= 256) {
+    hipLaunchKernelGGL(k_infer<16>, dim3(tiles16), dim3(256), 0, s, P, net.theta, x, h, w, dmax, c_ray, c_sweep, depth,
+                       counts);
+  } else {
+    const int tiles8 = ((w + 7) / 8) * ((h + 7) / 8) * n;
+    hipLaunchKernelGGL(k_infer<8>, dim3(tiles8), dim3(256), 0, s, P, net.theta, x, h, w, dmax, c_ray, c_sweep, depth,
+                       counts);
+  }
   return hipGetLastError();
 }
 

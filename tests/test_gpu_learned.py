@@ -213,6 +213,32 @@ def test_learned_equals_plain_bitwise(ctx, c_ray, c_sweep):
     net.close()
 
 
+@pytest.mark.parametrize("n0,nviews", [(16, 3), (64, 16)])
+def test_fused_inference_tile_sizes(ctx, n0, nviews):
+    """The fused inference runs 8x8 tiles on small maps (3 views of 16^2)
+    and 16x16 tiles on large ones (16 views of 64^2: 256 tiles): the chosen
+    depths follow the reference decision on the layer-by-layer logits."""
+    from paper_1010_5534_amd import air
+    g, f = inputs.winds2(seed=6, n=64)
+    scene = ctx.prepare(air.upload(g, f))
+    views = inputs.isotropic_views(nviews, seed=2)
+    prm = air.params(n0, 2, 0.4)
+    net = air.Network(ctx, he_params(4), np.array([-3.0, -1.0, 0.0, 1.0], np.float32), np.full(4, 2.0, np.float32))
+    say(f"fused inference n0={n0} views={nviews}")
+    plain = ctx.render(scene, views, prm)
+    learned = ctx.render_learned(scene, views, prm, net, 1.0, 30.0)
+    _assert_same(plain, learned)
+    ls = learned[4]
+    z = net.forward(ctx.features(scene, views, n0)).cpu().numpy()[..., :6]
+    d_ref, cost = ocnn.decide_depth(z, 1.0, 30.0, max_depth=2)
+    hist = np.bincount(d_ref.ravel(), minlength=6)
+    srt = np.sort(cost[..., :3], axis=-1)
+    near = int(np.sum(srt[..., 1] - srt[..., 0] <= 1e-5 * np.abs(srt[..., 0]) + 1e-12))
+    assert sum(ls["depth_hist"]) == nviews * n0 * n0
+    assert np.abs(hist[:3] - np.asarray(ls["depth_hist"][:3])).sum() <= 2 * near
+    net.close()
+
+
 def test_learned_equals_plain_amr_multiband(ctx):
     from paper_1010_5534_amd import air
     g, f = inputs.amr_winds(seed=1, base_cells=32, bs=4, max_level=2, frac=(0.2, 0.05),
