@@ -205,10 +205,24 @@ hipError_t launch_refine(const MarchArgs& a, int L, float xcI, float xcN, const 
 hipError_t launch_march_fixed(const MarchArgs& a, int level, float* images, int grid_blocks, hipStream_t s);
 hipError_t launch_trace_pixels(const MarchArgs& a, int64_t n, const int32_t* level, const int32_t* ix,
                                const int32_t* iy, float* I, float* N, int32_t* visits, hipStream_t s);
-// per chunk: existing nodes (chunk_counts) and the other counters
-// (chunk_stats[VS_N][n_chunks]); then per (view, level) sums in vstat
+// per chunk: existing nodes (chunk_counts), the other counters
+// (chunk_stats[VS_N][n_chunks]) and, if flux_partial is not null, the leaf
+// flux per band (flux_partial[n_chunks][nb])
 hipError_t launch_count(const MarchArgs& a, unsigned long long* chunk_counts, unsigned* chunk_stats,
-                        int64_t n_chunks, unsigned long long* vstat, hipStream_t s);
+                        int64_t n_chunks, double* flux_partial, hipStream_t s);
+// The result block of a render, copied to the host in one piece:
+// [0, CTR_COUNT) the device counters, then the per (view, level) counters
+// [V][MAXL][VS_N], then the flux [V][nb] (float64).  res_words gives its
+// size in 8-byte words.
+__host__ __device__ inline int64_t res_vstat_off() { return CTR_COUNT; }
+__host__ __device__ inline int64_t res_flux_off(int V) { return CTR_COUNT + (int64_t)V * MAXL * VS_N; }
+__host__ __device__ inline int64_t res_words(int V, int nb) { return res_flux_off(V) + (int64_t)V * nb; }
+// after the count, in one launch: the exclusive scan of chunk_counts (if
+// scan), the counter copy, the (view, level) sums and (if flux_partial) the
+// flux of each (view, band), all into res
+hipError_t launch_finish(const MarchArgs& a, unsigned long long* chunk_counts, int64_t n_chunks, bool scan,
+                         const unsigned* chunk_stats, const double* flux_partial, unsigned long long* res,
+                         hipStream_t s);
 hipError_t launch_scan(unsigned long long* chunk_counts, int64_t n_chunks, hipStream_t s);
 hipError_t launch_emit(const MarchArgs& a, const unsigned long long* chunk_offsets, int64_t n_chunks,
                        int32_t* id_map, uint64_t* node_pos, hipStream_t s);
@@ -229,8 +243,6 @@ struct TreeOut {
 hipError_t launch_write_tree(const MarchArgs& a, const unsigned long long* chunk_offsets, const int32_t* id_map,
                              const uint64_t* node_pos, const TreeOut* outs, int grid_blocks, hipStream_t s);
 hipError_t launch_assemble(const MarchArgs& a, float* images, hipStream_t s);
-hipError_t launch_flux(const MarchArgs& a, double* partial, int64_t n_chunks, double* flux_dev,
-                       hipStream_t s);
 hipError_t launch_fixed_flux(const float* images, int V, int nb, int64_t R, double pix_area, double* partial,
                              double* flux_dev, hipStream_t s);
 

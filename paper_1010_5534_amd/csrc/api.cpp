@@ -391,9 +391,8 @@ air_status setup_render(air_ctx* c, const air_grid* grid, const air_field* field
   if ((st = ensure(c, c->ctr, 8 * CTR_COUNT))) return st;
   if ((st = ensure(c, c->chunk, 8 * (n_chunks + 1)))) return st;
   if ((st = ensure(c, c->cstat, 4 * VS_N * n_chunks))) return st;
-  if ((st = ensure(c, c->vstat, 8 * (size_t)V * MAXL * VS_N))) return st;
+  if ((st = ensure(c, c->vstat, 8 * (size_t)res_words(V, nb)))) return st;
   if ((st = ensure(c, c->partial, 8 * n_chunks * nb))) return st;
-  if ((st = ensure(c, c->flux, 8 * V * nb))) return st;
   A.w.state = (uint8_t*)c->state.p;
   A.w.valI = (float*)c->valI.p;
   A.w.valN = (float*)c->valN.p;
@@ -507,15 +506,16 @@ air_status enqueue_render(air_ctx* c, const Plan& P, const Tune& tune, hipStream
     if (P.timing) HIPCHK(c, hipEventRecord(ev[4 + 4 * L], s));
   }
   unsigned long long* chunk = (unsigned long long*)c->chunk.p;
-  HIPCHK(c, launch_count(A, chunk, (unsigned*)c->cstat.p, P.n_chunks, (unsigned long long*)c->vstat.p, s));
+  double* fpart = P.flux ? (double*)c->partial.p : nullptr;
+  HIPCHK(c, launch_count(A, chunk, (unsigned*)c->cstat.p, P.n_chunks, fpart, s));
+  HIPCHK(c, launch_finish(A, chunk, P.n_chunks, P.trees, (const unsigned*)c->cstat.p, fpart,
+                          (unsigned long long*)c->vstat.p, s));
   if (P.trees) {
-    HIPCHK(c, launch_scan(chunk, P.n_chunks, s));
     HIPCHK(c, launch_emit(A, chunk, P.n_chunks, (int32_t*)c->idmap.p, (uint64_t*)c->nodepos.p, s));
     HIPCHK(c, launch_write_tree(A, chunk, (const int32_t*)c->idmap.p, (const uint64_t*)c->nodepos.p,
                                 (const TreeOut*)c->touts.p, c->num_cus * 8, s));
   }
   if (P.images) HIPCHK(c, launch_assemble(A, P.images, s));
-  if (P.flux) HIPCHK(c, launch_flux(A, (double*)c->partial.p, P.n_chunks, (double*)c->flux.p, s));
   return AIR_OK;
 }
 
@@ -662,25 +662,20 @@ air_status render_core(air_ctx* c, const air_grid* grid, const air_field* field,
   }
   HIPCHK(c, hipEventRecord(ev[1], s));
   const bool timing = P.timing;
-  unsigned long long* vstat = (unsigned long long*)c->vstat.p;
-  // one wait: counters, per-view counts, fluxes
-  const size_t vstat_bytes = 8 * (size_t)V * MAXL * VS_N;
-  if ((st = ensure_host(c, (void**)&c->host_vstat, &c->host_vstat_n, vstat_bytes))) return st;
-  HIPCHK(c, hipMemcpyAsync(c->host_ctr, A.w.ctr, 8 * CTR_COUNT, hipMemcpyDeviceToHost, s));
-  HIPCHK(c, hipMemcpyAsync(c->host_vstat, vstat, vstat_bytes, hipMemcpyDeviceToHost, s));
-  if (flux) {
-    if ((st = ensure_host(c, (void**)&c->host_flux, &c->host_flux_n, 8 * V * nb))) return st;
-    HIPCHK(c, hipMemcpyAsync(c->host_flux, c->flux.p, 8 * V * nb, hipMemcpyDeviceToHost, s));
-  }
+  // one copy, one wait: the result block (counters, per-view counts, fluxes)
+  const size_t res_bytes = 8 * (size_t)res_words(V, nb);
+  if ((st = ensure_host(c, (void**)&c->host_vstat, &c->host_vstat_n, res_bytes))) return st;
+  HIPCHK(c, hipMemcpyAsync(c->host_vstat, c->vstat.p, res_bytes, hipMemcpyDeviceToHost, s));
   std::vector<uint8_t> depth_h;
   if (learned && ls) {
     depth_h.resize((size_t)V * N0 * N0);
     HIPCHK(c, hipMemcpyAsync(depth_h.data(), c->depth8.p, depth_h.size(), hipMemcpyDeviceToHost, s));
   }
   HIPCHK(c, hipStreamSynchronize(s));
-  const unsigned long long* hc = c->host_ctr;
+  const unsigned long long* hc = c->host_vstat;  // the counters lead the result block
+  const unsigned long long* hv = c->host_vstat + res_vstat_off();
   if (hc[CTR_OVERFLOW]) return fail(c, AIR_EDEVICE, "internal work queue overflow");
-  if (flux) std::memcpy(flux, c->host_flux, 8 * V * nb);
+  if (flux) std::memcpy(flux, c->host_vstat + res_flux_off(V), 8 * V * nb);
   if (stats) {
     std::memset(stats, 0, sizeof *stats);
     for (int k = 0; k < CTR_SLOTS; ++k) {
@@ -689,7 +684,7 @@ air_status render_core(air_ctx* c, const air_grid* grid, const air_field* field,
     }
     for (int v = 0; v < V; ++v)
       for (int L = 0; L <= Lm; ++L) {
-        const unsigned long long* r = c->host_vstat + ((size_t)v * MAXL + L) * VS_N;
+        const unsigned long long* r = hv + ((size_t)v * MAXL + L) * VS_N;
         stats->rays_per_level[L] += (int64_t)r[VS_NODES];
         stats->leaves += (int64_t)r[VS_LEAVES];
         stats->tested += (int64_t)r[VS_TESTED];
@@ -717,7 +712,7 @@ air_status render_core(air_ctx* c, const air_grid* grid, const air_field* field,
     std::memset(ls, 0, sizeof *ls);
     for (int v = 0; v < V; ++v)
       for (int L = 0; L <= Lm; ++L) {
-        const unsigned long long* r = c->host_vstat + ((size_t)v * MAXL + L) * VS_N;
+        const unsigned long long* r = hv + ((size_t)v * MAXL + L) * VS_N;
         ls->spec_rays += (int64_t)r[VS_SPEC];
         ls->wasted += (int64_t)r[VS_WASTED];
         ls->missing += (int64_t)r[VS_MISSING];
@@ -733,7 +728,7 @@ air_status render_core(air_ctx* c, const air_grid* grid, const air_field* field,
   for (int k = 0; trees && k < V; ++k) {
     int64_t n = 0, leaves = 0;
     for (int L = 0; L < MAXL; ++L) {
-      const unsigned long long* r = c->host_vstat + ((size_t)k * MAXL + L) * VS_N;
+      const unsigned long long* r = hv + ((size_t)k * MAXL + L) * VS_N;
       trees[k].n_per_level[L] = L <= Lm ? (int64_t)r[VS_NODES] : 0;
       if (L <= Lm) {
         n += (int64_t)r[VS_NODES];

@@ -228,9 +228,11 @@ __device__ __forceinline__ unsigned long long block_sum_u64(unsigned long long x
   return t;
 }
 
-// per chunk of CHUNK positions: existing nodes (for the scan) and the tree
-// counters, written per chunk; no global atomics.  Each thread reads its 16
-// consecutive state bytes with one load.
+// per chunk of CHUNK positions: existing nodes (for the scan), the tree
+// counters, written per chunk (no global atomics), and, when flux_partial
+// is given, the chunk's leaf flux per band (pixel area x I, float64, each
+// thread's 16 positions in order, then a fixed tree).  Each thread reads its
+// 16 consecutive state bytes with one load.
 constexpr int PPT = CHUNK / 256;  // positions per thread
 static_assert(PPT == 16, "one 16-byte state load per thread");
 
@@ -242,15 +244,23 @@ __device__ __forceinline__ uint8_t byte_of(const uint4& q, int k) {
   return (uint8_t)(w >> (8 * (k & 3)));
 }
 
+__device__ __forceinline__ double wave_sum_f64(double x) {
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+  return x;
+}
+
 __global__ __launch_bounds__(256) void k_count(MarchArgs A, unsigned long long* chunk_counts, unsigned* chunk_stats,
-                                               int64_t n_chunks) {
+                                               int64_t n_chunks, double* flux_partial) {
   __shared__ unsigned sh[VS_N][4];
+  __shared__ double shf[MAXB][4];
   const int64_t c = blockIdx.x;
   unsigned cnt[VS_N];
 #pragma unroll
   for (int q = 0; q < VS_N; ++q) cnt[q] = 0;
-  const bool above0 = chunk_pos(A.img, c).L > 0;
-  const uint4 q4 = state16(A.w.state, c * CHUNK + threadIdx.x * PPT);
+  const ChunkPos cp = chunk_pos(A.img, c);
+  const bool above0 = cp.L > 0;
+  const int64_t p0 = c * CHUNK + threadIdx.x * PPT;
+  const uint4 q4 = state16(A.w.state, p0);
 #pragma unroll
   for (int k = 0; k < PPT; ++k) {
     const uint8_t s = byte_of(q4, k);
@@ -274,47 +284,40 @@ __global__ __launch_bounds__(256) void k_count(MarchArgs A, unsigned long long* 
     for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
     if ((threadIdx.x & (WAVE - 1)) == 0) sh[q][w] = x;
   }
+  const int nb = A.f.nb;
+  if (flux_partial) {  // uniform
+    const int64_t VS = (int64_t)A.img.V * A.img.S;
+    const double px = A.views[cp.v].width / (double)((int64_t)A.img.N0 << cp.L), area = px * px;
+    double f[MAXB];
+#pragma unroll
+    for (int b = 0; b < MAXB; ++b) f[b] = 0.0;
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+      const uint8_t st = byte_of(q4, k);
+      if ((st & AIR_NODE_EXIST) && !(st & AIR_NODE_REFINED))
+        for (int b = 0; b < nb; ++b) f[b] += area * (double)A.w.valI[b * VS + p0 + k];
+    }
+    for (int b = 0; b < nb; ++b) {
+      const double x = wave_sum_f64(f[b]);
+      if ((threadIdx.x & (WAVE - 1)) == 0) shf[b][w] = x;
+    }
+  }
   __syncthreads();
   if (threadIdx.x < VS_N) {
     const unsigned t = sh[threadIdx.x][0] + sh[threadIdx.x][1] + sh[threadIdx.x][2] + sh[threadIdx.x][3];
     chunk_stats[threadIdx.x * n_chunks + c] = t;
     if (threadIdx.x == VS_NODES) chunk_counts[c] = t;
   }
+  if (flux_partial && threadIdx.x < nb)
+    flux_partial[c * nb + threadIdx.x] =
+        ((shf[threadIdx.x][0] + shf[threadIdx.x][1]) + shf[threadIdx.x][2]) + shf[threadIdx.x][3];
 }
 
-// per (view, level): sum the counters of its chunks (levels start on a
-// chunk) in one pass, fixed order
-__global__ __launch_bounds__(256) void k_reduce_stats(MarchArgs A, const unsigned* chunk_stats, int64_t n_chunks,
-                                                      unsigned long long* vstat) {
-  __shared__ unsigned long long sh[VS_N][4];
-  const int v = blockIdx.x / (A.img.Lmax + 1), L = blockIdx.x % (A.img.Lmax + 1);
-  const int64_t c0 = ((int64_t)v * A.img.S + A.img.off[L]) / CHUNK;
-  const int64_t c1 = ((int64_t)v * A.img.S + A.img.off[L + 1]) / CHUNK;
-  unsigned long long x[VS_N];
-#pragma unroll
-  for (int q = 0; q < VS_N; ++q) x[q] = 0;
-  for (int64_t c = c0 + threadIdx.x; c < c1; c += 256)
-#pragma unroll
-    for (int q = 0; q < VS_N; ++q) x[q] += chunk_stats[q * n_chunks + c];
-  const int w = threadIdx.x / WAVE;
-#pragma unroll
-  for (int q = 0; q < VS_N; ++q) {
-    unsigned long long y = x[q];
-    for (int o = 32; o > 0; o >>= 1) y += __shfl_xor(y, o);
-    if ((threadIdx.x & (WAVE - 1)) == 0) sh[q][w] = y;
-  }
-  __syncthreads();
-  if (threadIdx.x < VS_N)
-    vstat[((int64_t)v * MAXL + L) * VS_N + threadIdx.x] =
-        sh[threadIdx.x][0] + sh[threadIdx.x][1] + sh[threadIdx.x][2] + sh[threadIdx.x][3];
-}
-
-// exclusive scan of n counts in one block of 1024 threads: each thread sums
+// exclusive scan of n counts by one block of 1024 threads: each thread sums
 // a contiguous run (16 independent loads at a time), the 1024 run sums are
 // scanned by wave prefix sums and the 16 wave totals, then each thread
 // rewrites its run; the total lands in a[n]
-__global__ __launch_bounds__(1024) void k_scan(unsigned long long* a, int64_t n) {
-  __shared__ unsigned long long wsum[1024 / WAVE];
+__device__ __forceinline__ void scan_block(unsigned long long* a, int64_t n, unsigned long long* wsum) {
   const int tid = threadIdx.x, lane = tid & (WAVE - 1), w = tid / WAVE;
   const int64_t per = (n + 1023) / 1024;
   const int64_t b = tid * per, e = min<int64_t>(b + per, n);
@@ -351,6 +354,69 @@ __global__ __launch_bounds__(1024) void k_scan(unsigned long long* a, int64_t n)
       }
   }
   if (tid == 0) a[n] = total;
+}
+
+__global__ __launch_bounds__(1024) void k_scan(unsigned long long* a, int64_t n) {
+  __shared__ unsigned long long wsum[1024 / WAVE];
+  scan_block(a, n, wsum);
+}
+
+// The closing launch of a render, one role per block: block 0 scans the
+// chunk counts (when the node list is built) and copies the device
+// counters; blocks 1 .. V (Lmax+1) sum the counters of one (view, level)'s
+// chunks (levels start on a chunk); the next V nb blocks sum one (view,
+// band)'s flux partials (each thread a fixed stride, then a fixed tree).
+// Everything goes to the result block res.
+__global__ __launch_bounds__(1024) void k_finish(MarchArgs A, unsigned long long* chunk_counts, int64_t n_chunks,
+                                                 int scan, const unsigned* chunk_stats, const double* flux_partial,
+                                                 unsigned long long* res) {
+  __shared__ unsigned long long wsum[1024 / WAVE];
+  __shared__ unsigned long long sh[VS_N][1024 / WAVE];
+  __shared__ double shd[1024];
+  const int nL = A.img.Lmax + 1, V = A.img.V, nb = A.f.nb;
+  const int role = blockIdx.x;
+  if (role == 0) {
+    for (int k = threadIdx.x; k < CTR_COUNT; k += 1024) res[k] = A.w.ctr[k];
+    if (scan) scan_block(chunk_counts, n_chunks, wsum);
+    return;
+  }
+  if (role <= V * nL) {
+    const int v = (role - 1) / nL, L = (role - 1) % nL;
+    const int64_t c0 = ((int64_t)v * A.img.S + A.img.off[L]) / CHUNK;
+    const int64_t c1 = ((int64_t)v * A.img.S + A.img.off[L + 1]) / CHUNK;
+    unsigned long long x[VS_N];
+#pragma unroll
+    for (int q = 0; q < VS_N; ++q) x[q] = 0;
+    for (int64_t c = c0 + threadIdx.x; c < c1; c += 1024)
+#pragma unroll
+      for (int q = 0; q < VS_N; ++q) x[q] += chunk_stats[q * n_chunks + c];
+    const int w = threadIdx.x / WAVE;
+#pragma unroll
+    for (int q = 0; q < VS_N; ++q) {
+      unsigned long long y = x[q];
+      for (int o = 32; o > 0; o >>= 1) y += __shfl_xor(y, o);
+      if ((threadIdx.x & (WAVE - 1)) == 0) sh[q][w] = y;
+    }
+    __syncthreads();
+    if (threadIdx.x < VS_N) {
+      unsigned long long t = 0;
+      for (int k = 0; k < 1024 / WAVE; ++k) t += sh[threadIdx.x][k];
+      res[res_vstat_off() + ((int64_t)v * MAXL + L) * VS_N + threadIdx.x] = t;
+    }
+    return;
+  }
+  const int fb = role - 1 - V * nL;  // (view, band)
+  const int v = fb / nb, b = fb % nb;
+  const int64_t cpv = n_chunks / V;
+  double x = 0.0;
+  for (int64_t c = threadIdx.x; c < cpv; c += 1024) x += flux_partial[((int64_t)v * cpv + c) * nb + b];
+  shd[threadIdx.x] = x;
+  __syncthreads();
+  for (int o = 512; o > 0; o >>= 1) {
+    if (threadIdx.x < o) shd[threadIdx.x] += shd[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) reinterpret_cast<double*>(res + res_flux_off(V))[fb] = shd[0];
 }
 
 // node ids: exclusive prefix of existing positions in canonical order; also
@@ -475,54 +541,6 @@ __global__ __launch_bounds__(256) void k_assemble(MarchArgs A, float* images) {
 // flux partials per chunk and band: sum over leaves of (pixel area) I_b,
 // float64, fixed reduction order; one pass over the chunk's states for all
 // bands
-__device__ __forceinline__ double wave_sum_f64(double x) {
-  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
-  return x;
-}
-
-__global__ __launch_bounds__(256) void k_flux_partial(MarchArgs A, const DevView* views, double* partial) {
-  __shared__ double sh[MAXB][4];
-  const int64_t c = blockIdx.x, VS = (int64_t)A.img.V * A.img.S;
-  const int nb = A.f.nb;
-  const ChunkPos cp = chunk_pos(A.img, c);
-  const double px = views[cp.v].width / (double)((int64_t)A.img.N0 << cp.L), area = px * px;
-  const int64_t p0 = c * CHUNK + threadIdx.x * PPT;
-  const uint4 q4 = state16(A.w.state, p0);
-  double s[MAXB];
-#pragma unroll
-  for (int b = 0; b < MAXB; ++b) s[b] = 0.0;
-#pragma unroll
-  for (int k = 0; k < PPT; ++k) {
-    const uint8_t st = byte_of(q4, k);
-    if ((st & AIR_NODE_EXIST) && !(st & AIR_NODE_REFINED))
-      for (int b = 0; b < nb; ++b) s[b] += area * (double)A.w.valI[b * VS + p0 + k];
-  }
-  const int w = threadIdx.x / WAVE;
-  for (int b = 0; b < nb; ++b) {
-    const double x = wave_sum_f64(s[b]);
-    if ((threadIdx.x & (WAVE - 1)) == 0) sh[b][w] = x;
-  }
-  __syncthreads();
-  if (threadIdx.x < nb) partial[c * nb + threadIdx.x] = ((sh[threadIdx.x][0] + sh[threadIdx.x][1]) + sh[threadIdx.x][2]) + sh[threadIdx.x][3];
-}
-
-// per (view, band): sum the view's chunk partials, fixed order (each thread
-// a fixed stride, then a fixed tree)
-__global__ __launch_bounds__(256) void k_flux_final(const double* partial, int64_t chunks_per_view, int nb,
-                                                    double* flux) {
-  __shared__ double sh[256];
-  const int v = blockIdx.x / nb, b = blockIdx.x % nb;
-  double x = 0.0;
-  for (int64_t c = threadIdx.x; c < chunks_per_view; c += 256) x += partial[((int64_t)v * chunks_per_view + c) * nb + b];
-  sh[threadIdx.x] = x;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) flux[blockIdx.x] = sh[0];
-}
-
 // fixed image flux: per (view, band, chunk of raster) partials
 __global__ __launch_bounds__(256) void k_fixed_partial(const float* images, int nb, int64_t R2, double area,
                                                        int64_t chunks_per_plane, double* partial) {
@@ -571,10 +589,18 @@ hipError_t launch_refine(const MarchArgs& a, int L, float xcI, float xcN, const 
 }
 
 hipError_t launch_count(const MarchArgs& a, unsigned long long* chunk_counts, unsigned* chunk_stats,
-                        int64_t n_chunks, unsigned long long* vstat, hipStream_t s) {
-  hipLaunchKernelGGL(k_count, dim3((unsigned)n_chunks), dim3(256), 0, s, a, chunk_counts, chunk_stats, n_chunks);
-  hipLaunchKernelGGL(k_reduce_stats, dim3((unsigned)(a.img.V * (a.img.Lmax + 1))), dim3(256), 0, s, a, chunk_stats,
-                     n_chunks, vstat);
+                        int64_t n_chunks, double* flux_partial, hipStream_t s) {
+  hipLaunchKernelGGL(k_count, dim3((unsigned)n_chunks), dim3(256), 0, s, a, chunk_counts, chunk_stats, n_chunks,
+                     flux_partial);
+  return hipGetLastError();
+}
+
+hipError_t launch_finish(const MarchArgs& a, unsigned long long* chunk_counts, int64_t n_chunks, bool scan,
+                         const unsigned* chunk_stats, const double* flux_partial, unsigned long long* res,
+                         hipStream_t s) {
+  const int blocks = 1 + a.img.V * (a.img.Lmax + 1) + (flux_partial ? a.img.V * a.f.nb : 0);
+  hipLaunchKernelGGL(k_finish, dim3(blocks), dim3(1024), 0, s, a, chunk_counts, n_chunks, scan ? 1 : 0, chunk_stats,
+                     flux_partial, res);
   return hipGetLastError();
 }
 
@@ -606,13 +632,6 @@ hipError_t launch_assemble(const MarchArgs& a, float* images, hipStream_t s) {
   else
     hipLaunchKernelGGL(k_assemble<1>, dim3((unsigned)((R * R + 255) / 256), (unsigned)a.img.V), dim3(256), 0, s, a,
                        images);
-  return hipGetLastError();
-}
-
-hipError_t launch_flux(const MarchArgs& a, double* partial, int64_t n_chunks, double* flux_dev, hipStream_t s) {
-  hipLaunchKernelGGL(k_flux_partial, dim3((unsigned)n_chunks), dim3(256), 0, s, a, a.views, partial);
-  hipLaunchKernelGGL(k_flux_final, dim3((unsigned)(a.img.V * a.f.nb)), dim3(256), 0, s, partial,
-                     n_chunks / a.img.V, a.f.nb, flux_dev);
   return hipGetLastError();
 }
 
