@@ -207,9 +207,10 @@ hipError_t launch_trace_pixels(const MarchArgs& a, int64_t n, const int32_t* lev
                                const int32_t* iy, float* I, float* N, int32_t* visits, hipStream_t s);
 // per chunk: existing nodes (chunk_counts), the other counters
 // (chunk_stats[VS_N][n_chunks]) and, if flux_partial is not null, the leaf
-// flux per band (flux_partial[n_chunks][nb])
+// flux per band (flux_partial[n_chunks][nb]); in the same launch, if images
+// is not null, the raster [V][nb + 1][R][R] painted from the leaves
 hipError_t launch_count(const MarchArgs& a, unsigned long long* chunk_counts, unsigned* chunk_stats,
-                        int64_t n_chunks, double* flux_partial, hipStream_t s);
+                        int64_t n_chunks, double* flux_partial, float* images, hipStream_t s);
 // The result block of a render, copied to the host in one piece:
 // [0, CTR_COUNT) the device counters, then the per (view, level) counters
 // [V][MAXL][VS_N], then the flux [V][nb] (float64).  res_words gives its
@@ -242,7 +243,6 @@ struct TreeOut {
 };
 hipError_t launch_write_tree(const MarchArgs& a, const unsigned long long* chunk_offsets, const int32_t* id_map,
                              const uint64_t* node_pos, const TreeOut* outs, int grid_blocks, hipStream_t s);
-hipError_t launch_assemble(const MarchArgs& a, float* images, hipStream_t s);
 hipError_t launch_fixed_flux(const float* images, int V, int nb, int64_t R, double pix_area, double* partial,
                              double* flux_dev, hipStream_t s);
 

@@ -507,7 +507,7 @@ air_status enqueue_render(air_ctx* c, const Plan& P, const Tune& tune, hipStream
   }
   unsigned long long* chunk = (unsigned long long*)c->chunk.p;
   double* fpart = P.flux ? (double*)c->partial.p : nullptr;
-  HIPCHK(c, launch_count(A, chunk, (unsigned*)c->cstat.p, P.n_chunks, fpart, s));
+  HIPCHK(c, launch_count(A, chunk, (unsigned*)c->cstat.p, P.n_chunks, fpart, P.images, s));
   HIPCHK(c, launch_finish(A, chunk, P.n_chunks, P.trees, (const unsigned*)c->cstat.p, fpart,
                           (unsigned long long*)c->vstat.p, s));
   if (P.trees) {
@@ -515,7 +515,6 @@ air_status enqueue_render(air_ctx* c, const Plan& P, const Tune& tune, hipStream
     HIPCHK(c, launch_write_tree(A, chunk, (const int32_t*)c->idmap.p, (const uint64_t*)c->nodepos.p,
                                 (const TreeOut*)c->touts.p, c->num_cus * 8, s));
   }
-  if (P.images) HIPCHK(c, launch_assemble(A, P.images, s));
   return AIR_OK;
 }
 

@@ -228,6 +228,67 @@ __device__ __forceinline__ unsigned long long block_sum_u64(unsigned long long x
   return t;
 }
 
+// the raster of the leaves: each thread paints QX consecutive pixels of one
+// row of view v (block xb of the view's pixels), each descending from its
+// coarse pixel to the leaf that holds it (16-byte stores per plane when
+// QX = 4)
+template <int QX>
+__device__ __forceinline__ void paint_pixels(const MarchArgs& A, float* images, int v, int64_t xb) {
+  const int N0 = A.img.N0, Lm = A.img.Lmax, nb = A.f.nb;
+  const uint32_t R = (uint32_t)N0 << Lm;
+  const int64_t R2 = (int64_t)R * R, VS = (int64_t)A.img.V * A.img.S;
+  const int64_t vb = (int64_t)v * A.img.S;
+  const int64_t e = (xb * 256 + threadIdx.x) * QX;
+  if (e >= R2) return;
+  const uint32_t i = (uint32_t)(e % R), j = (uint32_t)(e / R);
+  // the QX pixels (i a multiple of QX) lie in one node of level Lm - log2 QX:
+  // descend there once, then per pixel
+  constexpr int LQ = QX == 4 ? 2 : 0;
+  uint32_t key = (j >> Lm) * (uint32_t)N0 + (i >> Lm);
+  int L = 0;
+  int64_t p0 = vb + key;
+  while (L < Lm - LQ && (A.w.state[p0] & AIR_NODE_REFINED)) {
+    ++L;
+    const int sh = Lm - L;
+    key = 4u * key + (((i >> sh) & 1u) | (((j >> sh) & 1u) << 1));
+    p0 = vb + A.img.off[L] + key;
+  }
+  int64_t p[QX];
+#pragma unroll
+  for (int q = 0; q < QX; ++q) {
+    uint32_t kq = key;
+    int lq = L;
+    int64_t pq = p0;
+    while (lq < Lm && (A.w.state[pq] & AIR_NODE_REFINED)) {
+      ++lq;
+      const int sh = Lm - lq;
+      kq = 4u * kq + ((((i + q) >> sh) & 1u) | (((j >> sh) & 1u) << 1));
+      pq = vb + A.img.off[lq] + kq;
+    }
+    p[q] = pq;
+  }
+  float* img = images + (int64_t)v * (nb + 1) * R2 + e;
+  for (int b = 0; b <= nb; ++b) {
+    const float* src = b < nb ? A.w.valI + b * VS : A.w.valN;
+    if constexpr (QX == 4) {
+      float4 o;
+      o.x = src[p[0]];
+      o.y = src[p[1]];
+      o.z = src[p[2]];
+      o.w = src[p[3]];
+      *reinterpret_cast<float4*>(img + b * R2) = o;
+    } else {
+      img[b * R2] = src[p[0]];
+    }
+  }
+}
+
+template <int QX>
+__host__ __device__ inline int64_t paint_blocks_per_view(const Img& img) {
+  const int64_t R = (int64_t)img.N0 << img.Lmax;
+  return (R * R / QX + 255) / 256;
+}
+
 // per chunk of CHUNK positions: existing nodes (for the scan), the tree
 // counters, written per chunk (no global atomics), and, when flux_partial
 // is given, the chunk's leaf flux per band (pixel area x I, float64, each
@@ -249,11 +310,21 @@ __device__ __forceinline__ double wave_sum_f64(double x) {
   return x;
 }
 
+// QX > 0: the blocks after the n_chunks counting blocks paint the raster
+// (paint_pixels<QX>), which does not depend on the counts
+template <int QX>
 __global__ __launch_bounds__(256) void k_count(MarchArgs A, unsigned long long* chunk_counts, unsigned* chunk_stats,
-                                               int64_t n_chunks, double* flux_partial) {
+                                               int64_t n_chunks, double* flux_partial, float* images) {
   __shared__ unsigned sh[VS_N][4];
   __shared__ double shf[MAXB][4];
   const int64_t c = blockIdx.x;
+  if constexpr (QX > 0) {
+    if (c >= n_chunks) {  // uniform per block
+      const int64_t pb = paint_blocks_per_view<QX>(A.img), k = c - n_chunks;
+      paint_pixels<QX>(A, images, (int)(k / pb), k % pb);
+      return;
+    }
+  }
   unsigned cnt[VS_N];
 #pragma unroll
   for (int q = 0; q < VS_N; ++q) cnt[q] = 0;
@@ -492,55 +563,6 @@ __global__ __launch_bounds__(256) void k_write_tree(MarchArgs A, const unsigned 
   }
 }
 
-// raster of the leaves: each finest pixel descends from its coarse pixel to
-// the leaf holding it; a thread paints QX consecutive pixels of a row (16-byte
-// stores per plane when QX = 4); grid (pixels / QX / 256, views)
-__device__ __forceinline__ int64_t leaf_pos(const MarchArgs& A, int64_t vb, uint32_t i, uint32_t j) {
-  const int N0 = A.img.N0, Lm = A.img.Lmax;
-  uint32_t key = (j >> Lm) * (uint32_t)N0 + (i >> Lm);
-  int L = 0;
-  int64_t p = vb + key;
-  while (L < Lm && (A.w.state[p] & AIR_NODE_REFINED)) {
-    ++L;
-    const int sh = Lm - L;
-    key = 4u * key + (((i >> sh) & 1u) | (((j >> sh) & 1u) << 1));
-    p = vb + A.img.off[L] + key;
-  }
-  return p;
-}
-
-template <int QX>
-__global__ __launch_bounds__(256) void k_assemble(MarchArgs A, float* images) {
-  const int N0 = A.img.N0, Lm = A.img.Lmax, nb = A.f.nb;
-  const uint32_t R = (uint32_t)N0 << Lm;
-  const int64_t R2 = (int64_t)R * R, VS = (int64_t)A.img.V * A.img.S;
-  const int v = blockIdx.y;
-  const int64_t vb = (int64_t)v * A.img.S;
-  const int64_t e = ((int64_t)blockIdx.x * 256 + threadIdx.x) * QX;
-  if (e >= R2) return;
-  const uint32_t i = (uint32_t)(e % R), j = (uint32_t)(e / R);
-  int64_t p[QX];
-#pragma unroll
-  for (int q = 0; q < QX; ++q) p[q] = leaf_pos(A, vb, i + q, j);
-  float* img = images + (int64_t)v * (nb + 1) * R2 + e;
-  for (int b = 0; b <= nb; ++b) {
-    const float* src = b < nb ? A.w.valI + b * VS : A.w.valN;
-    if constexpr (QX == 4) {
-      float4 o;
-      o.x = src[p[0]];
-      o.y = src[p[1]];
-      o.z = src[p[2]];
-      o.w = src[p[3]];
-      *reinterpret_cast<float4*>(img + b * R2) = o;
-    } else {
-      img[b * R2] = src[p[0]];
-    }
-  }
-}
-
-// flux partials per chunk and band: sum over leaves of (pixel area) I_b,
-// float64, fixed reduction order; one pass over the chunk's states for all
-// bands
 // fixed image flux: per (view, band, chunk of raster) partials
 __global__ __launch_bounds__(256) void k_fixed_partial(const float* images, int nb, int64_t R2, double area,
                                                        int64_t chunks_per_plane, double* partial) {
@@ -589,9 +611,21 @@ hipError_t launch_refine(const MarchArgs& a, int L, float xcI, float xcN, const 
 }
 
 hipError_t launch_count(const MarchArgs& a, unsigned long long* chunk_counts, unsigned* chunk_stats,
-                        int64_t n_chunks, double* flux_partial, hipStream_t s) {
-  hipLaunchKernelGGL(k_count, dim3((unsigned)n_chunks), dim3(256), 0, s, a, chunk_counts, chunk_stats, n_chunks,
-                     flux_partial);
+                        int64_t n_chunks, double* flux_partial, float* images, hipStream_t s) {
+  const int64_t R = (int64_t)a.img.N0 << a.img.Lmax;
+  if (!images) {
+    hipLaunchKernelGGL(k_count<0>, dim3((unsigned)n_chunks), dim3(256), 0, s, a, chunk_counts, chunk_stats, n_chunks,
+                       flux_partial, images);
+  } else if (R % 4 == 0 && ((uintptr_t)images & 15) == 0) {
+    // rows of a multiple of 4 pixels, 16-byte aligned planes: four pixels per thread
+    const int64_t n = n_chunks + a.img.V * paint_blocks_per_view<4>(a.img);
+    hipLaunchKernelGGL(k_count<4>, dim3((unsigned)n), dim3(256), 0, s, a, chunk_counts, chunk_stats, n_chunks,
+                       flux_partial, images);
+  } else {
+    const int64_t n = n_chunks + a.img.V * paint_blocks_per_view<1>(a.img);
+    hipLaunchKernelGGL(k_count<1>, dim3((unsigned)n), dim3(256), 0, s, a, chunk_counts, chunk_stats, n_chunks,
+                       flux_partial, images);
+  }
   return hipGetLastError();
 }
 
@@ -620,18 +654,6 @@ hipError_t launch_write_tree(const MarchArgs& a, const unsigned long long* chunk
   const int64_t n_chunks = (int64_t)a.img.V * a.img.S / CHUNK;
   hipLaunchKernelGGL(k_write_tree, dim3(grid_blocks), dim3(256), 0, s, a, chunk_offsets, n_chunks, id_map, node_pos,
                      outs);
-  return hipGetLastError();
-}
-
-hipError_t launch_assemble(const MarchArgs& a, float* images, hipStream_t s) {
-  const int64_t R = (int64_t)a.img.N0 << a.img.Lmax;
-  // rows of a multiple of 4 pixels, 16-byte aligned planes: four pixels per thread
-  if (R % 4 == 0 && ((uintptr_t)images & 15) == 0)
-    hipLaunchKernelGGL(k_assemble<4>, dim3((unsigned)((R * R / 4 + 255) / 256), (unsigned)a.img.V), dim3(256), 0, s,
-                       a, images);
-  else
-    hipLaunchKernelGGL(k_assemble<1>, dim3((unsigned)((R * R + 255) / 256), (unsigned)a.img.V), dim3(256), 0, s, a,
-                       images);
   return hipGetLastError();
 }
 
