@@ -108,7 +108,20 @@ struct Work {
   uint64_t qcap;
   int skip_spec;    // learned mode: the level march skips nodes with ST_SPEC
   unsigned long long* ctr;  // [CTR_COUNT]
+  // split tiles: a queue launch of a level >= 1 that can hold at most
+  // split_tiles tiles runs its sub-interval marches as separate wave jobs
+  // with partials in parts ([tile][sub-interval][split_fields(NB)][64]
+  // floats); 0 = never
+  float* parts;
+  int64_t split_tiles;
 };
+// fields of one split job's partial record: I[NB], tau[NB], N, rmin, rmax,
+// cells walked, finest level, uniform-grid cell count, hit
+__host__ __device__ constexpr int split_fields(int nb) { return 2 * nb + 7; }
+// the march's band count for a field (1 for one-band records, else 2, 4, 8)
+__host__ __device__ inline int march_nb(int kind, int nb) {
+  return (kind == AIR_FIELD_RHO_J_KAPPA || nb == 1) ? 1 : nb <= 2 ? 2 : nb <= 4 ? 4 : 8;
+}
 
 // ------------------------------------------------------------ Morton keys
 __host__ __device__ inline uint32_t spread2(uint32_t x) {
@@ -177,6 +190,10 @@ __host__ __device__ inline int brick_index(int x, int y, int z, int bnx, int bny
   return ((((z >> 1) * bny + (y >> 1)) * bnx + (x >> 1)) << 3) | (x & 1) | ((y & 1) << 1) | ((z & 1) << 2);
 }
 hipError_t launch_march_queue(const MarchArgs& a, int L, int grid_blocks, hipStream_t s);
+// whether launch_march_queue runs level L as split tiles, and the tiles a
+// queue launch of level L can hold
+bool split_level(const MarchArgs& a, int L);
+int64_t queue_tile_bound(const MarchArgs& a, int L);
 // speculative march of the learned proposal: the n = *count entries of spec
 hipError_t launch_march_spec(const MarchArgs& a, const uint64_t* spec, const unsigned long long* count,
                              int grid_blocks, hipStream_t s);

@@ -33,9 +33,10 @@ struct air_ctx {
   int device = 0;
   int num_cus = 256;
   int seg_shift_override = -1;  // AIR_SEG_SHIFT: tuning knob for the lanes per ray
+  int64_t split_tiles = 4096;   // AIR_SPLIT_TILES: queue launches (levels >= 1) of at most this many tiles run split
   Tune eager;                   // launch shapes of air_render (AIR_MARCH_WAVES: march waves per CU)
   std::string err;
-  DevBuf state, valI, valN, xiI, xiN, visits, rmin, rmax, queue, ctr, chunk, cstat, vstat, idmap, partial, flux,
+  DevBuf state, valI, valN, xiI, xiN, visits, rmin, rmax, queue, ctr, chunk, cstat, vstat, idmap, partial, flux, parts,
       views, touts, pack;
   // learned proposal: coarse maps, network activations and gradients, depth
   // choice and speculative work list
@@ -402,6 +403,20 @@ air_status setup_render(air_ctx* c, const air_grid* grid, const air_field* field
   A.w.queue = (uint64_t*)c->queue.p;
   A.w.qcap = (uint64_t)VS;
   A.w.ctr = (unsigned long long*)c->ctr.p;
+  // split tiles for the coarse levels whose launches are small enough
+  // (level 1 has the smallest bound of them); the partial buffer is sized
+  // for the largest such launch
+  A.w.split_tiles = c->split_tiles;
+  if (Lm >= 1 && split_level(A, 1)) {
+    int64_t tiles = 0;
+    for (int L = 1; L <= Lm && split_level(A, L); ++L) tiles = queue_tile_bound(A, L);
+    const size_t pb = 4 * (size_t)tiles * ((size_t)1 << A.g.seg_shift) * split_fields(march_nb(A.f.kind, nb)) * WAVE;
+    if ((st = ensure(c, c->parts, pb))) return st;
+    A.w.parts = (float*)c->parts.p;
+    A.w.split_tiles = tiles;
+  } else {
+    A.w.split_tiles = 0;
+  }
   if (range) {
     const int64_t n0 = (int64_t)V * N0 * N0;
     if ((st = ensure(c, c->rmin, 4 * n0))) return st;
@@ -772,6 +787,10 @@ air_status air_create(air_ctx** out, int32_t device) {
     const int v = std::atoi(e);
     if (v >= 0 && (1 << v) <= MAX_SEG) c->seg_shift_override = v;
   }
+  if (const char* e = std::getenv("AIR_SPLIT_TILES")) {
+    const long long v = std::atoll(e);
+    if (v >= 0 && v <= (1 << 20)) c->split_tiles = v;
+  }
   size_t have = 0;
   if (ensure_host(c, (void**)&c->host_ctr, &have, sizeof(unsigned long long) * CTR_COUNT)) {
     delete c;
@@ -799,7 +818,7 @@ void air_destroy(air_ctx* c) {
                     &c->ctr, &c->chunk, &c->cstat, &c->vstat, &c->idmap, &c->partial, &c->flux, &c->views,
                     &c->touts, &c->pack, &c->nodepos, &c->lmax0, &c->feat, &c->cx0, &c->ca1, &c->ca2, &c->ca3, &c->cz,
                     &c->cdz, &c->cda, &c->cdb, &c->cwpart, &c->closs_part, &c->closs, &c->depth8, &c->scount,
-                    &c->spec})
+                    &c->spec, &c->parts})
     if (b->p) (void)hipFree(b->p);
   if (c->host_ctr) (void)hipHostFree(c->host_ctr);
   if (c->host_flux) (void)hipHostFree(c->host_flux);

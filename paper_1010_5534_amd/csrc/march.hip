@@ -510,21 +510,14 @@ struct TileLds {
   int hit[WAVE];
 };
 
-// A block of S = 2^sh waves traces a tile of 64 rays (one per lane): wave
-// k marches the k-th of S equal parameter sub-intervals of every ray's
-// chord, so at each step the 64 lanes of a wave read the cells of 64
-// neighbouring rays at a similar depth.  The partials meet in LDS and wave 0
-// folds them in order,
-//   I = sum_k exp(-tau_0 - ... - tau_{k-1}) I_k,
-// which is exact for piecewise-constant cells.  The split depends only on
-// the ray and S (fixed per grid), so a ray's result does not depend on which
-// block or kernel traced it.  Every thread of the block calls this; the
-// result is valid in wave 0.
+// Sub-interval k of the S = 2^sh equal parameter sub-intervals of the chord
+// of pixel (i, j)'s ray at level L (S a power of two: k/S is exact, so the
+// split depends only on the ray and S, fixed per grid).  Returns whether the
+// ray meets the grid; nvis = its uniform-grid cell count when k == 0.
 template <int NB, int FK, int GK, bool RANGE>
-__device__ __forceinline__ void trace_tile(const MarchArgs& A, TileLds<NB>& T, bool live, uint32_t v, int L,
-                                           uint32_t i, uint32_t j, int sh, RayRes<NB>& r) {
-  const int S = 1 << sh, lane = threadIdx.x & (WAVE - 1), k = threadIdx.x / WAVE;
-  Seg<NB> sg;
+__device__ __forceinline__ bool march_lane(const MarchArgs& A, bool live, uint32_t v, int L, uint32_t i, uint32_t j,
+                                           int k, int sh, Seg<NB>& sg, int& nvis) {
+  const int S = 1 << sh;
 #pragma unroll
   for (int b = 0; b < NB; ++b) sg.I[b] = sg.tau[b] = 0.0f;
   sg.N = 0.0f;
@@ -533,7 +526,7 @@ __device__ __forceinline__ void trace_tile(const MarchArgs& A, TileLds<NB>& T, b
   sg.nvis = 0;
   sg.lmax = -1;
   bool hit = false;
-  int nvis = 0;
+  nvis = 0;
   if (live) {
     const DevView& V = A.views[v];
     double o[3], t0, t1;
@@ -541,7 +534,7 @@ __device__ __forceinline__ void trace_tile(const MarchArgs& A, TileLds<NB>& T, b
     hit = slab(A.g, o, V.d, V.inv_d, t0, t1);
     if (hit) {
       if (GK == AIR_GRID_UNIFORM && k == 0) nvis = cells_between(A.g, o, V.d, t0, t1);  // frees t0, t1 early
-      const double len = t1 - t0, inv_s = 1.0 / (double)S;  // S a power of two: k/S exact
+      const double len = t1 - t0, inv_s = 1.0 / (double)S;
       const double ta = k == 0 ? t0 : t0 + len * ((double)k * inv_s);
       const double tb = k == S - 1 ? t1 : t0 + len * ((double)(k + 1) * inv_s);
       if constexpr (GK == AIR_GRID_UNIFORM)
@@ -550,6 +543,25 @@ __device__ __forceinline__ void trace_tile(const MarchArgs& A, TileLds<NB>& T, b
         march_amr_interval<NB, FK, RANGE>(A.g, A.f, o, V.d, V.inv_d, ta, tb, sg);
     }
   }
+  return hit;
+}
+
+// A block of S = 2^sh waves traces a tile of 64 rays (one per lane): wave
+// k marches the k-th of S equal parameter sub-intervals of every ray's
+// chord, so at each step the 64 lanes of a wave read the cells of 64
+// neighbouring rays at a similar depth.  The partials meet in LDS and wave 0
+// folds them in order,
+//   I = sum_k exp(-tau_0 - ... - tau_{k-1}) I_k,
+// which is exact for piecewise-constant cells; a ray's result does not
+// depend on which block or kernel traced it.  Every thread of the block
+// calls this; the result is valid in wave 0.
+template <int NB, int FK, int GK, bool RANGE>
+__device__ __forceinline__ void trace_tile(const MarchArgs& A, TileLds<NB>& T, bool live, uint32_t v, int L,
+                                           uint32_t i, uint32_t j, int sh, RayRes<NB>& r) {
+  const int S = 1 << sh, lane = threadIdx.x & (WAVE - 1), k = threadIdx.x / WAVE;
+  Seg<NB> sg;
+  int nvis;
+  const bool hit = march_lane<NB, FK, GK, RANGE>(A, live, v, L, i, j, k, sh, sg, nvis);
   __syncthreads();  // the previous tile's fold has read the staging area
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
@@ -650,6 +662,20 @@ __device__ __forceinline__ void block_stats(unsigned long long* ctr, unsigned lo
   }
   if (threadIdx.x == 0) {
     const int slot = blockIdx.x & (CTR_SLOTS - 1);
+    if (hit) atomicAdd(&ctr[CTR_HITS + slot], hit);
+    if (vis) atomicAdd(&ctr[CTR_VISITS + slot], vis);
+  }
+}
+
+// add one wave's hit and visit counts into a spread slot
+__device__ __forceinline__ void wave_stats(unsigned long long* ctr, unsigned long long hit, unsigned long long vis) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    hit += __shfl_xor(hit, o);
+    vis += __shfl_xor(vis, o);
+  }
+  if ((threadIdx.x & (WAVE - 1)) == 0) {
+    const int slot = (blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE) & (CTR_SLOTS - 1);
     if (hit) atomicAdd(&ctr[CTR_HITS + slot], hit);
     if (vis) atomicAdd(&ctr[CTR_VISITS + slot], vis);
   }
@@ -800,6 +826,157 @@ __global__ __launch_bounds__(64 * MAX_SEG) void k_march_queue(MarchArgs A, int L
     }
   }
   block_stats(ctr, hit, vis);
+}
+
+// Split tiles.  At the coarse levels a launch holds few tiles and their
+// rays lie cells apart, so the lanes of a wave read distinct cache lines
+// and a tile's time is set by how fast its one compute unit pulls lines
+// from L2.  There each (tile, sub-interval) march runs as its own wave job
+// (the jobs of one tile land in different blocks), the partials go to
+// A.w.parts, and k_fold_parts folds each tile's S partials in the order of
+// the LDS fold, so the results are bit-identical to trace_tile's.  The host
+// picks this form only when the launch cannot hold more than split_tiles
+// tiles; a larger count (impossible) is flagged as an overflow.
+template <int NB>
+__device__ __forceinline__ float* part_rec(const MarchArgs& A, long long t, int k, int sh) {
+  return A.w.parts + (((t << sh) + k) * split_fields(NB)) * WAVE + (threadIdx.x & (WAVE - 1));
+}
+
+template <int NB, int FK, int GK, bool RANGE>
+__global__ __launch_bounds__(256) void k_march_parts(MarchArgs A, int L) {
+  unsigned long long* ctr = A.w.ctr;
+  const unsigned long long qs = ctr[CTR_LSTART + L];
+  const unsigned long long qe = min(ctr[CTR_CURSOR], (unsigned long long)A.w.qcap);
+  if (blockIdx.x == 0 && threadIdx.x == 0) ctr[CTR_LSTART + L + 1] = qe;
+  const long long ntiles = (long long)((qe - qs + WAVE - 1) / WAVE);
+  if (ntiles > A.w.split_tiles) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&ctr[CTR_OVERFLOW], 1ull);
+    return;
+  }
+  const int lane = threadIdx.x & (WAVE - 1), sh = A.g.seg_shift, wpb = blockDim.x / WAVE, wv = threadIdx.x / WAVE;
+  const int64_t SV = A.img.S;
+  // job = k * ntiles + t: the waves of a block march neighbouring tiles, the
+  // S parts of a tile go to S different blocks
+  const long long njobs = ntiles << sh, nblk = (njobs + wpb - 1) / wpb;
+  Split sp = xcd_split(nblk);
+  const long long kend = xcd_items(nblk);
+  for (; sp.k < kend; sp.k += sp.step) {
+    if (!sp.ok()) continue;
+    const long long job = sp.tile() * wpb + wv;
+    if (job >= njobs) continue;  // uniform per wave
+    const int k = (int)(job / ntiles);
+    const long long t = job - (long long)k * ntiles;
+    const unsigned long long e = qs + (unsigned long long)t * WAVE + lane;
+    const bool live = e < qe;
+    uint32_t v = 0, lev = 0, key = 0, i = 0, j = 0;
+    bool trace = live;
+    if (live) {
+      qdecode(A.w.queue[e], v, lev, key);
+      coords_of(key, (int)lev, A.img.N0, i, j);
+      if (A.w.skip_spec) trace = !(A.w.state[(int64_t)v * SV + A.img.off[lev] + key] & ST_SPEC);
+    }
+    if (!__ballot(trace)) continue;  // the fold marks the tile
+    Seg<NB> sg;
+    int nvis;
+    const bool hit = march_lane<NB, FK, GK, RANGE>(A, trace, v, (int)lev, i, j, k, sh, sg, nvis);
+    float* P = part_rec<NB>(A, t, k, sh);
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      P[b * WAVE] = sg.I[b];
+      P[(NB + b) * WAVE] = sg.tau[b];
+    }
+    P[2 * NB * WAVE] = sg.N;
+    if constexpr (RANGE) {
+      P[(2 * NB + 1) * WAVE] = sg.rmin;
+      P[(2 * NB + 2) * WAVE] = sg.rmax;
+    }
+    if constexpr (GK == AIR_GRID_BLOCK_AMR) {
+      P[(2 * NB + 3) * WAVE] = __int_as_float(sg.nvis);
+      P[(2 * NB + 4) * WAVE] = __int_as_float(sg.lmax);
+    }
+    if (k == 0) {
+      P[(2 * NB + 5) * WAVE] = __int_as_float(nvis);
+      P[(2 * NB + 6) * WAVE] = hit ? 1.0f : 0.0f;
+    }
+  }
+}
+
+// one wave per tile: fold the tile's S partials (the arithmetic of
+// trace_tile's fold), then store like k_march_queue
+template <int NB, int GK, bool RANGE>
+__global__ __launch_bounds__(256) void k_fold_parts(MarchArgs A, int L) {
+  unsigned long long* ctr = A.w.ctr;
+  const unsigned long long qs = ctr[CTR_LSTART + L], qe = ctr[CTR_LSTART + L + 1];
+  const long long ntiles = (long long)((qe - qs + WAVE - 1) / WAVE);
+  if (ntiles > A.w.split_tiles) return;  // flagged by k_march_parts
+  const int lane = threadIdx.x & (WAVE - 1), sh = A.g.seg_shift, S = 1 << sh, wpb = blockDim.x / WAVE;
+  const int64_t SV = A.img.S, VS = (int64_t)A.img.V * SV;
+  unsigned long long hit = 0, vis = 0;
+  for (long long t = (long long)blockIdx.x * wpb + threadIdx.x / WAVE; t < ntiles; t += (long long)gridDim.x * wpb) {
+    const unsigned long long e = qs + (unsigned long long)t * WAVE + lane;
+    const bool live = e < qe;
+    uint32_t v = 0, lev = 0, key = 0;
+    bool trace = live;
+    if (live) {
+      qdecode(A.w.queue[e], v, lev, key);
+      if (A.w.skip_spec) trace = !(A.w.state[(int64_t)v * SV + A.img.off[lev] + key] & ST_SPEC);
+    }
+    const int64_t pos = (int64_t)v * SV + A.img.off[lev] + key;
+    if (live && !trace) A.w.state[pos] = A.w.state[pos] | ST_TRACED;
+    if (!trace) continue;  // no shuffles below: lanes may leave
+    const float* P0 = part_rec<NB>(A, t, 0, sh);
+    float accI[NB], accT[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      accI[b] = P0[b * WAVE];
+      accT[b] = P0[(NB + b) * WAVE];
+    }
+    float accN = P0[2 * NB * WAVE];
+    float mn = 0.0f, mx = 0.0f;
+    if constexpr (RANGE) {
+      mn = P0[(2 * NB + 1) * WAVE];
+      mx = P0[(2 * NB + 2) * WAVE];
+    }
+    int cells = 0, lm = -1;
+    if constexpr (GK == AIR_GRID_BLOCK_AMR) {
+      cells = __float_as_int(P0[(2 * NB + 3) * WAVE]);
+      lm = __float_as_int(P0[(2 * NB + 4) * WAVE]);
+    }
+    for (int q = 1; q < S; ++q) {
+      const float* P = part_rec<NB>(A, t, q, sh);
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        accI[b] += __builtin_amdgcn_exp2f(-accT[b] * LOG2E_F) * P[b * WAVE];
+        accT[b] += P[(NB + b) * WAVE];
+      }
+      accN += P[2 * NB * WAVE];
+      if constexpr (RANGE) {
+        mn = fminf(mn, P[(2 * NB + 1) * WAVE]);
+        mx = fmaxf(mx, P[(2 * NB + 2) * WAVE]);
+      }
+      if constexpr (GK == AIR_GRID_BLOCK_AMR) {
+        cells += __float_as_int(P[(2 * NB + 3) * WAVE]);
+        lm = max(lm, __float_as_int(P[(2 * NB + 4) * WAVE]));
+      }
+    }
+    const bool rhit = P0[(2 * NB + 6) * WAVE] != 0.0f;
+    const int rnvis = GK == AIR_GRID_BLOCK_AMR ? cells : __float_as_int(P0[(2 * NB + 5) * WAVE]);
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+      if (b < A.f.nb) A.w.valI[b * VS + pos] = accI[b];
+    A.w.valN[pos] = accN;
+    A.w.visits[pos] = rnvis;
+    A.w.state[pos] = A.w.state[pos] | ST_TRACED;
+    if constexpr (RANGE) {
+      const int64_t q0 = (int64_t)v * A.img.N0 * A.img.N0 + key;
+      A.w.rmin[q0] = rhit ? mn : 0.0f;
+      A.w.rmax[q0] = rhit ? mx : 0.0f;
+      A.w.lmax0[q0] = rhit ? (GK == AIR_GRID_BLOCK_AMR ? lm : 0) : -1;
+    }
+    hit += rhit;
+    vis += (unsigned long long)rnvis;
+  }
+  wave_stats(ctr, hit, vis);
 }
 
 // Speculative march of the learned proposal: the entries of spec, of any
@@ -970,9 +1147,30 @@ hipError_t launch_init(const MarchArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+// tiles a queue launch of level L can hold: the level's nodes and balance
+// nodes of coarser levels, at most every position of levels 0..L
+int64_t queue_tile_bound(const MarchArgs& a, int L) {
+  int64_t bound = 0;
+  for (int l = 0; l <= L; ++l) bound += ((int64_t)a.img.N0 * a.img.N0) << (2 * l);
+  return (bound * a.img.V + WAVE - 1) / WAVE;
+}
+
+bool split_level(const MarchArgs& a, int L) {
+  // level 0 reads the field cold and is bound by DRAM in either form
+  return L >= 1 && a.w.split_tiles > 0 && queue_tile_bound(a, L) <= a.w.split_tiles;
+}
+
 hipError_t launch_march_queue(const MarchArgs& a, int L, int grid_blocks, hipStream_t s) {
-  const dim3 blk(WAVE << a.g.seg_shift);
-  AIR_DISPATCH(a, hipLaunchKernelGGL((k_march_queue<NB_, FK_, GK_>), dim3(grid_blocks), blk, 0, s, a, L));
+  if (!split_level(a, L)) {
+    const dim3 blk(WAVE << a.g.seg_shift);
+    AIR_DISPATCH(a, hipLaunchKernelGGL((k_march_queue<NB_, FK_, GK_>), dim3(grid_blocks), blk, 0, s, a, L));
+    return hipGetLastError();
+  }
+  const int64_t tiles = queue_tile_bound(a, L), jobs = tiles << a.g.seg_shift;
+  const int pg = (int)std::min<int64_t>(std::max<int64_t>((jobs + 4 * 8 - 1) / (4 * 8) * 8, 8), 8192);
+  const int fg = (int)std::min<int64_t>((tiles + 3) / 4, 4096);
+  AIR_DISPATCH(a, hipLaunchKernelGGL((k_march_parts<NB_, FK_, GK_, false>), dim3(pg), dim3(256), 0, s, a, L));
+  AIR_DISPATCH(a, hipLaunchKernelGGL((k_fold_parts<NB_, GK_, false>), dim3(fg), dim3(256), 0, s, a, L));
   return hipGetLastError();
 }
 
