@@ -80,15 +80,14 @@ enum : int {
   CTR_CURSOR = 0,         // queue append cursor
   CTR_OVERFLOW = 1,       // set when an append would pass the capacity
   CTR_LSTART = 2,         // [MAXL + 2] queue start of each level
-  CTR_TILE = CTR_LSTART + MAXL + 2,  // [MAXL + 1] march tile tickets per level
+  CTR_TILE = CTR_LSTART + MAXL + 2,  // [MAXL + 1][8] march tile tickets per level and XCD
   // march statistics, spread over CTR_SLOTS addresses so that concurrent
   // blocks rarely add to the same word (same-address atomics serialise)
-  CTR_HITS = CTR_TILE + MAXL + 1,
+  CTR_HITS = CTR_TILE + 8 * (MAXL + 1),
   CTR_VISITS = CTR_HITS + 64,
   CTR_COUNT = CTR_VISITS + 64
 };
 constexpr int CTR_SLOTS = 64;
-// per (view, level) record of the tree counters, filled by the reduce pass
 // per (view, level) counts; SPEC = speculatively traced positions, WASTED =
 // those that are no tree node, MISSING = tree nodes below level 0 traced by
 // the level loop instead

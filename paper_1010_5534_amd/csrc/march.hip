@@ -763,7 +763,9 @@ __global__ void k_init(MarchArgs A) {
 }
 
 // Queue march of level L: tiles of 64 consecutive entries, one tile per
-// block at a time (S waves per block).
+// block at a time (S waves per block).  Tiles differ in cost (chord lengths,
+// misses); when a block has many to do it takes them from a ticket counter
+// of its XCD, in the XCD's chunk order of the static split.
 template <int NB, int FK, int GK>
 __global__ __launch_bounds__(64 * MAX_SEG) void k_march_queue(MarchArgs A, int L) {
   __shared__ TileLds<NB> T;
@@ -777,27 +779,11 @@ __global__ __launch_bounds__(64 * MAX_SEG) void k_march_queue(MarchArgs A, int L
   const bool range = L == 0 && A.w.rmin != nullptr;  // uniform: level 0 holds only level-0 nodes
   unsigned long long hit = 0, vis = 0;
   const long long ntiles = (long long)((qe - qs + WAVE - 1) / WAVE);
+  __shared__ unsigned long long s_ticket;
   Split sp = xcd_split(ntiles);
-  const long long kend = xcd_items(ntiles);
-  for (; sp.k < kend; sp.k += sp.step) {
-    if (!sp.ok()) continue;  // uniform per block
-    const unsigned long long e = qs + (unsigned long long)sp.tile() * WAVE + lane;
-    const bool live = e < qe;
-    uint32_t v = 0, lev = 0, key = 0, i = 0, j = 0;
-    bool trace = live;
-    if (live) {
-      qdecode(A.w.queue[e], v, lev, key);
-      coords_of(key, (int)lev, A.img.N0, i, j);
-      // learned mode: a speculatively traced node already holds its values
-      if (A.w.skip_spec) trace = !(A.w.state[(int64_t)v * SV + A.img.off[lev] + key] & ST_SPEC);
-    }
-    if (!__ballot(trace)) {  // the same 64 entries in every wave: uniform per block
-      if (threadIdx.x < WAVE && live) {
-        const int64_t pos = (int64_t)v * SV + A.img.off[lev] + key;
-        A.w.state[pos] = A.w.state[pos] | ST_TRACED;
-      }
-      continue;
-    }
+  unsigned long long* ticket = ctr + CTR_TILE + 8 * L + sp.x;
+  // trace the tile and store its rays' values (every thread of the block)
+  auto trace_and_store = [&](bool trace, bool live, uint32_t v, uint32_t lev, uint32_t key, uint32_t i, uint32_t j) {
     RayRes<NB> r;
     if (range)
       trace_tile<NB, FK, GK, true>(A, T, trace, v, (int)lev, i, j, sh, r);
@@ -823,6 +809,39 @@ __global__ __launch_bounds__(64 * MAX_SEG) void k_march_queue(MarchArgs A, int L
       }
       hit += r.hit;
       vis += (unsigned long long)r.nvis;
+    }
+  };
+  // many tiles per block: take them from the XCD's ticket counter (one
+  // atomic per tile); few: the static split (a ticket's round trip would sit
+  // on every tile's path)
+  const bool dyn = ntiles > 4 * (long long)gridDim.x;
+  const long long kend = xcd_items(ntiles);
+  for (;; sp.k += dyn ? 0 : sp.step) {
+    if (dyn) {
+      if (threadIdx.x == 0) s_ticket = atomicAdd(ticket, 1ull);
+      __syncthreads();
+      sp.k = (long long)s_ticket;
+      __syncthreads();  // s_ticket is rewritten by the next iteration
+      if (!sp.ok()) break;  // an XCD's tiles grow with k
+    } else {
+      if (sp.k >= kend) break;
+      if (!sp.ok()) continue;
+    }
+    const unsigned long long e = qs + (unsigned long long)sp.tile() * WAVE + lane;
+    const bool live = e < qe;
+    uint32_t v = 0, lev = 0, key = 0, i = 0, j = 0;
+    bool trace = live;
+    if (live) {
+      qdecode(A.w.queue[e], v, lev, key);
+      coords_of(key, (int)lev, A.img.N0, i, j);
+      // learned mode: a speculatively traced node already holds its values
+      if (A.w.skip_spec) trace = !(A.w.state[(int64_t)v * SV + A.img.off[lev] + key] & ST_SPEC);
+    }
+    if (__ballot(trace)) {  // the same 64 entries in every wave: uniform per block
+      trace_and_store(trace, live, v, lev, key, i, j);
+    } else if (threadIdx.x < WAVE && live) {
+      const int64_t pos = (int64_t)v * SV + A.img.off[lev] + key;
+      A.w.state[pos] = A.w.state[pos] | ST_TRACED;
     }
   }
   block_stats(ctr, hit, vis);
