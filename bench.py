@@ -254,8 +254,9 @@ def main():
     bytes_p = st_p["visits"] * BYTES_PER_VISIT + rays_p * BYTES_PER_RAY_QUEUE
     achieved = bytes_p / (march_p * 1e-3) / 1e9
     res["roofline"] = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
-                           frac=achieved / HBM_PEAK_GBS, traffic=traffic_from_profile("k_march_queue"),
-                           kernel="k_march_queue", launches=st_t["march_launches"],
+                           frac=achieved / HBM_PEAK_GBS, traffic=traffic_from_profile("march_level"),
+                           kernel="march of one level: k_march_queue, or k_march_parts + k_fold_parts on the "
+                                  "split coarse levels", launches=st_t["march_launches"],
                            avg_launch_ms=march_p / st_t["march_launches"],
                            bytes_per_launch=bytes_p / st_t["march_launches"],
                            bytes_rule=f"{BYTES_PER_VISIT} B/visit + {BYTES_PER_RAY_QUEUE} B/ray")
