@@ -16,6 +16,7 @@ namespace {
 
 constexpr int RB = 256;             // refine block size
 constexpr int STK = 2 * MAXL;       // closure stack depth bound: 2L + 1 with L <= MAXL - 2
+constexpr int BALQ = 16;            // closure refinements listed per thread (more go out directly)
 
 __device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
@@ -68,6 +69,8 @@ struct BandW {
 __global__ __launch_bounds__(RB) void k_refine(MarchArgs A, int L, float xcI, float xcN, BandW W) {
   __shared__ uint32_t stk_key[STK][RB];
   __shared__ uint8_t stk_lev[STK][RB];
+  __shared__ uint32_t bal_key[BALQ][RB];  // closure refinements awaiting their queue entries
+  __shared__ uint8_t bal_lev[BALQ][RB];
   __shared__ unsigned wcnt[RB / WAVE];
   __shared__ unsigned long long bbase;
   unsigned long long* ctr = A.w.ctr;
@@ -121,56 +124,45 @@ __global__ __launch_bounds__(RB) void k_refine(MarchArgs A, int L, float xcI, fl
         atomicOr(reinterpret_cast<uint32_t*>(A.w.state + vb + A.img.off[L + 1] + 4ll * key),
                  0x01010101u * (AIR_NODE_EXIST | AIR_NODE_TESTED));
     }
-    // children of the block's flagged nodes: one queue reservation per block
-    const uint64_t mask = __ballot(flag);
-    const int w = tid / WAVE;
-    if (lane == 0) wcnt[w] = (unsigned)__popcll(mask);
-    __syncthreads();
-    if (tid == 0) {
-      unsigned tot = 0;
-      for (int q = 0; q < RB / WAVE; ++q) tot += wcnt[q];
-      bbase = tot ? atomicAdd(&ctr[CTR_CURSOR], 4ull * tot) : 0ull;
-    }
-    __syncthreads();
-    {
-      unsigned before = 0;
-      for (int q = 0; q < w; ++q) before += wcnt[q];
-      unsigned long long dst = bbase + 4ull * (before + lanes_below(mask));
-      __syncthreads();  // wcnt and bbase are rewritten by the next iteration
-      if (flag) {
-        if (dst + 4 <= qcap) {
-#pragma unroll
-          for (uint32_t c = 0; c < 4; ++c) A.w.queue[dst + c] = qentry(v, L + 1, 4u * key + c);
-        } else {
-          atomicOr(&ctr[CTR_OVERFLOW], 1ull);
-        }
-      }
-    }
     // 2:1 closure: every edge/corner neighbour of a flagged node must exist
     // before its children do.  A missing neighbour's parent is refined, after
     // making that parent's own neighbours exist, recursively down the levels.
     // The REFINED bit is claimed atomically, so each refinement is done once
-    // and the result is the unique minimal closure whatever the order.
+    // and the result is the unique minimal closure whatever the order.  The
+    // refinements a thread claims are listed in LDS and their children queued
+    // with the block's flagged children below.
+    int nbal = 0;
     if (flag && L >= 1) {
       int sp = 0;
-      auto request = [&](int l, uint32_t qi, uint32_t qj) {
-        const uint32_t kq = key_of(qi, qj, l, N0);
-        const uint32_t old = state_or(A.w.state, vb + A.img.off[l] + kq, AIR_NODE_REFINED);
-        if (!(old & AIR_NODE_REFINED)) {
-          stk_key[sp][tid] = kq;
-          stk_lev[sp][tid] = (uint8_t)l;
-          ++sp;
-        }
-      };
-      // the parents of the 8 neighbours of (l, ni, nj), other than its own
+      // the parents of the 8 neighbours of (l, ni, nj), other than its own:
+      // the three claims go out together
       auto around = [&](int l, uint32_t ni, uint32_t nj) {
         const int pi = (int)(ni >> 1), pj = (int)(nj >> 1);
         const int ai = pi + ((ni & 1) ? 1 : -1), aj = pj + ((nj & 1) ? 1 : -1);
         const int R1 = N0 << (l - 1);
         const bool okx = ai >= 0 && ai < R1, oky = aj >= 0 && aj < R1;
-        if (okx) request(l - 1, (uint32_t)ai, (uint32_t)pj);
-        if (oky) request(l - 1, (uint32_t)pi, (uint32_t)aj);
-        if (okx && oky) request(l - 1, (uint32_t)ai, (uint32_t)aj);
+        const int64_t lb = vb + A.img.off[l - 1];
+        const uint32_t k0 = okx ? key_of((uint32_t)ai, (uint32_t)pj, l - 1, N0) : 0u;
+        const uint32_t k1 = oky ? key_of((uint32_t)pi, (uint32_t)aj, l - 1, N0) : 0u;
+        const uint32_t k2 = okx && oky ? key_of((uint32_t)ai, (uint32_t)aj, l - 1, N0) : 0u;
+        const uint32_t o0 = okx ? state_or(A.w.state, lb + k0, AIR_NODE_REFINED) : AIR_NODE_REFINED;
+        const uint32_t o1 = oky ? state_or(A.w.state, lb + k1, AIR_NODE_REFINED) : AIR_NODE_REFINED;
+        const uint32_t o2 = okx && oky ? state_or(A.w.state, lb + k2, AIR_NODE_REFINED) : AIR_NODE_REFINED;
+        if (!(o0 & AIR_NODE_REFINED)) {
+          stk_key[sp][tid] = k0;
+          stk_lev[sp][tid] = (uint8_t)(l - 1);
+          ++sp;
+        }
+        if (!(o1 & AIR_NODE_REFINED)) {
+          stk_key[sp][tid] = k1;
+          stk_lev[sp][tid] = (uint8_t)(l - 1);
+          ++sp;
+        }
+        if (!(o2 & AIR_NODE_REFINED)) {
+          stk_key[sp][tid] = k2;
+          stk_lev[sp][tid] = (uint8_t)(l - 1);
+          ++sp;
+        }
       };
       around(L, i, j);
       while (sp > 0) {
@@ -184,11 +176,56 @@ __global__ __launch_bounds__(RB) void k_refine(MarchArgs A, int L, float xcI, fl
         }
         atomicOr(reinterpret_cast<uint32_t*>(A.w.state + vb + A.img.off[l + 1] + 4ll * kq),
                  0x01010101u * (AIR_NODE_EXIST | AIR_NODE_BALANCE));
-        const unsigned long long d = atomicAdd(&ctr[CTR_CURSOR], 4ull);
-        if (d + 4 <= qcap) {
-          for (uint32_t c = 0; c < 4; ++c) A.w.queue[d + c] = qentry(v, l + 1, 4u * kq + c);
-        } else {
-          atomicOr(&ctr[CTR_OVERFLOW], 1ull);
+        if (nbal < BALQ) {
+          bal_key[nbal][tid] = kq;
+          bal_lev[nbal][tid] = (uint8_t)l;
+          ++nbal;
+        } else {  // list full: queue the four children directly
+          const unsigned long long d = atomicAdd(&ctr[CTR_CURSOR], 4ull);
+          if (d + 4 <= qcap) {
+            for (uint32_t c = 0; c < 4; ++c) A.w.queue[d + c] = qentry(v, l + 1, 4u * kq + c);
+          } else {
+            atomicOr(&ctr[CTR_OVERFLOW], 1ull);
+          }
+        }
+      }
+    }
+    // the block's new queue entries (children of its flagged nodes, then of
+    // its closure refinements): one reservation per block
+    const unsigned mine = (flag ? 1u : 0u) + (unsigned)nbal;  // groups of four
+    unsigned x = mine;  // inclusive prefix over the wave
+    for (int o = 1; o < WAVE; o <<= 1) {
+      const unsigned y = __shfl_up(x, o);
+      if (lane >= o) x += y;
+    }
+    const int w = tid / WAVE;
+    if (lane == WAVE - 1) wcnt[w] = x;
+    __syncthreads();
+    if (tid == 0) {
+      unsigned tot = 0;
+      for (int q = 0; q < RB / WAVE; ++q) tot += wcnt[q];
+      bbase = tot ? atomicAdd(&ctr[CTR_CURSOR], 4ull * tot) : 0ull;
+    }
+    __syncthreads();
+    {
+      unsigned before = x - mine;
+      for (int q = 0; q < w; ++q) before += wcnt[q];
+      unsigned long long dst = bbase + 4ull * before;
+      __syncthreads();  // wcnt and bbase are rewritten by the next iteration
+      if (mine && dst + 4ull * mine > qcap) {
+        atomicOr(&ctr[CTR_OVERFLOW], 1ull);
+      } else {
+        if (flag) {
+#pragma unroll
+          for (uint32_t c = 0; c < 4; ++c) A.w.queue[dst + c] = qentry(v, L + 1, 4u * key + c);
+          dst += 4;
+        }
+        for (int q = 0; q < nbal; ++q) {
+          const uint32_t kq = bal_key[q][tid];
+          const int l = bal_lev[q][tid];
+#pragma unroll
+          for (uint32_t c = 0; c < 4; ++c) A.w.queue[dst + c] = qentry(v, l + 1, 4u * kq + c);
+          dst += 4;
         }
       }
     }
