@@ -1067,8 +1067,8 @@ __global__ __launch_bounds__(64 * MAX_SEG) void k_march_fixed(MarchArgs A, int L
         float* img = images + (int64_t)v * (A.f.nb + 1) * R2 + (int64_t)j * R + i;
 #pragma unroll
         for (int b = 0; b < NB; ++b)
-          if (b < A.f.nb) img[b * R2] = r.I[b];
-        img[A.f.nb * R2] = r.N;
+          if (b < A.f.nb) __builtin_nontemporal_store(r.I[b], img + b * R2);  // write-once output
+        __builtin_nontemporal_store(r.N, img + A.f.nb * R2);
       }
       hit += r.hit;
       vis += (unsigned long long)r.nvis;

@@ -313,9 +313,12 @@ __device__ __forceinline__ void paint_pixels(const MarchArgs& A, float* images, 
       o.y = src[p[1]];
       o.z = src[p[2]];
       o.w = src[p[3]];
-      *reinterpret_cast<float4*>(img + b * R2) = o;
+      // a write-once output: streaming stores keep it from evicting the
+      // field and the maps from the caches
+      typedef float f4 __attribute__((ext_vector_type(4)));
+      __builtin_nontemporal_store(f4{o.x, o.y, o.z, o.w}, reinterpret_cast<f4*>(img + b * R2));
     } else {
-      img[b * R2] = src[p[0]];
+      __builtin_nontemporal_store(src[p[0]], img + b * R2);
     }
   }
 }
@@ -583,20 +586,25 @@ __global__ __launch_bounds__(256) void k_write_tree(MarchArgs A, const unsigned 
     const uint8_t s = A.w.state[p];
     uint32_t i, j;
     coords_of(key, L, N0, i, j);
-    if (T.level) T.level[id] = (int8_t)L;
-    if (T.ix) T.ix[id] = (int32_t)i;
-    if (T.iy) T.iy[id] = (int32_t)j;
-    if (T.parent) T.parent[id] = L == 0 ? -1 : (int32_t)(id_map[vb + A.img.off[L - 1] + (key >> 2)] - base);
+    // write-once outputs: streaming stores
+    if (T.level) __builtin_nontemporal_store((int8_t)L, T.level + id);
+    if (T.ix) __builtin_nontemporal_store((int32_t)i, T.ix + id);
+    if (T.iy) __builtin_nontemporal_store((int32_t)j, T.iy + id);
+    if (T.parent)
+      __builtin_nontemporal_store(L == 0 ? -1 : (int32_t)(id_map[vb + A.img.off[L - 1] + (key >> 2)] - base),
+                                  T.parent + id);
     if (T.first_child)
-      T.first_child[id] = (s & AIR_NODE_REFINED) ? (int32_t)(id_map[vb + A.img.off[L + 1] + 4ll * key] - base) : -1;
-    if (T.state) T.state[id] = s & (uint8_t)~(ST_TRACED | ST_SPEC);
+      __builtin_nontemporal_store(
+          (s & AIR_NODE_REFINED) ? (int32_t)(id_map[vb + A.img.off[L + 1] + 4ll * key] - base) : -1,
+          T.first_child + id);
+    if (T.state) __builtin_nontemporal_store((uint8_t)(s & (uint8_t)~(ST_TRACED | ST_SPEC)), T.state + id);
     if (T.I)
-      for (int b = 0; b < nb; ++b) T.I[b * T.capacity + id] = A.w.valI[b * VS + p];
-    if (T.N) T.N[id] = A.w.valN[p];
+      for (int b = 0; b < nb; ++b) __builtin_nontemporal_store(A.w.valI[b * VS + p], T.I + b * T.capacity + id);
+    if (T.N) __builtin_nontemporal_store(A.w.valN[p], T.N + id);
     const bool ev = (s & AIR_NODE_EVALUATED) != 0;
-    if (T.xi_I) T.xi_I[id] = ev ? A.w.xiI[p] : __builtin_nanf("");
-    if (T.xi_N) T.xi_N[id] = ev ? A.w.xiN[p] : __builtin_nanf("");
-    if (T.visits) T.visits[id] = A.w.visits[p];
+    if (T.xi_I) __builtin_nontemporal_store(ev ? A.w.xiI[p] : __builtin_nanf(""), T.xi_I + id);
+    if (T.xi_N) __builtin_nontemporal_store(ev ? A.w.xiN[p] : __builtin_nanf(""), T.xi_N + id);
+    if (T.visits) __builtin_nontemporal_store(A.w.visits[p], T.visits + id);
   }
 }
 
