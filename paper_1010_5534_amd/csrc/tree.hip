@@ -267,8 +267,7 @@ __device__ __forceinline__ unsigned long long block_sum_u64(unsigned long long x
 
 // the raster of the leaves: each thread paints QX consecutive pixels of one
 // row of view v (block xb of the view's pixels), each descending from its
-// coarse pixel to the leaf that holds it (16-byte stores per plane when
-// QX = 4)
+// coarse pixel to the leaf that holds it (16-byte stores when QX = 4)
 template <int QX>
 __device__ __forceinline__ void paint_pixels(const MarchArgs& A, float* images, int v, int64_t xb) {
   const int N0 = A.img.N0, Lm = A.img.Lmax, nb = A.f.nb;
@@ -305,18 +304,16 @@ __device__ __forceinline__ void paint_pixels(const MarchArgs& A, float* images, 
     p[q] = pq;
   }
   float* img = images + (int64_t)v * (nb + 1) * R2 + e;
+  // a write-once output: streaming stores keep it from evicting the field
+  // and the maps from the caches
+  typedef float f4 __attribute__((ext_vector_type(4)));
   for (int b = 0; b <= nb; ++b) {
     const float* src = b < nb ? A.w.valI + b * VS : A.w.valN;
-    if constexpr (QX == 4) {
-      float4 o;
-      o.x = src[p[0]];
-      o.y = src[p[1]];
-      o.z = src[p[2]];
-      o.w = src[p[3]];
-      // a write-once output: streaming stores keep it from evicting the
-      // field and the maps from the caches
-      typedef float f4 __attribute__((ext_vector_type(4)));
-      __builtin_nontemporal_store(f4{o.x, o.y, o.z, o.w}, reinterpret_cast<f4*>(img + b * R2));
+    if constexpr (QX >= 4) {
+#pragma unroll
+      for (int g = 0; g < QX; g += 4)
+        __builtin_nontemporal_store(f4{src[p[g]], src[p[g + 1]], src[p[g + 2]], src[p[g + 3]]},
+                                    reinterpret_cast<f4*>(img + b * R2 + g));
     } else {
       __builtin_nontemporal_store(src[p[0]], img + b * R2);
     }
