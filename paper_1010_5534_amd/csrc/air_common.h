@@ -73,6 +73,7 @@ struct Img {
   int N0, Lmax, V;
   int64_t S;              // positions per view (padded)
   int64_t off[MAXL + 1];  // level offsets inside a view (multiples of 256)
+  double min_width;       // narrowest view (launch-shape choices on the host)
 };
 
 // counters (uint64) in device memory
@@ -80,7 +81,8 @@ enum : int {
   CTR_CURSOR = 0,         // queue append cursor
   CTR_OVERFLOW = 1,       // set when an append would pass the capacity
   CTR_LSTART = 2,         // [MAXL + 2] queue start of each level
-  CTR_TILE = CTR_LSTART + MAXL + 2,  // [MAXL + 1][8] march tile tickets per level and XCD
+  CTR_SPEC = CTR_LSTART + MAXL + 2,  // length of the learned proposal's work list
+  CTR_TILE = CTR_SPEC + 1,           // [MAXL + 1][8] march tile tickets per level and XCD
   // march statistics, spread over CTR_SLOTS addresses so that concurrent
   // blocks rarely add to the same word (same-address atomics serialise)
   CTR_HITS = CTR_TILE + 8 * (MAXL + 1),
@@ -190,9 +192,10 @@ __host__ __device__ inline int brick_index(int x, int y, int z, int bnx, int bny
 }
 hipError_t launch_march_queue(const MarchArgs& a, int L, int grid_blocks, hipStream_t s);
 // whether launch_march_queue runs level L as split tiles, and the tiles a
-// queue launch of level L can hold
+// queue launch of level L can hold; whether its rays lie a cell or more apart
 bool split_level(const MarchArgs& a, int L);
 int64_t queue_tile_bound(const MarchArgs& a, int L);
+bool coarse_level(const MarchArgs& a, int L);
 // speculative march of the learned proposal: the n = *count entries of spec
 hipError_t launch_march_spec(const MarchArgs& a, const uint64_t* spec, const unsigned long long* count,
                              int grid_blocks, hipStream_t s);
@@ -240,7 +243,6 @@ __host__ __device__ inline int64_t res_words(int V, int nb) { return res_flux_of
 hipError_t launch_finish(const MarchArgs& a, unsigned long long* chunk_counts, int64_t n_chunks, bool scan,
                          const unsigned* chunk_stats, const double* flux_partial, unsigned long long* res,
                          hipStream_t s);
-hipError_t launch_scan(unsigned long long* chunk_counts, int64_t n_chunks, hipStream_t s);
 hipError_t launch_emit(const MarchArgs& a, const unsigned long long* chunk_offsets, int64_t n_chunks,
                        int32_t* id_map, uint64_t* node_pos, hipStream_t s);
 struct TreeOut {

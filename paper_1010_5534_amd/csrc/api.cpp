@@ -427,6 +427,8 @@ air_status setup_render(air_ctx* c, const air_grid* grid, const air_field* field
     A.w.lmax0 = (int*)c->lmax0.p;
   }
   if ((st = upload_views(c, views, V, s, &A.views))) return st;
+  A.img.min_width = views[0].width;
+  for (int k = 1; k < V; ++k) A.img.min_width = std::min(A.img.min_width, views[k].width);
   return ensure_packed(c, grid, field, A, s);
 }
 
@@ -478,12 +480,14 @@ air_status learned_steps(air_ctx* c, const MarchArgs& A, const air_cnn* net, con
   const int dmax = std::min(lp->max_depth, std::min(A.img.Lmax, DEPTH_CLASSES - 1));
   unsigned long long* cnt = (unsigned long long*)c->scount.p;
   // the four layers and the depth choice in one launch
+  // the work list's length is counted in a device counter (cleared by the
+  // render's init launch)
+  unsigned long long* spec_n = A.w.ctr + CTR_SPEC;
   HIPCHK(c, cnn::infer_depth(net->net, (const uint16_t*)c->cx0.p, V, N0, N0, dmax, lp->c_ray, lp->c_sweep,
-                             (uint8_t*)c->depth8.p, cnt, s));
-  HIPCHK(c, launch_scan(cnt, total, s));
+                             (uint8_t*)c->depth8.p, cnt, spec_n, s));
   HIPCHK(c, launch_spec_emit((const uint8_t*)c->depth8.p, cnt, total, (int64_t)N0 * N0, (uint64_t*)c->spec.p, s));
   if (timing) HIPCHK(c, hipEventRecord(c->ev[air_ctx::EV_SPEC0], s));
-  HIPCHK(c, launch_march_spec(A, (const uint64_t*)c->spec.p, cnt + total,
+  HIPCHK(c, launch_march_spec(A, (const uint64_t*)c->spec.p, spec_n,
                               march_blocks(c, A.g.seg_shift, tune.march_waves_per_cu), s));
   if (timing) HIPCHK(c, hipEventRecord(c->ev[air_ctx::EV_SPEC1], s));
   return AIR_OK;

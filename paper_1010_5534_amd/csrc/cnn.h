@@ -110,10 +110,13 @@ hipError_t loss_and_dz(const float* z, const int32_t* labels, int64_t P, const f
 size_t loss_partial_doubles();
 hipError_t adam(Net& net, int P, float lr, float beta1, float beta2, float eps, hipStream_t s);
 // inference of all four layers on n maps of bf16 input rows x [n*h*w][8]
-// (16x16 output tiles, activations kept in LDS) followed by the depth choice:
-// depth[p] and its speculative ray count counts[p] per pixel
+// (output tiles with their activations kept in LDS) followed by the depth
+// choice: depth[p] per pixel, and spec_off[p], the start of pixel p's
+// speculative rays in a work list whose length is counted in *spec_total
+// (which must hold 0 before the launch; ranges are reserved per block, in
+// no fixed order)
 hipError_t infer_depth(const Net& net, const uint16_t* x, int n, int h, int w, int dmax, float c_ray, float c_sweep,
-                       uint8_t* depth, unsigned long long* counts, hipStream_t s);
+                       uint8_t* depth, unsigned long long* spec_off, unsigned long long* spec_total, hipStream_t s);
 
 }  // namespace cnn
 }  // namespace air

@@ -427,7 +427,7 @@ __device__ __forceinline__ void fused_layer(const uint16_t* __restrict__ wmat, c
 template <int IT>
 __global__ __launch_bounds__(256) void k_infer(Prep W, const float* theta, const uint16_t* x, int h, int w, int dmax,
                                                float c_ray, float c_sweep, uint8_t* depth,
-                                               unsigned long long* counts) {
+                                               unsigned long long* spec_off, unsigned long long* spec_total) {
   constexpr int R0 = IT + 8, R1 = IT + 6, R2 = IT + 4, R3 = IT + 2;
   constexpr int NA = R0 * R0 * XC > R2 * R2 * HID ? R0 * R0 * XC : R2 * R2 * HID;
   __shared__ __attribute__((aligned(16))) uint16_t bufA[NA];             // input rows, then layer-1 output
@@ -454,13 +454,35 @@ __global__ __launch_bounds__(256) void k_infer(Prep W, const float* theta, const
   __syncthreads();
   fused_layer<IT, HID, 16>(W.wf[3], theta + o.b[3], CLASSES, bufB, R3, nullptr, z, y0, x0, h, w);
   __syncthreads();
+  // depth choice, then each pixel's speculative rays get a range of the
+  // work list: a block prefix sum and one atomic reservation per block
+  __shared__ unsigned long long wsum[256 / WAVE], base;
   const int py = threadIdx.x / IT, px = threadIdx.x % IT, gy = y0 + py, gx = x0 + px;
-  if (threadIdx.x < IT * IT && gy < h && gx < w) {
+  const bool in = threadIdx.x < IT * IT && gy < h && gx < w;
+  const int64_t e = (int64_t)map * h * w + (int64_t)gy * w + gx;
+  unsigned long long n = 0;
+  if (in) {
     const int d = depth_choice(z + threadIdx.x * 8, dmax, c_ray, c_sweep);
-    const int64_t e = (int64_t)map * h * w + (int64_t)gy * w + gx;
     depth[e] = (uint8_t)d;
-    counts[e] = subtree_rays(d);
+    n = subtree_rays(d);
   }
+  const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+  unsigned long long pre = n;  // inclusive prefix over the wave
+  for (int o = 1; o < WAVE; o <<= 1) {
+    const unsigned long long y = __shfl_up(pre, o);
+    if (lane >= o) pre += y;
+  }
+  if (lane == WAVE - 1) wsum[wv] = pre;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long t = 0;
+    for (int q = 0; q < 256 / WAVE; ++q) t += wsum[q];
+    base = t ? atomicAdd(spec_total, t) : 0ull;
+  }
+  __syncthreads();
+  unsigned long long before = base + pre - n;
+  for (int q = 0; q < wv; ++q) before += wsum[q];
+  if (in) spec_off[e] = before;
 }
 
 }  // namespace
@@ -566,7 +588,7 @@ hipError_t loss_and_dz(const float* z, const int32_t* labels, int64_t P, const f
 }
 
 hipError_t infer_depth(const Net& net, const uint16_t* x, int n, int h, int w, int dmax, float c_ray, float c_sweep,
-                       uint8_t* depth, unsigned long long* counts, hipStream_t s) {
+                       uint8_t* depth, unsigned long long* spec_off, unsigned long long* spec_total, hipStream_t s) {
   Prep P;
   P.theta = net.theta;
   for (int l = 0; l < LAYERS; ++l) {
@@ -577,11 +599,11 @@ hipError_t infer_depth(const Net& net, const uint16_t* x, int n, int h, int w, i
   const int tiles16 = ((w + 15) / 16) * ((h + 15) / 16) * n;
   if (tiles16 >= 256) {
     hipLaunchKernelGGL(k_infer<16>, dim3(tiles16), dim3(256), 0, s, P, net.theta, x, h, w, dmax, c_ray, c_sweep, depth,
-                       counts);
+                       spec_off, spec_total);
   } else {
     const int tiles8 = ((w + 7) / 8) * ((h + 7) / 8) * n;
     hipLaunchKernelGGL(k_infer<8>, dim3(tiles8), dim3(256), 0, s, P, net.theta, x, h, w, dmax, c_ray, c_sweep, depth,
-                       counts);
+                       spec_off, spec_total);
   }
   return hipGetLastError();
 }

@@ -206,32 +206,42 @@ __device__ __forceinline__ int cells_between(const Geo& g, const double o[3], co
 #define AIR_DDA_BATCH(V0, OFF, DS, RAW)                                   \
   _Pragma("unroll") for (int q = 0; q < KB; ++q) {                        \
     OFF[q] = idx;                                                         \
-    float tn;                                                             \
-    int ax = 3;                                                           \
-    if ((V0) + q >= nvis - 1) {                                           \
-      tn = S1;                                                            \
-    } else {                                                              \
-      tn = fminf(fminf(t0, t1), t2);                                      \
-      ax = tn == t0 ? 0 : (tn == t1 ? 1 : 2);                             \
-    }                                                                     \
+    const bool last = (V0) + q >= nvis - 1;                               \
+    const float tm = fminf(fminf(t0, t1), t2);                            \
+    const float tn = last ? S1 : tm;                                      \
+    const bool a0 = !last && tm == t0;                                    \
+    const bool a1 = !last && !a0 && tm == t1;                             \
+    const bool a2 = !last && !a0 && !a1;                                  \
     DS[q] = tn - tc;                                                      \
     tc = tn;                                                              \
-    if (ax == 0) {                                                        \
+    if constexpr (BF) { /* the three axis updates computed and selected */ \
+      k0 += a0 ? 1.0f : 0.0f;                                             \
+      k1 += a1 ? 1.0f : 0.0f;                                             \
+      k2 += a2 ? 1.0f : 0.0f;                                             \
+      t0 = a0 ? __builtin_fmaf(k0, D0, T00) : t0;                         \
+      t1 = a1 ? __builtin_fmaf(k1, D1, T01) : t1;                         \
+      t2 = a2 ? __builtin_fmaf(k2, D2, T02) : t2;                         \
+      cx = a0 ? min(max(cx + s0, 0), nx - 1) : cx;                        \
+      cy = a1 ? min(max(cy + s1, 0), ny - 1) : cy;                        \
+      cz = a2 ? min(max(cz + s2, 0), nz - 1) : cz;                        \
+    } else if (a0) { /* one update, a uniform branch for coherent rays */ \
       k0 += 1.0f;                                                         \
       t0 = __builtin_fmaf(k0, D0, T00);                                   \
       cx = min(max(cx + s0, 0), nx - 1);                                  \
-    } else if (ax == 1) {                                                 \
+    } else if (a1) {                                                      \
       k1 += 1.0f;                                                         \
       t1 = __builtin_fmaf(k1, D1, T01);                                   \
       cy = min(max(cy + s1, 0), ny - 1);                                  \
-    } else if (ax == 2) {                                                 \
+    } else if (a2) {                                                      \
       k2 += 1.0f;                                                         \
       t2 = __builtin_fmaf(k2, D2, T02);                                   \
       cz = min(max(cz + s2, 0), nz - 1);                                  \
     }                                                                     \
     idx = AIR_CELL_INDEX();                                              \
   }                                                                       \
-  _Pragma("unroll") for (int q = 0; q < KB; ++q) RAW[q] = load_raw<FK>(R, OFF[q]);
+  _Pragma("unroll") for (int q = 0; q < KB; ++q) RAW[q] = load_raw<FK>(R, OFF[q]); \
+  /* the batch's loads go out before the older batch is integrated */     \
+  __builtin_amdgcn_sched_barrier(0);
 
 // One batch of up to KB cells: plain float32 sums inside the batch (at most
 // KB terms), one Kahan step per batch into the running I, tau, N.  Each
@@ -249,25 +259,27 @@ __device__ __forceinline__ int cells_between(const Geo& g, const double o[3], co
       t0b[b] = tau[b] - ctau[b];                                          \
       Tb[b] = __builtin_amdgcn_exp2f(-t0b[b] * LOG2E_F);                  \
     }                                                                     \
+    /* past the last cell ds = 0 (the walk repeats that cell), so a cell  \
+       there adds exact zeros: the branch-free walk integrates it */      \
     _Pragma("unroll") for (int q = 0; q < KB; ++q) {                      \
-      if ((V0) + q < nvis) {                                              \
-        const float ds = DS[q];                                           \
-        float jb[NB], kb[NB];                                             \
-        optics<NB, FK>(f, RAW[q], jb, kb);                                \
-        _Pragma("unroll") for (int b = 0; b < NB; ++b) {                  \
-          const float dtau = kb[b] * ds;                                  \
-          bT[b] += dtau;                                                  \
-          const float Ta = __builtin_amdgcn_exp2f(-(t0b[b] + bT[b]) * LOG2E_F); \
-          const float thin = Tb[b] * (jb[b] * ds) * seg_weight_series(dtau); \
-          const float thick = (Tb[b] - Ta) * jb[b] * __builtin_amdgcn_rcpf(kb[b]); \
-          bI[b] += dtau < THICK ? thin : thick;                           \
-          Tb[b] = Ta;                                                     \
-        }                                                                 \
-        bN += RAW[q].rho * ds;                                            \
-        if constexpr (RANGE) {                                            \
-          rmin = fminf(rmin, RAW[q].rho);                                 \
-          rmax = fmaxf(rmax, RAW[q].rho);                                 \
-        }                                                                 \
+      if (!BF && (V0) + q >= nvis) continue;                              \
+      const float ds = DS[q];                                             \
+      float jb[NB], kb[NB];                                               \
+      optics<NB, FK>(f, RAW[q], jb, kb);                                  \
+      _Pragma("unroll") for (int b = 0; b < NB; ++b) {                    \
+        const float dtau = kb[b] * ds;                                    \
+        bT[b] += dtau;                                                    \
+        const float Ta = __builtin_amdgcn_exp2f(-(t0b[b] + bT[b]) * LOG2E_F); \
+        const float thin = Tb[b] * (jb[b] * ds) * seg_weight_series(dtau); \
+        const float thick = (Tb[b] - Ta) * jb[b] * __builtin_amdgcn_rcpf(kb[b]); \
+        bI[b] += dtau < THICK ? thin : thick;                             \
+        Tb[b] = Ta;                                                       \
+      }                                                                   \
+      bN += RAW[q].rho * ds;                                              \
+      if constexpr (RANGE) {                                              \
+        const bool in = (V0) + q < nvis;                                  \
+        rmin = in ? fminf(rmin, RAW[q].rho) : rmin;                       \
+        rmax = in ? fmaxf(rmax, RAW[q].rho) : rmax;                       \
       }                                                                   \
     }                                                                     \
     _Pragma("unroll") for (int b = 0; b < NB; ++b) {                      \
@@ -315,7 +327,9 @@ __device__ __forceinline__ int cells_between(const Geo& g, const double o[3], co
 // k-th crossing is the single-rounding t_a(k) = fma(k, dt_a, t_a(0)), so no
 // rounding accumulates and each segment length is a difference of two
 // freshly rounded values.
-template <int NB, int FK, bool RANGE>
+// BF: branch-free cell walk (rays of a wave step different axes: coarse
+// levels) or one uniform branch per step (coherent rays); same arithmetic
+template <int NB, int FK, bool RANGE, bool BF>
 __device__ void march_interval(const Geo& g, const Fld& f, const double o[3], const double d[3],
                                const double inv_d[3], double ta, double tb, Seg<NB>& r) {
   int c[3], st[3], nvis = 1;
@@ -388,7 +402,7 @@ __device__ __forceinline__ int fine_at(const Geo& g, const double o[3], const do
 // continue from there.  Crossing parameters restart at every block entry.
 // At most g.max_blocks blocks are visited, so every lane terminates; a block
 // entered exactly at its exit (a rounding corner) is stepped over by one ulp.
-template <int NB, int FK, bool RANGE>
+template <int NB, int FK, bool RANGE, bool BF>
 __device__ void march_amr_interval(const Geo& g, const Fld& f, const double o[3], const double d[3],
                                    const double inv_d[3], double ta, double tb, Seg<NB>& r) {
   const i32x4 R = field_rsrc(f);
@@ -514,7 +528,7 @@ struct TileLds {
 // of pixel (i, j)'s ray at level L (S a power of two: k/S is exact, so the
 // split depends only on the ray and S, fixed per grid).  Returns whether the
 // ray meets the grid; nvis = its uniform-grid cell count when k == 0.
-template <int NB, int FK, int GK, bool RANGE>
+template <int NB, int FK, int GK, bool RANGE, bool BF>
 __device__ __forceinline__ bool march_lane(const MarchArgs& A, bool live, uint32_t v, int L, uint32_t i, uint32_t j,
                                            int k, int sh, Seg<NB>& sg, int& nvis) {
   const int S = 1 << sh;
@@ -538,9 +552,9 @@ __device__ __forceinline__ bool march_lane(const MarchArgs& A, bool live, uint32
       const double ta = k == 0 ? t0 : t0 + len * ((double)k * inv_s);
       const double tb = k == S - 1 ? t1 : t0 + len * ((double)(k + 1) * inv_s);
       if constexpr (GK == AIR_GRID_UNIFORM)
-        march_interval<NB, FK, RANGE>(A.g, A.f, o, V.d, V.inv_d, ta, tb, sg);
+        march_interval<NB, FK, RANGE, BF>(A.g, A.f, o, V.d, V.inv_d, ta, tb, sg);
       else
-        march_amr_interval<NB, FK, RANGE>(A.g, A.f, o, V.d, V.inv_d, ta, tb, sg);
+        march_amr_interval<NB, FK, RANGE, BF>(A.g, A.f, o, V.d, V.inv_d, ta, tb, sg);
     }
   }
   return hit;
@@ -555,13 +569,13 @@ __device__ __forceinline__ bool march_lane(const MarchArgs& A, bool live, uint32
 // which is exact for piecewise-constant cells; a ray's result does not
 // depend on which block or kernel traced it.  Every thread of the block
 // calls this; the result is valid in wave 0.
-template <int NB, int FK, int GK, bool RANGE>
+template <int NB, int FK, int GK, bool RANGE, bool BF>
 __device__ __forceinline__ void trace_tile(const MarchArgs& A, TileLds<NB>& T, bool live, uint32_t v, int L,
                                            uint32_t i, uint32_t j, int sh, RayRes<NB>& r) {
   const int S = 1 << sh, lane = threadIdx.x & (WAVE - 1), k = threadIdx.x / WAVE;
   Seg<NB> sg;
   int nvis;
-  const bool hit = march_lane<NB, FK, GK, RANGE>(A, live, v, L, i, j, k, sh, sg, nvis);
+  const bool hit = march_lane<NB, FK, GK, RANGE, BF>(A, live, v, L, i, j, k, sh, sg, nvis);
   __syncthreads();  // the previous tile's fold has read the staging area
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
@@ -766,7 +780,7 @@ __global__ void k_init(MarchArgs A) {
 // block at a time (S waves per block).  Tiles differ in cost (chord lengths,
 // misses); when a block has many to do it takes them from a ticket counter
 // of its XCD, in the XCD's chunk order of the static split.
-template <int NB, int FK, int GK>
+template <int NB, int FK, int GK, bool BF>
 __global__ __launch_bounds__(64 * MAX_SEG) void k_march_queue(MarchArgs A, int L) {
   __shared__ TileLds<NB> T;
   unsigned long long* ctr = A.w.ctr;
@@ -786,9 +800,9 @@ __global__ __launch_bounds__(64 * MAX_SEG) void k_march_queue(MarchArgs A, int L
   auto trace_and_store = [&](bool trace, bool live, uint32_t v, uint32_t lev, uint32_t key, uint32_t i, uint32_t j) {
     RayRes<NB> r;
     if (range)
-      trace_tile<NB, FK, GK, true>(A, T, trace, v, (int)lev, i, j, sh, r);
+      trace_tile<NB, FK, GK, true, BF>(A, T, trace, v, (int)lev, i, j, sh, r);
     else
-      trace_tile<NB, FK, GK, false>(A, T, trace, v, (int)lev, i, j, sh, r);
+      trace_tile<NB, FK, GK, false, BF>(A, T, trace, v, (int)lev, i, j, sh, r);
     if (threadIdx.x < WAVE && live && !trace) {
       const int64_t pos = (int64_t)v * SV + A.img.off[lev] + key;
       A.w.state[pos] = A.w.state[pos] | ST_TRACED;
@@ -897,7 +911,7 @@ __global__ __launch_bounds__(256) void k_march_parts(MarchArgs A, int L) {
     if (!__ballot(trace)) continue;  // the fold marks the tile
     Seg<NB> sg;
     int nvis;
-    const bool hit = march_lane<NB, FK, GK, RANGE>(A, trace, v, (int)lev, i, j, k, sh, sg, nvis);
+    const bool hit = march_lane<NB, FK, GK, RANGE, true>(A, trace, v, (int)lev, i, j, k, sh, sg, nvis);
     float* P = part_rec<NB>(A, t, k, sh);
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
@@ -1023,7 +1037,7 @@ __global__ __launch_bounds__(64 * MAX_SEG) void k_march_spec(MarchArgs A, const 
       coords_of(key, (int)lev, A.img.N0, i, j);
     }
     RayRes<NB> r;
-    trace_tile<NB, FK, GK, false>(A, T, live, v, (int)lev, i, j, sh, r);
+    trace_tile<NB, FK, GK, false, false>(A, T, live, v, (int)lev, i, j, sh, r);
     if (threadIdx.x < WAVE && live) {
       const int64_t pos = (int64_t)v * SV + A.img.off[lev] + key;
 #pragma unroll
@@ -1061,7 +1075,7 @@ __global__ __launch_bounds__(64 * MAX_SEG) void k_march_fixed(MarchArgs A, int L
       coords_of(key, L, A.img.N0, i, j);
     }
     RayRes<NB> r;
-    trace_tile<NB, FK, GK, false>(A, T, live, v, L, i, j, sh, r);
+    trace_tile<NB, FK, GK, false, false>(A, T, live, v, L, i, j, sh, r);
     if (threadIdx.x < WAVE && live) {
       if (images) {
         float* img = images + (int64_t)v * (A.f.nb + 1) * R2 + (int64_t)j * R + i;
@@ -1087,7 +1101,7 @@ __global__ __launch_bounds__(64 * MAX_SEG) void k_trace_pixels(MarchArgs A, int6
     const int64_t k = b0 + lane;
     const bool live = k < n;
     RayRes<NB> r;
-    trace_tile<NB, FK, GK, false>(A, T, live, 0, live ? level[k] : 0, live ? (uint32_t)ix[k] : 0u,
+    trace_tile<NB, FK, GK, false, false>(A, T, live, 0, live ? level[k] : 0, live ? (uint32_t)ix[k] : 0u,
                                   live ? (uint32_t)iy[k] : 0u, sh, r);
     if (threadIdx.x < WAVE && live) {
 #pragma unroll
@@ -1174,6 +1188,14 @@ int64_t queue_tile_bound(const MarchArgs& a, int L) {
   return (bound * a.img.V + WAVE - 1) / WAVE;
 }
 
+// rays of level L at least one (coarsest-level) cell apart in every view:
+// the lanes of a wave step different axes, so the walk goes branch-free
+bool coarse_level(const MarchArgs& a, int L) {
+  double h = a.g.h[0];
+  for (int ax = 1; ax < 3; ++ax) h = std::max(h, a.g.h[ax]);
+  return a.img.min_width / (double)((int64_t)a.img.N0 << L) >= h;
+}
+
 bool split_level(const MarchArgs& a, int L) {
   // level 0 reads the field cold and is bound by DRAM in either form
   return L >= 1 && a.w.split_tiles > 0 && queue_tile_bound(a, L) <= a.w.split_tiles;
@@ -1182,7 +1204,10 @@ bool split_level(const MarchArgs& a, int L) {
 hipError_t launch_march_queue(const MarchArgs& a, int L, int grid_blocks, hipStream_t s) {
   if (!split_level(a, L)) {
     const dim3 blk(WAVE << a.g.seg_shift);
-    AIR_DISPATCH(a, hipLaunchKernelGGL((k_march_queue<NB_, FK_, GK_>), dim3(grid_blocks), blk, 0, s, a, L));
+    if (coarse_level(a, L))
+      AIR_DISPATCH(a, hipLaunchKernelGGL((k_march_queue<NB_, FK_, GK_, true>), dim3(grid_blocks), blk, 0, s, a, L));
+    else
+      AIR_DISPATCH(a, hipLaunchKernelGGL((k_march_queue<NB_, FK_, GK_, false>), dim3(grid_blocks), blk, 0, s, a, L));
     return hipGetLastError();
   }
   const int64_t tiles = queue_tile_bound(a, L), jobs = tiles << a.g.seg_shift;

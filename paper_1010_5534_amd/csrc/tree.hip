@@ -464,11 +464,6 @@ __device__ __forceinline__ void scan_block(unsigned long long* a, int64_t n, uns
   if (tid == 0) a[n] = total;
 }
 
-__global__ __launch_bounds__(1024) void k_scan(unsigned long long* a, int64_t n) {
-  __shared__ unsigned long long wsum[1024 / WAVE];
-  scan_block(a, n, wsum);
-}
-
 // The closing launch of a render, one role per block: block 0 scans the
 // chunk counts (when the node list is built) and copies the device
 // counters; blocks 1 .. V (Lmax+1) sum the counters of one (view, level)'s
@@ -677,11 +672,6 @@ hipError_t launch_finish(const MarchArgs& a, unsigned long long* chunk_counts, i
   const int blocks = 1 + a.img.V * (a.img.Lmax + 1) + (flux_partial ? a.img.V * a.f.nb : 0);
   hipLaunchKernelGGL(k_finish, dim3(blocks), dim3(1024), 0, s, a, chunk_counts, n_chunks, scan ? 1 : 0, chunk_stats,
                      flux_partial, res);
-  return hipGetLastError();
-}
-
-hipError_t launch_scan(unsigned long long* chunk_counts, int64_t n_chunks, hipStream_t s) {
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, chunk_counts, n_chunks);
   return hipGetLastError();
 }
 
