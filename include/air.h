@@ -176,8 +176,9 @@ int64_t air_field_packed_bytes(const air_grid* grid, const air_field* field);
  * index x fastest over ceil(n/2) bricks per axis; cell inside the brick
  * x&1 | (y&1)<<1 | (z&1)<<2; on a block-AMR grid the same inside each
  * block, blocks in table order) and each cell's values are adjacent, 16 B
- * (rho, j, kappa, 0) for RHO_J_KAPPA and for one-band RHO_T (its j and kappa
- * evaluated here, once, in float32 exactly as the march would), or 8 B
+ * (rho, j, kappa, 1/kappa) for RHO_J_KAPPA and for one-band RHO_T (its j,
+ * kappa and 1/kappa evaluated here, once, in float32 exactly as the march
+ * would), or 8 B
  * (rho, T) for RHO_T with 2..8 bands, so one brick of a one-band field is one
  * 128-byte cache line and a visit is one load.
  * Pass the buffer as field->packed to later calls; it holds a copy, so it

@@ -179,9 +179,8 @@ struct MarchArgs {
 hipError_t launch_init(const MarchArgs& a, hipStream_t s);
 hipError_t launch_pack(const Geo& g, const Fld& f, void* packed, hipStream_t s);
 hipError_t launch_pack_amr(const Geo& g, const Fld& f, void* packed, hipStream_t s);
-// bytes per packed cell
-// bytes of one packed cell record: (rho, j, kappa, 0) for RHO_J_KAPPA and for
-// one-band RHO_T (j, kappa evaluated once when packing), (rho, T) otherwise
+// bytes of one packed cell record: (rho, j, kappa, 1/kappa) for RHO_J_KAPPA and
+// for one-band RHO_T (j, kappa evaluated once when packing), (rho, T) otherwise
 inline int packed_cell_bytes(int field_kind, int n_bands) {
   return (field_kind == AIR_FIELD_RHO_J_KAPPA || n_bands == 1) ? 16 : 8;
 }

@@ -77,10 +77,10 @@ __device__ __forceinline__ float seg_weight_series(float x) {
 // raw cell data: (rho, j, kappa) or (rho, T)
 template <int FK>
 struct Raw {
-  float rho, a, b;
+  float rho, a, b, c;  // (rho, j, kappa, 1/kappa) or (rho, T, -, -)
 };
 
-// The packed field (air_field_pack): one 16-byte (rho, j, kappa, 0) record
+// The packed field (air_field_pack): one 16-byte (rho, j, kappa, 1/kappa) record
 // per cell (one-band (rho, T) fields get their j, kappa evaluated once when
 // packing: three transcendentals fewer per visit) or 8-byte (rho, T) for
 // several bands, in 2x2x2 bricks.  Loads go through a
@@ -115,21 +115,25 @@ __device__ __forceinline__ Raw<FK> load_raw(i32x4 R, int cell) {
     r.rho = q[0];
     r.a = q[1];
     r.b = q[2];
+    r.c = q[3];
   } else {
     const f32x2 q = buffer_load_f32x2(R, (int)((unsigned)cell * 8u), 0, 0);
     r.rho = q[0];
     r.a = q[1];
     r.b = 0.0f;
+    r.c = 0.0f;
   }
   return r;
 }
 
 // emissivity and opacity of each band from the raw cell data
+// (and 1/kappa: the packed one-band record carries it)
 template <int NB, int FK>
-__device__ __forceinline__ void optics(const Fld& f, const Raw<FK>& r, float* j, float* k) {
+__device__ __forceinline__ void optics(const Fld& f, const Raw<FK>& r, float* j, float* k, float* rk) {
   if constexpr (FK == AIR_FIELD_RHO_J_KAPPA) {
     j[0] = r.a;
     k[0] = r.b;
+    rk[0] = r.c;
   } else {
     const float lt = __builtin_amdgcn_logf(r.a);  // log2 T
     const float r2 = r.rho * r.rho;
@@ -137,6 +141,7 @@ __device__ __forceinline__ void optics(const Fld& f, const Raw<FK>& r, float* j,
     for (int b = 0; b < NB; ++b) {
       k[b] = f.k0[b] * r.rho * __builtin_amdgcn_exp2f(-f.s[b] * lt);
       j[b] = r2 * __builtin_amdgcn_exp2f(f.q[b] * lt);
+      rk[b] = __builtin_amdgcn_rcpf(k[b]);
     }
   }
 }
@@ -264,14 +269,14 @@ __device__ __forceinline__ int cells_between(const Geo& g, const double o[3], co
     _Pragma("unroll") for (int q = 0; q < KB; ++q) {                      \
       if (!BF && (V0) + q >= nvis) continue;                              \
       const float ds = DS[q];                                             \
-      float jb[NB], kb[NB];                                               \
-      optics<NB, FK>(f, RAW[q], jb, kb);                                  \
+      float jb[NB], kb[NB], rkb[NB];                                      \
+      optics<NB, FK>(f, RAW[q], jb, kb, rkb);                             \
       _Pragma("unroll") for (int b = 0; b < NB; ++b) {                    \
         const float dtau = kb[b] * ds;                                    \
         bT[b] += dtau;                                                    \
         const float Ta = __builtin_amdgcn_exp2f(-(t0b[b] + bT[b]) * LOG2E_F); \
         const float thin = Tb[b] * (jb[b] * ds) * seg_weight_series(dtau); \
-        const float thick = (Tb[b] - Ta) * jb[b] * __builtin_amdgcn_rcpf(kb[b]); \
+        const float thick = (Tb[b] - Ta) * jb[b] * rkb[b];               \
         bI[b] += dtau < THICK ? thin : thick;                             \
         Tb[b] = Ta;                                                       \
       }                                                                   \
@@ -697,7 +702,8 @@ __device__ __forceinline__ void wave_stats(unsigned long long* ctr, unsigned lon
 
 // ------------------------------------------------------------ kernels
 // packing modes: copy (rho, j, kappa); evaluate one band's (j, kappa) from
-// (rho, T) with the march's own optics; copy (rho, T)
+// (rho, T) with the march's own optics; copy (rho, T).  One-band records
+// carry 1/kappa (v_rcp_f32, as the march would take it) in their fourth word
 enum { PACK_RJK = 0, PACK_RT_TO_RJK = 1, PACK_RT = 2 };
 
 template <int PM>
@@ -709,15 +715,16 @@ __device__ __forceinline__ void pack_cell(const Fld& f, int64_t src, bool in, in
     float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
     if (in) {
       if constexpr (PM == PACK_RJK) {
-        v = make_float4(f.rho[src], f.emis[src], f.kappa[src], 0.0f);
+        const float kap = f.kappa[src];
+        v = make_float4(f.rho[src], f.emis[src], kap, __builtin_amdgcn_rcpf(kap));
       } else {
         Raw<AIR_FIELD_RHO_T> r;
         r.rho = f.rho[src];
         r.a = f.temp[src];
-        r.b = 0.0f;
-        float j[1], k[1];
-        optics<1, AIR_FIELD_RHO_T>(f, r, j, k);
-        v = make_float4(r.rho, j[0], k[0], 0.0f);
+        r.b = r.c = 0.0f;
+        float j[1], k[1], rk[1];
+        optics<1, AIR_FIELD_RHO_T>(f, r, j, k, rk);
+        v = make_float4(r.rho, j[0], k[0], rk[0]);
       }
     }
     reinterpret_cast<float4*>(const_cast<void*>(f.packed))[dst] = v;

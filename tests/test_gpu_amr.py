@@ -144,8 +144,8 @@ def test_amr_packed_layout_contents(ctx):
 
 
 def test_one_band_rho_t_packs_coefficients(ctx):
-    """A one-band (rho, T) field is packed as (rho, j, kappa, 0) records,
-    j = rho^2 T^q and kappa = k0 rho T^-s evaluated once."""
+    """A one-band (rho, T) field is packed as (rho, j, kappa, 1/kappa)
+    records, j = rho^2 T^q and kappa = k0 rho T^-s evaluated once."""
     from paper_1010_5534_amd import air
     g = inputs.amr_from_predicate(1, 4, 1, lambda l, blo, sz: l == 0)
     n = g.n_cells
@@ -158,8 +158,9 @@ def test_one_band_rho_t_packs_coefficients(ctx):
     r64, t64 = rho.astype(np.float64), T.astype(np.float64)
     ref = np.stack([r64, r64 * r64 * t64 ** 0.5, 0.7 * r64 * t64 ** -1.5, np.zeros(n)], axis=-1)
     ref = _amr_brick_order(ref, 4)
-    assert np.array_equal(got[:, 0], ref[:, 0].astype(np.float32)) and np.all(got[:, 3] == 0)
+    assert np.array_equal(got[:, 0], ref[:, 0].astype(np.float32))
     assert np.allclose(got[:, 1:3], ref[:, 1:3], rtol=2e-6, atol=0)
+    assert np.allclose(got[:, 3], 1.0 / got[:, 2].astype(np.float64), rtol=2.5e-7, atol=0)
 
 
 def _bad_tables():
