@@ -1,21 +1,25 @@
 // Ray march kernels for adaptive image ray-tracing on gfx950.
 //
-// One lane traces one pixel's ray (section 2 step ii); a wavefront takes 64
-// consecutive work-queue entries, which in forest-Morton order are an 8x8
-// pixel tile of a complete subtree, so its lanes walk neighbouring cell
-// columns and their field loads share cache lines.  Waves pull tiles from a
-// per-level ticket counter, so the grid is sized to the machine, not to the
-// (data-dependent) queue length.
+// A block of S waves traces a tile of 64 work-queue entries, one ray per
+// lane (section 2 step ii): wave k walks the k-th of S equal parameter
+// sub-intervals of every ray, and wave 0 folds the S partials in order.  In
+// forest-Morton order a tile is a patch of neighbouring pixels, so at each
+// step the 64 lanes read neighbouring cells.  Tiles are dealt to the XCDs in
+// chunks (static split, or per-XCD tickets when a block has many); on the
+// coarse levels, where a launch holds few tiles whose rays lie cells apart,
+// each (tile, sub-interval) runs as its own wave job and a second launch
+// folds the partials in the same order (split tiles).
 //
 // Along each ray the exact solution for cell-constant j, kappa, rho is
 // accumulated front to back:
 //   I_b += exp(-tau_b) j_b ds (1 - exp(-kappa_b ds)) / (kappa_b ds),
 //   tau_b += kappa_b ds,  N += rho ds,
-// in float32 with Kahan-compensated sums.  Ray-box entry and the DDA's
-// per-axis crossing parameters are formed in float64 and carried as
-// float-float pairs; each crossing time is rebuilt from its integer count
-// (t = t_first + k dt), so no rounding accumulates along the ray and every
-// segment length is a difference of two correctly rounded values.
+// in float32 with Kahan-compensated sums.  Ray-box entry, the sub-interval
+// bounds and each axis's first crossing and spacing (relative to the
+// sub-interval start) are formed in float64 and rounded once; the k-th
+// crossing is rebuilt as fma(k, dt, t_first), so no rounding accumulates
+// along the ray and every segment length is a difference of two freshly
+// rounded values.
 #include "air_common.h"
 
 namespace air {
@@ -27,28 +31,6 @@ constexpr float LOG2E_F = 1.4426950408889634f;
 #define AIR_KB 4
 #endif
 constexpr int KB = AIR_KB;  // cells per load batch in the march
-
-struct ff {
-  float hi, lo;
-};
-
-__device__ __forceinline__ ff ff_of(double x) {
-  float h = (float)x;
-  return {h, (float)(x - (double)h)};
-}
-
-// T0 + k*D, float-float, k a crossing count (exact in float)
-__device__ __forceinline__ ff ff_axpy(int k, ff D, ff T0) {
-#pragma clang fp contract(off)
-  float kf = (float)k;
-  float p = kf * D.hi;
-  float pe = __builtin_fmaf(kf, D.hi, -p);  // exact error of the product
-  float pl = __builtin_fmaf(kf, D.lo, pe);
-  float s = T0.hi + p;  // two-sum of T0.hi and p
-  float z = s - T0.hi;
-  float se = (T0.hi - (s - z)) + (p - z);
-  return {s, (se + pl) + T0.lo};
-}
 
 __device__ __forceinline__ void kadd(float& s, float& c, float x) {
 #pragma clang fp contract(off)

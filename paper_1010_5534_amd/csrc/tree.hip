@@ -18,10 +18,6 @@ constexpr int RB = 256;             // refine block size
 constexpr int STK = 2 * MAXL;       // closure stack depth bound: 2L + 1 with L <= MAXL - 2
 constexpr int BALQ = 16;            // closure refinements listed per thread (more go out directly)
 
-__device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
-  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-}
-
 __device__ __forceinline__ uint32_t state_or(uint8_t* state, int64_t p, uint32_t bits) {
   const uint32_t sh = 8u * (uint32_t)(p & 3);
   uint32_t old = atomicOr(reinterpret_cast<uint32_t*>(state + (p - (p & 3))), bits << sh);
