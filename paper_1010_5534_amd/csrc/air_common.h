@@ -65,6 +65,12 @@ struct Fld {
   const float* kappa;
   const float* temp;
   float k0[MAXB], s[MAXB], q[MAXB];
+  // band ladder: s_b = s0 + b ds and one q for every band (as in the power-law
+  // band tables of the workloads): then T^-s_b = T^-s0 (T^-ds)^b and j is
+  // shared, so a visit takes 5 transcendentals for its bands instead of 3 per
+  // band; rk0[b] = 1 / k0[b]
+  int ladder;
+  float s0, ds, q0, rk0[MAXB];
 };
 
 // image pyramid layout: per view, levels 0..Lmax of dense maps indexed by

@@ -305,6 +305,20 @@ void fill_fld(const air_field* f, const air_grid* g, Fld& F) {
     F.k0[b] = (float)f->band[b][0];
     F.s[b] = (float)f->band[b][1];
     F.q[b] = (float)f->band[b][2];
+    F.rk0[b] = (float)(1.0 / f->band[b][0]);
+  }
+  // the ladder form for two or more bands whose s step evenly and whose q agree
+  if (f->kind == AIR_FIELD_RHO_T && F.nb >= 2) {
+    const double s0 = f->band[0][1], ds = f->band[1][1] - f->band[0][1];
+    bool lad = true;
+    for (int b = 0; b < F.nb; ++b) {
+      lad = lad && f->band[b][2] == f->band[0][2] && f->band[b][0] > 0.0;
+      lad = lad && std::fabs(f->band[b][1] - (s0 + b * ds)) <= 1e-12 * (1.0 + std::fabs(s0) + std::fabs(b * ds));
+    }
+    F.ladder = lad ? 1 : 0;
+    F.s0 = (float)s0;
+    F.ds = (float)ds;
+    F.q0 = (float)f->band[0][2];
   }
 }
 

@@ -56,6 +56,10 @@ __device__ __forceinline__ float seg_weight_series(float x) {
   return p;
 }
 
+// field kinds of the march: the ABI's two, and (rho, T) with a band ladder
+// (Fld::ladder: s_b = s0 + b ds, one q), whose optics share work across bands
+constexpr int FK_LADDER = 2;
+
 // raw cell data: (rho, j, kappa) or (rho, T)
 template <int FK>
 struct Raw {
@@ -119,11 +123,27 @@ __device__ __forceinline__ void optics(const Fld& f, const Raw<FK>& r, float* j,
   } else {
     const float lt = __builtin_amdgcn_logf(r.a);  // log2 T
     const float r2 = r.rho * r.rho;
+    if constexpr (FK == FK_LADDER) {
+      const float jj = r2 * __builtin_amdgcn_exp2f(f.q0 * lt);
+      const float base = r.rho * __builtin_amdgcn_exp2f(-f.s0 * lt);  // rho T^-s0
+      const float step = __builtin_amdgcn_exp2f(-f.ds * lt);          // T^-ds
+      const float rbase = __builtin_amdgcn_rcpf(base), rstep = __builtin_amdgcn_rcpf(step);
+      float e = base, re = rbase;
 #pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      k[b] = f.k0[b] * r.rho * __builtin_amdgcn_exp2f(-f.s[b] * lt);
-      j[b] = r2 * __builtin_amdgcn_exp2f(f.q[b] * lt);
-      rk[b] = __builtin_amdgcn_rcpf(k[b]);
+      for (int b = 0; b < NB; ++b) {
+        k[b] = f.k0[b] * e;
+        rk[b] = f.rk0[b] * re;
+        j[b] = jj;
+        e *= step;
+        re *= rstep;
+      }
+    } else {
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        k[b] = f.k0[b] * r.rho * __builtin_amdgcn_exp2f(-f.s[b] * lt);
+        j[b] = r2 * __builtin_amdgcn_exp2f(f.q[b] * lt);
+        rk[b] = __builtin_amdgcn_rcpf(k[b]);
+      }
     }
   }
 }
@@ -1110,6 +1130,17 @@ __global__ __launch_bounds__(64 * MAX_SEG) void k_trace_pixels(MarchArgs A, int6
     if (FKV == AIR_FIELD_RHO_J_KAPPA || NBV == 1) {                              \
       constexpr int NB_ = 1, FK_ = AIR_FIELD_RHO_J_KAPPA, GK_ = GKV;             \
       __VA_ARGS__;                                                               \
+    } else if (FKV == FK_LADDER) {                                               \
+      if (NBV == 2) {                                                            \
+        constexpr int NB_ = 2, FK_ = FK_LADDER, GK_ = GKV;                       \
+        __VA_ARGS__;                                                             \
+      } else if (NBV <= 4) {                                                     \
+        constexpr int NB_ = 4, FK_ = FK_LADDER, GK_ = GKV;                       \
+        __VA_ARGS__;                                                             \
+      } else {                                                                   \
+        constexpr int NB_ = 8, FK_ = FK_LADDER, GK_ = GKV;                       \
+        __VA_ARGS__;                                                             \
+      }                                                                          \
     } else if (NBV == 2) {                                                       \
       constexpr int NB_ = 2, FK_ = AIR_FIELD_RHO_T, GK_ = GKV;                   \
       __VA_ARGS__;                                                               \
@@ -1123,10 +1154,11 @@ __global__ __launch_bounds__(64 * MAX_SEG) void k_trace_pixels(MarchArgs A, int6
   } while (0)
 #define AIR_DISPATCH(A_, ...)                                                    \
   do {                                                                           \
+    const int fk_ = (A_).f.ladder ? FK_LADDER : (A_).f.kind;                     \
     if ((A_).g.kind == AIR_GRID_BLOCK_AMR)                                       \
-      AIR_DISPATCH_NB((A_).f.nb, (A_).f.kind, AIR_GRID_BLOCK_AMR, __VA_ARGS__);   \
+      AIR_DISPATCH_NB((A_).f.nb, fk_, AIR_GRID_BLOCK_AMR, __VA_ARGS__);           \
     else                                                                         \
-      AIR_DISPATCH_NB((A_).f.nb, (A_).f.kind, AIR_GRID_UNIFORM, __VA_ARGS__);     \
+      AIR_DISPATCH_NB((A_).f.nb, fk_, AIR_GRID_UNIFORM, __VA_ARGS__);             \
   } while (0)
 
 hipError_t launch_march_spec(const MarchArgs& a, const uint64_t* spec, const unsigned long long* count,

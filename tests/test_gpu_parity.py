@@ -155,9 +155,14 @@ def test_air_tree_parity_winds(ctx, seed, direction):
     parity.assert_parity(rep)
 
 
-def test_multiband_rho_t(ctx):
+# the workloads' band tables step s evenly with one q (the march's ladder
+# form); an uneven table takes the per-band form
+UNEVEN_BANDS = np.array([[0.3, 1.1, 0.5], [3.0, 1.7, 0.4], [1.2, 1.3, 0.65], [8.0, 0.9, 0.5]])
+
+
+@pytest.mark.parametrize("bands", [inputs.default_bands(4), UNEVEN_BANDS], ids=["ladder", "uneven"])
+def test_multiband_rho_t(ctx, bands):
     from paper_1010_5534_amd import air
-    bands = inputs.default_bands(4)
     g, f = inputs.winds2(seed=6, n=48, kind=inputs.FIELD_RHO_T, bands=bands)
     scene = air.upload(g, f)
     v = inputs.view_for((0.4, 0.5, 0.77))
