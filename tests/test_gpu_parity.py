@@ -71,6 +71,36 @@ def test_fixed_oblique_views(ctx, direction):
     assert np.array_equal(gi[0] == 0, ref["I"][0] == 0)
 
 
+@pytest.mark.parametrize("case", ["edges", "corners"])
+def test_rays_on_cell_faces_and_corners(ctx, case):
+    """Exact ties of the geometry: with a 16^3 unit box and an 8x8 image of
+    width 1 looking along +z, every pixel centre lies on a cell edge (x and y
+    both on cell faces), so the half-open cell rule alone picks the cells; along
+    (1, 1, 0)/sqrt2 with an image of width sqrt2, every ray meets its x and y
+    faces at the same points (it passes through cell corners), so the walk
+    takes ties at every other step.  Both against the oracle."""
+    from paper_1010_5534_amd import air
+    g, f = inputs.gaussian(n=16)
+    scene = air.upload(g, f)
+    if case == "edges":
+        v = inputs.View((0.0, 0.0, 1.0), (0.0, 1.0, 0.0), (0.5, 0.5, 0.5), 1.0)
+        N0, L = 8, 0
+        u = (-0.5 + (np.arange(N0) + 0.5) / N0 + 0.5) * 16
+        assert np.all(u == np.round(u)) and np.all(u.astype(int) % 2 == 1)
+    else:
+        r = 1.0 / math.sqrt(2.0)
+        v = inputs.View((r, r, 0.0), (0.0, 0.0, 1.0), (0.5, 0.5, 0.5), math.sqrt(2.0))
+        N0, L = 8, 1
+    say(f"fixed gaussian16 {case} N0={N0} L={L}")
+    img, flux, st = ctx.render_fixed(scene, [v], N0, L)
+    ref = oracle.render_fixed(g, f, v, N0, L)
+    gi = img[0].cpu().numpy().astype(np.float64)
+    assert parity.rel_err(gi[0], ref["I"][0]).max() <= 1e-5
+    assert parity.rel_err(gi[1], ref["N"]).max() <= 1e-5
+    assert np.array_equal(gi[0] == 0, ref["I"][0] == 0)
+    assert st["hits"] == int(np.count_nonzero(ref["lmax"] >= 0))
+
+
 @pytest.mark.parametrize("xc", [0.2, 0.5, 0.8])
 def test_air_tree_parity_gaussian(ctx, gauss, xc):
     from paper_1010_5534_amd import air
