@@ -261,6 +261,7 @@ class Context:
             raise RuntimeError("no GPU visible: the AIR library runs on the GPU only")
         self.device = device
         self._cache = {}
+        self._views_key, self._views_arr = None, None
         self._p = C.c_void_p()
         rc = lib().air_create(C.byref(self._p), device)
         if rc != AIR_OK:
@@ -344,38 +345,60 @@ class Context:
         return out + (dict(spec_rays=ls.spec_rays, wasted=ls.wasted, missing=ls.missing,
                            depth_hist=list(ls.depth_hist)[:6], ms_features=ls.ms_features, ms_spec=ls.ms_spec),)
 
-    def _render(self, scene, views, prm, want_tree, want_image, want_flux, capacity, reuse, learned, ls):
-        torch = _torch()
-        V, nb = len(views), scene.n_bands
-        R = prm.coarse_n << prm.max_level
-        bound = sum((prm.coarse_n << L) ** 2 for L in range(prm.max_level + 1))
-        cap = min(bound, capacity or (1 << 21))
-        vs = _views(views)
-        ikey = ("img", V, nb, R)
-        if want_image and reuse and ikey in self._cache:
-            images = self._cache[ikey]
+    def _view_array(self, views) -> C.Array:
+        # the last conversion is kept: repeated calls with the same view
+        # values skip building the ctypes array
+        key = tuple((tuple(v.dir), tuple(v.up), tuple(v.center), v.width) for v in views)
+        if key != self._views_key:
+            self._views_arr, self._views_key = _views(views), key
+        return self._views_arr
+
+    def _tree_array(self, V, nb, cap, reuse):
+        trees = (air_tree * V)()
+        tkey = ("tree", V, nb, cap)
+        if reuse and tkey in self._cache:
+            pairs = self._cache[tkey]
         else:
-            images = torch.empty((V, nb + 1, R, R), dtype=torch.float32, device=f"cuda:{self.device}") \
-                if want_image else None
-            if want_image and reuse:
-                self._cache[ikey] = images
-        flux = np.zeros((V, nb), dtype=np.float64) if want_flux else None
-        st = air_stats()
+            pairs = [self._alloc_tree(cap, nb) for _ in range(V)]
+            if reuse:
+                self._cache[tkey] = pairs
+        keep = []
+        for k in range(V):
+            s, t = pairs[k]
+            trees[k] = s
+            keep.append(t)
+        return trees, keep
+
+    def _render(self, scene, views, prm, want_tree, want_image, want_flux, capacity, reuse, learned, ls):
+        V, nb = len(views), scene.n_bands
+        vs = self._view_array(views)
+        # with reuse, the output buffers and the argument structures of a call
+        # shape are built once (flux is handed back as a copy)
+        ckey = ("call", V, nb, prm.coarse_n, prm.max_level, capacity, want_tree, want_image, want_flux)
+        bundle = self._cache.get(ckey) if reuse else None
+        if bundle is None:
+            torch = _torch()
+            R = prm.coarse_n << prm.max_level
+            bound = sum((prm.coarse_n << L) ** 2 for L in range(prm.max_level + 1))
+            cap = min(bound, capacity or (1 << 21))
+            ikey = ("img", V, nb, R)
+            if want_image and reuse and ikey in self._cache:
+                images = self._cache[ikey]
+            else:
+                images = torch.empty((V, nb + 1, R, R), dtype=torch.float32, device=f"cuda:{self.device}") \
+                    if want_image else None
+                if want_image and reuse:
+                    self._cache[ikey] = images
+            flux = np.zeros((V, nb), dtype=np.float64) if want_flux else None
+            trees, keep = self._tree_array(V, nb, cap, reuse) if want_tree else (None, [])
+            bundle = [images, flux, air_stats(), trees, keep, cap]
+            if reuse:
+                self._cache[ckey] = bundle
+        images, flux, st, trees, keep, cap = bundle
+        C.memset(C.addressof(st), 0, C.sizeof(st))  # fields a call does not fill read as zero
+        if want_flux:
+            flux.fill(0.0)
         while True:
-            trees = (air_tree * V)() if want_tree else None
-            keep = []
-            if want_tree:
-                tkey = ("tree", V, nb, cap)
-                if reuse and tkey in self._cache:
-                    pairs = self._cache[tkey]
-                else:
-                    pairs = [self._alloc_tree(cap, nb) for _ in range(V)]
-                    if reuse:
-                        self._cache[tkey] = pairs
-                for k in range(V):
-                    s, t = pairs[k]
-                    trees[k] = s
-                    keep.append(t)
             targs = (C.addressof(trees) if want_tree else None, images.data_ptr() if want_image else None,
                      flux.ctypes.data if want_flux else None, C.addressof(st))
             if learned is None or learned == "batch":
@@ -388,6 +411,8 @@ class Context:
                                               C.addressof(learned[1]), *targs, C.addressof(ls), self._stream())
             if rc == AIR_ECAPACITY and want_tree:
                 cap = max(trees[k].n_nodes for k in range(V))
+                trees, keep = self._tree_array(V, nb, cap, reuse)
+                bundle[3:6] = [trees, keep, cap]
                 continue
             self._check(rc)
             break
@@ -397,7 +422,7 @@ class Context:
                 n = trees[k].n_nodes
                 t = keep[k]
                 out.append(Tree(n, list(trees[k].n_per_level), trees[k].n_leaves, t))
-        return out, images, flux, stats_dict(st)
+        return out, images, (flux.copy() if reuse and want_flux else flux), stats_dict(st)
 
     def render_fixed(self, scene: DeviceScene, views: Sequence, coarse_n: int, level: int, want_image=True,
                      want_flux=True):
