@@ -60,6 +60,27 @@ int main(void) {
                          air.air_tree.visits.offset, air.air_field.packed.offset]
 
 
+def test_stats_unpacking_reads_every_field():
+    """The binding's stats dictionary reports every air_stats field with its
+    value (distinct values in every field)."""
+    from paper_1010_5534_amd import air
+    s = air.air_stats()
+    names = [n for n, _ in air.air_stats._fields_]
+    for k, n in enumerate(names):
+        if n == "rays_per_level":
+            for i in range(air.MAX_LEVELS):
+                s.rays_per_level[i] = 1000 + 7 * i
+        elif n.startswith("ms_"):
+            setattr(s, n, 0.5 + k)
+        else:
+            setattr(s, n, 3 + 11 * k)
+    d = air.stats_dict(s)
+    assert set(d) == set(names)
+    for n in names:
+        want = list(getattr(s, n)) if n == "rays_per_level" else getattr(s, n)
+        assert d[n] == want, n
+
+
 def test_packed_bytes_without_device():
     """air_field_packed_bytes needs no device: 2x2x2 bricks, 16 B or 8 B cells."""
     import ctypes as C
