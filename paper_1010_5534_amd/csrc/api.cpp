@@ -90,6 +90,16 @@ air_status fail(air_ctx* c, air_status code, const char* fmt, ...) {
     if (e_ != hipSuccess) return fail(ctx, AIR_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
   } while (0)
 
+// a render's final wait is short (well under a millisecond): poll the
+// stream rather than a blocking synchronize, which may put the thread to
+// sleep and wake it late
+hipError_t spin_stream(hipStream_t s) {
+  hipError_t e;
+  while ((e = hipStreamQuery(s)) == hipErrorNotReady) {
+  }
+  return e;
+}
+
 air_status ensure(air_ctx* c, DevBuf& b, size_t bytes) {
   if (bytes == 0) bytes = 256;
   if (b.bytes >= bytes) return AIR_OK;
@@ -533,6 +543,10 @@ struct Plan {
   air_learn_params lp{};
   bool trees = false, flux = false, timing = false;
   float* images = nullptr;
+  // where k_finish writes the result block: the context's pinned host buffer
+  // (eager calls: no copy back) or its device buffer (captured sequences,
+  // whose launch arguments must not change)
+  unsigned long long* res = nullptr;
 };
 
 air_status enqueue_render(air_ctx* c, const Plan& P, const Tune& tune, hipStream_t s) {
@@ -557,8 +571,7 @@ air_status enqueue_render(air_ctx* c, const Plan& P, const Tune& tune, hipStream
   unsigned long long* chunk = (unsigned long long*)c->chunk.p;
   double* fpart = P.flux ? (double*)c->partial.p : nullptr;
   HIPCHK(c, launch_count(A, chunk, (unsigned*)c->cstat.p, P.n_chunks, fpart, P.images, s));
-  HIPCHK(c, launch_finish(A, chunk, P.n_chunks, P.trees, (const unsigned*)c->cstat.p, fpart,
-                          (unsigned long long*)c->vstat.p, s));
+  HIPCHK(c, launch_finish(A, chunk, P.n_chunks, P.trees, (const unsigned*)c->cstat.p, fpart, P.res, s));
   if (P.trees) {
     HIPCHK(c, launch_emit(A, chunk, P.n_chunks, (int32_t*)c->idmap.p, (uint64_t*)c->nodepos.p, s));
     HIPCHK(c, launch_write_tree(A, chunk, (const int32_t*)c->idmap.p, (const uint64_t*)c->nodepos.p,
@@ -655,6 +668,9 @@ air_status render_core(air_ctx* c, const air_grid* grid, const air_field* field,
   P.flux = flux != nullptr;
   P.images = images;
   P.timing = !batch && (prm->flags & AIR_FLAG_TIMING) != 0;
+  const size_t res_bytes = 8 * (size_t)res_words(V, nb);
+  if ((st = ensure_host(c, (void**)&c->host_vstat, &c->host_vstat_n, res_bytes))) return st;
+  P.res = batch ? (unsigned long long*)c->vstat.p : c->host_vstat;
   if (learned && (st = ensure_learned(c, A))) return st;
   if (trees) {
     if ((st = ensure(c, c->idmap, 4 * (size_t)V * A.img.S))) return st;
@@ -720,16 +736,17 @@ air_status render_core(air_ctx* c, const air_grid* grid, const air_field* field,
   }
   HIPCHK(c, hipEventRecord(ev[1], s));
   const bool timing = P.timing;
-  // one copy, one wait: the result block (counters, per-view counts, fluxes)
-  const size_t res_bytes = 8 * (size_t)res_words(V, nb);
-  if ((st = ensure_host(c, (void**)&c->host_vstat, &c->host_vstat_n, res_bytes))) return st;
-  HIPCHK(c, hipMemcpyAsync(c->host_vstat, c->vstat.p, res_bytes, hipMemcpyDeviceToHost, s));
+  // one wait for the result block (counters, per-view counts, fluxes):
+  // an eager call's k_finish wrote it to the pinned host buffer, a captured
+  // sequence's is copied there
+  if (P.res != c->host_vstat)
+    HIPCHK(c, hipMemcpyAsync(c->host_vstat, P.res, res_bytes, hipMemcpyDeviceToHost, s));
   std::vector<uint8_t> depth_h;
   if (learned && ls) {
     depth_h.resize((size_t)V * N0 * N0);
     HIPCHK(c, hipMemcpyAsync(depth_h.data(), c->depth8.p, depth_h.size(), hipMemcpyDeviceToHost, s));
   }
-  HIPCHK(c, hipStreamSynchronize(s));
+  HIPCHK(c, spin_stream(s));
   const unsigned long long* hc = c->host_vstat;  // the counters lead the result block
   const unsigned long long* hv = c->host_vstat + res_vstat_off();
   if (hc[CTR_OVERFLOW]) return fail(c, AIR_EDEVICE, "internal work queue overflow");

@@ -465,7 +465,8 @@ __device__ __forceinline__ void scan_block(unsigned long long* a, int64_t n, uns
 // counters; blocks 1 .. V (Lmax+1) sum the counters of one (view, level)'s
 // chunks (levels start on a chunk); the next V nb blocks sum one (view,
 // band)'s flux partials (each thread a fixed stride, then a fixed tree).
-// Everything goes to the result block res.
+// Everything goes to the result block res (device memory, or pinned host
+// memory that the host reads once the stream has finished).
 __global__ __launch_bounds__(1024) void k_finish(MarchArgs A, unsigned long long* chunk_counts, int64_t n_chunks,
                                                  int scan, const unsigned* chunk_stats, const double* flux_partial,
                                                  unsigned long long* res) {
@@ -476,6 +477,7 @@ __global__ __launch_bounds__(1024) void k_finish(MarchArgs A, unsigned long long
   const int role = blockIdx.x;
   if (role == 0) {
     for (int k = threadIdx.x; k < CTR_COUNT; k += 1024) res[k] = A.w.ctr[k];
+    __threadfence_system();  // res may be host memory, read once the stream is done
     if (scan) scan_block(chunk_counts, n_chunks, wsum);
     return;
   }
@@ -501,6 +503,7 @@ __global__ __launch_bounds__(1024) void k_finish(MarchArgs A, unsigned long long
       unsigned long long t = 0;
       for (int k = 0; k < 1024 / WAVE; ++k) t += sh[threadIdx.x][k];
       res[res_vstat_off() + ((int64_t)v * MAXL + L) * VS_N + threadIdx.x] = t;
+      __threadfence_system();
     }
     return;
   }
@@ -515,7 +518,10 @@ __global__ __launch_bounds__(1024) void k_finish(MarchArgs A, unsigned long long
     if (threadIdx.x < o) shd[threadIdx.x] += shd[threadIdx.x + o];
     __syncthreads();
   }
-  if (threadIdx.x == 0) reinterpret_cast<double*>(res + res_flux_off(V))[fb] = shd[0];
+  if (threadIdx.x == 0) {
+    reinterpret_cast<double*>(res + res_flux_off(V))[fb] = shd[0];
+    __threadfence_system();
+  }
 }
 
 // node ids: exclusive prefix of existing positions in canonical order; also
