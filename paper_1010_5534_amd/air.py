@@ -262,6 +262,7 @@ class Context:
         self.device = device
         self._cache = {}
         self._views_key, self._views_arr = None, None
+        self._cap_hint = {}
         self._p = C.c_void_p()
         rc = lib().air_create(C.byref(self._p), device)
         if rc != AIR_OK:
@@ -380,7 +381,10 @@ class Context:
             torch = _torch()
             R = prm.coarse_n << prm.max_level
             bound = sum((prm.coarse_n << L) ** 2 for L in range(prm.max_level + 1))
-            cap = min(bound, capacity or (1 << 21))
+            # start from the capacity this call shape needed last time, so a
+            # large tree does not come back AIR_ECAPACITY (and get rendered
+            # again) on every call
+            cap = max(min(bound, capacity or (1 << 21)), self._cap_hint.get(ckey, 0))
             ikey = ("img", V, nb, R)
             if want_image and reuse and ikey in self._cache:
                 images = self._cache[ikey]
@@ -411,6 +415,7 @@ class Context:
                                               C.addressof(learned[1]), *targs, C.addressof(ls), self._stream())
             if rc == AIR_ECAPACITY and want_tree:
                 cap = max(trees[k].n_nodes for k in range(V))
+                self._cap_hint[ckey] = cap
                 trees, keep = self._tree_array(V, nb, cap, reuse)
                 bundle[3:6] = [trees, keep, cap]
                 continue

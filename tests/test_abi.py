@@ -116,3 +116,52 @@ def test_product_path_does_not_import_oracle():
                 "paper_1010_5534_amd/csrc/tree.hip", "paper_1010_5534_amd/csrc/air_common.h"):
         txt = open(os.path.join(ROOT, rel)).read()
         assert "oracle" not in txt.lower(), rel
+
+
+def test_binding_keeps_the_grown_tree_capacity(monkeypatch):
+    """A call whose tree outgrows the capacity comes back AIR_ECAPACITY with
+    the size it needs; the binding retries with that size once and starts
+    the next call of the same shape from it, so a large tree is rendered
+    once per call (host logic only: the library is a stand-in that checks
+    the capacity it is handed)."""
+    from paper_1010_5534_amd import air
+    need = 5000
+    seen = []
+
+    class StandIn:
+        def air_render(self, ctx, grid, field, views, n_views, prm, trees, images, flux, stats, stream):
+            t = C.cast(trees, C.POINTER(air.air_tree))
+            caps = [t[k].capacity for k in range(n_views)]
+            seen.append(min(caps))
+            for k in range(n_views):
+                t[k].n_nodes = need
+            return air.AIR_OK if min(caps) >= need else air.AIR_ECAPACITY
+
+    monkeypatch.setattr(air, "lib", lambda: StandIn())
+    ctx = object.__new__(air.Context)
+    ctx.device, ctx._p, ctx._cache = 0, None, {}
+    ctx._views_key, ctx._views_arr, ctx._cap_hint = None, None, {}
+    ctx._stream = lambda: None
+
+    def alloc(cap, nb):
+        s = air.air_tree()
+        s.capacity = cap
+        return s, {}
+
+    ctx._alloc_tree = alloc
+
+    class Scene:
+        n_bands = 1
+        grid = C.c_int(0)
+        field = C.c_int(0)
+
+    from paper_1010_5534_amd import inputs
+    views = [inputs.gaussian_view()]
+    prm = air.params(16, 4, 0.5)
+    for reuse in (False, True):
+        seen.clear()
+        for _ in range(3):
+            trees, _, _, _ = ctx.render(Scene(), views, prm, want_image=False, want_flux=False, capacity=100,
+                                        reuse=reuse)
+            assert trees[0].n_nodes == need
+        assert seen == ([100, need, need, need] if not reuse else [need, need, need]), seen
