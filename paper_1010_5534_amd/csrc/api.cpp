@@ -36,7 +36,7 @@ struct air_ctx {
   int64_t split_tiles = 4096;   // AIR_SPLIT_TILES: queue launches (levels >= 1) of at most this many tiles run split
   Tune eager;                   // launch shapes of air_render (AIR_MARCH_WAVES: march waves per CU)
   std::string err;
-  DevBuf state, valI, valN, xiI, xiN, visits, rmin, rmax, queue, ctr, chunk, cstat, vstat, idmap, partial, flux, parts,
+  DevBuf state, valI, valN, xiI, xiN, visits, rmin, rmax, queue, ctr, chunk, cstat, idmap, partial, flux, parts,
       views, touts, pack;
   // learned proposal: coarse maps, network activations and gradients, depth
   // choice and speculative work list
@@ -61,7 +61,6 @@ struct air_ctx {
   // launch shapes chosen per workload shape
   std::string graph_key;
   hipStream_t cap_stream = nullptr;  // the graph is captured and replayed here
-  hipEvent_t cap_in = nullptr, cap_out = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   hipGraph_t graph = nullptr;
   std::map<std::string, air::Tune> tuned;
@@ -432,7 +431,6 @@ air_status setup_render(air_ctx* c, const air_grid* grid, const air_field* field
   if ((st = ensure(c, c->ctr, 8 * CTR_COUNT))) return st;
   if ((st = ensure(c, c->chunk, 8 * (n_chunks + 1)))) return st;
   if ((st = ensure(c, c->cstat, 4 * VS_N * n_chunks))) return st;
-  if ((st = ensure(c, c->vstat, 8 * (size_t)res_words(V, nb)))) return st;
   if ((st = ensure(c, c->partial, 8 * n_chunks * nb))) return st;
   A.w.state = (uint8_t*)c->state.p;
   A.w.valI = (float*)c->valI.p;
@@ -544,8 +542,7 @@ struct Plan {
   bool trees = false, flux = false, timing = false;
   float* images = nullptr;
   // where k_finish writes the result block: the context's pinned host buffer
-  // (eager calls: no copy back) or its device buffer (captured sequences,
-  // whose launch arguments must not change)
+  // (no copy back; a captured sequence is keyed on its address)
   unsigned long long* res = nullptr;
 };
 
@@ -594,6 +591,7 @@ std::string plan_key(const Plan& P, const Tune& t) {
   const char flags[3] = {(char)P.trees, (char)P.flux, (char)P.timing};
   k.append(flags, 3);
   k.append(reinterpret_cast<const char*>(&P.images), sizeof P.images);
+  k.append(reinterpret_cast<const char*>(&P.res), sizeof P.res);
   k.append(reinterpret_cast<const char*>(&t), sizeof t);
   return k;
 }
@@ -670,7 +668,7 @@ air_status render_core(air_ctx* c, const air_grid* grid, const air_field* field,
   P.timing = !batch && (prm->flags & AIR_FLAG_TIMING) != 0;
   const size_t res_bytes = 8 * (size_t)res_words(V, nb);
   if ((st = ensure_host(c, (void**)&c->host_vstat, &c->host_vstat_n, res_bytes))) return st;
-  P.res = batch ? (unsigned long long*)c->vstat.p : c->host_vstat;
+  P.res = c->host_vstat;
   if (learned && (st = ensure_learned(c, A))) return st;
   if (trees) {
     if ((st = ensure(c, c->idmap, 4 * (size_t)V * A.img.S))) return st;
@@ -700,9 +698,8 @@ air_status render_core(air_ctx* c, const air_grid* grid, const air_field* field,
     Tune tune;
     if ((st = autotune(c, P, s, tune))) return st;
     const std::string key = plan_key(P, tune);
-    // capture and replay on the context's own stream (the caller's may be
-    // the null stream, which cannot be captured), ordered after the uploads
-    // above and before the result copies below by two events
+    // capture on the context's own stream (the caller's may be the null
+    // stream, which cannot be captured), after the uploads above
     hipStream_t cs = c->cap_stream;
     if (key != c->graph_key || !c->graph_exec) {
       if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
@@ -724,23 +721,17 @@ air_status render_core(air_ctx* c, const air_grid* grid, const air_field* field,
       c->graph = g;
       c->graph_key = key;
     }
+    // replayed on the caller's stream, after the uploads above
     HIPCHK(c, hipEventRecord(ev[0], s));
-    HIPCHK(c, hipEventRecord(c->cap_in, s));
-    HIPCHK(c, hipStreamWaitEvent(cs, c->cap_in, 0));
-    HIPCHK(c, hipGraphLaunch(c->graph_exec, cs));
-    HIPCHK(c, hipEventRecord(c->cap_out, cs));
-    HIPCHK(c, hipStreamWaitEvent(s, c->cap_out, 0));
+    HIPCHK(c, hipGraphLaunch(c->graph_exec, s));
   } else {
     HIPCHK(c, hipEventRecord(ev[0], s));
     if ((st = enqueue_render(c, P, c->eager, s))) return st;
   }
   HIPCHK(c, hipEventRecord(ev[1], s));
   const bool timing = P.timing;
-  // one wait for the result block (counters, per-view counts, fluxes):
-  // an eager call's k_finish wrote it to the pinned host buffer, a captured
-  // sequence's is copied there
-  if (P.res != c->host_vstat)
-    HIPCHK(c, hipMemcpyAsync(c->host_vstat, P.res, res_bytes, hipMemcpyDeviceToHost, s));
+  // one wait for the result block (counters, per-view counts, fluxes),
+  // which k_finish wrote to the pinned host buffer
   std::vector<uint8_t> depth_h;
   if (learned && ls) {
     depth_h.resize((size_t)V * N0 * N0);
@@ -862,9 +853,7 @@ air_status air_create(air_ctx** out, int32_t device) {
       air_destroy(c);
       return AIR_EDEVICE;
     }
-  if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&c->cap_in, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&c->cap_out, hipEventDisableTiming) != hipSuccess) {
+  if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
     air_destroy(c);
     return AIR_EDEVICE;
   }
@@ -876,7 +865,7 @@ void air_destroy(air_ctx* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   for (DevBuf* b : {&c->state, &c->valI, &c->valN, &c->xiI, &c->xiN, &c->visits, &c->rmin, &c->rmax, &c->queue,
-                    &c->ctr, &c->chunk, &c->cstat, &c->vstat, &c->idmap, &c->partial, &c->flux, &c->views,
+                    &c->ctr, &c->chunk, &c->cstat, &c->idmap, &c->partial, &c->flux, &c->views,
                     &c->touts, &c->pack, &c->nodepos, &c->lmax0, &c->feat, &c->cx0, &c->ca1, &c->ca2, &c->ca3, &c->cz,
                     &c->cdz, &c->cda, &c->cdb, &c->cwpart, &c->closs_part, &c->closs, &c->depth8, &c->scount,
                     &c->spec, &c->parts})
@@ -888,8 +877,6 @@ void air_destroy(air_ctx* c) {
   if (c->stage2) (void)hipHostFree(c->stage2);
   if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
   if (c->graph) (void)hipGraphDestroy(c->graph);
-  if (c->cap_in) (void)hipEventDestroy(c->cap_in);
-  if (c->cap_out) (void)hipEventDestroy(c->cap_out);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   for (int k = 0; k < air_ctx::NEV; ++k)
     if (c->ev[k]) (void)hipEventDestroy(c->ev[k]);
