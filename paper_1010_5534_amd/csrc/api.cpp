@@ -119,7 +119,13 @@ air_status ensure(air_ctx* c, DevBuf& b, size_t bytes) {
 
 air_status ensure_host(air_ctx* c, void** p, size_t* have, size_t bytes) {
   if (*have >= bytes && *p) return AIR_OK;
-  if (*p) (void)hipHostFree(*p);
+  // kernels and copies read and write these buffers asynchronously (a call
+  // that failed after enqueueing did not wait for them): drain the device
+  // before the old buffer goes
+  if (*p) {
+    (void)hipDeviceSynchronize();
+    (void)hipHostFree(*p);
+  }
   *p = nullptr;
   if (hipHostMalloc(p, bytes) != hipSuccess) {
     *p = nullptr;
