@@ -57,6 +57,33 @@ def test_batch_equals_render_and_replays(ctx):
     _same(ctx.render(scene, views2, prm), ctx.render_batch(scene, views2, prm))
 
 
+def test_view_counts_changing_between_calls(ctx):
+    """The result block lives in a pinned host buffer that k_finish writes
+    directly; it grows (after the device drains) when a call has more views,
+    and a captured sequence is keyed on its address.  Calls with 1, 4, 2 and
+    6 views in turn, eager and captured, each equal to the views rendered one
+    at a time, bit for bit (trees, flux, counts)."""
+    from paper_1010_5534_amd import air
+    g, f = inputs.winds2(seed=3, n=48, kind=inputs.FIELD_RHO_T, bands=inputs.default_bands(2))
+    scene = ctx.prepare(air.upload(g, f))
+    prm = air.params(12, 3, 0.4)
+    pool = inputs.isotropic_views(6, seed=5)
+    single = [ctx.render(scene, [v], prm, want_image=False) for v in pool]
+    for n in (1, 4, 2, 6):
+        for mode in ("eager", "batch"):
+            say(f"view counts: {n} views, {mode}")
+            fn = ctx.render if mode == "eager" else ctx.render_batch
+            trees, _, flux, st = fn(scene, pool[:n], prm, want_image=False)
+            for k in range(n):
+                t1, f1, s1 = single[k][0][0], single[k][2], single[k][3]
+                assert trees[k].n_nodes == t1.n_nodes
+                for name in ("level", "ix", "iy", "state", "I", "N", "visits"):
+                    assert torch.equal(getattr(trees[k], name), getattr(t1, name)), (n, mode, k, name)
+                assert np.array_equal(flux[k], f1[0]), (n, mode, k)
+            assert st["rays"] == sum(single[k][3]["rays"] for k in range(n))
+            assert st["hits"] == sum(single[k][3]["hits"] for k in range(n))
+
+
 def test_batch_amr_many_views_bands(ctx):
     from paper_1010_5534_amd import air
     g, f = inputs.amr_winds(seed=3, base_cells=64, bs=8, max_level=2, frac=(0.10, 0.03),
