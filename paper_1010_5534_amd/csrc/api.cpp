@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
+#include <chrono>
 #include <cstring>
 #include <string>
 #include <map>
@@ -89,13 +90,14 @@ air_status fail(air_ctx* c, air_status code, const char* fmt, ...) {
     if (e_ != hipSuccess) return fail(ctx, AIR_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
   } while (0)
 
-// a render's final wait is short (well under a millisecond): poll the
-// stream rather than a blocking synchronize, which may put the thread to
-// sleep and wake it late
+// a render's final wait: poll the stream for up to 2 ms (a blocking
+// synchronize may put the thread to sleep and wake it late, which shows on
+// sub-millisecond calls), then block for longer ones
 hipError_t spin_stream(hipStream_t s) {
+  const auto t0 = std::chrono::steady_clock::now();
   hipError_t e;
-  while ((e = hipStreamQuery(s)) == hipErrorNotReady) {
-  }
+  while ((e = hipStreamQuery(s)) == hipErrorNotReady)
+    if (std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(2)) return hipStreamSynchronize(s);
   return e;
 }
 
