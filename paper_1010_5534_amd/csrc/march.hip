@@ -767,16 +767,17 @@ __global__ __launch_bounds__(256) void k_pack_amr(Geo g, Fld f) {
 __global__ void k_init(MarchArgs A) {
   const int64_t S = A.img.S, n0sq = (int64_t)A.img.N0 * A.img.N0;
   const int v = blockIdx.y;
-  uint32_t* st = reinterpret_cast<uint32_t*>(A.w.state + (int64_t)v * S);
+  // S is a multiple of CHUNK bytes: 16-byte stores
+  uint4* st = reinterpret_cast<uint4*>(A.w.state + (int64_t)v * S);
   const uint32_t base_bits = AIR_NODE_EXIST | AIR_NODE_TESTED;
-  for (int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; w < S / 4; w += (int64_t)gridDim.x * blockDim.x) {
-    uint32_t word = 0;
-    if (4 * w < n0sq) {  // level 0 occupies [0, N0^2) of the view
+  for (int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; w < S / 16; w += (int64_t)gridDim.x * blockDim.x) {
+    uint32_t word[4] = {0u, 0u, 0u, 0u};
+    if (16 * w < n0sq) {  // level 0 occupies [0, N0^2) of the view
 #pragma unroll
-      for (int b = 0; b < 4; ++b)
-        if (4 * w + b < n0sq) word |= base_bits << (8 * b);
+      for (int b = 0; b < 16; ++b)
+        if (16 * w + b < n0sq) word[b >> 2] |= base_bits << (8 * (b & 3));
     }
-    st[w] = word;
+    st[w] = uint4{word[0], word[1], word[2], word[3]};
   }
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n0sq; e += (int64_t)gridDim.x * blockDim.x)
     A.w.queue[(int64_t)v * n0sq + e] = qentry((uint32_t)v, 0, (uint32_t)e);
@@ -1196,7 +1197,7 @@ hipError_t launch_pack(const Geo& g, const Fld& f, void* packed, hipStream_t s) 
 }
 
 hipError_t launch_init(const MarchArgs& a, hipStream_t s) {
-  const int64_t per_view = std::max<int64_t>(1, std::min<int64_t>(2048, (a.img.S / 4 + 255) / 256));
+  const int64_t per_view = std::max<int64_t>(1, std::min<int64_t>(2048, (a.img.S / 16 + 255) / 256));
   hipLaunchKernelGGL(k_init, dim3((unsigned)per_view, (unsigned)a.img.V), dim3(256), 0, s, a);
   return hipGetLastError();
 }
