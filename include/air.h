@@ -318,6 +318,34 @@ air_status air_cnn_loss_grad(air_ctx* ctx, air_cnn* net, const float* features, 
                              int32_t n_maps, int32_t h, int32_t w, const float* class_weight, double* loss,
                              float* grad, void* stream);
 
+/*
+ * Intermediate tensors of the last air_cnn_forward or air_cnn_loss_grad call
+ * on this context (an air_render_learned call in between discards them), for
+ * inspection layer by layer.  P = n_maps * h * w pixels in the order of the
+ * features; every tensor is pixel-major with its channels adjacent:
+ *   AIR_CNN_T_X0  bfloat16 [P][8]: the standardised input maps (channels 0..3, 4..7 zero);
+ *   AIR_CNN_T_A1..A3  bfloat16 [P][32]: the outputs of layers 0..2 after bias and ReLU
+ *                  (the inputs of layers 1..3);
+ *   AIR_CNN_T_Z   float32 [P][8]: the logits (classes 0..5);
+ *   AIR_CNN_T_DZ  bfloat16 [P][8]: the loss gradient with respect to the logits
+ *                  (air_cnn_loss_grad only);
+ *   AIR_CNN_T_D3..D1  bfloat16 [P][32]: the loss gradient with respect to A3..A1,
+ *                  masked where the activation is zero (air_cnn_loss_grad only).
+ * Copies the tensor to out (device, at least the size above) on the stream.
+ * Errors: EINVAL (no such call, unknown tensor, gradients asked of a forward
+ * call, out too small).
+ */
+#define AIR_CNN_T_X0 0
+#define AIR_CNN_T_A1 1
+#define AIR_CNN_T_A2 2
+#define AIR_CNN_T_A3 3
+#define AIR_CNN_T_Z 4
+#define AIR_CNN_T_DZ 5
+#define AIR_CNN_T_D3 6
+#define AIR_CNN_T_D2 7
+#define AIR_CNN_T_D1 8
+air_status air_cnn_tensor(air_ctx* ctx, int32_t which, void* out, int64_t bytes, void* stream);
+
 /* One Adam step (bias-corrected) with the network's last gradient. */
 air_status air_cnn_adam(air_ctx* ctx, air_cnn* net, float lr, float beta1, float beta2, float eps, void* stream);
 

@@ -223,8 +223,15 @@ class Tree:
 
 
 def air(grid, field, view, N0, Lmax, xi_crit_I=0.5, xi_crit_N=2.0, band_w=None, force_flags=None,
-        want_rho_range=False) -> Tree:
-    """Plain AIR for one view (level-synchronous, 2:1 closure)."""
+        want_rho_range=False, values=None) -> Tree:
+    """Plain AIR for one view (level-synchronous, 2:1 closure).
+
+    force_flags (flat, one byte per position of the concatenated level
+    rasters) replaces the criterion's decision at every tested node; then no
+    ray is traced and the node values are those given in values = (I [total]
+    or [n_bands, total], N [total]) (zeros if None): the criterion is still
+    evaluated on them, with the tree as it stands when each level is tested,
+    so xiI / xiN are the estimates of those values on the forced tree."""
     sizes = [(N0 << L) ** 2 for L in range(Lmax + 1)]
     total = int(sum(sizes))
     nb = field.n_bands if field is not None else 1
@@ -233,6 +240,11 @@ def air(grid, field, view, N0, Lmax, xi_crit_I=0.5, xi_crit_N=2.0, band_w=None, 
     xiN = np.zeros(total)
     I = np.zeros((nb, total))
     N = np.zeros(total)
+    if values is not None:
+        if force_flags is None:
+            raise ValueError("values are only used with force_flags (no ray is traced then)")
+        I[...] = np.asarray(values[0], dtype=np.float64).reshape(nb, total)
+        N[...] = np.asarray(values[1], dtype=np.float64).reshape(total)
     lm = np.full(total, -1, dtype=np.int32)
     nv = np.zeros(total, dtype=np.int32)
     rmin = np.zeros(total) if want_rho_range else None

@@ -22,7 +22,7 @@ NODE_EXIST, NODE_TESTED, NODE_FLAGGED, NODE_BALANCE, NODE_REFINED, NODE_EVALUATE
 EXPORTS = ("air_create", "air_destroy", "air_last_error", "air_render", "air_render_fixed", "air_trace_pixels",
            "air_field_packed_bytes", "air_field_pack", "air_cnn_create", "air_cnn_destroy", "air_cnn_set",
            "air_cnn_get", "air_features", "air_cnn_forward", "air_cnn_loss_grad", "air_cnn_adam", "air_tree_depth",
-           "air_render_learned", "air_render_batch")
+           "air_render_learned", "air_render_batch", "air_cnn_tensor")
 CNN_FEATURES, CNN_CLASSES, CNN_PARAMS = 4, 6, 21414
 
 
@@ -116,9 +116,10 @@ def lib():
         L.air_cnn_loss_grad.argtypes = [vp, vp, vp, vp, i32, i32, i32, vp, vp, vp, vp]
         L.air_cnn_adam.argtypes = [vp, vp, C.c_float, C.c_float, C.c_float, C.c_float, vp]
         L.air_tree_depth.argtypes = [vp, vp, i32, vp, vp]
+        L.air_cnn_tensor.argtypes = [vp, i32, vp, C.c_int64, vp]
         L.air_render_learned.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         for name in ("air_cnn_create", "air_cnn_set", "air_cnn_get", "air_features", "air_cnn_forward",
-                     "air_cnn_loss_grad", "air_cnn_adam", "air_tree_depth", "air_render_learned"):
+                     "air_cnn_loss_grad", "air_cnn_adam", "air_tree_depth", "air_render_learned", "air_cnn_tensor"):
             getattr(L, name).restype = C.c_int32
         _lib = L
     return _lib
@@ -543,6 +544,20 @@ class Network:
                                                 cw.ctypes.data, C.byref(loss) if want_loss else None,
                                                 g.data_ptr() if want_grad else None, self.ctx._stream()))
         return (loss.value if want_loss else None), g
+
+    TENSORS = dict(x0=(0, 8), a1=(1, 32), a2=(2, 32), a3=(3, 32), z=(4, 8), dz=(5, 8), d3=(6, 32), d2=(7, 32),
+                   d1=(8, 32))
+
+    def tensor(self, name, pixels):
+        """Intermediate of the last forward / loss_grad call (air_cnn_tensor):
+        [pixels, channels], bfloat16 except the float32 logits."""
+        torch = _torch()
+        which, ch = Network.TENSORS[name]
+        dt = torch.float32 if name == "z" else torch.bfloat16
+        out = torch.empty((pixels, ch), dtype=dt, device=f"cuda:{self.ctx.device}")
+        self.ctx._check(lib().air_cnn_tensor(self.ctx._p, which, out.data_ptr(), out.numel() * out.element_size(),
+                                             self.ctx._stream()))
+        return out
 
     def adam(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
         self.ctx._check(lib().air_cnn_adam(self.ctx._p, self._p, lr, beta1, beta2, eps, self.ctx._stream()))

@@ -11,17 +11,21 @@ ARCH = os.environ.get("AIR_OFFLOAD_ARCH", "gfx950")
 
 
 def build(verbose: bool = False) -> str:
-    objs = []
     common = ["hipcc", "-x", "hip", f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=on",
               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
               "-Wall", "-Wno-unused-function", "-I", os.path.join(HERE, "..", "include")]
+    # the translation units compile in parallel
+    objs, procs = [], []
     for src in SOURCES:
         obj = os.path.join(CSRC, "_" + os.path.splitext(src)[0] + ".o")
         cmd = common + ["-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), file=sys.stderr)
-        subprocess.run(cmd, check=True)
+        procs.append((src, subprocess.Popen(cmd)))
         objs.append(obj)
+    failed = [src for src, p in procs if p.wait() != 0]
+    if failed:
+        raise subprocess.CalledProcessError(1, "hipcc " + " ".join(failed))
     cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", LIB + ".tmp"] + objs
     if verbose:
         print(" ".join(cmd), file=sys.stderr)

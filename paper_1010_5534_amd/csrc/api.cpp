@@ -41,7 +41,13 @@ struct air_ctx {
       views, touts, pack;
   // learned proposal: coarse maps, network activations and gradients, depth
   // choice and speculative work list
-  DevBuf nodepos, lmax0, feat, cx0, ca1, ca2, ca3, cz, cdz, cda, cdb, cwpart, closs_part, closs, depth8, scount, spec;
+  DevBuf nodepos, lmax0, feat, cx0, ca1, ca2, ca3, cz, cdz, cda, cdb, cdc, cwpart, closs_part, closs, depth8, scount,
+      spec;
+  // pixels of the last air_cnn_forward / air_cnn_loss_grad call whose
+  // intermediates the network buffers hold (-1: none), and whether that call
+  // computed gradients (air_cnn_tensor)
+  int64_t cnn_pixels = -1;
+  bool cnn_grads = false;
   unsigned long long* host_ctr = nullptr;  // pinned
   double* host_flux = nullptr;             // pinned
   unsigned long long* host_vstat = nullptr;
@@ -61,6 +67,9 @@ struct air_ctx {
   // air_render_batch: the captured launch sequence of the last call and the
   // launch shapes chosen per workload shape
   std::string graph_key;
+  // bumped whenever a context buffer is (re)allocated: captured launches hold
+  // the buffers' addresses, so a graph is replayed only while it is unchanged
+  uint64_t buf_gen = 0;
   hipStream_t cap_stream = nullptr;  // the graph is captured and replayed here
   hipGraphExec_t graph_exec = nullptr;
   hipGraph_t graph = nullptr;
@@ -104,6 +113,7 @@ hipError_t spin_stream(hipStream_t s) {
 air_status ensure(air_ctx* c, DevBuf& b, size_t bytes) {
   if (bytes == 0) bytes = 256;
   if (b.bytes >= bytes) return AIR_OK;
+  if (c) ++c->buf_gen;
   if (b.p) {
     (void)hipFree(b.p);
     b.p = nullptr;
@@ -121,6 +131,7 @@ air_status ensure(air_ctx* c, DevBuf& b, size_t bytes) {
 
 air_status ensure_host(air_ctx* c, void** p, size_t* have, size_t bytes) {
   if (*have >= bytes && *p) return AIR_OK;
+  if (c) ++c->buf_gen;
   // kernels and copies read and write these buffers asynchronously (a call
   // that failed after enqueueing did not wait for them): drain the device
   // before the old buffer goes
@@ -400,6 +411,7 @@ air_status ensure_cnn_work(air_ctx* c, int64_t P, bool training) {
   if ((st = ensure(c, c->cdz, 2 * cnn::ZC * P))) return st;
   if ((st = ensure(c, c->cda, 2 * cnn::HID * P))) return st;
   if ((st = ensure(c, c->cdb, 2 * cnn::HID * P))) return st;
+  if ((st = ensure(c, c->cdc, 2 * cnn::HID * P))) return st;
   if ((st = ensure(c, c->cwpart, 4 * cnn::wgrad_partial_floats()))) return st;
   if ((st = ensure(c, c->closs_part, 8 * cnn::loss_partial_doubles()))) return st;
   return ensure(c, c->closs, 16);
@@ -585,9 +597,12 @@ air_status enqueue_render(air_ctx* c, const Plan& P, const Tune& tune, hipStream
   return AIR_OK;
 }
 
-// the graph key: every argument of every launch (pointers, sizes, scalars)
-std::string plan_key(const Plan& P, const Tune& t) {
+// the graph key: every argument of every launch (pointers, sizes, scalars);
+// the context's buffer generation stands for the addresses of its own
+// buffers (queue maps, chunk counters, partial sums, tree index maps, ...)
+std::string plan_key(const air_ctx* c, const Plan& P, const Tune& t) {
   std::string k(reinterpret_cast<const char*>(&P.A), sizeof P.A);
+  k.append(reinterpret_cast<const char*>(&c->buf_gen), sizeof c->buf_gen);
   k.append(reinterpret_cast<const char*>(&P.n_chunks), sizeof P.n_chunks);
   k.append(reinterpret_cast<const char*>(&P.xcI), sizeof(float) * (2 + MAXB));
   k.append(reinterpret_cast<const char*>(&P.net), sizeof P.net);
@@ -678,6 +693,7 @@ air_status render_core(air_ctx* c, const air_grid* grid, const air_field* field,
   if ((st = ensure_host(c, (void**)&c->host_vstat, &c->host_vstat_n, res_bytes))) return st;
   P.res = c->host_vstat;
   if (learned && (st = ensure_learned(c, A))) return st;
+  if (learned) c->cnn_pixels = -1;  // the learned steps overwrite the network buffers
   if (trees) {
     if ((st = ensure(c, c->idmap, 4 * (size_t)V * A.img.S))) return st;
     if ((st = ensure(c, c->nodepos, 8 * (size_t)V * A.img.S))) return st;
@@ -705,7 +721,7 @@ air_status render_core(air_ctx* c, const air_grid* grid, const air_field* field,
   if (batch) {
     Tune tune;
     if ((st = autotune(c, P, s, tune))) return st;
-    const std::string key = plan_key(P, tune);
+    const std::string key = plan_key(c, P, tune);
     // capture on the context's own stream (the caller's may be the null
     // stream, which cannot be captured), after the uploads above
     hipStream_t cs = c->cap_stream;
@@ -875,7 +891,7 @@ void air_destroy(air_ctx* c) {
   for (DevBuf* b : {&c->state, &c->valI, &c->valN, &c->xiI, &c->xiN, &c->visits, &c->rmin, &c->rmax, &c->queue,
                     &c->ctr, &c->chunk, &c->cstat, &c->idmap, &c->partial, &c->flux, &c->views,
                     &c->touts, &c->pack, &c->nodepos, &c->lmax0, &c->feat, &c->cx0, &c->ca1, &c->ca2, &c->ca3, &c->cz,
-                    &c->cdz, &c->cda, &c->cdb, &c->cwpart, &c->closs_part, &c->closs, &c->depth8, &c->scount,
+                    &c->cdz, &c->cda, &c->cdb, &c->cdc, &c->cwpart, &c->closs_part, &c->closs, &c->depth8, &c->scount,
                     &c->spec, &c->parts})
     if (b->p) (void)hipFree(b->p);
   if (c->host_ctr) (void)hipHostFree(c->host_ctr);
@@ -1173,7 +1189,41 @@ air_status air_cnn_forward(air_ctx* c, air_cnn* n, const float* feat, int32_t n_
   if ((st = check_maps(c, n, feat, n_maps, h, w))) return st;
   if (!logits) return fail(c, AIR_EINVAL, "logits NULL");
   if ((st = ensure_cnn_work(c, (int64_t)n_maps * h * w, false))) return st;
-  return cnn_forward_all(c, n, feat, n_maps, h, w, logits, (hipStream_t)stream);
+  if ((st = cnn_forward_all(c, n, feat, n_maps, h, w, logits, (hipStream_t)stream))) return st;
+  // the logits went to the caller's buffer: keep a copy beside the other
+  // intermediates
+  HIPCHK(c, hipMemcpyAsync(c->cz.p, logits, 4 * (size_t)cnn::ZC * n_maps * h * w, hipMemcpyDeviceToDevice,
+                           (hipStream_t)stream));
+  c->cnn_pixels = (int64_t)n_maps * h * w;
+  c->cnn_grads = false;
+  return AIR_OK;
+}
+
+air_status air_cnn_tensor(air_ctx* c, int32_t which, void* out, int64_t bytes, void* stream) {
+  if (!c) return AIR_EINVAL;
+  c->err.clear();
+  if (c->cnn_pixels < 0) return fail(c, AIR_EINVAL, "no network call to inspect on this context");
+  const int64_t P = c->cnn_pixels;
+  const DevBuf* src = nullptr;
+  int64_t need = 0;
+  switch (which) {
+    case AIR_CNN_T_X0: src = &c->cx0; need = 2 * cnn::XC * P; break;
+    case AIR_CNN_T_A1: src = &c->ca1; need = 2 * cnn::HID * P; break;
+    case AIR_CNN_T_A2: src = &c->ca2; need = 2 * cnn::HID * P; break;
+    case AIR_CNN_T_A3: src = &c->ca3; need = 2 * cnn::HID * P; break;
+    case AIR_CNN_T_Z: src = &c->cz; need = 4 * cnn::ZC * P; break;
+    case AIR_CNN_T_DZ: src = &c->cdz; need = 2 * cnn::ZC * P; break;
+    case AIR_CNN_T_D3: src = &c->cda; need = 2 * cnn::HID * P; break;
+    case AIR_CNN_T_D2: src = &c->cdb; need = 2 * cnn::HID * P; break;
+    case AIR_CNN_T_D1: src = &c->cdc; need = 2 * cnn::HID * P; break;
+    default: return fail(c, AIR_EINVAL, "tensor %d unknown", which);
+  }
+  if (which >= AIR_CNN_T_DZ && !c->cnn_grads)
+    return fail(c, AIR_EINVAL, "the last network call computed no gradients");
+  if (!out || bytes < need) return fail(c, AIR_EINVAL, "output of %lld bytes, %lld needed", (long long)bytes, (long long)need);
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, AIR_EDEVICE, "hipSetDevice failed");
+  HIPCHK(c, hipMemcpyAsync(out, src->p, (size_t)need, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  return AIR_OK;
 }
 
 air_status air_cnn_loss_grad(air_ctx* c, air_cnn* n, const float* feat, const int32_t* labels, int32_t n_maps,
@@ -1195,17 +1245,20 @@ air_status air_cnn_loss_grad(air_ctx* c, air_cnn* n, const float* feat, const in
                              (double*)c->closs.p, (uint16_t*)c->cdz.p, s));
   float* wp = (float*)c->cwpart.p;
   const uint16_t* cdz = (const uint16_t*)c->cdz.p;
-  uint16_t* da = (uint16_t*)c->cda.p;
-  uint16_t* db = (uint16_t*)c->cdb.p;
+  uint16_t* d3 = (uint16_t*)c->cda.p;  // gradient at the input of layer 3 (= at a3), and so on
+  uint16_t* d2 = (uint16_t*)c->cdb.p;
+  uint16_t* d1 = (uint16_t*)c->cdc.p;
   // back through layers 3..0: weight gradient from (dy, input), then the
   // input gradient masked by the input's ReLU
   HIPCHK(c, cnn::conv_weight_grad(3, N, cdz, (const uint16_t*)c->ca3.p, n_maps, h, w, wp, s));
-  HIPCHK(c, cnn::conv_input_grad(3, N, cdz, (const uint16_t*)c->ca3.p, n_maps, h, w, da, s));
-  HIPCHK(c, cnn::conv_weight_grad(2, N, da, (const uint16_t*)c->ca2.p, n_maps, h, w, wp, s));
-  HIPCHK(c, cnn::conv_input_grad(2, N, da, (const uint16_t*)c->ca2.p, n_maps, h, w, db, s));
-  HIPCHK(c, cnn::conv_weight_grad(1, N, db, (const uint16_t*)c->ca1.p, n_maps, h, w, wp, s));
-  HIPCHK(c, cnn::conv_input_grad(1, N, db, (const uint16_t*)c->ca1.p, n_maps, h, w, da, s));
-  HIPCHK(c, cnn::conv_weight_grad(0, N, da, (const uint16_t*)c->cx0.p, n_maps, h, w, wp, s));
+  HIPCHK(c, cnn::conv_input_grad(3, N, cdz, (const uint16_t*)c->ca3.p, n_maps, h, w, d3, s));
+  HIPCHK(c, cnn::conv_weight_grad(2, N, d3, (const uint16_t*)c->ca2.p, n_maps, h, w, wp, s));
+  HIPCHK(c, cnn::conv_input_grad(2, N, d3, (const uint16_t*)c->ca2.p, n_maps, h, w, d2, s));
+  HIPCHK(c, cnn::conv_weight_grad(1, N, d2, (const uint16_t*)c->ca1.p, n_maps, h, w, wp, s));
+  HIPCHK(c, cnn::conv_input_grad(1, N, d2, (const uint16_t*)c->ca1.p, n_maps, h, w, d1, s));
+  HIPCHK(c, cnn::conv_weight_grad(0, N, d1, (const uint16_t*)c->cx0.p, n_maps, h, w, wp, s));
+  c->cnn_pixels = P;
+  c->cnn_grads = true;
   if (grad) HIPCHK(c, hipMemcpyAsync(grad, N.grad, 4 * (size_t)AIR_CNN_PARAMS, hipMemcpyDeviceToDevice, s));
   if (loss) {
     double host[2];

@@ -65,13 +65,10 @@ def test_amr_tree_parity(ctx, amr_small, xc):
     v = inputs.view_for((1, 1, 1))
     say(f"air amr_winds 64/8 L2 N0=16 Lmax=4 xi_crit={xc}")
     trees, img, flux, st = ctx.render(scene, [v], air.params(16, 4, xc))
-    t = oracle.air(g, f, v, 16, 4, xc)
-    rep = parity.compare(parity.gpu_dense(trees[0], 16, 4, 1), t, xc)
-    say({k: (x if not isinstance(x, list) else len(x)) for k, x in rep.items()})
+    rep = parity.check(trees[0], g, f, v, 16, 4, xc, image=img[0], flux=flux[0], own=True,
+                       label=f"amr_winds 64/8 xi_crit={xc}")
+    say(parity.summary(rep))
     parity.assert_parity(rep)
-    if rep["flips"] == 0:
-        assert trees[0].n_nodes == t.nodes
-        assert flux[0][0] == pytest.approx(oracle.leaf_flux(t, v.width, t.flat_I[0]), rel=1e-5)
 
 
 def test_amr_multiband_views_batch(ctx):
@@ -86,8 +83,9 @@ def test_amr_multiband_views_batch(ctx):
     trees, img, flux, _ = ctx.render(scene, views, prm)
     for k, v in enumerate(views):
         say(f"air amr_winds 32/4 4 bands view {k}")
-        t = oracle.air(g, f, v, 8, 3, 0.5, band_w=[1.0, 0.5, 0.25, 0.125])
-        rep = parity.compare(parity.gpu_dense(trees[k], 8, 3, 4), t, 0.5, band_w=[1.0, 0.5, 0.25, 0.125])
+        rep = parity.check(trees[k], g, f, v, 8, 3, 0.5, band_w=[1.0, 0.5, 0.25, 0.125], image=img[k],
+                           flux=flux[k], own=True, label=f"amr 4 bands view {k}")
+        say(parity.summary(rep))
         parity.assert_parity(rep)
         t1, i1, f1, _ = ctx.render(scene, [v], prm)
         assert torch.equal(t1[0].I, trees[k].I) and torch.equal(i1[0], img[k])

@@ -96,9 +96,9 @@ def test_batch_amr_many_views_bands(ctx):
     out = ctx.render_batch(scene, views, prm)
     _same(ref, out)
     for k in (0, 9):
-        t = oracle.air(g, f, views[k], 32, 3, 0.5)
-        rep = parity.compare(parity.gpu_dense(out[0][k], 32, 3, 8), t, 0.5)
-        say(k, {a: (b if not isinstance(b, list) else len(b)) for a, b in rep.items()})
+        rep = parity.check(out[0][k], g, f, views[k], 32, 3, 0.5, image=out[1][k], flux=out[2][k], own=True,
+                           label=f"batch amr 16 views x 8 bands, view {k}")
+        say(parity.summary(rep))
         parity.assert_parity(rep)
 
 
@@ -115,7 +115,29 @@ def test_batch_config3_full_size_sampled(ctx):
     out = ctx.render_batch(scene, views, prm, want_image=False)
     say(out[3]["rays"], out[3]["visits"])
     for k in (5, 40):
-        t = oracle.air(g, f, views[k], 128, 3, 0.5)
-        rep = parity.compare(parity.gpu_dense(out[0][k], 128, 3, 8), t, 0.5)
-        say(k, {a: (b if not isinstance(b, list) else len(b)) for a, b in rep.items()})
+        rep = parity.check(out[0][k], g, f, views[k], 128, 3, 0.5, flux=out[2][k],
+                           label=f"config3 64 views x 8 bands, view {k}")
+        say(parity.summary(rep))
         parity.assert_parity(rep)
+
+
+def test_graph_recaptured_after_context_buffers_grow(ctx):
+    """A captured sequence holds the addresses of the context's workspace.
+    Calls between two batched calls of one shape that grow that workspace
+    (a fixed image with flux at a larger size grows the partial sums; an
+    eager render of a larger tree grows the index maps) must not leave the
+    second batched call replaying launches into freed memory: it equals
+    air_render bit for bit."""
+    from paper_1010_5534_amd import air
+    g, f = inputs.winds2(seed=4, n=48, kind=inputs.FIELD_RHO_T, bands=inputs.default_bands(2))
+    scene = ctx.prepare(air.upload(g, f))
+    prm = air.params(12, 3, 0.4)
+    views = inputs.isotropic_views(2, seed=21)
+    say("graph buffers: batch, fixed with flux at 1024^2, batch")
+    ref = ctx.render(scene, views, prm, reuse=False)
+    _same(ref, ctx.render_batch(scene, views, prm))
+    ctx.render_fixed(scene, views, 64, 4)  # flux partial sums for 1024^2 images
+    _same(ref, ctx.render_batch(scene, views, prm))
+    say("graph buffers: batch, eager render of a larger tree, batch")
+    ctx.render(scene, views, air.params(32, 4, 0.3), want_image=False)
+    _same(ref, ctx.render_batch(scene, views, prm))

@@ -1,9 +1,11 @@
 """The large-scale workload at full size: uniform 512^3 (rho, T) field with
 three wind sources and their pairwise shells, 128x128 coarse image, 6 levels
 (8192^2 effective), 16 views x 4 bands in one call, plain and learned.  The
-oracle checks a seeded 1% sample of every sampled view's nodes ray by ray;
-the trees are checked for the method's invariants (2:1 balance of adjacent
-leaves, tested children of flagged nodes, flags consistent with xi)."""
+oracle checks a seeded 1% sample of every sampled view's nodes ray by ray,
+and the flags of a seeded 1% of the evaluated nodes by tracing their 3x3
+stencils and evaluating Eq. 3; the trees are checked for the method's
+invariants (2:1 balance of adjacent leaves over the whole image, tested
+children of flagged nodes, flags consistent with xi)."""
 import sys
 
 import numpy as np
@@ -79,6 +81,18 @@ def test_large_sampled_rays_match_oracle(large):
     assert worst <= 1e-5
 
 
+def test_large_sampled_flags_match_oracle(large):
+    scene, views, prm, out, rho, temp, bands = large
+    trees = out[0]
+    g, f = _host_field(rho, temp, bands)
+    for k in (0, 7, 15):
+        say(f"view {k}: oracle stencils of 1% of the evaluated nodes")
+        rep = parity.sampled_flags(trees[k], g, f, views[k], N0, LMAX, XC, band_w=[1.0] * 4, frac=0.01, seed=k,
+                                   label=f"large-scale view {k}")
+        say(parity.summary(rep))
+        parity.assert_sampled(rep)
+
+
 def test_large_tree_invariants(large):
     scene, views, prm, out, rho, temp, bands = large
     trees = out[0]
@@ -100,29 +114,11 @@ def test_large_tree_invariants(large):
         assert np.all(kids >= 0)
         for c in range(4):
             assert np.all((st[kids + c] & 2) > 0)
-        # 2:1: every leaf's 8 neighbours at its level exist or lie inside a
-        # leaf at most one level coarser (checked on the finest raster of a
-        # sampled window through leaf levels)
+        # the leaves tile the image: their areas add up to the whole raster
         leaf = (st & 1 > 0) & ~((st & 16) > 0)
-        R = N0 << LMAX
-        win = 2048
-        y0 = x0 = R // 2 - win // 2
-        depth = np.full((win, win), -1, np.int8)
-        for L in range(LMAX + 1):
-            m = leaf & (lv == L)
-            s = 1 << (LMAX - L)
-            ii, jj = ix[m], iy[m]
-            keep = (jj * s + s > y0) & (jj * s < y0 + win) & (ii * s + s > x0) & (ii * s < x0 + win)
-            ii, jj = ii[keep], jj[keep]
-            for dy in range(s):
-                for dx in range(s):
-                    y, x = jj * s + dy - y0, ii * s + dx - x0
-                    ok = (y >= 0) & (y < win) & (x >= 0) & (x < win)
-                    depth[y[ok], x[ok]] = L
-        assert np.all(depth >= 0)  # the leaves tile the window
-        d = depth.astype(np.int16)
-        assert np.all(np.abs(np.diff(d, axis=0)) <= 1) and np.all(np.abs(np.diff(d, axis=1)) <= 1)
-        assert np.all(np.abs(d[1:, 1:] - d[:-1, :-1]) <= 1) and np.all(np.abs(d[1:, :-1] - d[:-1, 1:]) <= 1)
+        assert int(np.sum(4.0 ** (LMAX - lv[leaf]))) == (N0 << LMAX) ** 2
+        # 2:1 between adjacent leaves, edges and corners, over the whole image
+        assert parity.balanced_everywhere(t) == 0
 
 
 def test_large_learned_equals_plain(ctx, large):

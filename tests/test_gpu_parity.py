@@ -108,18 +108,11 @@ def test_air_tree_parity_gaussian(ctx, gauss, xc):
     v = inputs.gaussian_view()
     say(f"air gaussian64 N0=16 Lmax=4 xi_crit={xc}")
     trees, img, flux, st = ctx.render(scene, [v], air.params(16, 4, xc))
-    t = oracle.air(g, f, v, 16, 4, xc)
-    gd = parity.gpu_dense(trees[0], 16, 4, 1)
-    rep = parity.compare(gd, t, xc)
-    say({k: (v if not isinstance(v, list) else len(v)) for k, v in rep.items()})
+    rep = parity.check(trees[0], g, f, v, 16, 4, xc, image=img[0], flux=flux[0], own=True,
+                       label=f"gaussian64 N0=16 Lmax=4 xi_crit={xc}")
+    say(parity.summary(rep))
     parity.assert_parity(rep)
     assert st["rays"] == trees[0].n_nodes
-    if rep["flips"] == 0:
-        assert trees[0].n_nodes == t.nodes
-        ref_flux = oracle.leaf_flux(t, 1.0, t.flat_I[0])
-        assert flux[0][0] == pytest.approx(ref_flux, rel=1e-5)
-        ref_img = oracle.paint_leaves(t, t.flat_I[0])
-        assert parity.rel_err(img[0, 0].cpu().numpy(), ref_img).max() <= 1e-5
 
 
 def test_full_refinement_equals_fixed_bitwise(ctx, gauss):
@@ -179,9 +172,9 @@ def test_air_tree_parity_winds(ctx, seed, direction):
     v = inputs.view_for(direction)
     say(f"air winds2 n=64 seed={seed} dir={direction} N0=16 Lmax=4")
     trees, img, flux, st = ctx.render(scene, [v], air.params(16, 4, 0.5))
-    t = oracle.air(g, f, v, 16, 4, 0.5)
-    rep = parity.compare(parity.gpu_dense(trees[0], 16, 4, 1), t, 0.5)
-    say({k: (v if not isinstance(v, list) else len(v)) for k, v in rep.items()})
+    rep = parity.check(trees[0], g, f, v, 16, 4, 0.5, image=img[0], flux=flux[0], own=True,
+                       label=f"winds2 n=64 seed={seed} dir={direction}")
+    say(parity.summary(rep))
     parity.assert_parity(rep)
 
 
@@ -199,9 +192,9 @@ def test_multiband_rho_t(ctx, bands):
     w = [1.0, 0.5, 2.0, 0.25]
     say("air winds2 rho/T 4 bands n=48 N0=12 Lmax=3")
     trees, img, flux, st = ctx.render(scene, [v], air.params(12, 3, 0.5, band_weight=w))
-    t = oracle.air(g, f, v, 12, 3, 0.5, band_w=w)
-    rep = parity.compare(parity.gpu_dense(trees[0], 12, 3, 4), t, 0.5, band_w=w)
-    say({k: (v if not isinstance(v, list) else len(v)) for k, v in rep.items()})
+    rep = parity.check(trees[0], g, f, v, 12, 3, 0.5, band_w=w, image=img[0], flux=flux[0], own=True,
+                       label="winds2 rho/T 4 bands")
+    say(parity.summary(rep))
     parity.assert_parity(rep)
     fimg, fflux, _ = ctx.render_fixed(scene, [v], 12, 3)
     ref = oracle.render_fixed(g, f, v, 12, 3)
@@ -214,11 +207,12 @@ def test_column_refinement_variable(ctx, gauss):
     from paper_1010_5534_amd import air
     g, f, scene = gauss
     v = inputs.gaussian_view()
-    trees, _, _, _ = ctx.render(scene, [v], air.params(16, 3, 1.01, 0.5))
-    t = oracle.air(g, f, v, 16, 3, 1.01, 0.5)
-    rep = parity.compare(parity.gpu_dense(trees[0], 16, 3, 1), t, 1.01, 0.5)
+    trees, img, flux, _ = ctx.render(scene, [v], air.params(16, 3, 1.01, 0.5))
+    rep = parity.check(trees[0], g, f, v, 16, 3, 1.01, 0.5, image=img[0], flux=flux[0], own=True,
+                       label="column variable")
+    say(parity.summary(rep))
     parity.assert_parity(rep)
-    assert t.nodes > 256
+    assert trees[0].n_nodes > 256
 
 
 @pytest.mark.parametrize("N0,Lmax", [(1, 3), (13, 2), (7, 0), (2, 5)])
@@ -229,8 +223,9 @@ def test_ragged_and_degenerate_images(ctx, N0, Lmax):
     v = inputs.view_for((0.1, 0.2, 1.0), width=1.3)
     say(f"air winds2 n=40 N0={N0} Lmax={Lmax}")
     trees, img, flux, st = ctx.render(scene, [v], air.params(N0, Lmax, 0.3))
-    t = oracle.air(g, f, v, N0, Lmax, 0.3)
-    rep = parity.compare(parity.gpu_dense(trees[0], N0, Lmax, 1), t, 0.3)
+    rep = parity.check(trees[0], g, f, v, N0, Lmax, 0.3, image=img[0], flux=flux[0], own=True,
+                       label=f"ragged N0={N0} Lmax={Lmax}")
+    say(parity.summary(rep))
     parity.assert_parity(rep)
 
 

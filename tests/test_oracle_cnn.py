@@ -204,3 +204,82 @@ def test_depth_labels_from_oracle_trees(orc):
         ex = (t.state[L] & 1) > 0
         jj, ii = np.nonzero(ex)
         assert np.all(d[jj >> L, ii >> L] >= L)
+
+
+# ----------------------------------------------- rounding points, by hand
+def _one_path_net():
+    """A network on a 1x1 map whose only live path runs through channel 0 of
+    every layer (centre tap), with values chosen so that each bfloat16
+    rounding point changes the result: see the hand derivation in the
+    tests below."""
+    p = {name: np.zeros(shape) for name, shape, _ in cnn.layout()}
+    p["w0"][0, 1, 1, 0] = 1 + 3 * 2 ** -9   # bf16 -> 1 + 2^-7
+    p["b0"][0] = 2 ** -9
+    p["w1"][0, 1, 1, 0] = 3.0
+    p["b1"][0] = -2 ** -6
+    p["w2"][0, 1, 1, 0] = 0.5
+    p["b2"][0] = 2 ** -10
+    for c in range(6):
+        p["w3"][c, 1, 1, 0] = c * (1 + 2 ** -8)
+        p["b3"][c] = 0.125 * c
+    x = np.zeros((1, 1, 1, 4))
+    x[0, 0, 0, 0] = 1 + 2 ** -9             # bf16 -> 1
+    return cnn.pack(p), x
+
+
+def test_forward_rounding_points_by_hand():
+    """Input rounded: 1 + 2^-9 -> 1.  Layer 0: 1 * (1 + 2^-7) + 2^-9, stored
+    as bf16 1 + 2^-7 (2^-9 is below half a step).  Layer 1: 3 (1 + 2^-7) -
+    2^-6 = 3 + 2^-7, a tie between 3 and 3 + 2^-6, stored as 3 (even).
+    Layer 2: 1.5 + 2^-10 -> 1.5.  Logits (not rounded): 1.5 bf16(c (1 +
+    2^-8)) + c / 8, the weights rounding to 0, 1, 2 (tie), 3 + 2^-6, 4 (tie),
+    5 + 2^-5."""
+    theta, x = _one_path_net()
+    z, acts = cnn.forward(theta, x, rounding=True)
+    assert acts[0][0, 0, 0, 0] == 1.0
+    assert acts[1][0, 0, 0, 0] == 1 + 2 ** -7
+    assert acts[2][0, 0, 0, 0] == 3.0
+    assert acts[3][0, 0, 0, 0] == 1.5
+    w3 = [0.0, 1.0, 2.0, 3 + 2 ** -6, 4.0, 5 + 2 ** -5]
+    assert list(z[0, 0, 0]) == [1.5 * w3[c] + 0.125 * c for c in range(6)]
+    # without the rounding points every value is carried exactly
+    z2, acts2 = cnn.forward(theta, x, rounding=False)
+    y0 = (1 + 2 ** -9) * (1 + 3 * 2 ** -9) + 2 ** -9
+    y1 = 3 * y0 - 2 ** -6
+    y2 = 0.5 * y1 + 2 ** -10
+    assert acts2[1][0, 0, 0, 0] == y0 and acts2[2][0, 0, 0, 0] == y1 and acts2[3][0, 0, 0, 0] == y2
+    assert np.allclose(z2[0, 0, 0], [y2 * c * (1 + 2 ** -8) + 0.125 * c for c in range(6)], rtol=1e-15)
+
+
+def test_backward_rounding_points_by_hand():
+    """On the same path: the logit gradient is rounded to bf16 before the
+    backward pass; the weight gradient of the last layer is that rounded
+    gradient times its stored input 1.5; the gradient at that input is the
+    sum over classes of rounded gradient times rounded weight, itself rounded
+    (the input is > 0), and makes the layer-2 weight gradient with layer 2's
+    stored input 3; and so on down to layer 0."""
+    theta, x = _one_path_net()
+    labels = np.array([[[2]]])
+    cw = np.ones(6)
+    z, _ = cnn.forward(theta, x, rounding=True)
+    _, dz = cnn.loss_and_logit_grad(z, labels, cw)
+    dzr = cnn.bf16(dz[0, 0, 0])
+    assert not np.array_equal(dzr, dz[0, 0, 0])  # the rounding point matters here
+    _, g = cnn.loss_and_grads(theta, x, labels, cw, rounding=True)
+    gp = cnn.unpack(g)
+    assert np.array_equal(gp["w3"][:, 1, 1, 0], dzr * 1.5)
+    assert np.array_equal(gp["b3"], dzr)
+    w3 = np.array([0.0, 1.0, 2.0, 3 + 2 ** -6, 4.0, 5 + 2 ** -5])
+    da2 = cnn.bf16(np.sum(dzr * w3))
+    assert gp["w2"][0, 1, 1, 0] == da2 * 3.0
+    assert gp["b2"][0] == da2
+    da1 = cnn.bf16(da2 * 0.5)
+    assert gp["w1"][0, 1, 1, 0] == da1 * (1 + 2 ** -7)
+    da0 = cnn.bf16(da1 * 3.0)
+    assert gp["w0"][0, 1, 1, 0] == da0 * 1.0
+    # every other weight and bias gradient is zero (a 1x1 map sees only the
+    # centre tap; the other channels carry zeros)
+    assert da0 != 0
+    assert np.count_nonzero(gp["w3"]) == np.count_nonzero(dzr)
+    for l in range(3):
+        assert np.count_nonzero(gp[f"w{l}"]) == 1 and np.count_nonzero(gp[f"b{l}"]) == 1

@@ -268,3 +268,109 @@ def test_grid_sum_flux(orc):
     t = orc.air(g, f, v, 8, 2, xi_crit_I=0.5)
     err = abs(orc.leaf_flux(t, 1.0, t.flat_I[0]) - exact) / exact
     assert 0 < err < 0.05
+
+
+# ------------------------------------------------ injection (coarser neighbours)
+def _injection_case():
+    """4x4 base, three levels below, forced flags: level 0 flags (1,1); level 1
+    flags its child (3,2), whose 2:1 closure refines base pixels (1,0), (2,0)
+    and (2,1) in the same step; level 2 flags (7,5), whose closure refines the
+    level-1 nodes (4,2), (3,3) and (4,3) in the same step.  Every position of
+    every level holds a distinct value (as if traced), so a stencil that reads
+    the wrong node gives a different estimate."""
+    import oracle
+    N0, Lmax = 4, 3
+    flags = [np.zeros((N0 << L, N0 << L), np.uint8) for L in range(Lmax + 1)]
+    flags[0][1, 1] = 1     # [j, i]
+    flags[1][2, 3] = 1     # (i, j) = (3, 2)
+    flags[2][5, 7] = 1     # (i, j) = (7, 5)
+    rng = np.random.default_rng(42)
+    vals = [rng.permutation((N0 << L) ** 2).reshape(N0 << L, N0 << L).astype(np.float64) * 0.37 + 100 * L + 1
+            for L in range(Lmax + 1)]
+    colv = [v[::-1, ::-1].copy() * 1.7 + 3.0 for v in vals]
+    flat = lambda a: np.concatenate([x.reshape(-1) for x in a])
+    t = oracle.air(None, None, inputs.gaussian_view(), N0, Lmax, force_flags=flat(flags),
+                   values=(flat(vals), flat(colv)))
+    return t, vals, colv
+
+
+# stencils written out by hand: for each tested node (L, i, j), the source of
+# each offset (a, b) (a along i, b along j), row by row b = -1, 0, 1, as
+# (level, i, j) of the node whose value the test must read.  A level-L
+# neighbour counts only if it existed when level L was tested: here that is
+# the four tested children of the level-(L-1) flag; every other position reads
+# the covering level-(L-1) node, including positions the same step's closure
+# creates afterwards.
+HAND_STENCILS = {
+    (1, 3, 3): [(1, 2, 2), (1, 3, 2), (0, 2, 1),
+                (1, 2, 3), (1, 3, 3), (0, 2, 1),
+                (0, 1, 2), (0, 1, 2), (0, 2, 2)],
+    (1, 2, 2): [(0, 0, 0), (0, 1, 0), (0, 1, 0),
+                (0, 0, 1), (1, 2, 2), (1, 3, 2),
+                (0, 0, 1), (1, 2, 3), (1, 3, 3)],
+    (1, 3, 2): [(0, 1, 0), (0, 1, 0), (0, 2, 0),
+                (1, 2, 2), (1, 3, 2), (0, 2, 1),
+                (1, 2, 3), (1, 3, 3), (0, 2, 1)],
+    (2, 6, 4): [(1, 2, 1), (1, 3, 1), (1, 3, 1),
+                (1, 2, 2), (2, 6, 4), (2, 7, 4),
+                (1, 2, 2), (2, 6, 5), (2, 7, 5)],
+    # (8, *) and (*, 6) read level-1 balance nodes created by step 1 (they
+    # existed when level 2 was tested) and are themselves created at level 2
+    # by the closure of (7, 5) in step 2 (too late to count)
+    (2, 7, 5): [(2, 6, 4), (2, 7, 4), (1, 4, 2),
+                (2, 6, 5), (2, 7, 5), (1, 4, 2),
+                (1, 3, 3), (1, 3, 3), (1, 4, 3)],
+}
+
+
+def test_injection_hand_stencils(orc):
+    """Eq. 3 at a node whose neighbours include coarser leaves takes the
+    covering level-(L-1) node's value; nodes created by the same step's 2:1
+    closure do not count (the test of a level sees the tree as it was before
+    the level changed).  Checked on hand-written stencils of intensity and
+    column at levels 1 and 2."""
+    t, vals, colv = _injection_case()
+    for (L, i, j), src in HAND_STENCILS.items():
+        assert t.state[L][j, i] & orc.TESTED, (L, i, j)
+        p = np.array([vals[l][jj, ii] for (l, ii, jj) in src]).reshape(3, 3)
+        q = np.array([colv[l][jj, ii] for (l, ii, jj) in src]).reshape(3, 3)
+        R = 4 << L
+        hx, hy = 0 < i < R - 1, 0 < j < R - 1
+        assert t.xiI[L][j, i] == orc.xi(p, hx, hy), (L, i, j)
+        assert t.xiN[L][j, i] == orc.xi(q, hx, hy), (L, i, j)
+
+
+def test_injection_case_creates_same_step_nodes(orc):
+    """The positions the hand stencils read through the coarser level do get
+    created, by the closure of the same step: so a test that counted them
+    would read them."""
+    t, _, _ = _injection_case()
+    for (L, i, j) in [(1, 4, 2), (1, 4, 3), (1, 2, 1), (1, 3, 1), (2, 8, 4), (2, 8, 5), (2, 8, 6), (2, 6, 6),
+                      (2, 7, 6)]:
+        assert t.state[L][j, i] & orc.EXIST, (L, i, j)
+        assert t.state[L][j, i] & orc.BALANCE, (L, i, j)
+        assert t.born[L][j, i] == L, (L, i, j)
+    # created one step later still (the closure of (7, 5) at level 2 needs the
+    # level-1 neighbours of (3, 3))
+    for (L, i, j) in [(1, 2, 4), (1, 3, 4), (1, 4, 4)]:
+        assert t.state[L][j, i] & orc.EXIST and t.born[L][j, i] == 2, (L, i, j)
+    for (L, i, j) in [(2, 5, 3), (2, 5, 4)]:
+        assert not t.state[L][j, i] & orc.EXIST, (L, i, j)
+
+
+def test_injection_detects_planted_mistakes(orc):
+    """The hand stencils would catch the two plausible mistakes: a covering
+    index rounded the other way and counting the same step's nodes."""
+    t, vals, _ = _injection_case()
+    L, i, j = 1, 3, 3
+    src = HAND_STENCILS[(L, i, j)]
+    wrong_cover = [(l, (ii + 1) >> 1, (jj + 1) >> 1) if l < L else (l, ii, jj)
+                   for (l, ii, jj) in [(1, 2, 2), (1, 3, 2), (0, 4, 2), (1, 2, 3), (1, 3, 3), (0, 4, 3),
+                                       (0, 2, 4), (0, 3, 4), (0, 4, 4)]]
+    same_step = [(1, 2, 2), (1, 3, 2), (1, 4, 2), (1, 2, 3), (1, 3, 3), (1, 4, 3), (0, 1, 2), (0, 1, 2), (0, 2, 2)]
+    good = orc.xi(np.array([vals[l][jj, ii] for (l, ii, jj) in src]).reshape(3, 3))
+    for bad in (wrong_cover, same_step):
+        p = np.array([vals[l][jj, ii] if jj < vals[l].shape[0] and ii < vals[l].shape[1] else 0.0
+                      for (l, ii, jj) in bad]).reshape(3, 3)
+        assert orc.xi(p) != good
+    assert t.xiI[L][j, i] == good
