@@ -80,9 +80,14 @@ typedef struct {
   const int32_t* block_coord; /* device [n_blocks][3]: block coordinate at its own level */
   const int32_t* block_child; /* device [n_blocks]: first of 8 children (offset cx+2cy+4cz) or -1 */
 } air_grid;
-/* Every call that takes a block-AMR grid first reads the three tables back
- * on its stream (a blocking copy of 20 bytes per block) and returns EINVAL
- * unless they describe one hierarchy: base block b at level 0 with
+/* A call that takes a block-AMR grid reads the three tables back on its
+ * stream (a blocking copy of 20 bytes per block) and returns EINVAL unless
+ * they describe one hierarchy (below).  air_field_pack always checks them and
+ * remembers, on its context, the tables it packed with: later calls on that
+ * context that pass the same tables (pointers and sizes) with that packed
+ * field skip the read-back.  Tables changed in place after packing must be
+ * packed again (the packed layout follows them anyway).  The hierarchy:
+ * base block b at level 0 with
  * coordinate (b % n0, b / n0 % n1, b / (n0 n1)); every other block the child
  * of exactly one earlier block; children stored consecutively after their
  * parent, one level deeper, at coordinate 2 * parent + offset bits; no

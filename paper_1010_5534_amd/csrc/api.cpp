@@ -30,8 +30,24 @@ struct air_cnn {
   air::cnn::Net net;
 };
 
+// block tables checked when a field was packed on this context, with the
+// packed buffer they went into: later calls that pass that packed field and
+// the same tables skip the read-back
+struct BlockSig {
+  const void* packed;
+  const void* lev;
+  const void* crd;
+  const void* chd;
+  int n_blocks, n0, n1, n2, bs, max_level;
+  bool operator==(const BlockSig& o) const {
+    return packed == o.packed && lev == o.lev && crd == o.crd && chd == o.chd && n_blocks == o.n_blocks &&
+           n0 == o.n0 && n1 == o.n1 && n2 == o.n2 && bs == o.bs && max_level == o.max_level;
+  }
+};
+
 struct air_ctx {
   int device = 0;
+  std::vector<BlockSig> checked;
   int num_cus = 256;
   int seg_shift_override = -1;  // AIR_SEG_SHIFT: tuning knob for the lanes per ray
   int64_t split_tiles = 4096;   // AIR_SPLIT_TILES: queue launches (levels >= 1) of at most this many tiles run split
@@ -179,11 +195,27 @@ air_status check_grid(air_ctx* c, const air_grid* g) {
   return AIR_OK;
 }
 
+BlockSig sig_of(const air_grid* g, const void* packed) {
+  return BlockSig{packed, g->block_level, g->block_coord, g->block_child, g->n_blocks, g->n[0], g->n[1], g->n[2],
+                  g->bs, g->max_level};
+}
+
+// tables checked for this packed field by air_field_pack on this context
+bool blocks_known(const air_ctx* c, const air_grid* g, const void* packed) {
+  if (!packed) return false;
+  const BlockSig k = sig_of(g, packed);
+  for (const BlockSig& b : c->checked)
+    if (b == k) return true;
+  return false;
+}
+
 // The block tables are device data: read them back (on the caller's stream,
 // so pending writes land first) and check that they describe one hierarchy,
-// so the march's descent stays inside the tables.
-air_status check_blocks(air_ctx* c, const air_grid* g, hipStream_t s) {
+// so the march's descent stays inside the tables.  Tables checked when the
+// field passed in `packed` was packed on this context are not read again.
+air_status check_blocks(air_ctx* c, const air_grid* g, hipStream_t s, const void* packed = nullptr) {
   if (g->kind != AIR_GRID_BLOCK_AMR) return AIR_OK;
+  if (blocks_known(c, g, packed)) return AIR_OK;
   const int nb = g->n_blocks;
   std::vector<int32_t> lev(nb), crd(3 * (size_t)nb), chd(nb);
   HIPCHK(c, hipMemcpyAsync(lev.data(), g->block_level, 4 * (size_t)nb, hipMemcpyDeviceToHost, s));
@@ -672,7 +704,7 @@ air_status render_core(air_ctx* c, const air_grid* grid, const air_field* field,
     if (trees[k].capacity < 0) return fail(c, AIR_EINVAL, "tree %d capacity < 0", k);
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, AIR_EDEVICE, "hipSetDevice failed");
   hipStream_t s = (hipStream_t)stream;
-  if ((st = check_blocks(c, grid, s))) return st;
+  if ((st = check_blocks(c, grid, s, field->packed))) return st;
   const bool learned = net != nullptr;
   const int N0 = prm->coarse_n, Lm = prm->max_level, V = n_views;
   Plan P;
@@ -955,7 +987,7 @@ air_status air_render_fixed(air_ctx* c, const air_grid* grid, const air_field* f
   if (flux && !images) return fail(c, AIR_EINVAL, "flux needs the image buffer");
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, AIR_EDEVICE, "hipSetDevice failed");
   hipStream_t s = (hipStream_t)stream;
-  if ((st = check_blocks(c, grid, s))) return st;
+  if ((st = check_blocks(c, grid, s, field->packed))) return st;
   MarchArgs A;
   std::memset(&A, 0, sizeof A);
   fill_geo(grid, A.g);
@@ -1028,7 +1060,7 @@ air_status air_trace_pixels(air_ctx* c, const air_grid* grid, const air_field* f
   if (n == 0) return AIR_OK;
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, AIR_EDEVICE, "hipSetDevice failed");
   hipStream_t s = (hipStream_t)stream;
-  if ((st = check_blocks(c, grid, s))) return st;
+  if ((st = check_blocks(c, grid, s, field->packed))) return st;
   MarchArgs A;
   std::memset(&A, 0, sizeof A);
   fill_geo(grid, A.g);
@@ -1067,6 +1099,13 @@ air_status air_field_pack(air_ctx* c, const air_grid* grid, const air_field* fie
   fill_geo(grid, A.g);
   fill_fld(field, grid, A.f);
   HIPCHK(c, pack_any(A.g, A.f, packed, (hipStream_t)stream));
+  if (grid->kind == AIR_GRID_BLOCK_AMR && !blocks_known(c, grid, packed)) {
+    // this packed field and these tables: later calls skip the read-back
+    auto& v = c->checked;
+    v.erase(std::remove_if(v.begin(), v.end(), [&](const BlockSig& b) { return b.packed == packed; }), v.end());
+    if (v.size() >= 64) v.erase(v.begin());
+    v.push_back(sig_of(grid, packed));
+  }
   return AIR_OK;
 }
 
@@ -1294,7 +1333,7 @@ air_status air_features(air_ctx* c, const air_grid* grid, const air_field* field
   if (!band_weight || !features) return fail(c, AIR_EINVAL, "band weights or features NULL");
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, AIR_EDEVICE, "hipSetDevice failed");
   hipStream_t s = (hipStream_t)stream;
-  if ((st = check_blocks(c, grid, s))) return st;
+  if ((st = check_blocks(c, grid, s, field->packed))) return st;
   MarchArgs A;
   int64_t n_chunks = 0;
   if ((st = setup_render(c, grid, field, views, n_views, coarse_n, 0, true, s, A, n_chunks))) return st;
