@@ -252,6 +252,31 @@ air_status air_render_fixed(air_ctx* ctx, const air_grid* grid, const air_field*
                             float* images, double* flux, air_stats* stats, void* stream);
 
 /*
+ * air_render_fixed for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same rays, kernels and results, with its workspace (counters, view
+ * table, flux partial sums) in a static device array of
+ * AIR_NOALLOC_SCRATCH_BYTES that the library holds on each GPU until the
+ * process ends.  It calls no allocation, no memset and no synchronisation, so
+ * it can be captured; it returns once the work is enqueued on `stream`.
+ *  images: device [n_views][n_bands + 1][R][R], R = coarse_n * 2^level;
+ *  flux:   DEVICE [n_views][n_bands] float64, may be NULL (needs images).
+ * Limits (EINVAL beyond them): n_views <= AIR_NOALLOC_MAX_VIEWS; with flux,
+ * n_views * n_bands * ceil(R^2 / 4096) * 8 bytes <= AIR_NOALLOC_SCRATCH_BYTES
+ * - 4096 (e.g. 16 views x 8 bands at R = 2048); field->packed must be set
+ * (air_field_pack), and a block-AMR grid's tables must have been checked by
+ * air_field_pack on this context for that packed field (nothing is read back).
+ * Every call on one GPU shares that GPU's array: calls that overlap on one
+ * GPU (other streams, other contexts, other threads) race; order them on one
+ * stream.  Errors: EINVAL, ENOTSUP, EDEVICE.
+ */
+#define AIR_NOALLOC_MAX_VIEWS 16
+#define AIR_NOALLOC_SCRATCH_BYTES (2u << 20)
+air_status air_render_fixed_noalloc(air_ctx* ctx, const air_grid* grid, const air_field* field,
+                                    const air_view* views, int32_t n_views, int32_t coarse_n, int32_t level,
+                                    float* images, double* flux, void* stream);
+
+/*
  * Trace n individual pixels of one view (section 2 step ii), e.g. to sample
  * a large image.  level/ix/iy: device [n]; I: device [n_bands][n]; N, visits
  * (nullable): device [n].

@@ -22,7 +22,7 @@ NODE_EXIST, NODE_TESTED, NODE_FLAGGED, NODE_BALANCE, NODE_REFINED, NODE_EVALUATE
 EXPORTS = ("air_create", "air_destroy", "air_last_error", "air_render", "air_render_fixed", "air_trace_pixels",
            "air_field_packed_bytes", "air_field_pack", "air_cnn_create", "air_cnn_destroy", "air_cnn_set",
            "air_cnn_get", "air_features", "air_cnn_forward", "air_cnn_loss_grad", "air_cnn_adam", "air_tree_depth",
-           "air_render_learned", "air_render_batch", "air_cnn_tensor")
+           "air_render_learned", "air_render_batch", "air_cnn_tensor", "air_render_fixed_noalloc")
 CNN_FEATURES, CNN_CLASSES, CNN_PARAMS = 4, 6, 21414
 
 
@@ -99,6 +99,8 @@ def lib():
         L.air_render_batch.restype = C.c_int32
         L.air_render_fixed.argtypes = [vp, vp, vp, vp, C.c_int32, C.c_int32, C.c_int32, vp, vp, vp, vp]
         L.air_render_fixed.restype = C.c_int32
+        L.air_render_fixed_noalloc.argtypes = [vp, vp, vp, vp, C.c_int32, C.c_int32, C.c_int32, vp, vp, vp]
+        L.air_render_fixed_noalloc.restype = C.c_int32
         L.air_trace_pixels.argtypes = [vp, vp, vp, vp, C.c_int32, C.c_int64, vp, vp, vp, vp, vp, vp, vp]
         L.air_trace_pixels.restype = C.c_int32
         L.air_field_packed_bytes.argtypes = [vp, vp]
@@ -445,6 +447,28 @@ class Context:
                                     flux.ctypes.data if want_flux else None, C.addressof(st), self._stream())
         self._check(rc)
         return images, flux, stats_dict(st)
+
+    def render_fixed_noalloc(self, scene: DeviceScene, views: Sequence, coarse_n: int, level: int, images=None,
+                             flux=None, want_flux=True):
+        """air_render_fixed_noalloc: the fixed-resolution render with its
+        workspace in the library's static device array (the scene must be
+        prepared).  images / flux: device tensors [V, nb + 1, R, R] float32 /
+        [V, nb] float64, allocated here when not given.  Returns (images,
+        flux); nothing waits for the stream."""
+        torch = _torch()
+        V, nb = len(views), scene.n_bands
+        R = coarse_n << level
+        dev = f"cuda:{self.device}"
+        if images is None:
+            images = torch.empty((V, nb + 1, R, R), dtype=torch.float32, device=dev)
+        if want_flux and flux is None:
+            flux = torch.empty((V, nb), dtype=torch.float64, device=dev)
+        vs = _views(views)
+        rc = lib().air_render_fixed_noalloc(self._p, C.addressof(scene.grid), C.addressof(scene.field),
+                                            C.addressof(vs), V, coarse_n, level, images.data_ptr(),
+                                            flux.data_ptr() if want_flux else None, self._stream())
+        self._check(rc)
+        return images, (flux if want_flux else None)
 
     def trace_pixels(self, scene: DeviceScene, view, coarse_n: int, level, ix, iy):
         torch = _torch()

@@ -271,4 +271,19 @@ hipError_t launch_fixed_flux(const float* images, int V, int nb, int64_t R, doub
 
 constexpr int64_t CHUNK = 4096;  // positions per block in counting passes; levels start on a chunk
 
+// allocation-free fixed render: layout of its static device workspace
+// (counters, then the view table, then the flux partial sums)
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)AIR_NOALLOC_SCRATCH_BYTES;
+constexpr size_t NOALLOC_CTR_OFF = 0;
+constexpr size_t NOALLOC_VIEWS_OFF = 2048;
+constexpr size_t NOALLOC_PARTIAL_OFF = 4096;
+static_assert(sizeof(unsigned long long) * CTR_COUNT <= NOALLOC_VIEWS_OFF, "counters overlap the view table");
+static_assert(NOALLOC_VIEWS_OFF + sizeof(DevView) * AIR_NOALLOC_MAX_VIEWS <= NOALLOC_PARTIAL_OFF,
+              "view table overlaps the partial sums");
+// the per-device address of the workspace (hipGetSymbolAddress once per
+// device, with that device current), and the launch that clears its counters
+// and writes the view table
+hipError_t noalloc_init(int device, void** out);
+hipError_t launch_noalloc_setup(const DevView* views, int n, void* scratch_ptr, hipStream_t s);
+
 }  // namespace air

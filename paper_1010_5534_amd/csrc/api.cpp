@@ -48,6 +48,7 @@ struct BlockSig {
 struct air_ctx {
   int device = 0;
   std::vector<BlockSig> checked;
+  void* noalloc = nullptr;  // this device's static workspace of air_render_fixed_noalloc
   int num_cus = 256;
   int seg_shift_override = -1;  // AIR_SEG_SHIFT: tuning knob for the lanes per ray
   int64_t split_tiles = 4096;   // AIR_SPLIT_TILES: queue launches (levels >= 1) of at most this many tiles run split
@@ -913,6 +914,12 @@ air_status air_create(air_ctx** out, int32_t device) {
     air_destroy(c);
     return AIR_EDEVICE;
   }
+  // the device is current: the static workspace's address on this device
+  if (noalloc_init(device, &c->noalloc) != hipSuccess) {
+    (void)hipGetLastError();
+    air_destroy(c);
+    return AIR_EDEVICE;
+  }
   *out = c;
   return AIR_OK;
 }
@@ -1042,6 +1049,64 @@ air_status air_render_fixed(air_ctx* c, const air_grid* grid, const air_field* f
     float ms = 0.0f;
     if (hipEventElapsedTime(&ms, c->ev[0], c->ev[1]) == hipSuccess) stats->ms_total = ms;
     if (hipEventElapsedTime(&ms, c->ev[2], c->ev[3]) == hipSuccess) stats->ms_march = ms;
+  }
+  return AIR_OK;
+}
+
+air_status air_render_fixed_noalloc(air_ctx* c, const air_grid* grid, const air_field* field,
+                                    const air_view* views, int32_t n_views, int32_t coarse_n, int32_t level,
+                                    float* images, double* flux, void* stream) {
+  if (!c) return AIR_EINVAL;
+  c->err.clear();
+  air_status st;
+  if ((st = check_grid(c, grid))) return st;
+  if ((st = check_field(c, field))) return st;
+  if (!views || n_views < 1 || n_views > AIR_NOALLOC_MAX_VIEWS)
+    return fail(c, AIR_EINVAL, "n_views %d out of range 1..%d (allocation-free limit)", n_views,
+                AIR_NOALLOC_MAX_VIEWS);
+  if (coarse_n < 1 || level < 0 || level >= AIR_MAX_LEVELS)
+    return fail(c, AIR_EINVAL, "coarse_n %d / level %d out of range", coarse_n, level);
+  const int64_t R = (int64_t)coarse_n << level;
+  if ((double)R * R > 4294967295.0) return fail(c, AIR_EINVAL, "raster exceeds 2^32 pixels per view");
+  if (flux && !images) return fail(c, AIR_EINVAL, "flux needs the image buffer");
+  if (!field->packed) return fail(c, AIR_EINVAL, "the allocation-free render needs a packed field (air_field_pack)");
+  if (packed_bytes_of(grid, field) >= ((int64_t)1 << 32))
+    return fail(c, AIR_ENOTSUP, "packed field exceeds 4 GiB");
+  if (grid->kind == AIR_GRID_BLOCK_AMR && !blocks_known(c, grid, field->packed))
+    return fail(c, AIR_EINVAL, "block tables not checked for this packed field: pack it with air_field_pack on "
+                               "this context first");
+  const int nb = field->kind == AIR_FIELD_RHO_J_KAPPA ? 1 : field->n_bands;
+  const int64_t cpp = (R * R + CHUNK - 1) / CHUNK;
+  const int64_t partial_bytes = 8 * (int64_t)n_views * nb * cpp;
+  if (flux && partial_bytes > (int64_t)(NOALLOC_SCRATCH_BYTES - NOALLOC_PARTIAL_OFF))
+    return fail(c, AIR_EINVAL, "flux partial sums of %lld bytes exceed the allocation-free workspace (%lld bytes)",
+                (long long)partial_bytes, (long long)(NOALLOC_SCRATCH_BYTES - NOALLOC_PARTIAL_OFF));
+  DevView hv[AIR_NOALLOC_MAX_VIEWS];
+  for (int k = 0; k < n_views; ++k)
+    if ((st = make_view(c, &views[k], hv[k]))) return st;
+  if (!c->noalloc) return fail(c, AIR_EDEVICE, "allocation-free workspace unavailable on this device");
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, AIR_EDEVICE, "hipSetDevice failed");
+  hipStream_t s = (hipStream_t)stream;
+  unsigned char* ws = static_cast<unsigned char*>(c->noalloc);
+  MarchArgs A;
+  std::memset(&A, 0, sizeof A);
+  fill_geo(grid, A.g);
+  if (c->seg_shift_override >= 0) A.g.seg_shift = c->seg_shift_override;
+  fill_fld(field, grid, A.f);
+  A.img.N0 = coarse_n;
+  A.img.Lmax = level;
+  A.img.V = n_views;
+  A.w.ctr = reinterpret_cast<unsigned long long*>(ws + NOALLOC_CTR_OFF);
+  A.views = reinterpret_cast<const DevView*>(ws + NOALLOC_VIEWS_OFF);
+  HIPCHK(c, launch_noalloc_setup(hv, n_views, ws, s));
+  HIPCHK(c, launch_march_fixed(A, level, images, march_blocks(c, A.g.seg_shift), s));
+  if (flux) {
+    double* partial = reinterpret_cast<double*>(ws + NOALLOC_PARTIAL_OFF);
+    for (int k = 0; k < n_views; ++k) {
+      const double px = views[k].width / (double)R;
+      HIPCHK(c, launch_fixed_flux(images + (size_t)k * (nb + 1) * R * R, 1, nb, R, px * px,
+                                  partial + (size_t)k * nb * cpp, flux + (size_t)k * nb, s));
+    }
   }
   return AIR_OK;
 }
