@@ -67,9 +67,30 @@ def cpu_baseline(g, f, views, min_seconds=10.0):
         dt = time.perf_counter() - t
         if dt >= min_seconds:
             break
-    return dict(value=nodes / dt, unit="rays/s", cores=oracle.num_threads(), kind="oracle",
+    cores = oracle.num_threads()
+    # one thread: plain AIR of the first view, repeated for about 5 s
+    oracle.set_threads(1)
+    t1, n1, r1 = time.perf_counter(), 0, 0
+    while True:
+        n1 += oracle.air(g, f, views[0], N0, LMAX, XI_CRIT).nodes
+        r1 += 1
+        d1 = time.perf_counter() - t1
+        if d1 >= min_seconds / 2:
+            break
+    oracle.set_threads(cores)
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return dict(value=nodes / dt, unit="rays/s", cores=cores, kind="oracle",
                 sample=f"full plain AIR of the 3 views, {reps} times ({nodes} rays) in {dt:.1f} s, FP64, OpenMP",
-                seconds=dt), first
+                seconds=dt, value_1_thread=n1 / d1,
+                sample_1_thread=f"plain AIR of view 0, {r1} times ({n1} rays) in {d1:.1f} s on 1 thread",
+                cpu_model=model, host_cpus=len(os.sched_getaffinity(0))), first
 
 
 def oracle_error(gpu_trees, orc_trees, np):
@@ -96,6 +117,86 @@ def oracle_error(gpu_trees, orc_trees, np):
                 else:
                     worst_n = max(worst_n, e)
     return dict(trees_identical=same, max_rel_err_I=worst_i, max_rel_err_N=worst_n, tolerance=1e-5)
+
+
+def device_median(fn, reps, torch):
+    """Median device time (ms) of fn over reps calls, from each call's own
+    air_stats.ms_total (HIP events on the call's stream), after one warm-up."""
+    out = fn()
+    ms = []
+    for _ in range(reps):
+        out = fn()
+        ms.append(out[-1]["ms_total"] if isinstance(out[-1], dict) else out[3]["ms_total"])
+    torch.cuda.synchronize()
+    ms.sort()
+    return out, ms[len(ms) // 2]
+
+
+def ring_experiment(ctx, air, inputs, np, torch, args):
+    """Section 3's experiment re-created (Eq. 1 ring, Table 1): the face-on
+    ring on a block hierarchy of 4^3 base blocks of 8^3 cells with 4 nested
+    levels (512^3 effective), a 32^2 base image with 4 image levels at
+    xi_crit 0.2, 0.5 and 0.8, against the fixed 512^2 image.  Error as in
+    Table 1: (F_exact - F) / F_exact with F_exact the emission summed over the
+    grid's leaf cells; time = median device time of one image."""
+    log("ring experiment (Table 1)")
+    g, f = inputs.ring()
+    scene = ctx.prepare(air.upload(g, f))
+    v = inputs.ring_view()
+    n0, lm, width = 32, 4, float(v.width)
+    bs = g.bs
+    leaf = np.repeat(np.asarray(g.block_child) < 0, bs ** 3)
+    h = (g.hi[0] - g.lo[0]) / (g.n[0] * bs) / 2.0 ** np.repeat(np.asarray(g.block_level), bs ** 3)
+    exact = float(np.sum(np.where(leaf, f.emis.astype(np.float64) * h ** 3, 0.0)))
+    reps = max(5, args.steps)
+    out_f, ms_f = device_median(lambda: ctx.render_fixed(scene, [v], n0, lm), reps, torch)
+    rows = [dict(calc="fixed", xi_crit=None, pixels=out_f[2]["rays"],
+                 flux_err=(exact - float(out_f[1][0][0])) / exact, ms=ms_f, speedup=1.0)]
+    for xc in (0.2, 0.5, 0.8):
+        prm = air.params(n0, lm, xc)
+        out, ms = device_median(lambda: ctx.render(scene, [v], prm, reuse=True), reps, torch)
+        rows.append(dict(calc="AIR", xi_crit=xc, pixels=out[3]["rays"],
+                         refined=(out[3]["rays"] - n0 * n0) // 4,
+                         flux_err=(exact - float(out[2][0][0])) / exact, ms=ms, speedup=ms_f / ms))
+    return dict(workload="Eq. 1 ring, block AMR 4^3 x 8^3 cells, 4 levels (512^3 effective), face-on view, "
+                         "32^2 base image, 4 image levels (512^2 effective)",
+                blocks=g.n_blocks, exact_flux=exact, rows=rows,
+                paper_table1="fixed 262144 px; AIR 0.2: 40512 px, 2e-6; 0.5: 23384 px, 1e-4; 0.8: 22748 px, 1e-4 "
+                             "(hardware not named; context only)")
+
+
+def xi_sweep(ctx, air, scene, views, flux_fixed, np, torch, args):
+    """The benchmark workload at xi_crit 0.2, 0.5 and 0.8: rays, device time
+    per call and the flux error against the fixed 2048^2 image per view."""
+    rows = []
+    for xc in (0.2, 0.5, 0.8):
+        prm = air.params(N0, LMAX, xc)
+        out, ms = device_median(lambda: ctx.render(scene, views, prm, want_image=False, reuse=True),
+                                max(3, args.steps // 2), torch)
+        err = None if flux_fixed is None else [float((flux_fixed[k][0] - out[2][k][0]) / flux_fixed[k][0])
+                                               for k in range(len(views))]
+        rows.append(dict(xi_crit=xc, rays=out[3]["rays"], ms_device=ms, flux_rel_err_vs_fixed=err))
+    return rows
+
+
+def hbm_probe(torch):
+    """Measured device-to-device copy bandwidth (read + write bytes per
+    second) of a 1 GiB buffer, best of 5, beside the vendor's 8 TB/s."""
+    src = torch.empty(256 << 20, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    best = None
+    for _ in range(5):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(src)
+        b.record()
+        b.synchronize()
+        ms = a.elapsed_time(b)
+        best = ms if best is None else min(best, ms)
+    gbs = 2 * src.numel() * 4 / (best * 1e-3) / 1e9
+    del src, dst
+    return gbs
 
 
 def batched_amr(ctx, air, inputs, np, torch, args):
@@ -186,6 +287,7 @@ def main():
     ap.add_argument("--skip-learned", action="store_true")
     ap.add_argument("--skip-amr", action="store_true")
     ap.add_argument("--skip-large", action="store_true")
+    ap.add_argument("--skip-ring", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the timed region, one 256 MiB device copy whose counters calibrate HBM bytes")
     args = ap.parse_args()
@@ -277,6 +379,8 @@ def main():
                                    flux_rel_err=[float((flux_f[k][0] - flux_p[k][0]) / flux_f[k][0])
                                                  for k in range(len(views))])
         del out_f, img_f
+    log("xi_crit sweep")
+    res["xi_sweep"] = xi_sweep(ctx, air, scene, views, None if args.skip_fixed else flux_f, np, torch, args)
 
     # the same plain AIR through the captured, autotuned launch sequence
     log("plain AIR, captured batch")
@@ -312,11 +416,16 @@ def main():
                                           "this workload's seed 0 is held out)")
         net.close()
 
+    if not args.skip_ring:
+        res["ring"] = ring_experiment(ctx, air, inputs, np, torch, args)
     if not args.skip_amr:
         res["batched_amr"] = batched_amr(ctx, air, inputs, np, torch, args)
     if not args.skip_large:
         res["large_scale"] = large_scale(ctx, air, inputs, np, torch, args)
 
+    gbs = hbm_probe(torch)
+    res["roofline"]["peak_measured_copy"] = gbs
+    res["roofline"]["frac_of_measured_copy"] = achieved / gbs
     if args.copy_probe:
         src = torch.empty(64 << 20, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -326,7 +435,8 @@ def main():
     if not args.no_cpu_baseline:
         log("oracle CPU baseline")
         cb, orc_trees = cpu_baseline(g, f, views)
-        res["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
+        res["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample", "value_1_thread",
+                                                  "sample_1_thread", "cpu_model", "host_cpus")}
         res["plain_air"]["vs_oracle"] = oracle_error(trees_host, orc_trees, np)
     else:
         res["cpu_baseline"] = None

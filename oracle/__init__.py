@@ -68,6 +68,8 @@ def lib():
         _lib.orc_leaf_flux.argtypes = [C.c_int, C.c_int, C.c_double, vp, vp]
         _lib.orc_leaf_flux.restype = C.c_double
         _lib.orc_num_threads.restype = C.c_int
+        _lib.orc_set_threads.argtypes = [C.c_int]
+        _lib.orc_set_threads.restype = None
         _lib.orc_xi_sens.argtypes = [C.c_int64, vp, vp, vp, C.c_double, vp, vp]
     return _lib
 
@@ -129,6 +131,11 @@ def _view(v) -> _View:
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's later parallel loops."""
+    lib().orc_set_threads(int(n))
 
 
 def trace(grid, field, origin, direction) -> Dict:

@@ -661,6 +661,15 @@ int orc_num_threads(void) {
 #endif
 }
 
+/* Threads of later parallel regions (n >= 1). */
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+  if (n >= 1) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 /* ------------------------------------------------- parity-test helper */
 /* First-order bound on how far xi can move when each stencil value p_k
  * moves by a relative amount delta (the value tolerance of a float32
