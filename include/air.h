@@ -119,6 +119,14 @@ typedef struct {
  * (air_stats.ms_march / ms_test; otherwise they are 0).  The events sit
  * between the kernels on the stream and lengthen the call a little. */
 #define AIR_FLAG_TIMING 1u
+/* air_params.flags: the images hold the super-resolved raster (section 2
+ * step vi: interpolation between adjacent pixels of differing resolution)
+ * instead of the painted leaves: each pixel of the finest raster, inside a
+ * level-L leaf, is the bilinear interpolation at its centre of the level-L
+ * samples around it (a level-L node's value, or where none exists the value
+ * of the level-(L-1) node covering the position; edges clamped).  Trees and
+ * fluxes (sums over leaves) are unchanged. */
+#define AIR_FLAG_SUPERRES 2u
 
 /* Refinement parameters (sections 2 and 3). */
 typedef struct {

@@ -65,6 +65,7 @@ def lib():
                                  vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         _lib.orc_air.restype = C.c_int64
         _lib.orc_paint_leaves.argtypes = [C.c_int, C.c_int, vp, vp, vp]
+        _lib.orc_superres.argtypes = [C.c_int, C.c_int, vp, vp, vp]
         _lib.orc_leaf_flux.argtypes = [C.c_int, C.c_int, C.c_double, vp, vp]
         _lib.orc_leaf_flux.restype = C.c_double
         _lib.orc_num_threads.restype = C.c_int
@@ -290,6 +291,16 @@ def paint_leaves(tree: Tree, vals_flat: np.ndarray) -> np.ndarray:
     out = np.zeros((R, R))
     v = np.ascontiguousarray(vals_flat, dtype=np.float64)
     lib().orc_paint_leaves(tree.N0, tree.Lmax, tree.flat_state.ctypes.data, v.ctypes.data, out.ctypes.data)
+    return out
+
+
+def superres(tree: Tree, vals_flat: np.ndarray) -> np.ndarray:
+    """The interpolated finest raster (section 2 step vi super-resolution,
+    reading in air_oracle.c: orc_superres)."""
+    R = tree.N0 << tree.Lmax
+    out = np.zeros((R, R))
+    v = np.ascontiguousarray(vals_flat, dtype=np.float64)
+    lib().orc_superres(tree.N0, tree.Lmax, tree.flat_state.ctypes.data, v.ctypes.data, out.ctypes.data)
     return out
 
 

@@ -637,6 +637,54 @@ void orc_paint_leaves(int N0, int Lmax, const uint8_t* state, const double* vals
   }
 }
 
+/* Super-resolution output (section 2 step vi suggests interpolating between
+ * adjacent pixels of differing resolution; the cited method is not given, so
+ * this is the reading stated in the design notes): every pixel of the finest
+ * raster lying in a level-L leaf takes the bilinear interpolation, at its
+ * centre, of the level-L point samples around it.  A level-L sample at
+ * (i, j) is the value of the level-L node if it exists in the final tree,
+ * otherwise of the level-(L-1) node covering that position (the 2:1 rule
+ * makes it exist for the neighbours of a leaf); positions beyond the image
+ * edge take the nearest edge position.  Level-L coordinates of a finest pixel
+ * x: u = (x + 1/2) / 2^(Lmax-L) - 1/2 (sample i sits at u = i). */
+static double sample_value(int N0, const int64_t* off, const uint8_t* state, const double* vals, int L,
+                           int64_t i, int64_t j) {
+  const int64_t R = (int64_t)N0 << L;
+  if (i < 0) i = 0;
+  if (j < 0) j = 0;
+  if (i > R - 1) i = R - 1;
+  if (j > R - 1) j = R - 1;
+  const int64_t p = off[L] + j * R + i;
+  if ((state[p] & ORC_EXIST) || L == 0) return vals[p];
+  return vals[off[L - 1] + (j >> 1) * (R >> 1) + (i >> 1)];
+}
+
+void orc_superres(int N0, int Lmax, const uint8_t* state, const double* vals, double* out) {
+  int64_t off[ORC_MAXL + 2];
+  off[0] = 0;
+  for (int L = 0; L <= Lmax; ++L) off[L + 1] = off[L] + ((int64_t)N0 << L) * ((int64_t)N0 << L);
+  const int64_t Rf = (int64_t)N0 << Lmax;
+  for (int L = 0; L <= Lmax; ++L) {
+    const int64_t R = (int64_t)N0 << L, sc = (int64_t)1 << (Lmax - L);
+    for (int64_t j = 0; j < R; ++j)
+      for (int64_t i = 0; i < R; ++i) {
+        const uint8_t s = state[off[L] + j * R + i];
+        if (!(s & ORC_EXIST) || (s & ORC_REFINED)) continue;
+        for (int64_t y = j * sc; y < (j + 1) * sc; ++y)
+          for (int64_t x = i * sc; x < (i + 1) * sc; ++x) {
+            const double u = ((double)x + 0.5) / (double)sc - 0.5, v = ((double)y + 0.5) / (double)sc - 0.5;
+            const int64_t i0 = (int64_t)floor(u), j0 = (int64_t)floor(v);
+            const double fu = u - (double)i0, fv = v - (double)j0;
+            const double a = sample_value(N0, off, state, vals, L, i0, j0);
+            const double b = sample_value(N0, off, state, vals, L, i0 + 1, j0);
+            const double c = sample_value(N0, off, state, vals, L, i0, j0 + 1);
+            const double d = sample_value(N0, off, state, vals, L, i0 + 1, j0 + 1);
+            out[y * Rf + x] = (1.0 - fu) * (1.0 - fv) * a + fu * (1.0 - fv) * b + (1.0 - fu) * fv * c + fu * fv * d;
+          }
+      }
+  }
+}
+
 /* Flux: sum over leaves of (pixel area) * value, Neumaier-compensated. */
 double orc_leaf_flux(int N0, int Lmax, double width, const uint8_t* state, const double* vals) {
   nsum s = {0, 0};

@@ -214,9 +214,11 @@ def _views(views) -> C.Array:
 
 
 FLAG_TIMING = 1
+FLAG_SUPERRES = 2
 
 
-def params(coarse_n, max_level, xi_crit_I=0.5, xi_crit_N=2.0, band_weight=None, timing=False) -> air_params:
+def params(coarse_n, max_level, xi_crit_I=0.5, xi_crit_N=2.0, band_weight=None, timing=False,
+           superres=False) -> air_params:
     p = air_params()
     p.coarse_n = coarse_n
     p.max_level = max_level
@@ -224,7 +226,7 @@ def params(coarse_n, max_level, xi_crit_I=0.5, xi_crit_N=2.0, band_weight=None, 
     p.xi_crit_N = xi_crit_N
     w = [1.0] * MAX_BANDS if band_weight is None else list(band_weight) + [0.0] * (MAX_BANDS - len(band_weight))
     p.band_weight[:] = [float(x) for x in w[:MAX_BANDS]]
-    p.flags = FLAG_TIMING if timing else 0
+    p.flags = (FLAG_TIMING if timing else 0) | (FLAG_SUPERRES if superres else 0)
     return p
 
 

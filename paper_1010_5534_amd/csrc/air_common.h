@@ -266,6 +266,9 @@ struct TreeOut {
 };
 hipError_t launch_write_tree(const MarchArgs& a, const unsigned long long* chunk_offsets, const int32_t* id_map,
                              const uint64_t* node_pos, const TreeOut* outs, int grid_blocks, hipStream_t s);
+// the interpolated raster of the finished tree (step vi super-resolution)
+// into images [V][nb + 1][R][R]
+hipError_t launch_superres(const MarchArgs& a, float* images, hipStream_t s);
 hipError_t launch_fixed_flux(const float* images, int V, int nb, int64_t R, double pix_area, double* partial,
                              double* flux_dev, hipStream_t s);
 

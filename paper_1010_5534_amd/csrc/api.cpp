@@ -538,7 +538,7 @@ air_status check_render_args(air_ctx* c, const air_grid* grid, const air_field* 
     return fail(c, AIR_EINVAL, "coarse_n^2 * 4^max_level exceeds 2^32 pixels per view");
   if (!std::isfinite(prm->xi_crit_I) || !std::isfinite(prm->xi_crit_N) || prm->xi_crit_I < 0 || prm->xi_crit_N < 0)
     return fail(c, AIR_EINVAL, "xi_crit must be finite and >= 0");
-  if (prm->flags & ~AIR_FLAG_TIMING) return fail(c, AIR_EINVAL, "params.flags has unknown bits");
+  if (prm->flags & ~(AIR_FLAG_TIMING | AIR_FLAG_SUPERRES)) return fail(c, AIR_EINVAL, "params.flags has unknown bits");
   return AIR_OK;
 }
 
@@ -592,7 +592,7 @@ struct Plan {
   float xcI = 0, xcN = 0, w[MAXB] = {};
   const air_cnn* net = nullptr;
   air_learn_params lp{};
-  bool trees = false, flux = false, timing = false;
+  bool trees = false, flux = false, timing = false, superres = false;
   float* images = nullptr;
   // where k_finish writes the result block: the context's pinned host buffer
   // (no copy back; a captured sequence is keyed on its address)
@@ -620,7 +620,8 @@ air_status enqueue_render(air_ctx* c, const Plan& P, const Tune& tune, hipStream
   }
   unsigned long long* chunk = (unsigned long long*)c->chunk.p;
   double* fpart = P.flux ? (double*)c->partial.p : nullptr;
-  HIPCHK(c, launch_count(A, chunk, (unsigned*)c->cstat.p, P.n_chunks, fpart, P.images, s));
+  HIPCHK(c, launch_count(A, chunk, (unsigned*)c->cstat.p, P.n_chunks, fpart, P.superres ? nullptr : P.images, s));
+  if (P.superres && P.images) HIPCHK(c, launch_superres(A, P.images, s));
   HIPCHK(c, launch_finish(A, chunk, P.n_chunks, P.trees, (const unsigned*)c->cstat.p, fpart, P.res, s));
   if (P.trees) {
     HIPCHK(c, launch_emit(A, chunk, P.n_chunks, (int32_t*)c->idmap.p, (uint64_t*)c->nodepos.p, s));
@@ -644,8 +645,8 @@ std::string plan_key(const air_ctx* c, const Plan& P, const Tune& t) {
     k.append(reinterpret_cast<const char*>(P.net->net.stdv), sizeof P.net->net.stdv);
   }
   k.append(reinterpret_cast<const char*>(&P.lp), sizeof P.lp);
-  const char flags[3] = {(char)P.trees, (char)P.flux, (char)P.timing};
-  k.append(flags, 3);
+  const char flags[4] = {(char)P.trees, (char)P.flux, (char)P.timing, (char)P.superres};
+  k.append(flags, 4);
   k.append(reinterpret_cast<const char*>(&P.images), sizeof P.images);
   k.append(reinterpret_cast<const char*>(&P.res), sizeof P.res);
   k.append(reinterpret_cast<const char*>(&t), sizeof t);
@@ -722,6 +723,7 @@ air_status render_core(air_ctx* c, const air_grid* grid, const air_field* field,
   P.flux = flux != nullptr;
   P.images = images;
   P.timing = !batch && (prm->flags & AIR_FLAG_TIMING) != 0;
+  P.superres = (prm->flags & AIR_FLAG_SUPERRES) != 0;
   const size_t res_bytes = 8 * (size_t)res_words(V, nb);
   if ((st = ensure_host(c, (void**)&c->host_vstat, &c->host_vstat_n, res_bytes))) return st;
   P.res = c->host_vstat;

@@ -316,6 +316,62 @@ __device__ __forceinline__ void paint_pixels(const MarchArgs& A, float* images, 
   }
 }
 
+// Step vi's super-resolution option (reading: the cited interpolation is not
+// given): each pixel of the finest raster, lying in a level-L leaf, takes the
+// bilinear interpolation at its centre of the level-L point samples around
+// it.  A sample is the level-L node's value where that node exists, else the
+// value of the level-(L-1) node covering the position (which the 2:1 rule
+// makes exist next to a leaf); positions beyond the image edge take the
+// nearest edge position.  In level-L units a finest pixel x sits at
+// u = (x + 1/2) / 2^(Lmax-L) - 1/2, exactly representable, so the weights are
+// exact and a level-Lmax leaf gives its own value bit for bit.
+__device__ __forceinline__ int64_t sample_pos(const MarchArgs& A, int64_t vb, int L, int i, int j) {
+  const int RL = A.img.N0 << L;
+  i = min(max(i, 0), RL - 1);
+  j = min(max(j, 0), RL - 1);
+  const uint32_t k = key_of((uint32_t)i, (uint32_t)j, L, A.img.N0);
+  const int64_t p = vb + A.img.off[L] + k;
+  if (L == 0 || (A.w.state[p] & AIR_NODE_EXIST)) return p;
+  return vb + A.img.off[L - 1] + (k >> 2);
+}
+
+__global__ __launch_bounds__(256) void k_superres(MarchArgs A, float* images) {
+  const int N0 = A.img.N0, Lm = A.img.Lmax, nb = A.f.nb;
+  const uint32_t R = (uint32_t)N0 << Lm;
+  const int64_t R2 = (int64_t)R * R, VS = (int64_t)A.img.V * A.img.S;
+  const int64_t total = (int64_t)A.img.V * R2;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+    const int v = (int)(e / R2);
+    const int64_t q = e - (int64_t)v * R2;
+    const uint32_t x = (uint32_t)(q % R), y = (uint32_t)(q / R);
+    const int64_t vb = (int64_t)v * A.img.S;
+    // the leaf holding the pixel
+    uint32_t key = (y >> Lm) * (uint32_t)N0 + (x >> Lm);
+    int L = 0;
+    int64_t p = vb + key;
+    while (L < Lm && (A.w.state[p] & AIR_NODE_REFINED)) {
+      ++L;
+      const int sh = Lm - L;
+      key = 4u * key + (((x >> sh) & 1u) | (((y >> sh) & 1u) << 1));
+      p = vb + A.img.off[L] + key;
+    }
+    const float inv_s = 1.0f / (float)(1u << (Lm - L));  // a power of two
+    const float u = ((float)x + 0.5f) * inv_s - 0.5f, w = ((float)y + 0.5f) * inv_s - 0.5f;
+    const float fi = floorf(u), fj = floorf(w);
+    const float fu = u - fi, fv = w - fj;
+    const int i0 = (int)fi, j0 = (int)fj;
+    const int64_t pa = sample_pos(A, vb, L, i0, j0), pb = sample_pos(A, vb, L, i0 + 1, j0);
+    const int64_t pc = sample_pos(A, vb, L, i0, j0 + 1), pd = sample_pos(A, vb, L, i0 + 1, j0 + 1);
+    const float wa = (1.0f - fu) * (1.0f - fv), wb = fu * (1.0f - fv), wc = (1.0f - fu) * fv, wd = fu * fv;
+    float* img = images + (int64_t)v * (nb + 1) * R2 + q;
+    for (int b = 0; b <= nb; ++b) {
+      const float* src = b < nb ? A.w.valI + b * VS : A.w.valN;
+      const float val = wa * src[pa] + wb * src[pb] + wc * src[pc] + wd * src[pd];
+      __builtin_nontemporal_store(val, img + b * R2);
+    }
+  }
+}
+
 template <int QX>
 __host__ __device__ inline int64_t paint_blocks_per_view(const Img& img) {
   const int64_t R = (int64_t)img.N0 << img.Lmax;
@@ -688,6 +744,13 @@ hipError_t launch_write_tree(const MarchArgs& a, const unsigned long long* chunk
   const int64_t n_chunks = (int64_t)a.img.V * a.img.S / CHUNK;
   hipLaunchKernelGGL(k_write_tree, dim3(grid_blocks), dim3(256), 0, s, a, chunk_offsets, n_chunks, id_map, node_pos,
                      outs);
+  return hipGetLastError();
+}
+
+hipError_t launch_superres(const MarchArgs& a, float* images, hipStream_t s) {
+  const int64_t R = (int64_t)a.img.N0 << a.img.Lmax, total = (int64_t)a.img.V * R * R;
+  const int64_t blocks = std::min<int64_t>(std::max<int64_t>((total + 255) / 256, 1), 65536);
+  hipLaunchKernelGGL(k_superres, dim3((unsigned)blocks), dim3(256), 0, s, a, images);
   return hipGetLastError();
 }
 

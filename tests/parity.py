@@ -118,9 +118,10 @@ def _stencils_of(tree, L, which, positions):
 
 
 def check(gtree, grid, field, view, N0, Lmax, xc_I, xc_N=2.0, band_w=None, image=None, flux=None, own=False,
-          label=""):
+          label="", superres=False):
     """Compare one GPU tree (air.Tree of `view`) with the oracle.  image:
-    the view's raster [nb + 1, R, R] (device or host), flux: its [nb] fluxes.
+    the view's raster [nb + 1, R, R] (device or host), painted from the leaves
+    or, with superres, interpolated (oracle.superres); flux: its [nb] fluxes.
     Returns a report; assert_parity() applies the bar."""
     nb = field.n_bands
     g = gpu_dense(gtree, N0, Lmax, nb)
@@ -207,7 +208,7 @@ def check(gtree, grid, field, view, N0, Lmax, xc_I, xc_N=2.0, band_w=None, image
         worst = 0.0
         for b in range(nb + 1):
             vals = _flat([o_I[L][b] for L in range(Lmax + 1)]) if b < nb else _flat(o_N)
-            ref_img = oracle.paint_leaves(t_o, vals)
+            ref_img = oracle.superres(t_o, vals) if superres else oracle.paint_leaves(t_o, vals)
             worst = max(worst, float(rel_err(img[b], ref_img).max()))
         rep["max_rel_image"] = worst
     if flux is not None:
