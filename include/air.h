@@ -295,6 +295,40 @@ air_status air_trace_pixels(air_ctx* ctx, const air_grid* grid, const air_field*
                             void* stream);
 
 /* ------------------------------------------------------------------------
+ * Per-pixel spectra (section 2 step vi: integrated quantities such as
+ * broadband images; an integrated spectrum needs every pixel's spectrum until
+ * the image is final).  A spectrum is n_bins energy bins of a (rho, T) field:
+ *   kappa_b = k0_b rho T^-s_b,   j_b = e0_b rho^2 T^q_b exp(-E_b / T)
+ * (T > 0), each integrated along the ray like a band.  The image is refined
+ * on the broadband sum_b weight_b I_b.
+ * ---------------------------------------------------------------------- */
+#define AIR_MAX_BINS 1024
+typedef struct {
+  int32_t n_bins;       /* 1..AIR_MAX_BINS */
+  const double* bins;   /* host [n_bins][5]: k0, s, e0, q, E */
+  const float* weight;  /* host [n_bins]: broadband weights (>= 0) */
+} air_spectrum;
+
+/*
+ * Plain AIR of n_views views on the broadband of `spectrum` (uniform grid,
+ * field kind AIR_FIELD_RHO_T; its n_bands and band table are not used):
+ * arguments and tree outputs as air_render, with the trees' I holding the one
+ * band sum_b weight_b I_b (params.band_weight is not used) and:
+ *  spectra  device [sum_k trees[k].capacity][n_bins] or NULL: every node's
+ *           spectrum, view k's nodes from row sum_{k' < k} trees[k'].capacity,
+ *           in the trees' canonical order;
+ *  images   device [n_views][2][R][R]: broadband and column of the leaves;
+ *  flux     host [n_views][n_bins] or NULL: the image's spectrum, sum over
+ *           leaves of pixel area x I_b (float64, fixed order).
+ * trees is required.  Errors as air_render; ENOTSUP for block-AMR grids or
+ * AIR_FLAG_SUPERRES.
+ */
+air_status air_render_spectra(air_ctx* ctx, const air_grid* grid, const air_field* field, const air_view* views,
+                              int32_t n_views, const air_params* params, const air_spectrum* spectrum,
+                              air_tree* trees, float* spectra, float* images, double* flux, air_stats* stats,
+                              void* stream);
+
+/* ------------------------------------------------------------------------
  * Learned depth proposal.  A small network (four 3x3 convolutions,
  * 4 -> 32 -> 32 -> 32 -> 6 channels, zero padding, ReLU after the first
  * three) reads four maps of the coarse trace and predicts, per coarse pixel,

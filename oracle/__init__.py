@@ -22,7 +22,7 @@ _LIB_PATH = os.path.join(HERE, "liboracle.so")
 _lib = None
 
 EXIST, TESTED, FLAGGED, BALANCE, REFINED = 1, 2, 4, 8, 16
-MAXB = 16
+MAXB = 1024
 
 
 class _Grid(C.Structure):

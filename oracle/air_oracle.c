@@ -34,7 +34,7 @@
 #include <omp.h>
 #endif
 
-#define ORC_MAXB 16
+#define ORC_MAXB 1024
 #define ORC_MAXL 16
 
 /* node state bits */
@@ -57,13 +57,17 @@ typedef struct {
 } orc_grid;
 
 typedef struct {
-  int32_t kind; /* 0: rho, emissivity, opacity (one band).  1: rho, T, power-law bands */
+  int32_t kind; /* 0: rho, emissivity, opacity (one band).  1: rho, T, power-law bands.
+                   2: rho, T, spectral bins */
   int32_t n_bands;
   const float* rho;
   const float* emis;
   const float* kappa;
   const float* temp;
-  const double* band; /* [n_bands][3] = kappa0, s, q : kappa = kappa0 rho T^-s, j = rho^2 T^q */
+  /* kind 1: [n_bands][3] = kappa0, s, q : kappa = kappa0 rho T^-s, j = rho^2 T^q.
+     kind 2: [n_bands][5] = kappa0, s, e0, q, E : kappa = kappa0 rho T^-s,
+             j = e0 rho^2 T^q exp(-E / T) */
+  const double* band;
 } orc_field;
 
 typedef struct {
@@ -170,11 +174,18 @@ static void cell_optics(const orc_field* f, int64_t idx, double* rho, double* jb
   if (f->kind == 0) {
     jb[0] = (double)f->emis[idx];
     kb[0] = (double)f->kappa[idx];
-  } else {
+  } else if (f->kind == 1) {
     double T = (double)f->temp[idx];
     for (int b = 0; b < f->n_bands; ++b) {
       kb[b] = f->band[3 * b + 0] * r * pow(T, -f->band[3 * b + 1]);
       jb[b] = r * r * pow(T, f->band[3 * b + 2]);
+    }
+  } else {
+    double T = (double)f->temp[idx];
+    for (int b = 0; b < f->n_bands; ++b) {
+      const double* q = f->band + 5 * b;
+      kb[b] = q[0] * r * pow(T, -q[1]);
+      jb[b] = q[2] * r * r * pow(T, q[3]) * exp(-q[4] / T);
     }
   }
 }

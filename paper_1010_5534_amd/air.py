@@ -22,7 +22,8 @@ NODE_EXIST, NODE_TESTED, NODE_FLAGGED, NODE_BALANCE, NODE_REFINED, NODE_EVALUATE
 EXPORTS = ("air_create", "air_destroy", "air_last_error", "air_render", "air_render_fixed", "air_trace_pixels",
            "air_field_packed_bytes", "air_field_pack", "air_cnn_create", "air_cnn_destroy", "air_cnn_set",
            "air_cnn_get", "air_features", "air_cnn_forward", "air_cnn_loss_grad", "air_cnn_adam", "air_tree_depth",
-           "air_render_learned", "air_render_batch", "air_cnn_tensor", "air_render_fixed_noalloc")
+           "air_render_learned", "air_render_batch", "air_cnn_tensor", "air_render_fixed_noalloc",
+           "air_render_spectra")
 CNN_FEATURES, CNN_CLASSES, CNN_PARAMS = 4, 6, 21414
 
 
@@ -67,6 +68,10 @@ class air_stats(C.Structure):
                 ("ms_total", C.c_double), ("ms_march", C.c_double), ("ms_test", C.c_double)]
 
 
+class air_spectrum(C.Structure):
+    _fields_ = [("n_bins", C.c_int32), ("bins", C.c_void_p), ("weight", C.c_void_p)]
+
+
 class air_learn_params(C.Structure):
     _fields_ = [("c_ray", C.c_float), ("c_sweep", C.c_float), ("max_depth", C.c_int32), ("flags", C.c_uint32)]
 
@@ -101,6 +106,8 @@ def lib():
         L.air_render_fixed.restype = C.c_int32
         L.air_render_fixed_noalloc.argtypes = [vp, vp, vp, vp, C.c_int32, C.c_int32, C.c_int32, vp, vp, vp]
         L.air_render_fixed_noalloc.restype = C.c_int32
+        L.air_render_spectra.argtypes = [vp, vp, vp, vp, C.c_int32, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.air_render_spectra.restype = C.c_int32
         L.air_trace_pixels.argtypes = [vp, vp, vp, vp, C.c_int32, C.c_int64, vp, vp, vp, vp, vp, vp, vp]
         L.air_trace_pixels.restype = C.c_int32
         L.air_field_packed_bytes.argtypes = [vp, vp]
@@ -449,6 +456,42 @@ class Context:
                                     flux.ctypes.data if want_flux else None, C.addressof(st), self._stream())
         self._check(rc)
         return images, flux, stats_dict(st)
+
+    def render_spectra(self, scene: DeviceScene, views: Sequence, prm: air_params, bins, weight,
+                       want_spectra=True, want_image=True, want_flux=True, capacity: Optional[int] = None):
+        """air_render_spectra: plain AIR on the broadband sum_b weight_b I_b
+        of the bin table bins [n_bins][5] (k0, s, e0, q, E).  Returns (trees,
+        spectra [V, capacity, n_bins] device or None, images [V, 2, R, R],
+        flux [V, n_bins] host (the image spectra), stats)."""
+        torch = _torch()
+        bins = np.ascontiguousarray(bins, dtype=np.float64).reshape(-1, 5)
+        w = np.ascontiguousarray(weight, dtype=np.float32).reshape(-1)
+        B, V = bins.shape[0], len(views)
+        spec = air_spectrum()
+        spec.n_bins, spec.bins, spec.weight = B, bins.ctypes.data, w.ctypes.data
+        R = prm.coarse_n << prm.max_level
+        bound = sum((prm.coarse_n << L) ** 2 for L in range(prm.max_level + 1))
+        cap = min(bound, capacity or (1 << 20))
+        dev = f"cuda:{self.device}"
+        vs = _views(views)
+        while True:
+            trees, keep = self._tree_array(V, 1, cap, False)
+            spectra = torch.empty((V, cap, B), dtype=torch.float32, device=dev) if want_spectra else None
+            images = torch.empty((V, 2, R, R), dtype=torch.float32, device=dev) if want_image else None
+            flux = np.zeros((V, B), dtype=np.float64) if want_flux else None
+            st = air_stats()
+            rc = lib().air_render_spectra(self._p, C.addressof(scene.grid), C.addressof(scene.field),
+                                          C.addressof(vs), V, C.addressof(prm), C.addressof(spec),
+                                          C.addressof(trees), spectra.data_ptr() if want_spectra else None,
+                                          images.data_ptr() if want_image else None,
+                                          flux.ctypes.data if want_flux else None, C.addressof(st), self._stream())
+            if rc == AIR_ECAPACITY:
+                cap = max(trees[k].n_nodes for k in range(V))
+                continue
+            self._check(rc)
+            break
+        out = [Tree(trees[k].n_nodes, list(trees[k].n_per_level), trees[k].n_leaves, keep[k]) for k in range(V)]
+        return out, spectra, images, flux, stats_dict(st)
 
     def render_fixed_noalloc(self, scene: DeviceScene, views: Sequence, coarse_n: int, level: int, images=None,
                              flux=None, want_flux=True):

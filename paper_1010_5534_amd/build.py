@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libair.so")
-SOURCES = ["api.cpp", "march.hip", "tree.hip", "learn.hip", "cnn.hip", "noalloc.hip"]
+SOURCES = ["api.cpp", "march.hip", "tree.hip", "learn.hip", "cnn.hip", "noalloc.hip", "spectra.hip"]
 ARCH = os.environ.get("AIR_OFFLOAD_ARCH", "gfx950")
 
 

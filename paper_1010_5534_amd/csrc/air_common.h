@@ -266,6 +266,29 @@ struct TreeOut {
 };
 hipError_t launch_write_tree(const MarchArgs& a, const unsigned long long* chunk_offsets, const int32_t* id_map,
                              const uint64_t* node_pos, const TreeOut* outs, int grid_blocks, hipStream_t s);
+// per-pixel spectra (spectra.hip): the bin table on the device, the store of
+// traced spectra by work-queue position and the map from level-map position
+// to queue position
+struct SpecArgs {
+  int nbins, stride;     // bins; row stride of the table (floats)
+  const float* tab;      // [6][stride]: k0, -s, q, -E log2(e), e0, broadband weight
+  float* store;          // [cap][nbins]
+  unsigned long long cap;
+  uint32_t* qpos;        // [V*S]
+  unsigned* overflow;    // set when a ray's queue position lies past the store
+};
+// spectra in canonical node order: view v's rows start at row0[v], at most
+// cap[v] of them (device arrays [V])
+struct SpecOut {
+  float* spectra;
+  const int64_t* row0;
+  const int64_t* cap;
+};
+constexpr int SPEC_CHUNK = 256;  // canonical nodes per partial sum of the image's spectrum
+hipError_t launch_march_spectra(const MarchArgs& a, const SpecArgs& s, int L, int grid_blocks, hipStream_t st);
+hipError_t launch_spectra_out(const MarchArgs& a, const SpecArgs& s, const unsigned long long* chunk_off,
+                              int64_t n_chunks, const uint64_t* node_pos, const SpecOut& o, int64_t chunks_per_view,
+                              double* partial, double* flux_dev, int grid_blocks, hipStream_t st);
 // the interpolated raster of the finished tree (step vi super-resolution)
 // into images [V][nb + 1][R][R]
 hipError_t launch_superres(const MarchArgs& a, float* images, hipStream_t s);

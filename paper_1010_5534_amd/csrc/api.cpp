@@ -58,6 +58,12 @@ struct air_ctx {
       views, touts, pack;
   // learned proposal: coarse maps, network activations and gradients, depth
   // choice and speculative work list
+  // per-pixel spectra: bin table, spectra by queue position, queue position
+  // per map position, per-view output rows, overflow flag, partial sums and
+  // the image spectra
+  DevBuf spec_tab, spec_store, spec_qpos, spec_rows, spec_flag, spec_part, spec_flux;
+  void* host_spec = nullptr;  // pinned: overflow flag, then the image spectra
+  size_t host_spec_n = 0;
   DevBuf nodepos, lmax0, feat, cx0, ca1, ca2, ca3, cz, cdz, cda, cdb, cdc, cwpart, closs_part, closs, depth8, scount,
       spec;
   // pixels of the last air_cnn_forward / air_cnn_loss_grad call whose
@@ -452,7 +458,8 @@ air_status ensure_cnn_work(air_ctx* c, int64_t P, bool training) {
 
 // device buffers and march arguments of one render of V views to Lm levels
 air_status setup_render(air_ctx* c, const air_grid* grid, const air_field* field, const air_view* views, int V,
-                        int N0, int Lm, bool range, hipStream_t s, MarchArgs& A, int64_t& n_chunks) {
+                        int N0, int Lm, bool range, hipStream_t s, MarchArgs& A, int64_t& n_chunks,
+                        bool pack = true) {
   std::memset(&A, 0, sizeof A);
   fill_geo(grid, A.g);
   if (c->seg_shift_override >= 0) A.g.seg_shift = c->seg_shift_override;
@@ -520,7 +527,7 @@ air_status setup_render(air_ctx* c, const air_grid* grid, const air_field* field
   if ((st = upload_views(c, views, V, s, &A.views))) return st;
   A.img.min_width = views[0].width;
   for (int k = 1; k < V; ++k) A.img.min_width = std::min(A.img.min_width, views[k].width);
-  return ensure_packed(c, grid, field, A, s);
+  return pack ? ensure_packed(c, grid, field, A, s) : AIR_OK;
 }
 
 air_status check_render_args(air_ctx* c, const air_grid* grid, const air_field* field, const air_view* views,
@@ -597,6 +604,14 @@ struct Plan {
   // where k_finish writes the result block: the context's pinned host buffer
   // (no copy back; a captured sequence is keyed on its address)
   unsigned long long* res = nullptr;
+  // per-pixel spectra (air_render_spectra): the spectral march replaces the
+  // band march, and the spectra are gathered and integrated after the tree
+  bool spectral = false;
+  SpecArgs spec{};
+  SpecOut spec_out{};
+  int64_t spec_cpv = 0;
+  double* spec_partial = nullptr;
+  double* spec_flux = nullptr;
 };
 
 air_status enqueue_render(air_ctx* c, const Plan& P, const Tune& tune, hipStream_t s) {
@@ -609,7 +624,10 @@ air_status enqueue_render(air_ctx* c, const Plan& P, const Tune& tune, hipStream
   HIPCHK(c, launch_init(A, s));
   for (int L = 0; L <= Lm; ++L) {
     if (P.timing) HIPCHK(c, hipEventRecord(ev[2 + 4 * L], s));
-    HIPCHK(c, launch_march_queue(A, L, march_blocks(c, A.g.seg_shift, tune.march_waves_per_cu), s));
+    if (P.spectral)
+      HIPCHK(c, launch_march_spectra(A, P.spec, L, c->num_cus * 8, s));
+    else
+      HIPCHK(c, launch_march_queue(A, L, march_blocks(c, A.g.seg_shift, tune.march_waves_per_cu), s));
     if (P.timing) HIPCHK(c, hipEventRecord(ev[3 + 4 * L], s));
     if (P.net && L == 0) {
       if ((st = learned_steps(c, A, P.net, &P.lp, P.w, P.timing, tune, s))) return st;
@@ -627,6 +645,9 @@ air_status enqueue_render(air_ctx* c, const Plan& P, const Tune& tune, hipStream
     HIPCHK(c, launch_emit(A, chunk, P.n_chunks, (int32_t*)c->idmap.p, (uint64_t*)c->nodepos.p, s));
     HIPCHK(c, launch_write_tree(A, chunk, (const int32_t*)c->idmap.p, (const uint64_t*)c->nodepos.p,
                                 (const TreeOut*)c->touts.p, c->num_cus * 8, s));
+    if (P.spectral)
+      HIPCHK(c, launch_spectra_out(A, P.spec, chunk, P.n_chunks, (const uint64_t*)c->nodepos.p, P.spec_out,
+                                   P.spec_cpv, P.spec_partial, P.spec_flux, c->num_cus * 8, s));
   }
   return AIR_OK;
 }
@@ -697,10 +718,19 @@ air_status autotune(air_ctx* c, const Plan& P, hipStream_t s, Tune& best) {
 air_status render_core(air_ctx* c, const air_grid* grid, const air_field* field, const air_view* views,
                        int32_t n_views, const air_params* prm, const air_cnn* net, const air_learn_params* lp,
                        air_tree* trees, float* images, double* flux, air_stats* stats, air_learn_stats* ls,
-                       void* stream, bool batch) {
+                       void* stream, bool batch, const air_spectrum* spectrum = nullptr, float* spectra = nullptr) {
   if (!c) return AIR_EINVAL;
   c->err.clear();
   air_status st;
+  // the spectral render traces (rho, T) with its bin table; the level loop
+  // refines on the broadband, carried as the one band of the maps
+  air_field fone;
+  if (spectrum) {
+    fone = *field;
+    fone.n_bands = 1;
+    fone.packed = nullptr;
+    field = &fone;
+  }
   if ((st = check_render_args(c, grid, field, views, n_views, prm))) return st;
   for (int k = 0; trees && k < n_views; ++k)
     if (trees[k].capacity < 0) return fail(c, AIR_EINVAL, "tree %d capacity < 0", k);
@@ -710,13 +740,58 @@ air_status render_core(air_ctx* c, const air_grid* grid, const air_field* field,
   const bool learned = net != nullptr;
   const int N0 = prm->coarse_n, Lm = prm->max_level, V = n_views;
   Plan P;
-  if ((st = setup_render(c, grid, field, views, V, N0, Lm, learned, s, P.A, P.n_chunks))) return st;
+  if ((st = setup_render(c, grid, field, views, V, N0, Lm, learned, s, P.A, P.n_chunks, !spectrum))) return st;
   const MarchArgs& A = P.A;
   const int nb = A.f.nb;
   P.A.w.skip_spec = learned ? 1 : 0;
   P.xcI = prm->xi_crit_I;
   P.xcN = prm->xi_crit_N;
   for (int b = 0; b < MAXB; ++b) P.w[b] = b < nb ? prm->band_weight[b] : 0.0f;
+  const int nbins = spectrum ? spectrum->n_bins : 0;
+  double* const spectrum_flux = spectrum ? flux : nullptr;  // the caller's [V][n_bins]
+  if (spectrum) {
+    P.w[0] = 1.0f;  // the broadband is already weighted
+    P.spectral = true;
+    // bin table [6][stride]: k0, -s, q, -E log2(e), e0, broadband weight
+    const int stride = (nbins + 63) / 64 * 64;
+    std::vector<float> tab(6 * (size_t)stride, 0.0f);
+    for (int b = 0; b < nbins; ++b) {
+      const double* r = spectrum->bins + 5 * (size_t)b;
+      tab[0 * stride + b] = (float)r[0];
+      tab[1 * stride + b] = (float)(-r[1]);
+      tab[2 * stride + b] = (float)r[3];
+      tab[3 * stride + b] = (float)(-r[4] * 1.4426950408889634);
+      tab[4 * stride + b] = (float)r[2];
+      tab[5 * stride + b] = spectrum->weight[b];
+    }
+    int64_t cap_total = 0, cap_max = 0;
+    std::vector<int64_t> rows(2 * (size_t)V);
+    for (int k = 0; k < V; ++k) {
+      rows[k] = cap_total;
+      rows[V + k] = trees[k].capacity;
+      cap_total += trees[k].capacity;
+      cap_max = std::max<int64_t>(cap_max, trees[k].capacity);
+    }
+    if (cap_total >= ((int64_t)1 << 32)) return fail(c, AIR_EINVAL, "total tree capacity reaches 2^32");
+    if ((st = ensure(c, c->spec_tab, 4 * tab.size()))) return st;
+    if ((st = ensure(c, c->spec_store, 4 * (size_t)std::max<int64_t>(cap_total, 1) * nbins))) return st;
+    if ((st = ensure(c, c->spec_qpos, 4 * (size_t)V * A.img.S))) return st;
+    if ((st = ensure(c, c->spec_rows, 8 * rows.size()))) return st;
+    if ((st = ensure(c, c->spec_flag, 16))) return st;
+    P.spec_cpv = (cap_max + SPEC_CHUNK - 1) / SPEC_CHUNK;
+    if ((st = ensure(c, c->spec_part, 8 * (size_t)V * std::max<int64_t>(P.spec_cpv, 1) * nbins))) return st;
+    if ((st = ensure(c, c->spec_flux, 8 * (size_t)V * nbins))) return st;
+    if ((st = ensure_host(c, &c->host_spec, &c->host_spec_n, 16 + 8 * (size_t)V * nbins))) return st;
+    HIPCHK(c, hipMemcpyAsync(c->spec_tab.p, tab.data(), 4 * tab.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(c->spec_rows.p, rows.data(), 8 * rows.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemsetAsync(c->spec_flag.p, 0, 16, s));
+    P.spec = SpecArgs{nbins, stride, (const float*)c->spec_tab.p, (float*)c->spec_store.p,
+                      (unsigned long long)cap_total, (uint32_t*)c->spec_qpos.p, (unsigned*)c->spec_flag.p};
+    P.spec_out = SpecOut{spectra, (const int64_t*)c->spec_rows.p, (const int64_t*)c->spec_rows.p + V};
+    P.spec_partial = (double*)c->spec_part.p;
+    P.spec_flux = flux ? (double*)c->spec_flux.p : nullptr;
+    flux = nullptr;  // the broadband flux of the result block is not asked for
+  }
   P.net = net;
   if (lp) P.lp = *lp;
   P.trees = trees != nullptr;
@@ -791,6 +866,11 @@ air_status render_core(air_ctx* c, const air_grid* grid, const air_field* field,
   const bool timing = P.timing;
   // one wait for the result block (counters, per-view counts, fluxes),
   // which k_finish wrote to the pinned host buffer
+  if (spectrum) {
+    unsigned char* hs = static_cast<unsigned char*>(c->host_spec);
+    HIPCHK(c, hipMemcpyAsync(hs, c->spec_flag.p, 4, hipMemcpyDeviceToHost, s));
+    if (P.spec_flux) HIPCHK(c, hipMemcpyAsync(hs + 16, P.spec_flux, 8 * (size_t)V * nbins, hipMemcpyDeviceToHost, s));
+  }
   std::vector<uint8_t> depth_h;
   if (learned && ls) {
     depth_h.resize((size_t)V * N0 * N0);
@@ -800,6 +880,12 @@ air_status render_core(air_ctx* c, const air_grid* grid, const air_field* field,
   const unsigned long long* hc = c->host_vstat;  // the counters lead the result block
   const unsigned long long* hv = c->host_vstat + res_vstat_off();
   if (hc[CTR_OVERFLOW]) return fail(c, AIR_EDEVICE, "internal work queue overflow");
+  bool spec_overflow = false;
+  if (spectrum) {
+    const unsigned char* hs = static_cast<const unsigned char*>(c->host_spec);
+    spec_overflow = *reinterpret_cast<const unsigned*>(hs) != 0;
+    if (spectrum_flux) std::memcpy(spectrum_flux, hs + 16, 8 * (size_t)V * nbins);
+  }
   if (flux) std::memcpy(flux, c->host_vstat + res_flux_off(V), 8 * V * nb);
   if (stats) {
     std::memset(stats, 0, sizeof *stats);
@@ -866,6 +952,8 @@ air_status render_core(air_ctx* c, const air_grid* grid, const air_field* field,
       res = fail(c, AIR_ECAPACITY, "tree %d needs %lld nodes, capacity %lld", k, (long long)n,
                  (long long)trees[k].capacity);
   }
+  if (res == AIR_OK && spec_overflow)
+    res = fail(c, AIR_ECAPACITY, "traced rays exceed the trees' total capacity (spectra store)");
   return res;
 }
 
@@ -933,8 +1021,10 @@ void air_destroy(air_ctx* c) {
                     &c->ctr, &c->chunk, &c->cstat, &c->idmap, &c->partial, &c->flux, &c->views,
                     &c->touts, &c->pack, &c->nodepos, &c->lmax0, &c->feat, &c->cx0, &c->ca1, &c->ca2, &c->ca3, &c->cz,
                     &c->cdz, &c->cda, &c->cdb, &c->cdc, &c->cwpart, &c->closs_part, &c->closs, &c->depth8, &c->scount,
-                    &c->spec, &c->parts})
+                    &c->spec, &c->parts, &c->spec_tab, &c->spec_store, &c->spec_qpos, &c->spec_rows,
+                    &c->spec_flag, &c->spec_part, &c->spec_flux})
     if (b->p) (void)hipFree(b->p);
+  if (c->host_spec) (void)hipHostFree(c->host_spec);
   if (c->host_ctr) (void)hipHostFree(c->host_ctr);
   if (c->host_flux) (void)hipHostFree(c->host_flux);
   if (c->host_vstat) (void)hipHostFree(c->host_vstat);
@@ -977,6 +1067,29 @@ air_status air_render_learned(air_ctx* c, const air_grid* grid, const air_field*
   if (learn->max_depth < 0 || learn->flags != 0) return fail(c, AIR_EINVAL, "max_depth < 0 or flags != 0");
   return render_core(c, grid, field, views, n_views, prm, net, learn, trees, images, flux, stats, learn_stats,
                      stream, false);
+}
+
+air_status air_render_spectra(air_ctx* c, const air_grid* grid, const air_field* field, const air_view* views,
+                              int32_t n_views, const air_params* prm, const air_spectrum* spectrum, air_tree* trees,
+                              float* spectra, float* images, double* flux, air_stats* stats, void* stream) {
+  if (!c) return AIR_EINVAL;
+  c->err.clear();
+  if (!spectrum || spectrum->n_bins < 1 || spectrum->n_bins > AIR_MAX_BINS || !spectrum->bins || !spectrum->weight)
+    return fail(c, AIR_EINVAL, "spectrum: 1..%d bins with their table and weights", AIR_MAX_BINS);
+  for (int b = 0; b < spectrum->n_bins; ++b) {
+    const double* r = spectrum->bins + 5 * (size_t)b;
+    if (!std::isfinite(r[0]) || !std::isfinite(r[1]) || !std::isfinite(r[2]) || !std::isfinite(r[3]) ||
+        !std::isfinite(r[4]) || r[0] < 0 || r[2] < 0 || !std::isfinite(spectrum->weight[b]) || spectrum->weight[b] < 0)
+      return fail(c, AIR_EINVAL, "bin %d: parameters must be finite, k0, e0 and the weight >= 0", b);
+  }
+  if (!grid || grid->kind != AIR_GRID_UNIFORM)
+    return fail(c, grid ? AIR_ENOTSUP : AIR_EINVAL, "spectra are traced on uniform grids");
+  if (!field || field->kind != AIR_FIELD_RHO_T || !field->rho || !field->temp)
+    return fail(c, AIR_EINVAL, "spectra need a (rho, T) field");
+  if (!trees) return fail(c, AIR_EINVAL, "spectra need the trees");
+  if (prm && (prm->flags & AIR_FLAG_SUPERRES)) return fail(c, AIR_ENOTSUP, "no super-resolution with spectra");
+  return render_core(c, grid, field, views, n_views, prm, nullptr, nullptr, trees, images, flux, stats, nullptr,
+                     stream, false, spectrum, spectra);
 }
 
 air_status air_render_fixed(air_ctx* c, const air_grid* grid, const air_field* field, const air_view* views,

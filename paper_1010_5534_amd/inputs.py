@@ -69,7 +69,9 @@ class Grid:
 class Field:
     """Cell data.  kind 0: rho, emis, kappa (one band).  kind 1: rho, temp and
     bands [n_bands][3] = (kappa0, s, q) with kappa_b = kappa0 rho T^-s and
-    j_b = rho^2 T^q."""
+    j_b = rho^2 T^q.  kind 2 (spectral bins): rho, temp and bands
+    [n_bins][5] = (kappa0, s, e0, q, E) with kappa_b = kappa0 rho T^-s and
+    j_b = e0 rho^2 T^q exp(-E / T)."""
 
     kind: int
     rho: np.ndarray
@@ -245,6 +247,24 @@ def default_bands(n_bands: int = 8) -> np.ndarray:
     if n_bands == 4:
         return tab[[0, 2, 5, 7]]
     return tab[:n_bands]
+
+
+FIELD_SPECTRAL = 2
+
+
+def spectral_bins(n_bins: int, e_lo: float = 0.1, e_hi: float = 20.0, band=(1.0, 10.0)):
+    """A synthetic spectrum table standing in for the paper's MEKAL tables
+    (missing): n_bins log-spaced bin energies E in [e_lo, e_hi] (the field's
+    temperature units; the wind is at 1, the shocked shell at 10), opacity
+    kappa0 = 0.5 / (1 + E)^2 with s = 1.5, emission e0 = 1, q = -0.5 (a
+    thermal-bremsstrahlung-like shape), and broadband weights equal to the
+    bin widths for E in `band` (the analogue of the 1-10 keV band), else 0.
+    Returns (table [n_bins][5] float64, weights [n_bins] float32)."""
+    edges = np.geomspace(e_lo, e_hi, n_bins + 1)
+    E = np.sqrt(edges[:-1] * edges[1:])
+    tab = np.stack([0.5 / (1.0 + E) ** 2, np.full(n_bins, 1.5), np.ones(n_bins), np.full(n_bins, -0.5), E], axis=1)
+    w = np.where((E >= band[0]) & (E <= band[1]), np.diff(edges), 0.0).astype(np.float32)
+    return tab, w
 
 
 def winds2_views() -> List[View]:

@@ -118,12 +118,17 @@ def _stencils_of(tree, L, which, positions):
 
 
 def check(gtree, grid, field, view, N0, Lmax, xc_I, xc_N=2.0, band_w=None, image=None, flux=None, own=False,
-          label="", superres=False):
+          label="", superres=False, ref=None, own_band_w=None):
     """Compare one GPU tree (air.Tree of `view`) with the oracle.  image:
     the view's raster [nb + 1, R, R] (device or host), painted from the leaves
     or, with superres, interpolated (oracle.superres); flux: its [nb] fluxes.
+    ref: the oracle's values at the GPU's nodes (I [nb, n], N [n], in the
+    tree's node order) when they are computed elsewhere (spectra: the
+    broadband of the oracle's bins); else the oracle traces them here.
+    own_band_w: the band weights of the oracle's own run when they differ
+    from band_w (with ref, the bins' broadband weights).
     Returns a report; assert_parity() applies the bar."""
-    nb = field.n_bands
+    nb = field.n_bands if ref is None else np.asarray(ref["I"]).shape[0]
     g = gpu_dense(gtree, N0, Lmax, nb)
     rep = dict(label=label, nodes_gpu=int(gtree.n_nodes), structure_mismatch=0, max_rel_I=0.0, max_rel_N=0.0,
                flips=0, set1=[], set2=[], set3=[], xi_arith_fail=0, max_xi_gpu_err=0.0, ambiguous_band=0,
@@ -131,7 +136,8 @@ def check(gtree, grid, field, view, N0, Lmax, xc_I, xc_N=2.0, band_w=None, image
     flags = _flat([(s & oracle.FLAGGED) > 0 for s in g["state"]]).astype(np.uint8)
     # 2. oracle values at every GPU node
     lv, ix, iy = g["nodes"]
-    ref = oracle.trace_pixels(grid, field, view, N0, lv, ix, iy)
+    if ref is None:
+        ref = oracle.trace_pixels(grid, field, view, N0, lv, ix, iy)
     rI = rel_err(g["node_I"], ref["I"])
     rN = rel_err(g["node_N"], ref["N"])
     rep["max_rel_I"] = float(rI.max()) if rI.size else 0.0
@@ -219,7 +225,7 @@ def check(gtree, grid, field, view, N0, Lmax, xc_I, xc_N=2.0, band_w=None, image
         rep["rel_flux"] = worst
     # 5. the oracle's own tree
     if own:
-        t = oracle.air(grid, field, view, N0, Lmax, xc_I, xc_N, band_w=band_w)
+        t = oracle.air(grid, field, view, N0, Lmax, xc_I, xc_N, band_w=band_w if own_band_w is None else own_band_w)
         rep["nodes_oracle_own"] = t.nodes
         rep["own_structure_diff"] = int(sum(((t.state[L] & BIT_MASK) != (g["state"][L] & BIT_MASK)).sum()
                                             for L in range(Lmax + 1)))
