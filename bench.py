@@ -179,6 +179,31 @@ def xi_sweep(ctx, air, scene, views, flux_fixed, np, torch, args):
     return rows
 
 
+def spectra_run(ctx, air, inputs, np, torch, g, f, views, args):
+    """Per-pixel spectra: the benchmark's field and views with a 256-bin
+    synthetic thermal spectrum (inputs.spectral_bins), refined on the 1-10
+    band; trees, every node's spectrum, the broadband raster and the images'
+    spectra in one call.  Time = median device time per call."""
+    log("spectra: 256 bins")
+    table, w = inputs.spectral_bins(256)
+    scene = air.upload(g, f)
+    prm = air.params(N0, LMAX, XI_CRIT)
+    ms = []
+    out = ctx.render_spectra(scene, views, prm, table, w)
+    for _ in range(max(3, args.steps // 3)):
+        out = ctx.render_spectra(scene, views, prm, table, w, capacity=out[0][0].n_nodes + 65536)
+        ms.append(out[4]["ms_total"])
+    torch.cuda.synchronize()
+    ms.sort()
+    t = ms[len(ms) // 2]
+    st = out[4]
+    return dict(workload=f"winds2 {NGRID}^3 (rho, T) seed {SEED}, 256 spectral bins, 3 views, {N0}^2 coarse, "
+                         f"{LMAX} levels, refined on the 1-10 broadband",
+                bins=256, rays=st["rays"], visits=st["visits"], ms_device=t, per_image_ms=t / len(views),
+                bin_visits_per_s=256 * st["visits"] / (t * 1e-3), rays_per_s=st["rays"] / (t * 1e-3),
+                spectra_bytes=int(st["rays"]) * 256 * 4)
+
+
 def hbm_probe(torch):
     """Measured device-to-device copy bandwidth (read + write bytes per
     second) of a 1 GiB buffer, best of 5, beside the vendor's 8 TB/s."""
@@ -288,6 +313,7 @@ def main():
     ap.add_argument("--skip-amr", action="store_true")
     ap.add_argument("--skip-large", action="store_true")
     ap.add_argument("--skip-ring", action="store_true")
+    ap.add_argument("--skip-spectra", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the timed region, one 256 MiB device copy whose counters calibrate HBM bytes")
     args = ap.parse_args()
@@ -418,6 +444,8 @@ def main():
 
     if not args.skip_ring:
         res["ring"] = ring_experiment(ctx, air, inputs, np, torch, args)
+    if not args.skip_spectra:
+        res["spectra"] = spectra_run(ctx, air, inputs, np, torch, g, f, views, args)
     if not args.skip_amr:
         res["batched_amr"] = batched_amr(ctx, air, inputs, np, torch, args)
     if not args.skip_large:

@@ -288,7 +288,7 @@ def test_argument_errors(ctx, gauss):
             ctx.render(scene, [view], prm, want_tree=False, want_image=False, want_flux=False)
         assert e.value.code == air.AIR_EINVAL
     prm = air.params(8, 2)
-    prm.flags = 2  # unknown bit
+    prm.flags = 4  # unknown bit
     with pytest.raises(air.AirError):
         ctx.render(scene, [v], prm, want_tree=False, want_image=False, want_flux=False)
 
