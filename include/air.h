@@ -120,7 +120,7 @@ typedef struct {
  * between the kernels on the stream and lengthen the call a little. */
 #define AIR_FLAG_TIMING 1u
 /* air_params.flags: the images hold the super-resolved raster (section 2
- * step vi: interpolation between adjacent pixels of differing resolution)
+ * step vi: interpolation across neighbouring pixels of different levels)
  * instead of the painted leaves: each pixel of the finest raster, inside a
  * level-L leaf, is the bilinear interpolation at its centre of the level-L
  * samples around it (a level-L node's value, or where none exists the value

@@ -649,7 +649,7 @@ void orc_paint_leaves(int N0, int Lmax, const uint8_t* state, const double* vals
 }
 
 /* Super-resolution output (section 2 step vi suggests interpolating between
- * adjacent pixels of differing resolution; the cited method is not given, so
+ * neighbouring pixels whose levels differ; the cited method is not given, so
  * this is the reading stated in the design notes): every pixel of the finest
  * raster lying in a level-L leaf takes the bilinear interpolation, at its
  * centre, of the level-L point samples around it.  A level-L sample at

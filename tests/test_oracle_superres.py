@@ -1,6 +1,6 @@
 """Pins of the oracle's super-resolution output (section 2 step vi: the
-final image may interpolate between adjacent pixels of differing
-resolution; reading: bilinear interpolation of the leaf level's point
+final image may be sharpened by interpolating across neighbouring pixels
+whose levels differ; reading: bilinear interpolation of the leaf level's point
 samples, a missing sample taken from the covering node one level up, edges
 clamped).  Pinned by hand values on small forced trees, by the limits (a
 fully refined tree gives the painted image; an unrefined tree with affine
