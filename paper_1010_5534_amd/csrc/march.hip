@@ -428,16 +428,20 @@ __device__ void march_amr_interval(const Geo& g, const Fld& f, const double o[3]
     for (int a = 0; a < 3; ++a) F[a] = fine_at(g, o, d, a, t, true);
     int b = (((F[2] >> mL) >> lbs) * g.n[1] + ((F[1] >> mL) >> lbs)) * g.n[0] + ((F[0] >> mL) >> lbs);
     int l = 0;
+    // descent through the child table: a child's coordinate is twice its
+    // parent's plus its offset bit (the tables were checked for it), so the
+    // offset at level l is the low bit of the point's level-l block
+    // coordinate and no coordinate has to be read
     for (int ch = g.bchild[b]; ch >= 0 && l < mL; ch = g.bchild[b]) {
       ++l;
       int off = 0;
 #pragma unroll
-      for (int a = 0; a < 3; ++a) off |= (((F[a] >> (mL - l)) >> lbs) - 2 * g.bcoord[3 * b + a]) << a;
+      for (int a = 0; a < 3; ++a) off |= (((F[a] >> (mL - l)) >> lbs) & 1) << a;
       b = min(ch + off, g.n_blocks - 1);  // the host checked the tables; this only bounds the reads
     }
     int bc[3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) bc[a] = g.bcoord[3 * b + a];
+    for (int a = 0; a < 3; ++a) bc[a] = (F[a] >> (mL - l)) >> lbs;
     const double scale = 1.0 / (double)(1 << l);
     double t_exit = __builtin_huge_val();
 #pragma unroll
