@@ -126,7 +126,8 @@ def device_median(fn, reps, torch):
     ms = []
     for _ in range(reps):
         out = fn()
-        ms.append(out[-1]["ms_total"] if isinstance(out[-1], dict) else out[3]["ms_total"])
+        # render calls return (trees, images, flux, stats[, learn stats]); render_fixed (images, flux, stats)
+        ms.append((out[3] if len(out) >= 4 else out[-1])["ms_total"])
     torch.cuda.synchronize()
     ms.sort()
     return out, ms[len(ms) // 2]
@@ -202,6 +203,56 @@ def spectra_run(ctx, air, inputs, np, torch, g, f, views, args):
                 bins=256, rays=st["rays"], visits=st["visits"], ms_device=t, per_image_ms=t / len(views),
                 bin_visits_per_s=256 * st["visits"] / (t * 1e-3), rays_per_s=st["rays"] / (t * 1e-3),
                 spectra_bytes=int(st["rays"]) * 256 * 4)
+
+
+def learned_eval(ctx, air, inputs, np, torch, args, seeds=range(2001, 2009)):
+    """The learned proposal on held-out seeds (the network was trained on
+    seeds 1..2000): per seed, the two-wind 256^3 field and seeded isotropic
+    view of the training set, 64^2 coarse, 5 levels; median device time per
+    image of plain AIR, the learned proposal (committed network and cost
+    model), speculation to a constant depth 1 or 2, and speculation to the
+    true depths (the deepest level of each coarse pixel in the plain tree: the
+    best any depth proposal can do).  Every proposal's output is checked equal
+    to plain AIR's."""
+    log("learned proposal: held-out seeds")
+    wpath = os.path.join(ROOT, "paper_1010_5534_amd", "weights", "depth_cnn.npz")
+    wz = np.load(wpath)
+    net = air.Network(ctx, wz["params"], wz["mean"], wz["scale"])
+    c_ray, c_sweep = float(wz["c_ray"]), float(wz["c_sweep"])
+    prm = air.params(N0, LMAX, XI_CRIT)
+    reps = 5
+    tot = dict(plain=0.0, learned=0.0, depth1=0.0, depth2=0.0, true_depth=0.0)
+    rays = dict(plain=0, learned=0, depth1=0, depth2=0, true_depth=0)
+    missing = dict(learned=0, depth1=0, depth2=0, true_depth=0)
+    equal = True
+    for seed in seeds:
+        src, etas, view = inputs.training_scene(seed)
+        rho, temp = inputs.winds_field_torch(src, etas, NGRID, "cuda")
+        scene = ctx.prepare(air.scene_from_tensors(NGRID, rho, temp, [[1.0, 1.5, 0.5]]))
+        runs = {"plain": lambda: ctx.render(scene, [view], prm, reuse=True),
+                "learned": lambda: ctx.render_learned(scene, [view], prm, net, c_ray, c_sweep, reuse=True)}
+        ref = ctx.render(scene, [view], prm, reuse=False)
+        true = ctx.tree_depth(ref[0][0], N0).to(torch.uint8)[None]
+        for name, d in (("depth1", torch.full_like(true, 1)), ("depth2", torch.full_like(true, 2)),
+                        ("true_depth", true)):
+            runs[name] = (lambda dd: (lambda: ctx.render_proposal(scene, [view], prm, dd, reuse=True)))(d)
+        for name, fn in runs.items():
+            out, ms = device_median(fn, reps, torch)
+            tot[name] += ms
+            st = out[3]
+            rays[name] += st["rays"] + (out[4]["wasted"] if len(out) > 4 else 0)
+            if len(out) > 4:
+                missing[name] += out[4]["missing"]
+            equal = equal and bool(torch.equal(out[1].view(torch.int32), ref[1].view(torch.int32))
+                                   and np.array_equal(out[2], ref[2]))
+        del scene, rho, temp
+    n = len(seeds)
+    net.close()
+    return dict(workload=f"winds2 {NGRID}^3 seeds {seeds[0]}..{seeds[-1]} (held out), isotropic views, "
+                         f"{N0}^2 coarse, {LMAX} levels, xi_crit {XI_CRIT}",
+                per_image_ms={k: v / n for k, v in tot.items()},
+                speedup_vs_plain={k: tot["plain"] / v for k, v in tot.items()},
+                rays_traced=rays, missing=missing, outputs_equal_to_plain=equal, c_ray=c_ray, c_sweep=c_sweep)
 
 
 def hbm_probe(torch):
@@ -446,6 +497,8 @@ def main():
         res["ring"] = ring_experiment(ctx, air, inputs, np, torch, args)
     if not args.skip_spectra:
         res["spectra"] = spectra_run(ctx, air, inputs, np, torch, g, f, views, args)
+    if not args.skip_learned:
+        res["learned_eval"] = learned_eval(ctx, air, inputs, np, torch, args)
     if not args.skip_amr:
         res["batched_amr"] = batched_amr(ctx, air, inputs, np, torch, args)
     if not args.skip_large:

@@ -454,6 +454,22 @@ air_status air_render_learned(air_ctx* ctx, const air_grid* grid, const air_fiel
                               const air_learn_params* learn, air_tree* trees, float* images, double* flux,
                               air_stats* stats, air_learn_stats* learn_stats, void* stream);
 
+/*
+ * air_render with a given speculation depth per coarse pixel in place of the
+ * network's choice: the baselines the learned proposal is measured against
+ * (a constant depth, or the true depths of a finished tree from
+ * air_tree_depth).  depth: device uint8 [n_views][coarse_n][coarse_n] in
+ * raster order, each clamped to min(max_depth, params.max_level, 5); the
+ * nodes of each coarse pixel's subtree down to that depth are traced in one
+ * speculative march before the level loop.  Outputs equal air_render's bit
+ * for bit; learn_stats (may be NULL) counts speculative, wasted and missing
+ * rays.  Errors as air_render.
+ */
+air_status air_render_proposal(air_ctx* ctx, const air_grid* grid, const air_field* field, const air_view* views,
+                               int32_t n_views, const air_params* params, const uint8_t* depth, int32_t max_depth,
+                               air_tree* trees, float* images, double* flux, air_stats* stats,
+                               air_learn_stats* learn_stats, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

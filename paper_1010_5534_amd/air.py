@@ -23,7 +23,7 @@ EXPORTS = ("air_create", "air_destroy", "air_last_error", "air_render", "air_ren
            "air_field_packed_bytes", "air_field_pack", "air_cnn_create", "air_cnn_destroy", "air_cnn_set",
            "air_cnn_get", "air_features", "air_cnn_forward", "air_cnn_loss_grad", "air_cnn_adam", "air_tree_depth",
            "air_render_learned", "air_render_batch", "air_cnn_tensor", "air_render_fixed_noalloc",
-           "air_render_spectra")
+           "air_render_spectra", "air_render_proposal")
 CNN_FEATURES, CNN_CLASSES, CNN_PARAMS = 4, 6, 21414
 
 
@@ -108,6 +108,8 @@ def lib():
         L.air_render_fixed_noalloc.restype = C.c_int32
         L.air_render_spectra.argtypes = [vp, vp, vp, vp, C.c_int32, vp, vp, vp, vp, vp, vp, vp, vp]
         L.air_render_spectra.restype = C.c_int32
+        L.air_render_proposal.argtypes = [vp, vp, vp, vp, C.c_int32, vp, vp, C.c_int32, vp, vp, vp, vp, vp, vp]
+        L.air_render_proposal.restype = C.c_int32
         L.air_trace_pixels.argtypes = [vp, vp, vp, vp, C.c_int32, C.c_int64, vp, vp, vp, vp, vp, vp, vp]
         L.air_trace_pixels.restype = C.c_int32
         L.air_field_packed_bytes.argtypes = [vp, vp]
@@ -358,6 +360,20 @@ class Context:
         return out + (dict(spec_rays=ls.spec_rays, wasted=ls.wasted, missing=ls.missing,
                            depth_hist=list(ls.depth_hist)[:6], ms_features=ls.ms_features, ms_spec=ls.ms_spec),)
 
+    def render_proposal(self, scene: DeviceScene, views: Sequence, prm: air_params, depth, max_depth: int = 5,
+                        want_tree=True, want_image=True, want_flux=True, capacity: Optional[int] = None,
+                        reuse: bool = False):
+        """air_render_proposal: speculation to the given depth per coarse
+        pixel (device uint8 [V, N0, N0]) in place of the network's choice.
+        Returns (trees, images, flux, stats, learn_stats); outputs equal
+        render()'s."""
+        depth = depth.contiguous()
+        ls = air_learn_stats()
+        out = self._render(scene, views, prm, want_tree, want_image, want_flux, capacity, reuse,
+                           ("proposal", depth, max_depth), ls)
+        return out + (dict(spec_rays=ls.spec_rays, wasted=ls.wasted, missing=ls.missing,
+                           depth_hist=list(ls.depth_hist)[:6], ms_features=ls.ms_features, ms_spec=ls.ms_spec),)
+
     def _view_array(self, views) -> C.Array:
         # the last conversion is kept: repeated calls with the same view
         # values skip building the ctypes array
@@ -417,7 +433,11 @@ class Context:
         while True:
             targs = (C.addressof(trees) if want_tree else None, images.data_ptr() if want_image else None,
                      flux.ctypes.data if want_flux else None, C.addressof(st))
-            if learned is None or learned == "batch":
+            if isinstance(learned, tuple) and learned[0] == "proposal":
+                rc = lib().air_render_proposal(self._p, C.addressof(scene.grid), C.addressof(scene.field),
+                                               C.addressof(vs), V, C.addressof(prm), learned[1].data_ptr(),
+                                               learned[2], *targs, C.addressof(ls), self._stream())
+            elif learned is None or learned == "batch":
                 fn = lib().air_render if learned is None else lib().air_render_batch
                 rc = fn(self._p, C.addressof(scene.grid), C.addressof(scene.field), C.addressof(vs),
                         V, C.addressof(prm), *targs, self._stream())

@@ -222,6 +222,11 @@ struct FeatNorm {
 hipError_t launch_features_bf16(const MarchArgs& a, const LearnW& w, const FeatNorm& nm, uint16_t* x0, hipStream_t s);
 hipError_t launch_spec_emit(const uint8_t* depth, const unsigned long long* offsets, int64_t total, int64_t n0sq,
                             uint64_t* spec, hipStream_t s);
+// a given speculation depth per coarse pixel instead of the network's choice:
+// depth bytes, per-pixel work-list offsets and the list length (*spec_total
+// must hold 0 before the launch)
+hipError_t launch_spec_reserve(const uint8_t* given, int dmax, int64_t total, uint8_t* depth,
+                               unsigned long long* off, unsigned long long* spec_total, hipStream_t s);
 hipError_t launch_tree_depth(const int8_t* level, const int32_t* ix, const int32_t* iy, int64_t n, int N0,
                              int* depth, hipStream_t s);
 hipError_t launch_refine(const MarchArgs& a, int L, float xcI, float xcN, const float* w, int grid_blocks,

@@ -563,26 +563,31 @@ air_status ensure_learned(air_ctx* c, const MarchArgs& A) {
 // the learned steps after the coarse march: feature maps, network, depth
 // choice, work list, speculative march
 air_status learned_steps(air_ctx* c, const MarchArgs& A, const air_cnn* net, const air_learn_params* lp,
-                         const float* w, bool timing, const Tune& tune, hipStream_t s) {
+                         const uint8_t* given_depth, const float* w, bool timing, const Tune& tune, hipStream_t s) {
   const int V = A.img.V, N0 = A.img.N0;
   const int64_t total = (int64_t)V * N0 * N0;
-  LearnW W;
-  for (int b = 0; b < MAXB; ++b) W.w[b] = w[b];
   if (timing) HIPCHK(c, hipEventRecord(c->ev[air_ctx::EV_FEAT0], s));
-  FeatNorm nm;
-  for (int k = 0; k < 4; ++k) {
-    nm.mean[k] = net->net.mean[k];
-    nm.inv_std[k] = 1.0f / net->net.stdv[k];
-  }
-  HIPCHK(c, launch_features_bf16(A, W, nm, (uint16_t*)c->cx0.p, s));
   const int dmax = std::min(lp->max_depth, std::min(A.img.Lmax, DEPTH_CLASSES - 1));
   unsigned long long* cnt = (unsigned long long*)c->scount.p;
-  // the four layers and the depth choice in one launch
   // the work list's length is counted in a device counter (cleared by the
   // render's init launch)
   unsigned long long* spec_n = A.w.ctr + CTR_SPEC;
-  HIPCHK(c, cnn::infer_depth(net->net, (const uint16_t*)c->cx0.p, V, N0, N0, dmax, lp->c_ray, lp->c_sweep,
-                             (uint8_t*)c->depth8.p, cnt, spec_n, s));
+  if (given_depth) {
+    // the caller's depths instead of the network's choice
+    HIPCHK(c, launch_spec_reserve(given_depth, dmax, total, (uint8_t*)c->depth8.p, cnt, spec_n, s));
+  } else {
+    LearnW W;
+    for (int b = 0; b < MAXB; ++b) W.w[b] = w[b];
+    FeatNorm nm;
+    for (int k = 0; k < 4; ++k) {
+      nm.mean[k] = net->net.mean[k];
+      nm.inv_std[k] = 1.0f / net->net.stdv[k];
+    }
+    HIPCHK(c, launch_features_bf16(A, W, nm, (uint16_t*)c->cx0.p, s));
+    // the four layers and the depth choice in one launch
+    HIPCHK(c, cnn::infer_depth(net->net, (const uint16_t*)c->cx0.p, V, N0, N0, dmax, lp->c_ray, lp->c_sweep,
+                               (uint8_t*)c->depth8.p, cnt, spec_n, s));
+  }
   HIPCHK(c, launch_spec_emit((const uint8_t*)c->depth8.p, cnt, total, (int64_t)N0 * N0, (uint64_t*)c->spec.p, s));
   if (timing) HIPCHK(c, hipEventRecord(c->ev[air_ctx::EV_SPEC0], s));
   HIPCHK(c, launch_march_spec(A, (const uint64_t*)c->spec.p, spec_n,
@@ -598,6 +603,7 @@ struct Plan {
   int64_t n_chunks = 0;
   float xcI = 0, xcN = 0, w[MAXB] = {};
   const air_cnn* net = nullptr;
+  const uint8_t* depth_in = nullptr;  // given speculation depths (air_render_proposal)
   air_learn_params lp{};
   bool trees = false, flux = false, timing = false, superres = false;
   float* images = nullptr;
@@ -629,8 +635,8 @@ air_status enqueue_render(air_ctx* c, const Plan& P, const Tune& tune, hipStream
     else
       HIPCHK(c, launch_march_queue(A, L, march_blocks(c, A.g.seg_shift, tune.march_waves_per_cu), s));
     if (P.timing) HIPCHK(c, hipEventRecord(ev[3 + 4 * L], s));
-    if (P.net && L == 0) {
-      if ((st = learned_steps(c, A, P.net, &P.lp, P.w, P.timing, tune, s))) return st;
+    if ((P.net || P.depth_in) && L == 0) {
+      if ((st = learned_steps(c, A, P.net, &P.lp, P.depth_in, P.w, P.timing, tune, s))) return st;
       if (P.timing) HIPCHK(c, hipEventRecord(ev[3 + 4 * L], s));  // the test timing starts after the learned steps
     }
     if (L < Lm) HIPCHK(c, launch_refine(A, L, P.xcI, P.xcN, P.w, c->num_cus * tune.refine_blocks_per_cu, s));
@@ -661,6 +667,7 @@ std::string plan_key(const air_ctx* c, const Plan& P, const Tune& t) {
   k.append(reinterpret_cast<const char*>(&P.n_chunks), sizeof P.n_chunks);
   k.append(reinterpret_cast<const char*>(&P.xcI), sizeof(float) * (2 + MAXB));
   k.append(reinterpret_cast<const char*>(&P.net), sizeof P.net);
+  k.append(reinterpret_cast<const char*>(&P.depth_in), sizeof P.depth_in);
   if (P.net) {  // the standardisation is a kernel argument of the captured sequence
     k.append(reinterpret_cast<const char*>(P.net->net.mean), sizeof P.net->net.mean);
     k.append(reinterpret_cast<const char*>(P.net->net.stdv), sizeof P.net->net.stdv);
@@ -679,7 +686,7 @@ std::string shape_key(const Plan& P) {
   char b[256];
   snprintf(b, sizeof b, "%d/%d,%d,%d/%d,%d/%d/%d/%d/%d", P.A.g.kind, P.A.g.n[0], P.A.g.n[1], P.A.g.n[2],
            P.A.g.bs, P.A.g.max_level, P.A.img.V, P.A.img.N0, P.A.img.Lmax, P.A.f.nb);
-  return std::string(b) + (P.net ? "/learned" : "/plain");
+  return std::string(b) + (P.net ? "/learned" : P.depth_in ? "/proposal" : "/plain");
 }
 
 // pick the launch shapes by timing the whole render once per candidate
@@ -718,7 +725,8 @@ air_status autotune(air_ctx* c, const Plan& P, hipStream_t s, Tune& best) {
 air_status render_core(air_ctx* c, const air_grid* grid, const air_field* field, const air_view* views,
                        int32_t n_views, const air_params* prm, const air_cnn* net, const air_learn_params* lp,
                        air_tree* trees, float* images, double* flux, air_stats* stats, air_learn_stats* ls,
-                       void* stream, bool batch, const air_spectrum* spectrum = nullptr, float* spectra = nullptr) {
+                       void* stream, bool batch, const air_spectrum* spectrum = nullptr, float* spectra = nullptr,
+                       const uint8_t* given_depth = nullptr) {
   if (!c) return AIR_EINVAL;
   c->err.clear();
   air_status st;
@@ -737,10 +745,10 @@ air_status render_core(air_ctx* c, const air_grid* grid, const air_field* field,
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, AIR_EDEVICE, "hipSetDevice failed");
   hipStream_t s = (hipStream_t)stream;
   if ((st = check_blocks(c, grid, s, field->packed))) return st;
-  const bool learned = net != nullptr;
+  const bool learned = net != nullptr || given_depth != nullptr;
   const int N0 = prm->coarse_n, Lm = prm->max_level, V = n_views;
   Plan P;
-  if ((st = setup_render(c, grid, field, views, V, N0, Lm, learned, s, P.A, P.n_chunks, !spectrum))) return st;
+  if ((st = setup_render(c, grid, field, views, V, N0, Lm, net != nullptr, s, P.A, P.n_chunks, !spectrum))) return st;
   const MarchArgs& A = P.A;
   const int nb = A.f.nb;
   P.A.w.skip_spec = learned ? 1 : 0;
@@ -793,6 +801,7 @@ air_status render_core(air_ctx* c, const air_grid* grid, const air_field* field,
     flux = nullptr;  // the broadband flux of the result block is not asked for
   }
   P.net = net;
+  P.depth_in = given_depth;
   if (lp) P.lp = *lp;
   P.trees = trees != nullptr;
   P.flux = flux != nullptr;
@@ -1090,6 +1099,20 @@ air_status air_render_spectra(air_ctx* c, const air_grid* grid, const air_field*
   if (prm && (prm->flags & AIR_FLAG_SUPERRES)) return fail(c, AIR_ENOTSUP, "no super-resolution with spectra");
   return render_core(c, grid, field, views, n_views, prm, nullptr, nullptr, trees, images, flux, stats, nullptr,
                      stream, false, spectrum, spectra);
+}
+
+air_status air_render_proposal(air_ctx* c, const air_grid* grid, const air_field* field, const air_view* views,
+                               int32_t n_views, const air_params* prm, const uint8_t* depth, int32_t max_depth,
+                               air_tree* trees, float* images, double* flux, air_stats* stats,
+                               air_learn_stats* learn_stats, void* stream) {
+  if (!c) return AIR_EINVAL;
+  c->err.clear();
+  if (!depth) return fail(c, AIR_EINVAL, "depth is NULL");
+  if (max_depth < 0) return fail(c, AIR_EINVAL, "max_depth < 0");
+  air_learn_params lp{};
+  lp.max_depth = max_depth;
+  return render_core(c, grid, field, views, n_views, prm, nullptr, &lp, trees, images, flux, stats, learn_stats,
+                     stream, false, nullptr, nullptr, depth);
 }
 
 air_status air_render_fixed(air_ctx* c, const air_grid* grid, const air_field* field, const air_view* views,

@@ -71,6 +71,39 @@ __global__ __launch_bounds__(256) void k_spec_emit(const uint8_t* depth, const u
   }
 }
 
+// a given speculation depth per coarse pixel (clamped to dmax): its depth
+// byte and the start of its speculative rays in the work list, a block's
+// range reserved with one atomic on the list's length (the order of the
+// ranges changes no traced value)
+__global__ __launch_bounds__(256) void k_spec_reserve(const uint8_t* given, int dmax, int64_t total, uint8_t* depth,
+                                                      unsigned long long* off, unsigned long long* spec_total) {
+  __shared__ unsigned long long wsum[4];
+  __shared__ unsigned long long base;
+  const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+  for (int64_t b0 = (int64_t)blockIdx.x * blockDim.x; b0 < total; b0 += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t e = b0 + threadIdx.x;
+    int d = 0;
+    if (e < total) d = min((int)given[e], dmax);
+    const unsigned long long mine = e < total ? cnn::subtree_rays(d) : 0ull;
+    unsigned long long x = mine;  // inclusive prefix in the wave
+    for (int o = 1; o < WAVE; o <<= 1) {
+      const unsigned long long y = __shfl_up(x, o);
+      if (lane >= o) x += y;
+    }
+    if (lane == WAVE - 1) wsum[w] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) base = atomicAdd(spec_total, wsum[0] + wsum[1] + wsum[2] + wsum[3]);
+    __syncthreads();
+    unsigned long long before = base + x - mine;
+    for (int q = 0; q < w; ++q) before += wsum[q];
+    if (e < total) {
+      depth[e] = (uint8_t)d;
+      off[e] = before;
+    }
+    __syncthreads();  // wsum and base are rewritten by the next round
+  }
+}
+
 // deepest level of a finished tree inside each coarse pixel
 __global__ __launch_bounds__(256) void k_tree_depth(const int8_t* level, const int32_t* ix, const int32_t* iy,
                                                     int64_t n, int N0, int* depth) {
@@ -100,6 +133,12 @@ hipError_t launch_spec_emit(const uint8_t* depth, const unsigned long long* offs
                             uint64_t* spec, hipStream_t s) {
   const int blocks = (int)std::min<int64_t>((total + 3) / 4, 8192);  // 4 waves per block
   hipLaunchKernelGGL(k_spec_emit, dim3(std::max(blocks, 1)), dim3(256), 0, s, depth, offsets, total, n0sq, spec);
+  return hipGetLastError();
+}
+
+hipError_t launch_spec_reserve(const uint8_t* given, int dmax, int64_t total, uint8_t* depth,
+                               unsigned long long* off, unsigned long long* spec_total, hipStream_t s) {
+  hipLaunchKernelGGL(k_spec_reserve, dim3(grid_for(total)), dim3(256), 0, s, given, dmax, total, depth, off, spec_total);
   return hipGetLastError();
 }
 

@@ -358,3 +358,32 @@ def test_learned_argument_errors(ctx):
     with pytest.raises(air.AirError):
         net.set(np.zeros(air.CNN_PARAMS, np.float32), scale=np.zeros(4, np.float32))
     net.close()
+
+
+# ----------------------------------------------- proposal baselines (config 4)
+def test_proposal_baselines_equal_plain(ctx):
+    """Speculation to a given depth (air_render_proposal): constant depths
+    0, 1, 2 and the deepest possible, and the true depths of the plain tree,
+    all give air_render's outputs bit for bit; the counters follow from the
+    depths (with the true depths no tree node is left for the level loop)."""
+    from paper_1010_5534_amd import air
+    g, f = inputs.winds2(seed=6, n=64)
+    scene = ctx.prepare(air.upload(g, f))
+    views = [inputs.view_for((0.3, 0.5, 0.8)), inputs.view_for((0, 1, 0))]
+    N0, Lm = 16, 4
+    prm = air.params(N0, Lm, 0.5)
+    plain = ctx.render(scene, views, prm)
+    V = len(views)
+    for d in (0, 1, 2, 7):
+        depth = torch.full((V, N0, N0), d, dtype=torch.uint8, device="cuda")
+        out = ctx.render_proposal(scene, views, prm, depth)
+        _assert_same(plain, out)
+        dd = min(d, Lm)
+        assert out[4]["spec_rays"] == V * N0 * N0 * sum(4 ** l for l in range(1, dd + 1))
+        assert out[4]["depth_hist"][dd] == V * N0 * N0
+    true = torch.stack([ctx.tree_depth(t, N0) for t in plain[0]]).to(torch.uint8)
+    out = ctx.render_proposal(scene, views, prm, true)
+    _assert_same(plain, out)
+    say(out[4])
+    assert out[4]["missing"] == 0
+    assert out[4]["spec_rays"] - out[4]["wasted"] == sum(t.n_nodes for t in plain[0]) - V * N0 * N0
