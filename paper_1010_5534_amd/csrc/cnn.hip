@@ -8,12 +8,13 @@
 //   y[p, o] = bias[o] + sum_{ky, kx, c} x[p shifted by (ky-1, kx-1), c] W[o, ky, kx, c]
 // is the product D = A B with A = W as a [rows][K] matrix (K = 9 taps x
 // stored input channels, padded to 32) and B[k][p] = the shifted input; one
-// wave computes a 16-pixel column block for every output row, holding all of
-// A in registers, and each lane gathers its pixel's 8 consecutive channels
-// of one tap with a single 16-byte load.  The input gradient is the same
-// product with the flipped, transposed weights; the weight gradient stages a
-// 32-pixel chunk of both operands transposed in LDS and reduces over pixels
-// into per-block partials that one more kernel sums in a fixed order.
+// wave computes 16-pixel column blocks for every output row, four per pass,
+// holding all of A in registers, and each lane gathers its pixel's 8
+// consecutive channels of one tap with a single 16-byte load.  The input
+// gradient is the same product with the flipped, transposed weights; the
+// weight gradient stages 64-pixel chunks of both operands transposed in LDS
+// and reduces over pixels into per-block partials that one more kernel sums
+// in a fixed order.
 #include <algorithm>
 #include <cmath>
 
@@ -103,7 +104,13 @@ __global__ __launch_bounds__(256) void k_input(const float* feat, int64_t P, Nor
 enum { MODE_HIDDEN = 0, MODE_LOGITS = 1, MODE_MASK = 2 };
 
 // D[rows][pixels] = A[rows][K] B[K][pixels]; CS = stored input channels,
-// CSO = stored output channels, NBIAS = real output channels (bias length)
+// CSO = stored output channels, NBIAS = real output channels (bias length).
+// A wave keeps all of A in registers and takes CONV_TPW 16-pixel tiles per
+// pass (their gathers issued together), so the weights are read once per
+// wave rather than once per tile.
+constexpr int CONV_TPW = 4;
+constexpr int CONV_MAX_BLOCKS = 1024;
+
 template <int CS, int RW, int CSO, int MODE>
 __global__ __launch_bounds__(256) void k_conv(const uint16_t* __restrict__ wmat, const float* __restrict__ bias,
                                               int nbias, const uint16_t* __restrict__ x,
@@ -117,60 +124,71 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t* __restrict__ wmat,
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks)
       a[mb][ks] = *reinterpret_cast<const u16x8*>(wmat + (mb * 16 + c16) * KP + ks * 32 + 8 * g);
-  const int64_t P = (int64_t)n * h * w, tiles = (P + 15) / 16;
-  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / WAVE;
-  for (int64_t t = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE; t < tiles; t += nwaves) {
-    const int64_t p = t * 16 + c16;
-    const bool ok = p < P;
-    int xx = 0, y = 0;
-    int64_t b = 0;
-    if (ok) {
-      xx = (int)(p % w);
-      y = (int)((p / w) % h);
-      b = p / ((int64_t)w * h);
-    }
-    f32x4 acc[MB];
+  const int P = n * h * w, tiles = (P + 15) / 16;  // P < 2^25, checked by the caller
+  const int nwaves = (gridDim.x * blockDim.x) / WAVE;
+  for (int t0 = ((blockIdx.x * blockDim.x + threadIdx.x) / WAVE) * CONV_TPW; t0 < tiles; t0 += nwaves * CONV_TPW) {
+    int p[CONV_TPW], xx[CONV_TPW], y[CONV_TPW], base[CONV_TPW];
+    bool ok[CONV_TPW];
 #pragma unroll
-    for (int mb = 0; mb < MB; ++mb) acc[mb] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int u = 0; u < CONV_TPW; ++u) {
+      p[u] = (t0 + u) * 16 + c16;
+      ok[u] = p[u] < P;
+      const int row = ok[u] ? p[u] / w : 0;
+      xx[u] = ok[u] ? p[u] - row * w : 0;
+      y[u] = row % h;
+      base[u] = (row - y[u]) * w;  // first pixel of the map
+    }
+    f32x4 acc[CONV_TPW][MB];
+#pragma unroll
+    for (int u = 0; u < CONV_TPW; ++u)
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) acc[u][mb] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
       const int k0 = ks * 32 + 8 * g;
-      u16x8 bv = {0, 0, 0, 0, 0, 0, 0, 0};
-      if (ok && k0 < K) {
-        const int tap = k0 / CS, c0 = k0 % CS;
-        const int yy = y + tap / 3 - 1, xs = xx + tap % 3 - 1;
-        if (yy >= 0 && yy < h && xs >= 0 && xs < w)
-          bv = *reinterpret_cast<const u16x8*>(x + ((b * h + yy) * w + xs) * CS + c0);
+      const int tap = k0 / CS, c0 = k0 % CS, dy = tap / 3 - 1, dx = tap % 3 - 1;
+      u16x8 bv[CONV_TPW];
+#pragma unroll
+      for (int u = 0; u < CONV_TPW; ++u) {
+        const int yy = y[u] + dy, xs = xx[u] + dx;
+        const bool in = ok[u] && k0 < K && (unsigned)yy < (unsigned)h && (unsigned)xs < (unsigned)w;
+        bv[u] = in ? *reinterpret_cast<const u16x8*>(x + (base[u] + yy * w + xs) * CS + c0)
+                   : u16x8{0, 0, 0, 0, 0, 0, 0, 0};
       }
 #pragma unroll
-      for (int mb = 0; mb < MB; ++mb) acc[mb] = mfma(a[mb][ks], bv, acc[mb]);
+      for (int u = 0; u < CONV_TPW; ++u)
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) acc[u][mb] = mfma(a[mb][ks], bv[u], acc[u][mb]);
     }
-    if (!ok) continue;
     // lane holds rows mb*16 + 4g + i of pixel p
 #pragma unroll
-    for (int mb = 0; mb < MB; ++mb) {
-      const int r0 = mb * 16 + 4 * g;
-      if (r0 >= CSO) continue;
-      if constexpr (MODE == MODE_LOGITS) {
-        float4 o;
-        o.x = acc[mb][0] + (r0 + 0 < nbias ? bias[r0 + 0] : 0.0f);
-        o.y = acc[mb][1] + (r0 + 1 < nbias ? bias[r0 + 1] : 0.0f);
-        o.z = acc[mb][2] + (r0 + 2 < nbias ? bias[r0 + 2] : 0.0f);
-        o.w = acc[mb][3] + (r0 + 3 < nbias ? bias[r0 + 3] : 0.0f);
-        *reinterpret_cast<float4*>(static_cast<float*>(out) + p * CSO + r0) = o;
-      } else {
-        u16x4 o;
+    for (int u = 0; u < CONV_TPW; ++u) {
+      if (!ok[u]) continue;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          float v = acc[mb][i];
-          if constexpr (MODE == MODE_HIDDEN) {
-            v = fmaxf(v + (r0 + i < nbias ? bias[r0 + i] : 0.0f), 0.0f);
-          } else {
-            v = bf_pos(act[p * CSO + r0 + i]) ? v : 0.0f;
+      for (int mb = 0; mb < MB; ++mb) {
+        const int r0 = mb * 16 + 4 * g;
+        if (r0 >= CSO) continue;
+        if constexpr (MODE == MODE_LOGITS) {
+          float4 o;
+          o.x = acc[u][mb][0] + (r0 + 0 < nbias ? bias[r0 + 0] : 0.0f);
+          o.y = acc[u][mb][1] + (r0 + 1 < nbias ? bias[r0 + 1] : 0.0f);
+          o.z = acc[u][mb][2] + (r0 + 2 < nbias ? bias[r0 + 2] : 0.0f);
+          o.w = acc[u][mb][3] + (r0 + 3 < nbias ? bias[r0 + 3] : 0.0f);
+          *reinterpret_cast<float4*>(static_cast<float*>(out) + (int64_t)p[u] * CSO + r0) = o;
+        } else {
+          u16x4 o;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            float v = acc[u][mb][i];
+            if constexpr (MODE == MODE_HIDDEN) {
+              v = fmaxf(v + (r0 + i < nbias ? bias[r0 + i] : 0.0f), 0.0f);
+            } else {
+              v = bf_pos(act[(int64_t)p[u] * CSO + r0 + i]) ? v : 0.0f;
+            }
+            o[i] = f2bf(v);
           }
-          o[i] = f2bf(v);
+          *reinterpret_cast<u16x4*>(static_cast<uint16_t*>(out) + (int64_t)p[u] * CSO + r0) = o;
         }
-        *reinterpret_cast<u16x4*>(static_cast<uint16_t*>(out) + p * CSO + r0) = o;
       }
     }
   }
@@ -178,85 +196,192 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t* __restrict__ wmat,
 
 // weight gradient: G[o][n] = sum_p dy[p, o] X[p, n], n = tap * CS + c, plus
 // the bias column n = 9 CS of ones.  CS = stored input channels, DC = stored
-// dy channels, RW = padded rows.
-constexpr int WG_BLOCKS = 256;
+// dy channels, RW = padded rows.  The reduction runs over pixels, which NHWC
+// stores with channels contiguous, so each 64-pixel chunk of both operands is
+// transposed into LDS: a thread loads 16 bytes (8 channels) of 4 consecutive
+// pixels and writes them as 8 rows of 4 pixels (one 8-byte LDS store each).
+// The next chunk's global loads are issued before the current chunk's
+// matrix products, so their latency hides behind them.  Each wave owns every
+// fourth 16-column block with all row blocks, so a B operand is read from LDS
+// once per k-step.
+constexpr int WG_BLOCKS = 512;
 constexpr int WG_MAX_FLOATS = HID * ((9 * HID + 1 + 15) / 16 * 16);
+constexpr int WG_CHUNK = 64;
+constexpr int WG_LD = WG_CHUNK + 8;  // LDS row stride in bf16 (144 bytes: conflict-free 16-byte reads)
 
 template <int CS, int DC, int RW>
 __global__ __launch_bounds__(256) void k_wgrad(const uint16_t* __restrict__ dy, const uint16_t* __restrict__ x,
                                                int n, int h, int w, float* __restrict__ partial) {
-  constexpr int N = 9 * CS + 1, NBK = (N + 15) / 16, NP = NBK * 16, MB = RW / 16, TILES = MB * NBK;
-  constexpr int PER = (TILES + 3) / 4;
-  __shared__ __attribute__((aligned(16))) uint16_t dyT[RW][32];
-  __shared__ __attribute__((aligned(16))) uint16_t xs[9 * CS][32];
+  constexpr int N = 9 * CS + 1, NBK = (N + 15) / 16, NP = NBK * 16, MB = RW / 16, NBPW = (NBK + 3) / 4;
+  constexpr int DO = DC / 8, XO = CS / 8, QUADS = WG_CHUNK / 4;
+  constexpr int DT = QUADS * DO, TT = DT + 9 * QUADS * XO, TPT = (TT + 255) / 256;
+  static_assert(DC % 8 == 0 && CS % 8 == 0 && DC <= RW && RW % 16 == 0, "operand shapes");
+  // rows [0, RW): dy transposed; rows [RW, RW + NP): the 9 shifted inputs
+  // transposed, then the ones row of the bias and zero padding
+  __shared__ __attribute__((aligned(16))) uint16_t T[(RW + NP) * WG_LD];
+  __shared__ __attribute__((aligned(16))) int pix_y[WG_CHUNK], pix_x[WG_CHUNK];
   const int tid = threadIdx.x, wv = tid / WAVE, lane = tid & (WAVE - 1), g = lane >> 4, c16 = lane & 15;
-  f32x4 acc[PER];
-#pragma unroll
-  for (int q = 0; q < PER; ++q) acc[q] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-  const int64_t P = (int64_t)n * h * w, chunks = (P + 31) / 32;
-  for (int64_t ch = blockIdx.x; ch < chunks; ch += gridDim.x) {
-    __syncthreads();  // the previous chunk's operands are consumed
-    for (int e = tid; e < RW * 32; e += 256) {
-      const int r = e % RW, px = e / RW;
-      const int64_t p = ch * 32 + px;
-      dyT[r][px] = (p < P && r < DC) ? dy[p * DC + r] : (uint16_t)0;
-    }
-    for (int e = tid; e < 9 * CS * 32; e += 256) {
-      const int c = e % CS, rest = e / CS, px = rest % 32, tap = rest / 32;
-      const int64_t p = ch * 32 + px;
-      uint16_t val = 0;
+  const int P = n * h * w, chunks = (P + WG_CHUNK - 1) / WG_CHUNK;  // P < 2^25, checked by the caller
+
+  // rows no chunk writes: dy padding rows, the ones row, input padding rows
+  for (int e = tid; e < (RW - DC) * WG_CHUNK; e += 256)
+    T[(DC + e / WG_CHUNK) * WG_LD + e % WG_CHUNK] = 0;
+  for (int e = tid; e < (NP - 9 * CS) * WG_CHUNK; e += 256) {
+    const int r = 9 * CS + e / WG_CHUNK;
+    T[(RW + r) * WG_LD + e % WG_CHUNK] = r == 9 * CS ? BF16_ONE : (uint16_t)0;
+  }
+  // (y, x) of a chunk's pixels; y far out of range past the last pixel
+  auto set_pix = [&](int c) {
+    if (tid < WG_CHUNK) {
+      const int p = c * WG_CHUNK + tid;
+      int yy = -(1 << 28), xx = 0;
       if (p < P) {
-        const int xx = (int)(p % w), y = (int)((p / w) % h);
-        const int64_t b = p / ((int64_t)w * h);
-        const int yy = y + tap / 3 - 1, xq = xx + tap % 3 - 1;
-        if (yy >= 0 && yy < h && xq >= 0 && xq < w) val = x[((b * h + yy) * w + xq) * CS + c];
+        const int row = p / w;
+        xx = p - row * w;
+        yy = row % h;
       }
-      xs[tap * CS + c][px] = val;
+      pix_y[tid] = yy;
+      pix_x[tid] = xx;
     }
-    __syncthreads();
+  };
+  // task e: 4 consecutive pixels x 8 channels of dy (e < DT) or of one tap
+  // of the input
+  u16x8 v[TPT][4];
+  auto load = [&](int c) {
 #pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const int tile = wv + 4 * q;
-      if (tile >= TILES) break;  // uniform per wave
-      const int mb = tile / NBK, nb = tile % NBK;
-      const u16x8 av = *reinterpret_cast<const u16x8*>(&dyT[mb * 16 + c16][8 * g]);
-      const int col = nb * 16 + c16;
-      u16x8 bv = {0, 0, 0, 0, 0, 0, 0, 0};
-      if (col < 9 * CS) {
-        bv = *reinterpret_cast<const u16x8*>(&xs[col][8 * g]);
-      } else if (col == 9 * CS) {
-        const int64_t p0 = ch * 32 + 8 * g;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) bv[e] = p0 + e < P ? BF16_ONE : (uint16_t)0;
+    for (int k = 0; k < TPT; ++k) {
+      const int e = tid + 256 * k;
+      if (e >= TT) break;
+      const uint16_t* base;
+      int oct, quad, stride, sy = 0, sx = 0;
+      if (e < DT) {
+        oct = e % DO;
+        quad = e / DO;
+        base = dy;
+        stride = DC;
+      } else {
+        const int f = e - DT, rest = f / XO, tap = rest / QUADS;
+        oct = f % XO;
+        quad = rest % QUADS;
+        base = x;
+        stride = CS;
+        sy = tap / 3 - 1;
+        sx = tap % 3 - 1;
       }
-      acc[q] = mfma(av, bv, acc[q]);
+      const int4 py = *reinterpret_cast<const int4*>(&pix_y[4 * quad]);
+      const int4 px = *reinterpret_cast<const int4*>(&pix_x[4 * quad]);
+      const int ys[4] = {py.x, py.y, py.z, py.w}, xs[4] = {px.x, px.y, px.z, px.w};
+      const int p0 = c * WG_CHUNK + 4 * quad + sy * w + sx;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const bool ok = (unsigned)(ys[j] + sy) < (unsigned)h && (unsigned)(xs[j] + sx) < (unsigned)w;
+        v[k][j] = ok ? *reinterpret_cast<const u16x8*>(base + (p0 + j) * stride + 8 * oct)
+                     : u16x8{0, 0, 0, 0, 0, 0, 0, 0};
+      }
+    }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int k = 0; k < TPT; ++k) {
+      const int e = tid + 256 * k;
+      if (e >= TT) break;
+      int row, quad;
+      if (e < DT) {
+        row = 8 * (e % DO);
+        quad = e / DO;
+      } else {
+        const int f = e - DT, rest = f / XO;
+        row = RW + (rest / QUADS) * CS + 8 * (f % XO);
+        quad = rest % QUADS;
+      }
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        uint2 pr;
+        pr.x = (uint32_t)v[k][0][i] | ((uint32_t)v[k][1][i] << 16);
+        pr.y = (uint32_t)v[k][2][i] | ((uint32_t)v[k][3][i] << 16);
+        *reinterpret_cast<uint2*>(&T[(row + i) * WG_LD + 4 * quad]) = pr;
+      }
+    }
+  };
+
+  f32x4 acc[NBPW][MB];
+#pragma unroll
+  for (int t = 0; t < NBPW; ++t)
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) acc[t][mb] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  int ch = blockIdx.x;  // the launch has at most `chunks` blocks
+  set_pix(ch);
+  __syncthreads();
+  load(ch);
+  for (; ch < chunks; ch += gridDim.x) {
+    __syncthreads();  // the previous chunk's products have read T, the loads have read pix
+    store();
+    const int nx = ch + gridDim.x;
+    if (nx < chunks) set_pix(nx);
+    __syncthreads();
+    if (nx < chunks) load(nx);
+    u16x8 a[MB][2];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int kk = 0; kk < 2; ++kk)
+        a[mb][kk] = *reinterpret_cast<const u16x8*>(&T[(mb * 16 + c16) * WG_LD + kk * 32 + 8 * g]);
+#pragma unroll
+    for (int t = 0; t < NBPW; ++t) {
+      const int nb = wv + 4 * t;
+      if (nb >= NBK) break;  // uniform per wave
+#pragma unroll
+      for (int kk = 0; kk < 2; ++kk) {
+        const u16x8 b = *reinterpret_cast<const u16x8*>(&T[(RW + nb * 16 + c16) * WG_LD + kk * 32 + 8 * g]);
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) acc[t][mb] = mfma(a[mb][kk], b, acc[t][mb]);
+      }
     }
   }
   float* out = partial + (int64_t)blockIdx.x * RW * NP;
 #pragma unroll
-  for (int q = 0; q < PER; ++q) {
-    const int tile = wv + 4 * q;
-    if (tile >= TILES) break;
-    const int mb = tile / NBK, nb = tile % NBK;
+  for (int t = 0; t < NBPW; ++t) {
+    const int nb = wv + 4 * t;
+    if (nb >= NBK) break;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) out[(mb * 16 + 4 * g + i) * NP + nb * 16 + c16] = acc[q][i];
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) out[(mb * 16 + 4 * g + i) * NP + nb * 16 + c16] = acc[t][mb][i];
   }
 }
 
-// sum the per-block partials in block order into the flat gradient
-__global__ __launch_bounds__(256) void k_wgrad_reduce(const float* partial, int nblocks, int rw, int np, int cs,
-                                                      int cin, int cout, float* gw, float* gb) {
-  const int total = cout * (9 * cs + 1);
-  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
-    const int o = e / (9 * cs + 1), col = e % (9 * cs + 1);
-    if (col < 9 * cs && col % cs >= cin) continue;  // padding channel
-    float s = 0.0f;
-    for (int b = 0; b < nblocks; ++b) s += partial[(int64_t)b * rw * np + o * np + col];
-    if (col == 9 * cs)
-      gb[o] = s;
-    else
-      gw[(o * 9 + col / cs) * cin + col % cs] = s;
+// sum the per-block partials into the flat gradient: 64 entries per block,
+// each wave adds a contiguous quarter of the partial blocks in order and the
+// quarters are added in wave order (a fixed order: the result is
+// deterministic)
+__global__ __launch_bounds__(256) void k_wgrad_reduce(const float* __restrict__ partial, int nblocks, int rw, int np,
+                                                      int cs, int cin, int cout, float* gw, float* gb) {
+  __shared__ float sh[4][WAVE];
+  const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+  const int total = rw * np, e = blockIdx.x * WAVE + lane;
+  float s = 0.0f;
+  if (e < total) {
+    const int per = (nblocks + 3) / 4, b0 = min(nblocks, wv * per), b1 = min(nblocks, b0 + per);
+    int b = b0;
+    for (; b + 8 <= b1; b += 8) {
+      float t[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) t[u] = partial[(int64_t)(b + u) * total + e];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += t[u];
+    }
+    for (; b < b1; ++b) s += partial[(int64_t)b * total + e];
   }
+  sh[wv][lane] = s;
+  __syncthreads();
+  if (wv != 0 || e >= total) return;
+  s = ((sh[0][lane] + sh[1][lane]) + sh[2][lane]) + sh[3][lane];
+  const int o = e / np, col = e % np;
+  if (o >= cout || col > 9 * cs) return;
+  if (col == 9 * cs)
+    gb[o] = s;
+  else if (col % cs < cin)
+    gw[(o * 9 + col / cs) * cin + col % cs] = s;
 }
 
 struct ClassW {
@@ -354,8 +479,8 @@ __global__ __launch_bounds__(256) void k_adam(float* theta, float* m, float* v, 
 }
 
 int conv_blocks(int64_t P) {
-  const int64_t tiles = (P + 15) / 16, waves = 4;  // 4 waves per block
-  return (int)std::min<int64_t>(std::max<int64_t>((tiles + waves - 1) / waves, 1), 2048);
+  const int64_t tiles = (P + 15) / 16, per_block = 4 * CONV_TPW;  // 4 waves per block
+  return (int)std::min<int64_t>(std::max<int64_t>((tiles + per_block - 1) / per_block, 1), CONV_MAX_BLOCKS);
 }
 
 // ---------------------------------------------------------------- inference
@@ -550,7 +675,8 @@ size_t wgrad_partial_floats() { return (size_t)WG_BLOCKS * WG_MAX_FLOATS; }
 hipError_t conv_weight_grad(int l, const Net& net, const uint16_t* dy, const uint16_t* x, int n, int h, int w,
                             float* partial, hipStream_t s) {
   const int64_t P = (int64_t)n * h * w;
-  const int blocks = (int)std::min<int64_t>(std::max<int64_t>((P + 31) / 32, 1), WG_BLOCKS);
+  if (P < 1 || P >= ((int64_t)1 << 25)) return hipErrorInvalidValue;  // the kernel indexes pixels in 32 bits
+  const int blocks = (int)std::min<int64_t>((P + WG_CHUNK - 1) / WG_CHUNK, WG_BLOCKS);
   const Offsets o = offsets();
   int cs, rw;
   if (l == 0) {
@@ -569,7 +695,8 @@ hipError_t conv_weight_grad(int l, const Net& net, const uint16_t* dy, const uin
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int np = (9 * cs + 1 + 15) / 16 * 16;
-  hipLaunchKernelGGL(k_wgrad_reduce, dim3(64), dim3(256), 0, s, partial, blocks, rw, np, cs, CIN[l], COUT[l],
+  hipLaunchKernelGGL(k_wgrad_reduce, dim3((rw * np + WAVE - 1) / WAVE), dim3(256), 0, s, partial, blocks, rw, np, cs,
+                     CIN[l], COUT[l],
                      net.grad + o.w[l], net.grad + o.b[l]);
   return hipGetLastError();
 }
