@@ -119,15 +119,18 @@ def test_forward_layers_elementwise(ctx, n, h, w):
     net.close()
 
 
-def test_backward_layers_elementwise(ctx):
+# (3, 13, 21): 819 pixels, a ragged last 64-pixel chunk of the weight
+# gradient, rows of a width that is not a multiple of 4 (pixel quads cross
+# rows) and map borders inside chunks; (1, 3, 5): a single partial chunk
+@pytest.mark.parametrize("n,h,w", [(2, 64, 64), (3, 13, 21), (1, 3, 5)])
+def test_backward_layers_elementwise(ctx, n, h, w):
     from paper_1010_5534_amd import air
     theta = he_params(3)
     net = air.Network(ctx, theta)
-    n, h, w = 2, 64, 64
     P = n * h * w
     x, labels = _maps(4, n, h, w)
     cw = np.array([0.5, 1.0, 2.0, 1.5, 3.0, 4.0], np.float32)
-    say("cnn loss and gradient, layer by layer")
+    say(f"cnn loss and gradient n={n} {h}x{w}, layer by layer")
     loss, g = net.loss_grad(torch.from_numpy(x).cuda(), torch.from_numpy(labels).cuda(), cw, want_grad=True)
     g = g.cpu().numpy().astype(np.float64)
     T, acts, z, bad = _forward_layers(net, theta, x, 0.0, 1.0, (n, h, w))
