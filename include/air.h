@@ -209,6 +209,32 @@ void air_destroy(air_ctx* ctx);
 /* Message for the last failure on this context ("" if none). */
 const char* air_last_error(const air_ctx* ctx);
 
+/* The launch shapes air_render_batch tuned on this context (one entry per
+ * workload shape: grid, views, coarse size, levels, bands; results never
+ * depend on them, only time does), kept across processes.
+ * air_tune_save writes them to a text file at path: a header line naming the
+ * device's architecture and compute-unit count, then one line per shape.
+ * air_tune_load reads such a file into the context (entries of the same
+ * shape are replaced) so that later batches skip their tuning runs; it
+ * rejects the whole file, taking nothing, if the header names another
+ * device type or any entry is malformed.  Host file I/O only.
+ * Errors: EINVAL (NULL path, unreadable or unwritable file, bad contents,
+ * other device type; the reason in air_last_error), EDEVICE. */
+air_status air_tune_save(air_ctx* ctx, const char* path);
+air_status air_tune_load(air_ctx* ctx, const char* path);
+
+/* Library-owned tree buffers (the air_tree arrays, any render's output):
+ * air_tree_alloc allocates every array of *tree on the context's device for
+ * `capacity` nodes and n_bands bands (1..AIR_MAX_BANDS) and sets
+ * tree->capacity; air_tree_free frees the arrays of a tree made by
+ * air_tree_alloc (never caller-allocated arrays) and zeroes the struct.
+ * The caller owns the result until it calls air_tree_free; destroying the
+ * context does not free it.  Errors: EINVAL (NULL tree, capacity outside
+ * 1..2^31-1, n_bands out of range), ENOMEM (nothing stays allocated),
+ * EDEVICE. */
+air_status air_tree_alloc(air_ctx* ctx, int32_t n_bands, int64_t capacity, air_tree* tree);
+air_status air_tree_free(air_ctx* ctx, air_tree* tree);
+
 /*
  * Plain AIR for n_views views of one grid (section 2 steps i-vi), the views
  * refined level by level in lockstep.  For each view:
@@ -356,6 +382,18 @@ air_status air_cnn_set(air_ctx* ctx, air_cnn* net, const float* params, const fl
 /* Copy the parameters and the standardisation back to the host (any may be
  * NULL); synchronises the context's device. */
 air_status air_cnn_get(air_ctx* ctx, const air_cnn* net, float* params, float* feat_mean, float* feat_scale);
+/* Checkpoint of a network for resuming its training: air_cnn_save writes the
+ * parameters, the feature standardisation, the optimiser's moment estimates
+ * and step count to the file at path (a binary header, then float32 arrays,
+ * in the host's byte order); air_cnn_load reads such a file into net,
+ * replacing all of these, so that the next air_cnn_adam continues exactly
+ * where the saved network stopped.  Both synchronise the context's device.
+ * air_cnn_load checks the header, the sizes and that every value is finite
+ * (scales > 0, second moments >= 0) before it changes net.
+ * Errors: EINVAL (NULL path, unreadable or unwritable file, a file that is
+ * not such a checkpoint; the reason in air_last_error), EDEVICE. */
+air_status air_cnn_save(air_ctx* ctx, const air_cnn* net, const char* path);
+air_status air_cnn_load(air_ctx* ctx, air_cnn* net, const char* path);
 
 /*
  * Raw input maps of the coarse trace, device [n_views][coarse_n][coarse_n][4]

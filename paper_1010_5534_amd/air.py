@@ -23,7 +23,8 @@ EXPORTS = ("air_create", "air_destroy", "air_last_error", "air_render", "air_ren
            "air_field_packed_bytes", "air_field_pack", "air_cnn_create", "air_cnn_destroy", "air_cnn_set",
            "air_cnn_get", "air_features", "air_cnn_forward", "air_cnn_loss_grad", "air_cnn_adam", "air_tree_depth",
            "air_render_learned", "air_render_batch", "air_cnn_tensor", "air_render_fixed_noalloc",
-           "air_render_spectra", "air_render_proposal")
+           "air_render_spectra", "air_render_proposal", "air_cnn_save", "air_cnn_load", "air_tune_save",
+           "air_tune_load", "air_tree_alloc", "air_tree_free")
 CNN_FEATURES, CNN_CLASSES, CNN_PARAMS = 4, 6, 21414
 
 
@@ -129,8 +130,17 @@ def lib():
         L.air_tree_depth.argtypes = [vp, vp, i32, vp, vp]
         L.air_cnn_tensor.argtypes = [vp, i32, vp, C.c_int64, vp]
         L.air_render_learned.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        cp = C.c_char_p
+        L.air_cnn_save.argtypes = [vp, vp, cp]
+        L.air_cnn_load.argtypes = [vp, vp, cp]
+        L.air_tune_save.argtypes = [vp, cp]
+        L.air_tune_load.argtypes = [vp, cp]
+        L.air_tree_alloc.argtypes = [vp, i32, C.c_int64, vp]
+        L.air_tree_free.argtypes = [vp, vp]
         for name in ("air_cnn_create", "air_cnn_set", "air_cnn_get", "air_features", "air_cnn_forward",
-                     "air_cnn_loss_grad", "air_cnn_adam", "air_tree_depth", "air_render_learned", "air_cnn_tensor"):
+                     "air_cnn_loss_grad", "air_cnn_adam", "air_tree_depth", "air_render_learned", "air_cnn_tensor",
+                     "air_cnn_save", "air_cnn_load", "air_tune_save", "air_tune_load", "air_tree_alloc",
+                     "air_tree_free"):
             getattr(L, name).restype = C.c_int32
         _lib = L
     return _lib
@@ -299,6 +309,14 @@ class Context:
 
     def _stream(self):
         return _torch().cuda.current_stream(self.device).cuda_stream
+
+    def tune_save(self, path):
+        """Write the batch's tuned launch shapes to a text file (air_tune_save)."""
+        self._check(lib().air_tune_save(self._p, os.fsencode(path)))
+
+    def tune_load(self, path):
+        """Read launch shapes written by tune_save (air_tune_load)."""
+        self._check(lib().air_tune_load(self._p, os.fsencode(path)))
 
     def prepare(self, scene: DeviceScene) -> DeviceScene:
         """Write the field's march layout once (air_field_pack) and attach it,
@@ -603,6 +621,14 @@ class Network:
         m = np.zeros(CNN_FEATURES, np.float32) if mean is None else np.ascontiguousarray(mean, np.float32)
         s = np.ones(CNN_FEATURES, np.float32) if scale is None else np.ascontiguousarray(scale, np.float32)
         self.ctx._check(lib().air_cnn_set(self.ctx._p, self._p, p.ctypes.data, m.ctypes.data, s.ctypes.data))
+
+    def save(self, path):
+        """Checkpoint: parameters, standardisation and optimiser state (air_cnn_save)."""
+        self.ctx._check(lib().air_cnn_save(self.ctx._p, self._p, os.fsencode(path)))
+
+    def load(self, path):
+        """Restore a checkpoint written by save (air_cnn_load)."""
+        self.ctx._check(lib().air_cnn_load(self.ctx._p, self._p, os.fsencode(path)))
 
     def get(self):
         p = np.zeros(CNN_PARAMS, np.float32)

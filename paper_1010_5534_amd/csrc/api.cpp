@@ -1563,4 +1563,202 @@ air_status air_tree_depth(air_ctx* c, const air_tree* tree, int32_t coarse_n, in
   return AIR_OK;
 }
 
+
+// ---------------------------------------------------------------- checkpoints, tune cache, trees
+
+namespace {
+// network checkpoint: header, feature standardisation, parameters and the
+// optimiser state, in native byte order
+struct CnnFileHeader {
+  char magic[8];
+  int32_t n_params;
+  int32_t n_features;
+  int64_t step;
+};
+constexpr char CNN_MAGIC[8] = {'A', 'I', 'R', 'C', 'N', 'N', '0', '1'};
+constexpr char TUNE_MAGIC[] = "libair-tune 1";
+
+bool all_finite(const std::vector<float>& v, size_t b, size_t e) {
+  for (size_t k = b; k < e; ++k)
+    if (!std::isfinite(v[k])) return false;
+  return true;
+}
+}  // namespace
+
+air_status air_cnn_save(air_ctx* c, const air_cnn* n, const char* path) {
+  if (!c || !n) return AIR_EINVAL;
+  c->err.clear();
+  if (!path) return fail(c, AIR_EINVAL, "path is NULL");
+  if (n->device != c->device) return fail(c, AIR_EINVAL, "network and context are on different devices");
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, AIR_EDEVICE, "hipSetDevice failed");
+  const cnn::Net& N = n->net;
+  const size_t P = AIR_CNN_PARAMS;
+  std::vector<float> buf(3 * P);
+  HIPCHK(c, hipDeviceSynchronize());
+  HIPCHK(c, hipMemcpy(buf.data(), N.theta, 4 * P, hipMemcpyDeviceToHost));
+  HIPCHK(c, hipMemcpy(buf.data() + P, N.m, 4 * P, hipMemcpyDeviceToHost));
+  HIPCHK(c, hipMemcpy(buf.data() + 2 * P, N.v, 4 * P, hipMemcpyDeviceToHost));
+  CnnFileHeader h;
+  std::memcpy(h.magic, CNN_MAGIC, sizeof h.magic);
+  h.n_params = AIR_CNN_PARAMS;
+  h.n_features = cnn::FEAT;
+  h.step = N.step;
+  FILE* f = std::fopen(path, "wb");
+  if (!f) return fail(c, AIR_EINVAL, "cannot open %s for writing", path);
+  bool ok = std::fwrite(&h, sizeof h, 1, f) == 1 && std::fwrite(N.mean, 4, cnn::FEAT, f) == (size_t)cnn::FEAT &&
+            std::fwrite(N.stdv, 4, cnn::FEAT, f) == (size_t)cnn::FEAT &&
+            std::fwrite(buf.data(), 4, buf.size(), f) == buf.size();
+  ok = (std::fclose(f) == 0) && ok;
+  if (!ok) return fail(c, AIR_EINVAL, "writing %s failed", path);
+  return AIR_OK;
+}
+
+air_status air_cnn_load(air_ctx* c, air_cnn* n, const char* path) {
+  if (!c || !n) return AIR_EINVAL;
+  c->err.clear();
+  if (!path) return fail(c, AIR_EINVAL, "path is NULL");
+  if (n->device != c->device) return fail(c, AIR_EINVAL, "network and context are on different devices");
+  FILE* f = std::fopen(path, "rb");
+  if (!f) return fail(c, AIR_EINVAL, "cannot open %s", path);
+  const size_t P = AIR_CNN_PARAMS;
+  CnnFileHeader h;
+  float mean[cnn::FEAT], scale[cnn::FEAT];
+  std::vector<float> buf(3 * P);
+  bool ok = std::fread(&h, sizeof h, 1, f) == 1 && std::memcmp(h.magic, CNN_MAGIC, sizeof h.magic) == 0 &&
+            h.n_params == AIR_CNN_PARAMS && h.n_features == cnn::FEAT && h.step >= 0 &&
+            std::fread(mean, 4, cnn::FEAT, f) == (size_t)cnn::FEAT &&
+            std::fread(scale, 4, cnn::FEAT, f) == (size_t)cnn::FEAT &&
+            std::fread(buf.data(), 4, buf.size(), f) == buf.size();
+  char extra;
+  ok = ok && std::fread(&extra, 1, 1, f) == 0;  // nothing after the optimiser state
+  std::fclose(f);
+  if (!ok) return fail(c, AIR_EINVAL, "%s is not a checkpoint of this network", path);
+  for (int k = 0; k < cnn::FEAT; ++k)
+    if (!std::isfinite(mean[k]) || !std::isfinite(scale[k]) || !(scale[k] > 0))
+      return fail(c, AIR_EINVAL, "%s: feature mean must be finite and scale > 0", path);
+  if (!all_finite(buf, 0, 3 * P)) return fail(c, AIR_EINVAL, "%s: parameters or moments not finite", path);
+  for (size_t k = 2 * P; k < 3 * P; ++k)
+    if (buf[k] < 0.0f) return fail(c, AIR_EINVAL, "%s: negative second moment", path);
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, AIR_EDEVICE, "hipSetDevice failed");
+  cnn::Net& N = n->net;
+  HIPCHK(c, hipDeviceSynchronize());
+  HIPCHK(c, hipMemcpy(N.theta, buf.data(), 4 * P, hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(N.m, buf.data() + P, 4 * P, hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(N.v, buf.data() + 2 * P, 4 * P, hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemset(N.grad, 0, 4 * P));
+  for (int k = 0; k < cnn::FEAT; ++k) {
+    N.mean[k] = mean[k];
+    N.stdv[k] = scale[k];
+  }
+  N.step = h.step;
+  HIPCHK(c, cnn::prep_weights(N, nullptr));
+  HIPCHK(c, hipDeviceSynchronize());
+  return AIR_OK;
+}
+
+air_status air_tune_save(air_ctx* c, const char* path) {
+  if (!c) return AIR_EINVAL;
+  c->err.clear();
+  if (!path) return fail(c, AIR_EINVAL, "path is NULL");
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, c->device) != hipSuccess) return fail(c, AIR_EDEVICE, "device query failed");
+  FILE* f = std::fopen(path, "w");
+  if (!f) return fail(c, AIR_EINVAL, "cannot open %s for writing", path);
+  bool ok = std::fprintf(f, "%s %s %d\n", TUNE_MAGIC, prop.gcnArchName, c->num_cus) > 0;
+  for (const auto& kv : c->tuned)
+    ok = ok && std::fprintf(f, "%s %d %d\n", kv.first.c_str(), kv.second.march_waves_per_cu,
+                            kv.second.refine_blocks_per_cu) > 0;
+  ok = (std::fclose(f) == 0) && ok;
+  if (!ok) return fail(c, AIR_EINVAL, "writing %s failed", path);
+  return AIR_OK;
+}
+
+air_status air_tune_load(air_ctx* c, const char* path) {
+  if (!c) return AIR_EINVAL;
+  c->err.clear();
+  if (!path) return fail(c, AIR_EINVAL, "path is NULL");
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, c->device) != hipSuccess) return fail(c, AIR_EDEVICE, "device query failed");
+  FILE* f = std::fopen(path, "r");
+  if (!f) return fail(c, AIR_EINVAL, "cannot open %s", path);
+  char line[512], arch[256];
+  int cus = 0;
+  const size_t ml = sizeof TUNE_MAGIC - 1;
+  if (!std::fgets(line, sizeof line, f) || std::strncmp(line, TUNE_MAGIC, ml) != 0 ||
+      std::sscanf(line + ml, " %255s %d", arch, &cus) != 2) {
+    std::fclose(f);
+    return fail(c, AIR_EINVAL, "%s is not a launch-shape cache", path);
+  }
+  if (std::strcmp(arch, prop.gcnArchName) != 0 || cus != c->num_cus) {
+    std::fclose(f);
+    return fail(c, AIR_EINVAL, "%s was tuned on %s with %d CUs, this device is %s with %d", path, arch, cus,
+                prop.gcnArchName, c->num_cus);
+  }
+  // every entry is checked before any is taken
+  std::map<std::string, Tune> got;
+  char key[256];
+  int mw = 0, rb = 0, lno = 1;
+  while (std::fgets(line, sizeof line, f)) {
+    ++lno;
+    if (std::sscanf(line, "%255s %d %d", key, &mw, &rb) != 3 || !(mw == 8 || mw == 16 || mw == 32) ||
+        !(rb == 2 || rb == 4 || rb == 8)) {
+      std::fclose(f);
+      return fail(c, AIR_EINVAL, "%s line %d: not an entry of launch shapes", path, lno);
+    }
+    Tune t;
+    t.march_waves_per_cu = mw;
+    t.refine_blocks_per_cu = rb;
+    got[key] = t;
+  }
+  std::fclose(f);
+  for (const auto& kv : got) c->tuned[kv.first] = kv.second;
+  return AIR_OK;
+}
+
+air_status air_tree_free(air_ctx* c, air_tree* t) {
+  if (!c) return AIR_EINVAL;
+  c->err.clear();
+  if (!t) return fail(c, AIR_EINVAL, "tree is NULL");
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, AIR_EDEVICE, "hipSetDevice failed");
+  void* ptrs[] = {t->level, t->ix, t->iy, t->parent, t->first_child, t->state, t->I, t->N, t->xi_I, t->xi_N,
+                  t->visits};
+  hipError_t e = hipSuccess;
+  for (void* q : ptrs)
+    if (q) {
+      const hipError_t r = hipFree(q);
+      if (e == hipSuccess) e = r;
+    }
+  std::memset(t, 0, sizeof *t);
+  if (e != hipSuccess) return fail(c, AIR_EDEVICE, "hipFree failed: %s", hipGetErrorString(e));
+  return AIR_OK;
+}
+
+air_status air_tree_alloc(air_ctx* c, int32_t n_bands, int64_t capacity, air_tree* t) {
+  if (!c) return AIR_EINVAL;
+  c->err.clear();
+  if (!t) return fail(c, AIR_EINVAL, "tree is NULL");
+  if (n_bands < 1 || n_bands > AIR_MAX_BANDS) return fail(c, AIR_EINVAL, "n_bands %d out of range", n_bands);
+  if (capacity < 1 || capacity >= ((int64_t)1 << 31)) return fail(c, AIR_EINVAL, "capacity out of range");
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, AIR_EDEVICE, "hipSetDevice failed");
+  std::memset(t, 0, sizeof *t);
+  const size_t n = (size_t)capacity;
+  struct {
+    void** p;
+    size_t bytes;
+  } arrays[] = {{(void**)&t->level, n},         {(void**)&t->ix, 4 * n},     {(void**)&t->iy, 4 * n},
+                {(void**)&t->parent, 4 * n},    {(void**)&t->first_child, 4 * n},
+                {(void**)&t->state, n},         {(void**)&t->I, 4 * n * n_bands},
+                {(void**)&t->N, 4 * n},         {(void**)&t->xi_I, 4 * n},   {(void**)&t->xi_N, 4 * n},
+                {(void**)&t->visits, 4 * n}};
+  for (auto& a : arrays)
+    if (hipMalloc(a.p, a.bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      *a.p = nullptr;
+      (void)air_tree_free(c, t);
+      return fail(c, AIR_ENOMEM, "tree of %lld nodes does not fit", (long long)capacity);
+    }
+  t->capacity = capacity;
+  return AIR_OK;
+}
+
 }  // extern "C"

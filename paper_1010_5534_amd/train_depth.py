@@ -60,6 +60,31 @@ def build_dataset(ctx, seeds):
     return feats, labels
 
 
+def train_epochs(net, ftr, ltr, cw, epochs, batch, lr, rng, first_epoch=0, on_epoch=None, fva=None, lva=None):
+    """Adam over shuffled batches, epochs first_epoch .. epochs-1.  rng (a
+    numpy Generator) draws each epoch's permutation; on_epoch(epoch, hist)
+    runs after every epoch (checkpointing).  Returns the loss history of
+    these epochs."""
+    import torch
+    nb = len(ftr) // batch
+    hist = []
+    for ep in range(first_epoch, epochs):
+        order = torch.as_tensor(rng.permutation(len(ftr)), device="cuda")
+        for b in range(nb):
+            idx = order[b * batch:(b + 1) * batch]
+            net.loss_grad(ftr[idx].contiguous(), ltr[idx].contiguous(), cw, want_loss=False)
+            net.adam(lr=lr)
+        ltrain, _ = net.loss_grad(ftr[:256].contiguous(), ltr[:256].contiguous(), cw)
+        rec = dict(epoch=ep + 1, train_loss=ltrain)
+        if fva is not None:
+            rec["val_loss"] = net.loss_grad(fva, lva, cw)[0]
+        hist.append(rec)
+        log(f"epoch {ep + 1}: train {ltrain:.4f}" + (f"  held-out {rec['val_loss']:.4f}" if fva is not None else ""))
+        if on_epoch is not None:
+            on_epoch(ep + 1, hist)
+    return hist
+
+
 def evaluate_labels(net, feats, labels):
     import torch
     z = net.forward(feats)[..., :6]
@@ -110,6 +135,12 @@ def main():
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--init-seed", type=int, default=0)
     ap.add_argument("--out", default=os.path.join(HERE, "weights", "depth_cnn"))
+    ap.add_argument("--data-cache", default=None,
+                    help=".npz of the training and held-out maps and labels: read if present, else written")
+    ap.add_argument("--checkpoint", default=None,
+                    help="path prefix: <prefix>.ckpt (network and optimiser) and <prefix>.json (epoch, "
+                         "history, shuffling state) written after every epoch")
+    ap.add_argument("--resume", action="store_true", help="continue from --checkpoint if it exists")
     args = ap.parse_args()
 
     import torch
@@ -117,10 +148,23 @@ def main():
     ctx = air.Context(0)
     train_seeds = list(range(1, args.train + 1))
     val_seeds = list(range(args.train + 1, args.train + args.val + 1))
-    log(f"building {len(train_seeds)} training and {len(val_seeds)} held-out maps")
     t0 = time.time()
-    ftr, ltr = build_dataset(ctx, train_seeds)
-    fva, lva = build_dataset(ctx, val_seeds)
+    if args.data_cache and os.path.exists(args.data_cache):
+        log(f"maps and labels from {args.data_cache}")
+        z = np.load(args.data_cache)
+        assert z["train_seeds"].tolist() == [1, args.train] and z["val_seeds"].tolist() == [len(train_seeds) + 1,
+                                                                                            len(train_seeds) +
+                                                                                            args.val], \
+            "the cache holds other seeds"
+        ftr, ltr, fva, lva = (torch.from_numpy(z[k]).cuda() for k in ("ftr", "ltr", "fva", "lva"))
+    else:
+        log(f"building {len(train_seeds)} training and {len(val_seeds)} held-out maps")
+        ftr, ltr = build_dataset(ctx, train_seeds)
+        fva, lva = build_dataset(ctx, val_seeds)
+        if args.data_cache:
+            np.savez(args.data_cache, ftr=ftr.cpu().numpy(), ltr=ltr.cpu().numpy(), fva=fva.cpu().numpy(),
+                     lva=lva.cpu().numpy(), train_seeds=np.array([1, args.train]),
+                     val_seeds=np.array([len(train_seeds) + 1, len(train_seeds) + args.val]))
     t_data = time.time() - t0
     # standardisation and class weights from the training set
     flat = ftr.reshape(-1, 4).double()
@@ -134,19 +178,22 @@ def main():
 
     net = air.Network(ctx, inputs.cnn_init(args.init_seed), mean, scale)
     rng = np.random.default_rng(1234)
-    hist = []
-    nb = len(train_seeds) // args.batch
+    hist, first = [], 0
+    if args.resume and args.checkpoint and os.path.exists(args.checkpoint + ".json"):
+        meta = json.load(open(args.checkpoint + ".json"))
+        net.load(args.checkpoint + ".ckpt")
+        rng.bit_generator.state = meta["rng"]
+        hist, first = meta["history"], meta["epoch"]
+        log(f"resumed after epoch {first} from {args.checkpoint}")
+
+    def save(epoch, h):
+        if args.checkpoint:
+            net.save(args.checkpoint + ".ckpt")
+            with open(args.checkpoint + ".json", "w") as fh:
+                json.dump(dict(epoch=epoch, history=hist + h, rng=rng.bit_generator.state), fh)
+
     t1 = time.time()
-    for ep in range(args.epochs):
-        order = torch.as_tensor(rng.permutation(len(train_seeds)), device="cuda")
-        for b in range(nb):
-            idx = order[b * args.batch:(b + 1) * args.batch]
-            net.loss_grad(ftr[idx].contiguous(), ltr[idx].contiguous(), cw, want_loss=False)
-            net.adam(lr=args.lr)
-        ltrain, _ = net.loss_grad(ftr[:256].contiguous(), ltr[:256].contiguous(), cw)
-        lval, _ = net.loss_grad(fva, lva, cw)
-        hist.append(dict(epoch=ep + 1, train_loss=ltrain, val_loss=lval))
-        log(f"epoch {ep + 1}: train {ltrain:.4f}  held-out {lval:.4f}")
+    hist = hist + train_epochs(net, ftr, ltr, cw, args.epochs, args.batch, args.lr, rng, first, save, fva, lva)
     torch.cuda.synchronize()
     t_train = time.time() - t1
     ev = evaluate_labels(net, fva, lva)
