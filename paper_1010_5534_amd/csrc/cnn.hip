@@ -7,10 +7,11 @@
 // even), logits float32.  A convolution
 //   y[p, o] = bias[o] + sum_{ky, kx, c} x[p shifted by (ky-1, kx-1), c] W[o, ky, kx, c]
 // is the product D = A B with A = W as a [rows][K] matrix (K = 9 taps x
-// stored input channels, padded to 32) and B[k][p] = the shifted input; one
-// wave computes 16-pixel column blocks for every output row, four per pass,
-// holding all of A in registers, and each lane gathers its pixel's 8
-// consecutive channels of one tap with a single 16-byte load.  The input
+// stored input channels, padded to 32) and B[k][p] = the shifted input; a
+// block stages a 16 x 16 pixel tile of the input with its halo in LDS and
+// its waves compute 16-pixel column blocks for every output row, holding all
+// of A in registers, each lane reading its pixel's 8 consecutive channels
+// of one tap with a single 16-byte LDS load.  The input
 // gradient is the same product with the flipped, transposed weights; the
 // weight gradient stages 64-pixel chunks of both operands transposed in LDS
 // and reduces over pixels into per-block partials that one more kernel sums
@@ -105,89 +106,113 @@ enum { MODE_HIDDEN = 0, MODE_LOGITS = 1, MODE_MASK = 2 };
 
 // D[rows][pixels] = A[rows][K] B[K][pixels]; CS = stored input channels,
 // CSO = stored output channels, NBIAS = real output channels (bias length).
-// A wave keeps all of A in registers and takes CONV_TPW 16-pixel tiles per
-// pass (their gathers issued together), so the weights are read once per
-// wave rather than once per tile.
-constexpr int CONV_TPW = 4;
+// A block takes 16 x 16 output pixels of one map at a time: the input tile
+// with its one-pixel halo (18 x 18 pixels) is staged in LDS once, so an
+// input pixel leaves L2 about 1.27 times instead of once per tap, and the
+// B operands are 16-byte LDS reads; each wave computes four of the tile's
+// rows as 16-pixel column blocks with all of A in registers (loaded once per
+// block through LDS).  Tiles are taken in a grid-stride loop, the next
+// tile's input loaded while the current one is multiplied.
+constexpr int CT = 16;         // output tile edge
+constexpr int CTH = CT + 2;    // with the halo
 constexpr int CONV_MAX_BLOCKS = 1024;
+// bf16 per staged pixel: 32 channels padded to 40 spread a column block's
+// 16-byte reads over the LDS banks
+template <int CS>
+constexpr int conv_px_stride() {
+  return CS == 32 ? 40 : CS;
+}
 
 template <int CS, int RW, int CSO, int MODE>
 __global__ __launch_bounds__(256) void k_conv(const uint16_t* __restrict__ wmat, const float* __restrict__ bias,
                                               int nbias, const uint16_t* __restrict__ x,
                                               const uint16_t* __restrict__ act, int n, int h, int w,
                                               void* __restrict__ out) {
-  constexpr int K = 9 * CS, KP = (K + 31) / 32 * 32, KS = KP / 32, MB = RW / 16;
-  const int lane = threadIdx.x & (WAVE - 1), g = lane >> 4, c16 = lane & 15;
+  constexpr int K = 9 * CS, KP = (K + 31) / 32 * 32, KS = KP / 32, MB = RW / 16, PS = conv_px_stride<CS>();
+  constexpr int OCT = CS / 8, ROWS_PER_WAVE = CT / 4;
+  static_assert(CS % 8 == 0 && RW % 16 == 0, "operand shapes");
+  __shared__ __attribute__((aligned(16))) uint16_t xt[CTH * CTH * PS];
+  __shared__ __attribute__((aligned(16))) uint16_t at[RW * KP];
+  const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE, g = lane >> 4, c16 = lane & 15;
+  for (int e = threadIdx.x; e < RW * KP / 8; e += blockDim.x)
+    *reinterpret_cast<u16x8*>(at + 8 * e) = *reinterpret_cast<const u16x8*>(wmat + 8 * e);
+  __syncthreads();
   u16x8 a[MB][KS];
 #pragma unroll
   for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks)
-      a[mb][ks] = *reinterpret_cast<const u16x8*>(wmat + (mb * 16 + c16) * KP + ks * 32 + 8 * g);
-  const int P = n * h * w, tiles = (P + 15) / 16;  // P < 2^25, checked by the caller
-  const int nwaves = (gridDim.x * blockDim.x) / WAVE;
-  for (int t0 = ((blockIdx.x * blockDim.x + threadIdx.x) / WAVE) * CONV_TPW; t0 < tiles; t0 += nwaves * CONV_TPW) {
-    int p[CONV_TPW], xx[CONV_TPW], y[CONV_TPW], base[CONV_TPW];
-    bool ok[CONV_TPW];
+      a[mb][ks] = *reinterpret_cast<const u16x8*>(at + (mb * 16 + c16) * KP + ks * 32 + 8 * g);
+  const int tx = (w + CT - 1) / CT, ty = (h + CT - 1) / CT, tiles = n * tx * ty;  // n h w < 2^25
+  // the halo tile's 16-byte pieces, held in registers between their load
+  // and their LDS store so that the next tile's loads fly during this
+  // tile's products
+  constexpr int HL = (CTH * CTH * OCT + 255) / 256;
+  u16x8 hv[HL];
+  auto load_halo = [&](int t) {
+    const int b = t / (tx * ty), r = t - b * (tx * ty), y0 = (r / tx) * CT, x0 = (r % tx) * CT;
 #pragma unroll
-    for (int u = 0; u < CONV_TPW; ++u) {
-      p[u] = (t0 + u) * 16 + c16;
-      ok[u] = p[u] < P;
-      const int row = ok[u] ? p[u] / w : 0;
-      xx[u] = ok[u] ? p[u] - row * w : 0;
-      y[u] = row % h;
-      base[u] = (row - y[u]) * w;  // first pixel of the map
+    for (int q = 0; q < HL; ++q) {
+      const int e = threadIdx.x + 256 * q;
+      const int o = e % OCT, px = e / OCT, yy = y0 - 1 + px / CTH, xx = x0 - 1 + px % CTH;
+      hv[q] = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
+      if (e < CTH * CTH * OCT && (unsigned)yy < (unsigned)h && (unsigned)xx < (unsigned)w)
+        hv[q] = *reinterpret_cast<const u16x8*>(x + ((b * h + yy) * w + xx) * CS + 8 * o);
     }
-    f32x4 acc[CONV_TPW][MB];
+  };
+  if (blockIdx.x < tiles) load_halo(blockIdx.x);
+  for (int t = blockIdx.x; t < tiles; t += gridDim.x) {
+    const int b = t / (tx * ty), r = t - b * (tx * ty), y0 = (r / tx) * CT, x0 = (r % tx) * CT;
+    __syncthreads();  // the previous tile's reads of xt are done
 #pragma unroll
-    for (int u = 0; u < CONV_TPW; ++u)
+    for (int q = 0; q < HL; ++q) {
+      const int e = threadIdx.x + 256 * q;
+      if (e < CTH * CTH * OCT) *reinterpret_cast<u16x8*>(xt + (e / OCT) * PS + 8 * (e % OCT)) = hv[q];
+    }
+    __syncthreads();
+    if (t + (int)gridDim.x < tiles) load_halo(t + gridDim.x);
+#pragma unroll 1
+    for (int rr = 0; rr < ROWS_PER_WAVE; ++rr) {
+      const int row = wv * ROWS_PER_WAVE + rr, y = y0 + row, xq = x0 + c16;
+      f32x4 acc[MB];
 #pragma unroll
-      for (int mb = 0; mb < MB; ++mb) acc[u][mb] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+      for (int mb = 0; mb < MB; ++mb) acc[mb] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-      const int k0 = ks * 32 + 8 * g;
-      const int tap = k0 / CS, c0 = k0 % CS, dy = tap / 3 - 1, dx = tap % 3 - 1;
-      u16x8 bv[CONV_TPW];
+      for (int ks = 0; ks < KS; ++ks) {
+        const int k0 = ks * 32 + 8 * g;
+        const int tap = k0 / CS, c0 = k0 % CS, dy = tap / 3, dx = tap % 3;
+        u16x8 bv = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (k0 < K) bv = *reinterpret_cast<const u16x8*>(xt + ((row + dy) * CTH + c16 + dx) * PS + c0);
 #pragma unroll
-      for (int u = 0; u < CONV_TPW; ++u) {
-        const int yy = y[u] + dy, xs = xx[u] + dx;
-        const bool in = ok[u] && k0 < K && (unsigned)yy < (unsigned)h && (unsigned)xs < (unsigned)w;
-        bv[u] = in ? *reinterpret_cast<const u16x8*>(x + (base[u] + yy * w + xs) * CS + c0)
-                   : u16x8{0, 0, 0, 0, 0, 0, 0, 0};
+        for (int mb = 0; mb < MB; ++mb) acc[mb] = mfma(a[mb][ks], bv, acc[mb]);
       }
-#pragma unroll
-      for (int u = 0; u < CONV_TPW; ++u)
-#pragma unroll
-        for (int mb = 0; mb < MB; ++mb) acc[u][mb] = mfma(a[mb][ks], bv[u], acc[u][mb]);
-    }
-    // lane holds rows mb*16 + 4g + i of pixel p
-#pragma unroll
-    for (int u = 0; u < CONV_TPW; ++u) {
-      if (!ok[u]) continue;
+      if (y >= h || xq >= w) continue;
+      const int64_t p = ((int64_t)b * h + y) * w + xq;
+      // lane holds rows mb*16 + 4g + i of pixel p
 #pragma unroll
       for (int mb = 0; mb < MB; ++mb) {
         const int r0 = mb * 16 + 4 * g;
         if (r0 >= CSO) continue;
         if constexpr (MODE == MODE_LOGITS) {
           float4 o;
-          o.x = acc[u][mb][0] + (r0 + 0 < nbias ? bias[r0 + 0] : 0.0f);
-          o.y = acc[u][mb][1] + (r0 + 1 < nbias ? bias[r0 + 1] : 0.0f);
-          o.z = acc[u][mb][2] + (r0 + 2 < nbias ? bias[r0 + 2] : 0.0f);
-          o.w = acc[u][mb][3] + (r0 + 3 < nbias ? bias[r0 + 3] : 0.0f);
-          *reinterpret_cast<float4*>(static_cast<float*>(out) + (int64_t)p[u] * CSO + r0) = o;
+          o.x = acc[mb][0] + (r0 + 0 < nbias ? bias[r0 + 0] : 0.0f);
+          o.y = acc[mb][1] + (r0 + 1 < nbias ? bias[r0 + 1] : 0.0f);
+          o.z = acc[mb][2] + (r0 + 2 < nbias ? bias[r0 + 2] : 0.0f);
+          o.w = acc[mb][3] + (r0 + 3 < nbias ? bias[r0 + 3] : 0.0f);
+          *reinterpret_cast<float4*>(static_cast<float*>(out) + p * CSO + r0) = o;
         } else {
           u16x4 o;
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
-            float v = acc[u][mb][i];
+            float v = acc[mb][i];
             if constexpr (MODE == MODE_HIDDEN) {
               v = fmaxf(v + (r0 + i < nbias ? bias[r0 + i] : 0.0f), 0.0f);
             } else {
-              v = bf_pos(act[(int64_t)p[u] * CSO + r0 + i]) ? v : 0.0f;
+              v = bf_pos(act[p * CSO + r0 + i]) ? v : 0.0f;
             }
             o[i] = f2bf(v);
           }
-          *reinterpret_cast<u16x4*>(static_cast<uint16_t*>(out) + (int64_t)p[u] * CSO + r0) = o;
+          *reinterpret_cast<u16x4*>(static_cast<uint16_t*>(out) + p * CSO + r0) = o;
         }
       }
     }
@@ -478,9 +503,9 @@ __global__ __launch_bounds__(256) void k_adam(float* theta, float* m, float* v, 
   }
 }
 
-int conv_blocks(int64_t P) {
-  const int64_t tiles = (P + 15) / 16, per_block = 4 * CONV_TPW;  // 4 waves per block
-  return (int)std::min<int64_t>(std::max<int64_t>((tiles + per_block - 1) / per_block, 1), CONV_MAX_BLOCKS);
+int conv_blocks(int n, int h, int w) {
+  const int64_t tiles = (int64_t)n * ((h + CT - 1) / CT) * ((w + CT - 1) / CT);
+  return (int)std::min<int64_t>(std::max<int64_t>(tiles, 1), CONV_MAX_BLOCKS);
 }
 
 // ---------------------------------------------------------------- inference
@@ -640,7 +665,7 @@ hipError_t input_maps(const float* feat, int64_t P, const float* mean, const flo
 hipError_t conv_forward(int l, const Net& net, const uint16_t* x, int n, int h, int w, void* y, hipStream_t s) {
   const Offsets o = offsets();
   const float* bias = net.theta + o.b[l];
-  const int blocks = conv_blocks((int64_t)n * h * w);
+  const int blocks = conv_blocks(n, h, w);
   switch (l) {
     case 0:
       hipLaunchKernelGGL((k_conv<XC, HID, HID, MODE_HIDDEN>), dim3(blocks), dim3(256), 0, s, net.wf[0], bias, HID, x,
@@ -660,7 +685,7 @@ hipError_t conv_forward(int l, const Net& net, const uint16_t* x, int n, int h, 
 
 hipError_t conv_input_grad(int l, const Net& net, const uint16_t* dy, const uint16_t* act, int n, int h, int w,
                            uint16_t* dx, hipStream_t s) {
-  const int blocks = conv_blocks((int64_t)n * h * w);
+  const int blocks = conv_blocks(n, h, w);
   if (l == 3)
     hipLaunchKernelGGL((k_conv<ZC, HID, HID, MODE_MASK>), dim3(blocks), dim3(256), 0, s, net.wt[3], nullptr, 0, dy,
                        act, n, h, w, dx);
