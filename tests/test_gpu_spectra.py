@@ -32,7 +32,9 @@ def ctx():
     c.close()
 
 
-@pytest.mark.parametrize("n_bins,seed,direction", [(64, 2, (0.3, 0.5, 0.8)), (300, 5, (1, 1, 1)), (7, 1, (0, 0, 1))])
+# 1 bin and the maximum of 1024 (four passes of 256) are the edges
+@pytest.mark.parametrize("n_bins,seed,direction", [(64, 2, (0.3, 0.5, 0.8)), (300, 5, (1, 1, 1)), (7, 1, (0, 0, 1)),
+                                                   (1, 4, (0.6, -0.2, 0.7)), (1024, 6, (-0.5, 0.4, 0.3))])
 def test_spectra_match_oracle(ctx, n_bins, seed, direction):
     from paper_1010_5534_amd import air
     g, f = inputs.winds2(seed=seed, n=48, kind=inputs.FIELD_RHO_T, bands=inputs.default_bands(1))
@@ -83,3 +85,16 @@ def test_spectra_bins_per_pass_edges(ctx):
         # the nodes of a tree that does not depend on it: level 0
         n0 = 64
         assert torch.equal(part[1][0, :n0], big[1][0, :n0, :nb])
+
+
+def test_spectra_bin_count_limits(ctx):
+    """0 bins and more than AIR_MAX_BINS are rejected before any launch."""
+    from paper_1010_5534_amd import air
+    g, f = inputs.winds2(seed=3, n=16, kind=inputs.FIELD_RHO_T, bands=inputs.default_bands(1))
+    scene = air.upload(g, f)
+    v = inputs.view_for((0.0, 0.0, 1.0))
+    table, w = inputs.spectral_bins(1025)
+    for nb in (0, 1025):
+        with pytest.raises(air.AirError) as e:
+            ctx.render_spectra(scene, [v], air.params(8, 1, 0.5), table[:nb], w[:nb])
+        assert e.value.code == air.AIR_EINVAL
