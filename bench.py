@@ -255,6 +255,67 @@ def learned_eval(ctx, air, inputs, np, torch, args, seeds=range(2001, 2009)):
                 rays_traced=rays, missing=missing, outputs_equal_to_plain=equal, c_ray=c_ray, c_sweep=c_sweep)
 
 
+def ring_learned(ctx, air, inputs, np, torch, args):
+    """The learned proposal on the section-3 ring family (network trained on
+    ring geometries 1..8; geometries 0 = the section's ring, 9 and 10 held
+    out): 32x32 coarse, 4 levels, xi_crit 0.2, per held-out render the median
+    device time of plain AIR, the learned proposal (committed ring network
+    and cost model), speculation to the true depths and to a constant depth
+    2.  Renders: the section's face-on view of ring 0, then held-out keys
+    41..52 of the training script's ring family (geometry (0, 9, 10)[s mod
+    3], view seed 1000000 + s), which were not used to pick the cost model.
+    Every proposal's output is checked equal to plain AIR's."""
+    log("learned proposal: ring family")
+    wz = np.load(os.path.join(ROOT, "paper_1010_5534_amd", "weights", "ring_cnn.npz"))
+    net = air.Network(ctx, wz["params"], wz["mean"], wz["scale"])
+    c_ray, c_sweep = float(wz["c_ray"]), float(wz["c_sweep"])
+    n0, lm, xc = 32, 4, 0.2
+    prm = air.params(n0, lm, xc)
+    scenes = {}
+
+    def scene(k):
+        if k not in scenes:
+            g, f = inputs.ring(**inputs.ring_geometry(k))
+            scenes[k] = ctx.prepare(air.upload(g, f))
+        return scenes[k]
+
+    renders = [(0, inputs.ring_view(), "ring 0 face-on")]
+    renders += [((0, 9, 10)[s % 3], inputs.ring_family_view(1000000 + s), f"key {s}") for s in range(41, 53)]
+    names = ("plain", "learned", "true_depth", "depth2")
+    tot = {k: 0.0 for k in names}
+    rays = {k: 0 for k in names}
+    rows, equal = [], True
+    for k, view, label in renders:
+        sc = scene(k)
+        ref = ctx.render(sc, [view], prm, reuse=False)
+        depth = ctx.tree_depth(ref[0][0], n0).to(torch.uint8)[None]
+        runs = {"plain": lambda: ctx.render(sc, [view], prm, reuse=True),
+                "learned": lambda: ctx.render_learned(sc, [view], prm, net, c_ray, c_sweep, max_depth=lm, reuse=True),
+                "true_depth": lambda: ctx.render_proposal(sc, [view], prm, depth, max_depth=lm, reuse=True),
+                "depth2": lambda: ctx.render_proposal(sc, [view], prm, torch.full_like(depth, 2), max_depth=lm,
+                                                      reuse=True)}
+        row = dict(render=label, geometry=k, rays=ref[3]["rays"])
+        for name in names:
+            out, ms = device_median(runs[name], 5, torch)
+            tot[name] += ms
+            rays[name] += out[3]["rays"] + (out[4]["wasted"] if len(out) > 4 else 0)
+            row[name + "_ms"] = ms
+            equal = equal and bool(np.array_equal(out[2], ref[2])
+                                   and torch.equal(out[1].view(torch.int32), ref[1].view(torch.int32))
+                                   and out[0][0].n_nodes == ref[0][0].n_nodes
+                                   and torch.equal(out[0][0].state, ref[0][0].state)
+                                   and torch.equal(out[0][0].I.view(torch.int32), ref[0][0].I.view(torch.int32)))
+        rows.append(row)
+    net.close()
+    n = len(renders)
+    return dict(workload="section-3 ring family, 32x32 coarse, 4 levels, xi_crit 0.2; ring 0 face-on and 12 held-out "
+                         "renders (geometries 0, 9, 10; network trained on geometries 1-8)",
+                per_image_ms={k: v / n for k, v in tot.items()},
+                speedup_vs_plain={k: tot["plain"] / v for k, v in tot.items()},
+                rays_traced=rays, outputs_equal_to_plain=equal, c_ray=c_ray, c_sweep=c_sweep, renders=rows,
+                network="paper_1010_5534_amd/weights/ring_cnn.npz")
+
+
 def hbm_probe(torch):
     """Measured device-to-device copy bandwidth (read + write bytes per
     second) of a 1 GiB buffer, best of 5, beside the vendor's 8 TB/s."""
@@ -499,6 +560,7 @@ def main():
         res["spectra"] = spectra_run(ctx, air, inputs, np, torch, g, f, views, args)
     if not args.skip_learned:
         res["learned_eval"] = learned_eval(ctx, air, inputs, np, torch, args)
+        res["ring_learned"] = ring_learned(ctx, air, inputs, np, torch, args)
     if not args.skip_amr:
         res["batched_amr"] = batched_amr(ctx, air, inputs, np, torch, args)
     if not args.skip_large:

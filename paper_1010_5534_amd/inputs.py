@@ -414,17 +414,19 @@ def uniform_as_amr(grid: Grid, field: Field, bs: int) -> (Grid, Field):
 
 
 # ------------------------------------------------------------ the ring test
-def ring(base_blocks: int = 4, bs: int = 8, max_level: int = 4, beta: float = 2.5e9) -> (Grid, Field):
+def ring(base_blocks: int = 4, bs: int = 8, max_level: int = 4, beta: float = 2.5e9, r_inner: float = 3.5e17,
+         r_outer: float = 4e17, width: float = 1e17) -> (Grid, Field):
     """Section-3 ring (Eq. 1) in scaled units: length unit 1e17 cm, density
     unit 1e-26 g/cm^3 (cgs rho^2 underflows float32).  rho = beta / r_yz^2
     for r_i <= r_yz <= r_o and |x| < w/2, else 1e-25 g/cm^3; T = 1e8 K
-    inside, 1e4 K outside; box +-5e17 cm.  beta is in g/cm.  The block
-    hierarchy is refined where a block straddles the ring surface.  Emission
-    is rho^2 inside the ring and 0 outside (1-10 keV emission of 1e4 K gas is
+    inside, 1e4 K outside; box +-5e17 cm.  beta is in g/cm, the radii and
+    the width in cm (the defaults are the section's).  The block hierarchy
+    is refined where a block straddles the ring surface.  Emission is rho^2
+    inside the ring and 0 outside (1-10 keV emission of 1e4 K gas is
     negligible); no absorption.  Returned as a one-band rho/j/kappa field."""
     lu, du = 1e17, 1e-26
     L = 5e17 / lu
-    w, ri, ro = 1e17 / lu, 3.5e17 / lu, 4e17 / lu
+    w, ri, ro = width / lu, r_inner / lu, r_outer / lu
     beta_s = beta / (lu * lu) / du  # rho[du] = beta_s / r[lu]^2
     lo, hi = (-L, -L, -L), (L, L, L)
 
@@ -454,6 +456,36 @@ def ring(base_blocks: int = 4, bs: int = 8, max_level: int = 4, beta: float = 2.
 def ring_view() -> View:
     """Face-on: looking along +x, up = +z, so (u, v) = (y, z) (Fig. 1 note)."""
     return View((1.0, 0.0, 0.0), (0.0, 0.0, 1.0), (0.0, 0.0, 0.0), 10.0)
+
+
+def ring_geometry(k: int) -> dict:
+    """Ring k of a family for training and evaluating the depth proposal:
+    k = 0 is the section-3 ring; k > 0 draws the inner radius (2.5-4.0e17
+    cm), the radial thickness (0.3-1.0e17 cm, outer radius at most 4.6e17
+    cm) and the width along the axis (0.5-1.5e17 cm) from default_rng(k).
+    Keyword arguments of ring()."""
+    if k == 0:
+        return {}
+    rng = np.random.default_rng(1000 + k)
+    ri = rng.uniform(2.5e17, 4.0e17)
+    ro = min(ri + rng.uniform(0.3e17, 1.0e17), 4.6e17)
+    return dict(r_inner=float(ri), r_outer=float(ro), width=float(rng.uniform(0.5e17, 1.5e17)))
+
+
+def ring_family_view(seed: int) -> View:
+    """A seeded view of the ring family: the looking direction within 70
+    degrees of face-on (+x), uniform in solid angle, a random roll of the
+    up vector, image width 10 (the box face)."""
+    rng = np.random.default_rng(seed)
+    cos_max = math.cos(math.radians(70.0))
+    ct = rng.uniform(cos_max, 1.0)
+    st, ph = math.sqrt(max(0.0, 1.0 - ct * ct)), rng.uniform(0.0, 2.0 * math.pi)
+    d = np.array([ct, st * math.cos(ph), st * math.sin(ph)])
+    # roll: a random direction perpendicular to d
+    a = rng.normal(size=3)
+    up = a - np.dot(a, d) * d
+    up = up / np.linalg.norm(up)
+    return View(tuple(float(x) for x in d), tuple(float(x) for x in up), (0.0, 0.0, 0.0), 10.0)
 
 
 # ------------------------------------------------- depth-proposal network

@@ -390,3 +390,50 @@ def test_proposal_baselines_equal_plain(ctx):
     say(out[4])
     assert out[4]["missing"] == 0
     assert out[4]["spec_rays"] - out[4]["wasted"] == sum(t.n_nodes for t in plain[0]) - V * N0 * N0
+
+
+def test_learned_ring_beats_plain(ctx):
+    """The committed ring network (trained on ring geometries 1-8) on held-out
+    renders of geometries 0, 9 and 10 (keys 41..46 of the training script's
+    ring family): every output equals plain AIR's bit for bit, and the
+    learned proposal takes less device time per image than plain AIR (its
+    levels are latency-bound, so tracing the predicted subtrees in one
+    launch saves more than the extra rays cost)."""
+    import os
+    from paper_1010_5534_amd import air
+    wz = np.load(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1010_5534_amd",
+                              "weights", "ring_cnn.npz"))
+    net = air.Network(ctx, wz["params"], wz["mean"], wz["scale"])
+    c_ray, c_sweep = float(wz["c_ray"]), float(wz["c_sweep"])
+    prm = air.params(32, 4, 0.2)
+    scenes, tp, tl = {}, 0.0, 0.0
+
+    def med(fn):
+        fn()
+        ms = sorted(fn()[3]["ms_total"] for _ in range(5))
+        return ms[2]
+
+    for s in range(41, 47):
+        k = (0, 9, 10)[s % 3]
+        if k not in scenes:
+            g, f = inputs.ring(**inputs.ring_geometry(k))
+            scenes[k] = ctx.prepare(air.upload(g, f))
+        sc, view = scenes[k], inputs.ring_family_view(1000000 + s)
+        ref = ctx.render(sc, [view], prm)
+        out = ctx.render_learned(sc, [view], prm, net, c_ray, c_sweep, max_depth=4)
+        t, r = out[0][0], ref[0][0]
+        assert t.n_nodes == r.n_nodes and np.array_equal(out[2], ref[2])
+        for name in ("level", "ix", "iy", "parent", "first_child", "state", "visits"):
+            assert torch.equal(getattr(t, name), getattr(r, name)), name
+        assert torch.equal(t.I.view(torch.int32), r.I.view(torch.int32))
+        assert torch.equal(out[1].view(torch.int32), ref[1].view(torch.int32))
+        p_ms = med(lambda: ctx.render(sc, [view], prm, reuse=True))
+        l_ms = med(lambda: ctx.render_learned(sc, [view], prm, net, c_ray, c_sweep, max_depth=4, reuse=True))
+        say(f"ring geometry {k} view {1000000 + s}: plain {p_ms:.3f} ms, learned {l_ms:.3f} ms "
+            f"({r.n_nodes} rays; speculative {out[4]['spec_rays']}, wasted {out[4]['wasted']}, "
+            f"missing {out[4]['missing']})")
+        tp, tl = tp + p_ms, tl + l_ms
+    say(f"ring family, 6 held-out renders: plain {tp / 6:.3f} ms, learned {tl / 6:.3f} ms per image "
+        f"({tp / tl:.2f}x)")
+    assert tl < 0.9 * tp
+    net.close()
