@@ -255,7 +255,7 @@ def main():
     # held-out renders, the rest kept for the final evaluation
     pick, rest_keys = fam.val[:40], fam.val[40:]
     sweep = []
-    for cs in (0.0, 20.0, 60.0, 200.0, 600.0, 2000.0, 6000.0, 20000.0):
+    for cs in (0.0, 20.0, 60.0, 200.0, 600.0, 2000.0, 6000.0, 20000.0, 60000.0, 200000.0):
         r = time_renders(ctx, net, fam, pick, 1.0, cs, repeats=2)
         sweep.append(dict(c_sweep=cs, **r))
         log(f"c_sweep {cs}: plain {r['plain_ms']:.3f} ms learned {r['learned_ms']:.3f} ms "
