@@ -13,9 +13,9 @@
 // of A in registers, each lane reading its pixel's 8 consecutive channels
 // of one tap with a single 16-byte LDS load.  The input
 // gradient is the same product with the flipped, transposed weights; the
-// weight gradient stages 64-pixel chunks of both operands transposed in LDS
-// and reduces over pixels into per-block partials that one more kernel sums
-// in a fixed order.
+// weight gradient stages 8 x 8 pixel tiles of both operands transposed in
+// LDS (the input once per tile, with its halo) and reduces over pixels into
+// per-block partials that one more kernel sums in a fixed order.
 #include <algorithm>
 #include <cmath>
 
@@ -221,111 +221,92 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t* __restrict__ wmat,
 
 // weight gradient: G[o][n] = sum_p dy[p, o] X[p, n], n = tap * CS + c, plus
 // the bias column n = 9 CS of ones.  CS = stored input channels, DC = stored
-// dy channels, RW = padded rows.  The reduction runs over pixels, which NHWC
-// stores with channels contiguous, so each 64-pixel chunk of both operands is
-// transposed into LDS: a thread loads 16 bytes (8 channels) of 4 consecutive
-// pixels and writes them as 8 rows of 4 pixels (one 8-byte LDS store each).
-// The next chunk's global loads are issued before the current chunk's
-// matrix products, so their latency hides behind them.  Each wave owns every
-// fourth 16-column block with all row blocks, so a B operand is read from LDS
-// once per k-step.
+// dy channels, RW = padded rows.  The reduction runs over pixels, taken in
+// 8 x 8 tiles of one map (64 pixels, two MFMA k-steps; pixel k of a tile is
+// row k / 8, column k % 8).  dy of the tile is transposed into LDS; the
+// input's 10 x 10 halo is transposed into LDS three times, shifted by the
+// tap's column offset, so the B operand of tap (ky, kx) for a lane's 8
+// pixels (one tile row) is one aligned 16-byte LDS read of copy kx at halo
+// row row + ky.  A thread transposes an 8 x 8 block (8 pixels x 8
+// channels) in registers and stores it as 8 rows of 16 bytes, so an input
+// pixel is loaded at most three times (once per column offset) instead of
+// nine, and no LDS store is narrower than 16 bytes.  The next tile's loads are issued
+// before the current tile's products; each wave owns every fourth 16-column
+// block of G with all row blocks.
 constexpr int WG_BLOCKS = 512;
 constexpr int WG_MAX_FLOATS = HID * ((9 * HID + 1 + 15) / 16 * 16);
-constexpr int WG_CHUNK = 64;
-constexpr int WG_LD = WG_CHUNK + 8;  // LDS row stride in bf16 (144 bytes: conflict-free 16-byte reads)
+constexpr int WG_T = 8;               // tile edge
+constexpr int WG_H = WG_T + 2;        // halo edge
+constexpr int WG_LD = WG_T * WG_T + 8;  // dy row stride in bf16 (144 bytes: conflict-free 16-byte reads)
+constexpr int WG_HR = WG_H + 1;       // halo rows per channel, padded (176 bytes between channels)
 
 template <int CS, int DC, int RW>
 __global__ __launch_bounds__(256) void k_wgrad(const uint16_t* __restrict__ dy, const uint16_t* __restrict__ x,
                                                int n, int h, int w, float* __restrict__ partial) {
   constexpr int N = 9 * CS + 1, NBK = (N + 15) / 16, NP = NBK * 16, MB = RW / 16, NBPW = (NBK + 3) / 4;
-  constexpr int DO = DC / 8, XO = CS / 8, QUADS = WG_CHUNK / 4;
-  constexpr int DT = QUADS * DO, TT = DT + 9 * QUADS * XO, TPT = (TT + 255) / 256;
+  constexpr int DO = DC / 8, XO = CS / 8;
+  // task e: one tile row of dy (8 pixels x 8 channels, e < DT), or one halo
+  // row's 8 pixels starting at column kx (one copy) x 8 channels of the
+  // input; its 8 x 8 block is transposed in registers and stored as 8 rows
+  // of 16 bytes
+  constexpr int DT = WG_T * DO, TT = DT + WG_H * XO * 3;
+  static_assert(TT <= 256, "one task per thread");
   static_assert(DC % 8 == 0 && CS % 8 == 0 && DC <= RW && RW % 16 == 0, "operand shapes");
-  // rows [0, RW): dy transposed; rows [RW, RW + NP): the 9 shifted inputs
-  // transposed, then the ones row of the bias and zero padding
-  __shared__ __attribute__((aligned(16))) uint16_t T[(RW + NP) * WG_LD];
-  __shared__ __attribute__((aligned(16))) int pix_y[WG_CHUNK], pix_x[WG_CHUNK];
+  __shared__ __attribute__((aligned(16))) uint16_t dT[RW * WG_LD];                // [o][pixel]
+  __shared__ __attribute__((aligned(16))) uint16_t hT[3 * CS * WG_HR * WG_T];     // [kx][c][halo row][column]
   const int tid = threadIdx.x, wv = tid / WAVE, lane = tid & (WAVE - 1), g = lane >> 4, c16 = lane & 15;
-  const int P = n * h * w, chunks = (P + WG_CHUNK - 1) / WG_CHUNK;  // P < 2^25, checked by the caller
+  const int tx_n = (w + WG_T - 1) / WG_T, ty_n = (h + WG_T - 1) / WG_T, tiles = n * tx_n * ty_n;  // P < 2^25
 
-  // rows no chunk writes: dy padding rows, the ones row, input padding rows
-  for (int e = tid; e < (RW - DC) * WG_CHUNK; e += 256)
-    T[(DC + e / WG_CHUNK) * WG_LD + e % WG_CHUNK] = 0;
-  for (int e = tid; e < (NP - 9 * CS) * WG_CHUNK; e += 256) {
-    const int r = 9 * CS + e / WG_CHUNK;
-    T[(RW + r) * WG_LD + e % WG_CHUNK] = r == 9 * CS ? BF16_ONE : (uint16_t)0;
-  }
-  // (y, x) of a chunk's pixels; y far out of range past the last pixel
-  auto set_pix = [&](int c) {
-    if (tid < WG_CHUNK) {
-      const int p = c * WG_CHUNK + tid;
-      int yy = -(1 << 28), xx = 0;
-      if (p < P) {
-        const int row = p / w;
-        xx = p - row * w;
-        yy = row % h;
-      }
-      pix_y[tid] = yy;
-      pix_x[tid] = xx;
+  // dy rows no tile writes stay zero
+  for (int e = tid; e < (RW - DC) * WG_LD; e += 256) dT[DC * WG_LD + e] = 0;
+  u16x8 v[WG_T];
+  auto load = [&](int t) {
+    const int b = t / (tx_n * ty_n), r = t - b * (tx_n * ty_n), y0 = (r / tx_n) * WG_T, x0 = (r % tx_n) * WG_T;
+    int yy, xs, stride, oct;
+    const uint16_t* base;
+    if (tid < DT) {
+      oct = tid % DO;
+      yy = y0 + tid / DO;
+      xs = x0;
+      base = dy;
+      stride = DC;
+    } else {
+      const int f = tid - DT, kx = f % 3, rest = f / 3;
+      oct = rest % XO;
+      yy = y0 - 1 + rest / XO;
+      xs = x0 - 1 + kx;
+      base = x;
+      stride = CS;
     }
-  };
-  // task e: 4 consecutive pixels x 8 channels of dy (e < DT) or of one tap
-  // of the input
-  u16x8 v[TPT][4];
-  auto load = [&](int c) {
+    const bool row_ok = tid < TT && (unsigned)yy < (unsigned)h;
 #pragma unroll
-    for (int k = 0; k < TPT; ++k) {
-      const int e = tid + 256 * k;
-      if (e >= TT) break;
-      const uint16_t* base;
-      int oct, quad, stride, sy = 0, sx = 0;
-      if (e < DT) {
-        oct = e % DO;
-        quad = e / DO;
-        base = dy;
-        stride = DC;
-      } else {
-        const int f = e - DT, rest = f / XO, tap = rest / QUADS;
-        oct = f % XO;
-        quad = rest % QUADS;
-        base = x;
-        stride = CS;
-        sy = tap / 3 - 1;
-        sx = tap % 3 - 1;
-      }
-      const int4 py = *reinterpret_cast<const int4*>(&pix_y[4 * quad]);
-      const int4 px = *reinterpret_cast<const int4*>(&pix_x[4 * quad]);
-      const int ys[4] = {py.x, py.y, py.z, py.w}, xs[4] = {px.x, px.y, px.z, px.w};
-      const int p0 = c * WG_CHUNK + 4 * quad + sy * w + sx;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const bool ok = (unsigned)(ys[j] + sy) < (unsigned)h && (unsigned)(xs[j] + sx) < (unsigned)w;
-        v[k][j] = ok ? *reinterpret_cast<const u16x8*>(base + (p0 + j) * stride + 8 * oct)
-                     : u16x8{0, 0, 0, 0, 0, 0, 0, 0};
-      }
+    for (int j = 0; j < WG_T; ++j) {
+      v[j] = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
+      if (row_ok && (unsigned)(xs + j) < (unsigned)w)
+        v[j] = *reinterpret_cast<const u16x8*>(base + ((b * h + yy) * w + xs + j) * stride + 8 * oct);
     }
   };
   auto store = [&]() {
+    if (tid >= TT) return;
+    uint16_t* dst;
+    int row_stride;
+    if (tid < DT) {
+      dst = dT + (8 * (tid % DO)) * WG_LD + (tid / DO) * WG_T;
+      row_stride = WG_LD;
+    } else {
+      const int f = tid - DT, kx = f % 3, rest = f / 3;
+      dst = hT + ((kx * CS + 8 * (rest % XO)) * WG_HR + rest / XO) * WG_T;
+      row_stride = WG_HR * WG_T;
+    }
+    // transpose: row i (channel) holds the 8 pixels' channel i
 #pragma unroll
-    for (int k = 0; k < TPT; ++k) {
-      const int e = tid + 256 * k;
-      if (e >= TT) break;
-      int row, quad;
-      if (e < DT) {
-        row = 8 * (e % DO);
-        quad = e / DO;
-      } else {
-        const int f = e - DT, rest = f / XO;
-        row = RW + (rest / QUADS) * CS + 8 * (f % XO);
-        quad = rest % QUADS;
-      }
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        uint2 pr;
-        pr.x = (uint32_t)v[k][0][i] | ((uint32_t)v[k][1][i] << 16);
-        pr.y = (uint32_t)v[k][2][i] | ((uint32_t)v[k][3][i] << 16);
-        *reinterpret_cast<uint2*>(&T[(row + i) * WG_LD + 4 * quad]) = pr;
-      }
+    for (int i = 0; i < 8; ++i) {
+      uint4 q;
+      q.x = (uint32_t)v[0][i] | ((uint32_t)v[1][i] << 16);
+      q.y = (uint32_t)v[2][i] | ((uint32_t)v[3][i] << 16);
+      q.z = (uint32_t)v[4][i] | ((uint32_t)v[5][i] << 16);
+      q.w = (uint32_t)v[6][i] | ((uint32_t)v[7][i] << 16);
+      *reinterpret_cast<uint4*>(dst + i * row_stride) = q;
     }
   };
 
@@ -334,44 +315,45 @@ __global__ __launch_bounds__(256) void k_wgrad(const uint16_t* __restrict__ dy, 
   for (int t = 0; t < NBPW; ++t)
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb) acc[t][mb] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-  int ch = blockIdx.x;  // the launch has at most `chunks` blocks
-  set_pix(ch);
-  __syncthreads();
-  load(ch);
-  for (; ch < chunks; ch += gridDim.x) {
-    __syncthreads();  // the previous chunk's products have read T, the loads have read pix
+  int t = blockIdx.x;  // the launch has at most `tiles` blocks
+  load(t);
+  for (; t < tiles; t += gridDim.x) {
+    __syncthreads();  // the previous tile's products have read dT and hT
     store();
-    const int nx = ch + gridDim.x;
-    if (nx < chunks) set_pix(nx);
     __syncthreads();
-    if (nx < chunks) load(nx);
+    if (t + (int)gridDim.x < tiles) load(t + gridDim.x);
     u16x8 a[MB][2];
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
       for (int kk = 0; kk < 2; ++kk)
-        a[mb][kk] = *reinterpret_cast<const u16x8*>(&T[(mb * 16 + c16) * WG_LD + kk * 32 + 8 * g]);
+        a[mb][kk] = *reinterpret_cast<const u16x8*>(&dT[(mb * 16 + c16) * WG_LD + kk * 32 + 8 * g]);
 #pragma unroll
-    for (int t = 0; t < NBPW; ++t) {
-      const int nb = wv + 4 * t;
+    for (int q = 0; q < NBPW; ++q) {
+      const int nb = wv + 4 * q;
       if (nb >= NBK) break;  // uniform per wave
+      const int col = nb * 16 + c16, tap = col / CS, c = col % CS, ky = tap / 3, kx = tap % 3;
 #pragma unroll
       for (int kk = 0; kk < 2; ++kk) {
-        const u16x8 b = *reinterpret_cast<const u16x8*>(&T[(RW + nb * 16 + c16) * WG_LD + kk * 32 + 8 * g]);
+        u16x8 bv = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (col < 9 * CS)
+          bv = *reinterpret_cast<const u16x8*>(&hT[((kx * CS + c) * WG_HR + 4 * kk + g + ky) * WG_T]);
+        else if (col == 9 * CS)
+          bv = u16x8{BF16_ONE, BF16_ONE, BF16_ONE, BF16_ONE, BF16_ONE, BF16_ONE, BF16_ONE, BF16_ONE};
 #pragma unroll
-        for (int mb = 0; mb < MB; ++mb) acc[t][mb] = mfma(a[mb][kk], b, acc[t][mb]);
+        for (int mb = 0; mb < MB; ++mb) acc[q][mb] = mfma(a[mb][kk], bv, acc[q][mb]);
       }
     }
   }
   float* out = partial + (int64_t)blockIdx.x * RW * NP;
 #pragma unroll
-  for (int t = 0; t < NBPW; ++t) {
-    const int nb = wv + 4 * t;
+  for (int q = 0; q < NBPW; ++q) {
+    const int nb = wv + 4 * q;
     if (nb >= NBK) break;
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) out[(mb * 16 + 4 * g + i) * NP + nb * 16 + c16] = acc[t][mb][i];
+      for (int i = 0; i < 4; ++i) out[(mb * 16 + 4 * g + i) * NP + nb * 16 + c16] = acc[q][mb][i];
   }
 }
 
@@ -701,7 +683,8 @@ hipError_t conv_weight_grad(int l, const Net& net, const uint16_t* dy, const uin
                             float* partial, hipStream_t s) {
   const int64_t P = (int64_t)n * h * w;
   if (P < 1 || P >= ((int64_t)1 << 25)) return hipErrorInvalidValue;  // the kernel indexes pixels in 32 bits
-  const int blocks = (int)std::min<int64_t>((P + WG_CHUNK - 1) / WG_CHUNK, WG_BLOCKS);
+  const int64_t tiles = (int64_t)n * ((h + WG_T - 1) / WG_T) * ((w + WG_T - 1) / WG_T);
+  const int blocks = (int)std::min<int64_t>(tiles, WG_BLOCKS);
   const Offsets o = offsets();
   int cs, rw;
   if (l == 0) {
