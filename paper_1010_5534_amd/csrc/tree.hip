@@ -262,8 +262,12 @@ __device__ __forceinline__ unsigned long long block_sum_u64(unsigned long long x
 }
 
 // the raster of the leaves: each thread paints QX consecutive pixels of one
-// row of view v (block xb of the view's pixels), each descending from its
-// coarse pixel to the leaf that holds it (16-byte stores when QX = 4)
+// row of view v (block xb of the view's pixels).  An ancestor's key follows
+// from the pixel alone, so the state bytes of every level above the pixels
+// are loaded together (one round of loads, not one per level), the leaf is
+// the shallowest ancestor that is not refined, and its value is gathered.
+// QX = 4 (i a multiple of 4): levels up to Lm - 2 are shared by the four
+// pixels, level Lm - 1 by pairs; 16-byte stores.
 template <int QX>
 __device__ __forceinline__ void paint_pixels(const MarchArgs& A, float* images, int v, int64_t xb) {
   const int N0 = A.img.N0, Lm = A.img.Lmax, nb = A.f.nb;
@@ -273,45 +277,89 @@ __device__ __forceinline__ void paint_pixels(const MarchArgs& A, float* images, 
   const int64_t e = (xb * 256 + threadIdx.x) * QX;
   if (e >= R2) return;
   const uint32_t i = (uint32_t)(e % R), j = (uint32_t)(e / R);
-  // the QX pixels (i a multiple of QX) lie in one node of level Lm - log2 QX:
-  // descend there once, then per pixel
-  constexpr int LQ = QX == 4 ? 2 : 0;
-  uint32_t key = (j >> Lm) * (uint32_t)N0 + (i >> Lm);
-  int L = 0;
-  int64_t p0 = vb + key;
-  while (L < Lm - LQ && (A.w.state[p0] & AIR_NODE_REFINED)) {
-    ++L;
-    const int sh = Lm - L;
-    key = 4u * key + (((i >> sh) & 1u) | (((j >> sh) & 1u) << 1));
-    p0 = vb + A.img.off[L] + key;
+  const uint8_t* state = A.w.state + vb;
+  int64_t offm = 0, offm1 = 0;  // offsets of levels Lm and Lm - 1 (selected statically: uniform registers)
+#pragma unroll
+  for (int L = 0; L <= MAXL; ++L) {
+    if (L == Lm) offm = A.img.off[L];
+    if (L == Lm - 1) offm1 = A.img.off[L];
   }
+  // shared levels 0 .. ng - 1, their keys and state bytes
+  const int ng = QX == 4 ? max(Lm - 1, 0) : Lm;
+  uint32_t kk[MAXL];
+  uint8_t st[MAXL];
+  uint32_t key = (j >> Lm) * (uint32_t)N0 + (i >> Lm);
+#pragma unroll
+  for (int L = 0; L < MAXL; ++L) {
+    kk[L] = 0;
+    st[L] = 0;
+    if (L < ng) {  // uniform
+      if (L > 0) {
+        const int sh = Lm - L;
+        key = 4u * key + (((i >> sh) & 1u) | (((j >> sh) & 1u) << 1));
+      }
+      kk[L] = key;
+      st[L] = state[A.img.off[L] + key];
+    }
+  }
+  // QX = 4: the pairs' level-(Lm - 1) nodes (i0 = 4k, so pair h's bit along u is h)
+  uint32_t kp[2] = {0u, 0u};
+  uint8_t sp[2] = {0, 0};
+  if (QX == 4 && Lm >= 1) {
+    const uint32_t base = Lm >= 2 ? 4u * key + (((j >> 1) & 1u) << 1) : (j >> 1) * (uint32_t)N0 + (i >> 1);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      kp[h] = base + (uint32_t)h;
+      sp[h] = state[offm1 + kp[h]];
+    }
+  }
+  int lf = ng;  // the shallowest shared level whose node is a leaf, ng if none
+#pragma unroll
+  for (int L = MAXL - 1; L >= 0; --L)
+    if (L < ng && !(st[L] & AIR_NODE_REFINED)) lf = L;
+  int64_t pg = 0;  // the shared leaf's position
+#pragma unroll
+  for (int L = 0; L < MAXL; ++L)
+    if (L == lf) pg = A.img.off[L] + kk[L];
   int64_t p[QX];
 #pragma unroll
   for (int q = 0; q < QX; ++q) {
-    uint32_t kq = key;
-    int lq = L;
-    int64_t pq = p0;
-    while (lq < Lm && (A.w.state[pq] & AIR_NODE_REFINED)) {
-      ++lq;
-      const int sh = Lm - lq;
-      kq = 4u * kq + ((((i + q) >> sh) & 1u) | (((j >> sh) & 1u) << 1));
-      pq = vb + A.img.off[lq] + kq;
+    const uint32_t bits = ((i + q) & 1u) | ((j & 1u) << 1);
+    if (lf < ng) {
+      p[q] = pg;
+    } else if (QX == 4 && Lm >= 1) {
+      const int h = q >> 1;
+      p[q] = (sp[h] & AIR_NODE_REFINED) ? offm + 4u * kp[h] + bits : offm1 + kp[h];
+    } else {  // every level above the pixels refined, or Lm = 0 (then pixel q is key + q)
+      p[q] = Lm > 0 ? offm + 4u * key + bits : offm + key + (uint32_t)q;
     }
-    p[q] = pq;
+    p[q] += vb;
   }
   float* img = images + (int64_t)v * (nb + 1) * R2 + e;
   // a write-once output: streaming stores keep it from evicting the field
   // and the maps from the caches
   typedef float f4 __attribute__((ext_vector_type(4)));
-  for (int b = 0; b <= nb; ++b) {
-    const float* src = b < nb ? A.w.valI + b * VS : A.w.valN;
-    if constexpr (QX >= 4) {
+  // two planes per trip: their gathers are in flight together
+  for (int b0 = 0; b0 <= nb; b0 += 2) {
+    float x[2][QX];
 #pragma unroll
-      for (int g = 0; g < QX; g += 4)
-        __builtin_nontemporal_store(f4{src[p[g]], src[p[g + 1]], src[p[g + 2]], src[p[g + 3]]},
-                                    reinterpret_cast<f4*>(img + b * R2 + g));
-    } else {
-      __builtin_nontemporal_store(src[p[0]], img + b * R2);
+    for (int u = 0; u < 2; ++u) {
+      const int b = min(b0 + u, nb);
+      const float* src = b < nb ? A.w.valI + b * VS : A.w.valN;
+#pragma unroll
+      for (int q = 0; q < QX; ++q) x[u][q] = src[p[q]];
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      if (b0 + u > nb) break;
+      float* dst = img + (int64_t)(b0 + u) * R2;
+      if constexpr (QX >= 4) {
+#pragma unroll
+        for (int g = 0; g < QX; g += 4)
+          __builtin_nontemporal_store(f4{x[u][g], x[u][g + 1], x[u][g + 2], x[u][g + 3]}, reinterpret_cast<f4*>(dst + g));
+      } else {
+        __builtin_nontemporal_store(x[u][0], dst);
+      }
     }
   }
 }

@@ -215,7 +215,10 @@ def test_column_refinement_variable(ctx, gauss):
     assert trees[0].n_nodes > 256
 
 
-@pytest.mark.parametrize("N0,Lmax", [(1, 3), (13, 2), (7, 0), (2, 5)])
+# the raster is painted four pixels per thread when its side is a multiple
+# of 4, else one: (4, 0) and (6, 1) take the first form with no or one level
+# above the pixels, (7, 0) and (7, 1) the second
+@pytest.mark.parametrize("N0,Lmax", [(1, 3), (13, 2), (7, 0), (2, 5), (4, 0), (6, 1), (7, 1)])
 def test_ragged_and_degenerate_images(ctx, N0, Lmax):
     from paper_1010_5534_amd import air
     g, f = inputs.winds2(seed=7, n=40)
