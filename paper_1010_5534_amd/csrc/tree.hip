@@ -89,25 +89,38 @@ __global__ __launch_bounds__(RB) void k_refine(MarchArgs A, int L, float xcI, fl
     if (live) {
       coords_of(key, L, N0, i, j);
       vb = (int64_t)v * S;
+      // the 3x3 stencil: the nine state bytes go out together, then the
+      // nine positions' values (a neighbour not yet traced takes the
+      // covering coarser node's; one outside the image is 0)
+      const int64_t lb = vb + A.img.off[L], cb = vb + (L > 0 ? A.img.off[L - 1] : 0);
+      uint32_t kq[9];
+      bool in[9];
+      uint8_t sq[9];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) {
+        const int qi = (int)i + k % 3 - 1, qj = (int)j + k / 3 - 1;
+        in[k] = qi >= 0 && qj >= 0 && qi < (int)R && qj < (int)R;
+        kq[k] = in[k] ? key_of((uint32_t)qi, (uint32_t)qj, L, N0) : key;  // outside: a valid stand-in
+        sq[k] = A.w.state[lb + kq[k]];
+      }
+      int64_t pp[9];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) pp[k] = (sq[k] & ST_TRACED) ? lb + kq[k] : cb + (kq[k] >> 2);
       float pI[9], pN[9];
 #pragma unroll
-      for (int b = -1; b <= 1; ++b)
+      for (int k = 0; k < 9; ++k) {
+        pN[k] = A.w.valN[pp[k]];  // in flight with the first band's values
+        pI[k] = 0.0f;
+      }
+      for (int bb = 0; bb < nb; ++bb) {
+        const float wb = W.w[bb];
+        const float* src = A.w.valI + bb * VS;
 #pragma unroll
-        for (int a = -1; a <= 1; ++a) {
-          const int k = (b + 1) * 3 + (a + 1);
-          const int qi = (int)i + a, qj = (int)j + b;
-          if (qi < 0 || qj < 0 || qi >= (int)R || qj >= (int)R) {
-            pI[k] = pN[k] = 0.0f;
-            continue;
-          }
-          const uint32_t kq = key_of((uint32_t)qi, (uint32_t)qj, L, N0);
-          int64_t p = vb + A.img.off[L] + kq;
-          if (!(A.w.state[p] & ST_TRACED)) p = vb + A.img.off[L - 1] + (kq >> 2);  // covering coarser node
-          float s = 0.0f;
-          for (int bb = 0; bb < nb; ++bb) s += W.w[bb] * A.w.valI[bb * VS + p];
-          pI[k] = s;
-          pN[k] = A.w.valN[p];
-        }
+        for (int k = 0; k < 9; ++k) pI[k] += wb * src[pp[k]];
+      }
+#pragma unroll
+      for (int k = 0; k < 9; ++k)
+        if (!in[k]) pI[k] = pN[k] = 0.0f;
       const bool hx = i > 0 && i + 1 < R, hy = j > 0 && j + 1 < R;
       const float xI = xi_of(pI, hx, hy), xN = xi_of(pN, hx, hy);
       const int64_t pos = vb + A.img.off[L] + key;
