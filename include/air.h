@@ -193,10 +193,14 @@ int64_t air_field_packed_bytes(const air_grid* grid, const air_field* field);
  * kappa and 1/kappa evaluated here, once, in float32 exactly as the march
  * would), or 8 B
  * (rho, T) for RHO_T with 2..8 bands, so one brick of a one-band field is one
- * 128-byte cache line and a visit is one load.
+ * 128-byte cache line and a visit is one load.  A one-band RHO_T field on a
+ * uniform grid is followed, at the next multiple of 256 bytes, by the same
+ * bricks as 8-byte (rho, T) records: the marches of levels whose rays lie at
+ * least half a cell apart read those (two bricks per line), evaluating the
+ * same optics, so either copy gives the same bits.
  * Pass the buffer as field->packed to later calls; it holds a copy, so it
  * must be packed again after the arrays change.  Errors: EINVAL (sizes,
- * NULL pointers, block tables), ENOTSUP (packed size >= 4 GiB).
+ * NULL pointers, block tables), ENOTSUP (either copy >= 4 GiB).
  */
 air_status air_field_pack(air_ctx* ctx, const air_grid* grid, const air_field* field, void* packed,
                           int64_t bytes, void* stream);

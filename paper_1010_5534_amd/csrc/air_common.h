@@ -59,6 +59,10 @@ struct Fld {
   int kind, nb;
   const void* packed;  // bricked march layout (see air_field_pack)
   uint32_t packed_bytes;
+  // one-band (rho, T) on a uniform grid: the same cells again as 8-byte
+  // (rho, T) records, rt_off bytes into the packed buffer (0 bytes: none)
+  uint32_t rt_bytes;
+  int64_t rt_off;
   int bnx, bny, bnz;   // bricks per axis
   const float* rho;
   const float* emis;

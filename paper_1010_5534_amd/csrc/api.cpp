@@ -352,10 +352,34 @@ int64_t cells_of(const air_grid* g) {
 
 // both layouts are whole 2x2x2 bricks: the uniform grid rounds each axis up
 // to even, a block of bs^3 cells (bs even) is bs^3/8 bricks
-int64_t packed_bytes_of(const air_grid* g, const air_field* f) {
+int64_t packed_main_bytes(const air_grid* g, const air_field* f) {
   if (g->kind == AIR_GRID_BLOCK_AMR) return cells_of(g) * packed_cell_bytes(f->kind, f->n_bands);
   const int64_t bricks = (int64_t)((g->n[0] + 1) / 2) * ((g->n[1] + 1) / 2) * ((g->n[2] + 1) / 2);
   return 8 * bricks * packed_cell_bytes(f->kind, f->n_bands);
+}
+
+// A one-band (rho, T) field on a uniform grid also keeps its (rho, T) as
+// 8-byte records after the 16-byte ones (256-byte aligned): the marches of
+// the levels whose rays lie at least half a cell apart read those, since a
+// 128-byte line then holds 4x2x2 cells instead of 2x2x2 and scattered rays
+// fetch fewer lines.  The optics they evaluate are the packing's own, so a
+// ray's values are the same bits from either copy.
+int64_t packed_rt_bytes(const air_grid* g, const air_field* f) {
+  if (g->kind != AIR_GRID_UNIFORM || f->kind != AIR_FIELD_RHO_T || f->n_bands != 1) return 0;
+  const int64_t bricks = (int64_t)((g->n[0] + 1) / 2) * ((g->n[1] + 1) / 2) * ((g->n[2] + 1) / 2);
+  return 8 * bricks * 8;
+}
+
+int64_t packed_rt_off(const air_grid* g, const air_field* f) { return (packed_main_bytes(g, f) + 255) / 256 * 256; }
+
+int64_t packed_bytes_of(const air_grid* g, const air_field* f) {
+  const int64_t rt = packed_rt_bytes(g, f);
+  return rt ? packed_rt_off(g, f) + rt : packed_main_bytes(g, f);
+}
+
+// each copy is read through a buffer resource with a 32-bit size
+bool packed_too_large(const air_grid* g, const air_field* f) {
+  return packed_main_bytes(g, f) >= ((int64_t)1 << 32) || packed_rt_bytes(g, f) >= ((int64_t)1 << 32);
 }
 
 void fill_fld(const air_field* f, const air_grid* g, Fld& F) {
@@ -372,7 +396,9 @@ void fill_fld(const air_field* f, const air_grid* g, Fld& F) {
     F.bny = (g->n[1] + 1) / 2;
     F.bnz = (g->n[2] + 1) / 2;
   }
-  F.packed_bytes = (uint32_t)packed_bytes_of(g, f);
+  F.packed_bytes = (uint32_t)packed_main_bytes(g, f);
+  F.rt_bytes = (uint32_t)packed_rt_bytes(g, f);
+  F.rt_off = F.rt_bytes ? packed_rt_off(g, f) : 0;
   for (int b = 0; b < F.nb && f->kind == AIR_FIELD_RHO_T; ++b) {
     F.k0[b] = (float)f->band[b][0];
     F.s[b] = (float)f->band[b][1];
@@ -401,7 +427,7 @@ hipError_t pack_any(const Geo& g, const Fld& f, void* packed, hipStream_t s) {
 // point the march at a packed layout: the caller's, or one written now
 air_status ensure_packed(air_ctx* c, const air_grid* g, const air_field* f, MarchArgs& A, hipStream_t s) {
   const int64_t need = packed_bytes_of(g, f);
-  if (need >= ((int64_t)1 << 32)) return fail(c, AIR_ENOTSUP, "packed field of %lld bytes exceeds 4 GiB", (long long)need);
+  if (packed_too_large(g, f)) return fail(c, AIR_ENOTSUP, "packed field of %lld bytes: a copy exceeds 4 GiB", (long long)need);
   if (f->packed) return AIR_OK;
   air_status st = ensure(c, c->pack, (size_t)need);
   if (st) return st;
@@ -1213,8 +1239,7 @@ air_status air_render_fixed_noalloc(air_ctx* c, const air_grid* grid, const air_
   if ((double)R * R > 4294967295.0) return fail(c, AIR_EINVAL, "raster exceeds 2^32 pixels per view");
   if (flux && !images) return fail(c, AIR_EINVAL, "flux needs the image buffer");
   if (!field->packed) return fail(c, AIR_EINVAL, "the allocation-free render needs a packed field (air_field_pack)");
-  if (packed_bytes_of(grid, field) >= ((int64_t)1 << 32))
-    return fail(c, AIR_ENOTSUP, "packed field exceeds 4 GiB");
+  if (packed_too_large(grid, field)) return fail(c, AIR_ENOTSUP, "packed field: a copy exceeds 4 GiB");
   if (grid->kind == AIR_GRID_BLOCK_AMR && !blocks_known(c, grid, field->packed))
     return fail(c, AIR_EINVAL, "block tables not checked for this packed field: pack it with air_field_pack on "
                                "this context first");
@@ -1299,7 +1324,8 @@ air_status air_field_pack(air_ctx* c, const air_grid* grid, const air_field* fie
   if ((st = check_field(c, field))) return st;
   const int64_t need = packed_bytes_of(grid, field);
   if (!packed || bytes < need) return fail(c, AIR_EINVAL, "packed buffer of %lld bytes, %lld needed", (long long)bytes, (long long)need);
-  if (need >= ((int64_t)1 << 32)) return fail(c, AIR_ENOTSUP, "packed field of %lld bytes exceeds 4 GiB", (long long)need);
+  if (packed_too_large(grid, field))
+    return fail(c, AIR_ENOTSUP, "packed field of %lld bytes: a copy exceeds 4 GiB", (long long)need);
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, AIR_EDEVICE, "hipSetDevice failed");
   if ((st = check_blocks(c, grid, (hipStream_t)stream))) return st;
   MarchArgs A;

@@ -734,6 +734,10 @@ __device__ __forceinline__ void pack_cell(const Fld& f, int64_t src, bool in, in
       }
     }
     reinterpret_cast<float4*>(const_cast<void*>(f.packed))[dst] = v;
+    if (PM == PACK_RT_TO_RJK && f.rt_bytes) {  // the (rho, T) copy
+      char* rt = static_cast<char*>(const_cast<void*>(f.packed)) + f.rt_off;
+      reinterpret_cast<float2*>(rt)[dst] = in ? make_float2(f.rho[src], f.temp[src]) : make_float2(0.f, 0.f);
+    }
   }
 }
 
@@ -1227,21 +1231,40 @@ bool split_level(const MarchArgs& a, int L) {
   return L >= 1 && a.w.split_tiles > 0 && queue_tile_bound(a, L) <= a.w.split_tiles;
 }
 
-hipError_t launch_march_queue(const MarchArgs& a, int L, int grid_blocks, hipStream_t s) {
+// rays of level L at least half a (coarsest-level) cell apart in every view
+bool sparse_level(const MarchArgs& a, int L) {
+  double h = a.g.h[0];
+  for (int ax = 1; ax < 3; ++ax) h = std::max(h, a.g.h[ax]);
+  return a.img.min_width / (double)((int64_t)a.img.N0 << L) >= 0.5 * h;
+}
+
+template <int NB, int FK, int GK>
+hipError_t queue_launch(const MarchArgs& a, int L, int grid_blocks, hipStream_t s) {
   if (!split_level(a, L)) {
     const dim3 blk(WAVE << a.g.seg_shift);
     if (coarse_level(a, L))
-      AIR_DISPATCH(a, hipLaunchKernelGGL((k_march_queue<NB_, FK_, GK_, true>), dim3(grid_blocks), blk, 0, s, a, L));
+      hipLaunchKernelGGL((k_march_queue<NB, FK, GK, true>), dim3(grid_blocks), blk, 0, s, a, L);
     else
-      AIR_DISPATCH(a, hipLaunchKernelGGL((k_march_queue<NB_, FK_, GK_, false>), dim3(grid_blocks), blk, 0, s, a, L));
+      hipLaunchKernelGGL((k_march_queue<NB, FK, GK, false>), dim3(grid_blocks), blk, 0, s, a, L);
     return hipGetLastError();
   }
   const int64_t tiles = queue_tile_bound(a, L), jobs = tiles << a.g.seg_shift;
   const int pg = (int)std::min<int64_t>(std::max<int64_t>((jobs + 4 * 8 - 1) / (4 * 8) * 8, 8), 8192);
   const int fg = (int)std::min<int64_t>((tiles + 3) / 4, 4096);
-  AIR_DISPATCH(a, hipLaunchKernelGGL((k_march_parts<NB_, FK_, GK_, false>), dim3(pg), dim3(256), 0, s, a, L));
-  AIR_DISPATCH(a, hipLaunchKernelGGL((k_fold_parts<NB_, GK_, false>), dim3(fg), dim3(256), 0, s, a, L));
+  hipLaunchKernelGGL((k_march_parts<NB, FK, GK, false>), dim3(pg), dim3(256), 0, s, a, L);
+  hipLaunchKernelGGL((k_fold_parts<NB, GK, false>), dim3(fg), dim3(256), 0, s, a, L);
   return hipGetLastError();
+}
+
+hipError_t launch_march_queue(const MarchArgs& a, int L, int grid_blocks, hipStream_t s) {
+  if (a.f.rt_bytes && a.f.packed && sparse_level(a, L)) {  // the (rho, T) copy
+    MarchArgs b = a;
+    b.f.packed = static_cast<const char*>(a.f.packed) + a.f.rt_off;
+    b.f.packed_bytes = a.f.rt_bytes;
+    return queue_launch<1, AIR_FIELD_RHO_T, AIR_GRID_UNIFORM>(b, L, grid_blocks, s);
+  }
+  AIR_DISPATCH(a, return (queue_launch<NB_, FK_, GK_>(a, L, grid_blocks, s)));
+  return hipSuccess;
 }
 
 hipError_t launch_march_fixed(const MarchArgs& a, int level, float* images, int grid_blocks, hipStream_t s) {

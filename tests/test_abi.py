@@ -94,8 +94,13 @@ def test_packed_bytes_without_device():
     assert air.lib().air_field_packed_bytes(C.addressof(g), C.addressof(f)) == 3 * 4 * 2 * 8 * 16
     f.kind, f.temp, f.n_bands = 1, 16, 4
     assert air.lib().air_field_packed_bytes(C.addressof(g), C.addressof(f)) == 3 * 4 * 2 * 8 * 8
-    f.n_bands = 1  # one band: (rho, j, kappa) evaluated once when packing
-    assert air.lib().air_field_packed_bytes(C.addressof(g), C.addressof(f)) == 3 * 4 * 2 * 8 * 16
+    # one band: (rho, j, kappa) evaluated once when packing, then the (rho, T)
+    # copy at the next multiple of 256 bytes
+    f.n_bands = 1
+    assert air.lib().air_field_packed_bytes(C.addressof(g), C.addressof(f)) == 3 * 4 * 2 * 8 * 16 + 3 * 4 * 2 * 8 * 8
+    g.n[:] = [5, 6, 5]  # 27 bricks: 3456 bytes of records, the copy at 3584
+    assert air.lib().air_field_packed_bytes(C.addressof(g), C.addressof(f)) == 3584 + 27 * 8 * 8
+    g.n[:] = [5, 8, 3]
     f.n_bands = 9
     assert air.lib().air_field_packed_bytes(C.addressof(g), C.addressof(f)) == air.AIR_EINVAL
 
