@@ -248,7 +248,10 @@ __global__ __launch_bounds__(256) void k_wgrad(const uint16_t* __restrict__ dy, 
   // task e: one tile row of dy (8 pixels x 8 channels, e < DT), or one halo
   // row's 8 pixels starting at column kx (one copy) x 8 channels of the
   // input; its 8 x 8 block is transposed in registers and stored as 8 rows
-  // of 16 bytes
+  // of 16 bytes.  Neighbouring tasks take neighbouring rows, whose 16-byte
+  // pieces sit 16 bytes apart in LDS (a channel octet's rows lie a multiple
+  // of 128 bytes apart, so octet-major order would put a store's lanes on
+  // the same banks)
   constexpr int DT = WG_T * DO, TT = DT + WG_H * XO * 3;
   static_assert(TT <= 256, "one task per thread");
   static_assert(DC % 8 == 0 && CS % 8 == 0 && DC <= RW && RW % 16 == 0, "operand shapes");
@@ -265,15 +268,15 @@ __global__ __launch_bounds__(256) void k_wgrad(const uint16_t* __restrict__ dy, 
     int yy, xs, stride, oct;
     const uint16_t* base;
     if (tid < DT) {
-      oct = tid % DO;
-      yy = y0 + tid / DO;
+      oct = tid / WG_T;
+      yy = y0 + tid % WG_T;
       xs = x0;
       base = dy;
       stride = DC;
     } else {
-      const int f = tid - DT, kx = f % 3, rest = f / 3;
-      oct = rest % XO;
-      yy = y0 - 1 + rest / XO;
+      const int f = tid - DT, rest = f / WG_H, kx = rest % 3;
+      oct = rest / 3;
+      yy = y0 - 1 + f % WG_H;
       xs = x0 - 1 + kx;
       base = x;
       stride = CS;
@@ -291,11 +294,11 @@ __global__ __launch_bounds__(256) void k_wgrad(const uint16_t* __restrict__ dy, 
     uint16_t* dst;
     int row_stride;
     if (tid < DT) {
-      dst = dT + (8 * (tid % DO)) * WG_LD + (tid / DO) * WG_T;
+      dst = dT + (8 * (tid / WG_T)) * WG_LD + (tid % WG_T) * WG_T;
       row_stride = WG_LD;
     } else {
-      const int f = tid - DT, kx = f % 3, rest = f / 3;
-      dst = hT + ((kx * CS + 8 * (rest % XO)) * WG_HR + rest / XO) * WG_T;
+      const int f = tid - DT, rest = f / WG_H, kx = rest % 3;
+      dst = hT + ((kx * CS + 8 * (rest / 3)) * WG_HR + f % WG_H) * WG_T;
       row_stride = WG_HR * WG_T;
     }
     // transpose: row i (channel) holds the 8 pixels' channel i
