@@ -197,7 +197,12 @@ int64_t air_field_packed_bytes(const air_grid* grid, const air_field* field);
  * uniform grid is followed, at the next multiple of 256 bytes, by the same
  * bricks as 8-byte (rho, T) records: the marches of levels whose rays lie at
  * least half a cell apart read those (two bricks per line), evaluating the
- * same optics, so either copy gives the same bits.
+ * same optics, so either copy gives the same bits.  A block-AMR field is
+ * followed, at the next multiple of 256 bytes, by the leaf block of every
+ * position of the finest block lattice ((n[0] n[1] n[2]) << 3 max_level
+ * uint32 entries, x fastest, each leaf id << 4 | its level; none when that
+ * lattice has more than 2^26 positions or max_level > 15), so the march
+ * locates a block with one load instead of a descent of the child table.
  * Pass the buffer as field->packed to later calls; it holds a copy, so it
  * must be packed again after the arrays change.  Errors: EINVAL (sizes,
  * NULL pointers, block tables), ENOTSUP (either copy >= 4 GiB).

@@ -63,6 +63,11 @@ struct Fld {
   // (rho, T) records, rt_off bytes into the packed buffer (0 bytes: none)
   uint32_t rt_bytes;
   int64_t rt_off;
+  // block AMR: the leaf block of every finest-level block position, (id << 4)
+  // | level, leaf_off bytes into the packed buffer (leaf_map 0: none, the
+  // march descends the child table)
+  int leaf_map;
+  int64_t leaf_off;
   int bnx, bny, bnz;   // bricks per axis
   const float* rho;
   const float* emis;
@@ -189,6 +194,7 @@ struct MarchArgs {
 hipError_t launch_init(const MarchArgs& a, hipStream_t s);
 hipError_t launch_pack(const Geo& g, const Fld& f, void* packed, hipStream_t s);
 hipError_t launch_pack_amr(const Geo& g, const Fld& f, void* packed, hipStream_t s);
+hipError_t launch_leaf_map(const Geo& g, const Fld& f, void* packed, hipStream_t s);
 // bytes of one packed cell record: (rho, j, kappa, 1/kappa) for RHO_J_KAPPA and
 // for one-band RHO_T (j, kappa evaluated once when packing), (rho, T) otherwise
 inline int packed_cell_bytes(int field_kind, int n_bands) {

@@ -370,11 +370,29 @@ int64_t packed_rt_bytes(const air_grid* g, const air_field* f) {
   return 8 * bricks * 8;
 }
 
+// A block-AMR field is followed by the leaf block of every position of the
+// finest block lattice (4 bytes each), so the march locates a leaf with one
+// load instead of a chain of child-table loads; lattices of more than 2^26
+// positions have no map (the march descends the table).
+int64_t packed_leaf_entries(const air_grid* g) {
+  // an entry holds the leaf id in 28 bits and its level in 4
+  if (g->kind != AIR_GRID_BLOCK_AMR || g->max_level < 0 || g->max_level > 15 || g->n_blocks >= (1 << 28)) return 0;
+  int64_t e = 1;
+  for (int a = 0; a < 3; ++a) {
+    e *= (int64_t)g->n[a] << g->max_level;
+    if (e > ((int64_t)1 << 26)) return 0;
+  }
+  return e;
+}
+
+// the copy or the map starts at the next multiple of 256 bytes
 int64_t packed_rt_off(const air_grid* g, const air_field* f) { return (packed_main_bytes(g, f) + 255) / 256 * 256; }
 
 int64_t packed_bytes_of(const air_grid* g, const air_field* f) {
-  const int64_t rt = packed_rt_bytes(g, f);
-  return rt ? packed_rt_off(g, f) + rt : packed_main_bytes(g, f);
+  const int64_t rt = packed_rt_bytes(g, f), lm = 4 * packed_leaf_entries(g);
+  if (rt) return packed_rt_off(g, f) + rt;
+  if (lm) return packed_rt_off(g, f) + lm;
+  return packed_main_bytes(g, f);
 }
 
 // each copy is read through a buffer resource with a 32-bit size
@@ -399,6 +417,8 @@ void fill_fld(const air_field* f, const air_grid* g, Fld& F) {
   F.packed_bytes = (uint32_t)packed_main_bytes(g, f);
   F.rt_bytes = (uint32_t)packed_rt_bytes(g, f);
   F.rt_off = F.rt_bytes ? packed_rt_off(g, f) : 0;
+  F.leaf_map = packed_leaf_entries(g) > 0 ? 1 : 0;
+  F.leaf_off = F.leaf_map ? packed_rt_off(g, f) : 0;
   for (int b = 0; b < F.nb && f->kind == AIR_FIELD_RHO_T; ++b) {
     F.k0[b] = (float)f->band[b][0];
     F.s[b] = (float)f->band[b][1];
@@ -421,14 +441,21 @@ void fill_fld(const air_field* f, const air_grid* g, Fld& F) {
 }
 
 hipError_t pack_any(const Geo& g, const Fld& f, void* packed, hipStream_t s) {
-  return g.kind == AIR_GRID_BLOCK_AMR ? launch_pack_amr(g, f, packed, s) : launch_pack(g, f, packed, s);
+  if (g.kind != AIR_GRID_BLOCK_AMR) return launch_pack(g, f, packed, s);
+  const hipError_t e = launch_pack_amr(g, f, packed, s);
+  return e == hipSuccess && f.leaf_map ? launch_leaf_map(g, f, packed, s) : e;
 }
 
 // point the march at a packed layout: the caller's, or one written now
 air_status ensure_packed(air_ctx* c, const air_grid* g, const air_field* f, MarchArgs& A, hipStream_t s) {
   const int64_t need = packed_bytes_of(g, f);
   if (packed_too_large(g, f)) return fail(c, AIR_ENOTSUP, "packed field of %lld bytes: a copy exceeds 4 GiB", (long long)need);
-  if (f->packed) return AIR_OK;
+  if (f->packed) {
+    // the leaf map is trusted only for a buffer packed on this context with
+    // these tables and this shape; otherwise the march descends the table
+    if (A.f.leaf_map && !blocks_known(c, g, f->packed)) A.f.leaf_map = 0;
+    return AIR_OK;
+  }
   air_status st = ensure(c, c->pack, (size_t)need);
   if (st) return st;
   A.f.packed = c->pack.p;

@@ -403,6 +403,23 @@ __device__ __forceinline__ int fine_at(const Geo& g, const double o[3], const do
   return min(max(k, 0), g.nf[a] - 1);
 }
 
+// Leaf block of finest-level block position (fx, fy, fz) and its level:
+// descent through the child table from the base block.  A child's
+// coordinate is twice its parent's plus its offset bit (the tables were
+// checked for it), so the offset at level l is the low bit of the
+// position's level-l block coordinate and no coordinate has to be read.
+__device__ __forceinline__ int leaf_of(const Geo& g, int fx, int fy, int fz, int& l) {
+  const int mL = g.max_level;
+  int b = ((fz >> mL) * g.n[1] + (fy >> mL)) * g.n[0] + (fx >> mL);
+  l = 0;
+  for (int ch = g.bchild[b]; ch >= 0 && l < mL; ch = g.bchild[b]) {
+    ++l;
+    const int off = ((fx >> (mL - l)) & 1) | (((fy >> (mL - l)) & 1) << 1) | (((fz >> (mL - l)) & 1) << 2);
+    b = min(ch + off, g.n_blocks - 1);  // the host checked the tables; this only bounds the reads
+  }
+  return b;
+}
+
 // March [ta, tb] through a block-AMR grid: locate the leaf block just after
 // the current parameter (integer fine coordinates, descent through the child
 // table), walk its cells at its level's spacing up to the block exit, and
@@ -426,18 +443,15 @@ __device__ void march_amr_interval(const Geo& g, const Fld& f, const double o[3]
     int F[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) F[a] = fine_at(g, o, d, a, t, true);
-    int b = (((F[2] >> mL) >> lbs) * g.n[1] + ((F[1] >> mL) >> lbs)) * g.n[0] + ((F[0] >> mL) >> lbs);
-    int l = 0;
-    // descent through the child table: a child's coordinate is twice its
-    // parent's plus its offset bit (the tables were checked for it), so the
-    // offset at level l is the low bit of the point's level-l block
-    // coordinate and no coordinate has to be read
-    for (int ch = g.bchild[b]; ch >= 0 && l < mL; ch = g.bchild[b]) {
-      ++l;
-      int off = 0;
-#pragma unroll
-      for (int a = 0; a < 3; ++a) off |= (((F[a] >> (mL - l)) >> lbs) & 1) << a;
-      b = min(ch + off, g.n_blocks - 1);  // the host checked the tables; this only bounds the reads
+    int b, l;
+    if (f.leaf_map) {  // the leaf of the point's finest-level block position
+      const uint32_t* lm = reinterpret_cast<const uint32_t*>(static_cast<const char*>(f.packed) + f.leaf_off);
+      const int nfx = g.n[0] << mL, nfy = g.n[1] << mL;
+      const uint32_t m = lm[((int64_t)(F[2] >> lbs) * nfy + (F[1] >> lbs)) * nfx + (F[0] >> lbs)];
+      b = (int)(m >> 4);
+      l = (int)(m & 15u);
+    } else {
+      b = leaf_of(g, F[0] >> lbs, F[1] >> lbs, F[2] >> lbs, l);
     }
     int bc[3];
 #pragma unroll
@@ -767,6 +781,20 @@ __global__ __launch_bounds__(256) void k_pack_amr(Geo g, Fld f) {
     const int loc = (int)(q - b * bs * bs * bs);
     const int x = loc % bs, y = (loc / bs) % bs, z = loc / (bs * bs);
     pack_cell<PM>(f, q, true, b * bs * bs * bs + brick_index(x, y, z, hb, hb));
+  }
+}
+
+// the leaf map of a packed block-AMR field: one entry per finest-level block
+// position, x fastest
+__global__ __launch_bounds__(256) void k_leaf_map(Geo g, Fld f) {
+  const int mL = g.max_level, nfx = g.n[0] << mL, nfy = g.n[1] << mL, nfz = g.n[2] << mL;
+  uint32_t* lm = reinterpret_cast<uint32_t*>(static_cast<char*>(const_cast<void*>(f.packed)) + f.leaf_off);
+  const int64_t total = (int64_t)nfx * nfy * nfz;
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < total; q += (int64_t)gridDim.x * blockDim.x) {
+    const int fx = (int)(q % nfx), fy = (int)((q / nfx) % nfy), fz = (int)(q / ((int64_t)nfx * nfy));
+    int l;
+    const int b = leaf_of(g, fx, fy, fz, l);
+    lm[q] = ((uint32_t)b << 4) | (uint32_t)l;
   }
 }
 
@@ -1190,6 +1218,13 @@ hipError_t launch_pack_amr(const Geo& g, const Fld& f, void* packed, hipStream_t
     case PACK_RT_TO_RJK: hipLaunchKernelGGL(k_pack_amr<PACK_RT_TO_RJK>, dim3(4096), dim3(256), 0, s, g, F); break;
     default: hipLaunchKernelGGL(k_pack_amr<PACK_RT>, dim3(4096), dim3(256), 0, s, g, F);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_leaf_map(const Geo& g, const Fld& f, void* packed, hipStream_t s) {
+  Fld F = f;
+  F.packed = packed;
+  hipLaunchKernelGGL(k_leaf_map, dim3(1024), dim3(256), 0, s, g, F);
   return hipGetLastError();
 }
 

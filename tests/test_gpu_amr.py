@@ -137,8 +137,16 @@ def test_amr_packed_layout_contents(ctx):
     f = inputs.Field(1, np.arange(n, dtype=np.float32), temp=1000 + np.arange(n, dtype=np.float32),
                      bands=inputs.default_bands(2))
     sc = ctx.prepare(air.upload(g, f))
-    got = sc.tensors[-1].cpu().numpy().view(np.float32).reshape(-1, 2)
+    raw = sc.tensors[-1].cpu().numpy().view(np.uint8)
+    got = raw[:8 * n].view(np.float32).reshape(-1, 2)
     assert np.array_equal(got, _amr_brick_order(np.stack([f.rho, f.temp], axis=-1), 4))
+    # then, 256-byte aligned, the leaf of each position of the finest block
+    # lattice (2x2x2 here, x fastest): child 1 + (x + 2y + 4z) of the base
+    # block, at level 1, as (id << 4) | level
+    off = (8 * n + 255) // 256 * 256
+    leaf = raw[off:off + 32].view(np.uint32)
+    assert leaf.tolist() == [((1 + k) << 4) | 1 for k in range(8)]
+    assert raw.size == off + 32
 
 
 def test_one_band_rho_t_packs_coefficients(ctx):
@@ -152,7 +160,9 @@ def test_one_band_rho_t_packs_coefficients(ctx):
     T = rng.uniform(0.5, 10.0, n).astype(np.float32)
     band = np.array([[0.7, 1.5, 0.5]])
     f = inputs.Field(1, rho, temp=T, bands=band)
-    got = ctx.prepare(air.upload(g, f)).tensors[-1].cpu().numpy().view(np.float32).reshape(-1, 4)
+    # the records, then (256-byte aligned) the leaf map
+    got = ctx.prepare(air.upload(g, f)).tensors[-1].cpu().numpy().view(np.uint8)[:16 * n].view(np.float32)
+    got = got.reshape(-1, 4)
     r64, t64 = rho.astype(np.float64), T.astype(np.float64)
     ref = np.stack([r64, r64 * r64 * t64 ** 0.5, 0.7 * r64 * t64 ** -1.5, np.zeros(n)], axis=-1)
     ref = _amr_brick_order(ref, 4)

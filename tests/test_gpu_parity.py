@@ -380,3 +380,24 @@ def test_tree_links_consistent(ctx, gauss):
         assert np.all(par[c:c + 4] == k)
         assert set(zip(ix[c:c + 4] - 2 * ix[k], iy[c:c + 4] - 2 * iy[k])) == {(0, 0), (1, 0), (0, 1), (1, 1)}
     assert np.array_equal(fc >= 0, (st & air.NODE_REFINED) > 0)
+
+
+def test_packed_rho_t_copy_contents(ctx):
+    """A one-band (rho, T) field on a uniform grid: the 16-byte records, then
+    at the next multiple of 256 bytes the same bricks as (rho, T) pairs (the
+    copy the sparse levels march)."""
+    from paper_1010_5534_amd import air
+    g = inputs.Grid(inputs.GRID_UNIFORM, (5, 5, 5))
+    rho = np.arange(125, dtype=np.float32).reshape(5, 5, 5) + 1.0
+    T = 1000 + np.arange(125, dtype=np.float32).reshape(5, 5, 5)
+    f = inputs.Field(1, rho, temp=T, bands=np.array([[1.0, 1.5, 0.5]]))
+    raw = ctx.prepare(air.upload(g, f)).tensors[-1].cpu().numpy().view(np.uint8)
+    bricks = 3 * 3 * 3  # odd: the records end off a 256-byte boundary
+    main = bricks * 8 * 16
+    off = (main + 255) // 256 * 256
+    assert off > main and raw.size == off + bricks * 8 * 8
+    recs = raw[:main].view(np.float32).reshape(-1, 4)
+    copy = raw[off:].view(np.float32).reshape(-1, 2)
+    ref = _brick_order(np.stack([rho, T], axis=-1), g.n)
+    assert np.array_equal(copy, ref)
+    assert np.array_equal(recs[:, 0], ref[:, 0])
