@@ -424,7 +424,8 @@ __device__ __forceinline__ int leaf_of(const Geo& g, int fx, int fy, int fz, int
 // the current parameter (integer fine coordinates, descent through the child
 // table), walk its cells at its level's spacing up to the block exit, and
 // continue from there.  Crossing parameters restart at every block entry.
-// At most g.max_blocks blocks are visited, so every lane terminates; a block
+// At most g.max_blocks blocks are visited, so every lane terminates; the
+// block after an exit is the one across the face the ray leaves by; a block
 // entered exactly at its exit (a rounding corner) is stepped over by one ulp.
 template <int NB, int FK, bool RANGE, bool BF>
 __device__ void march_amr_interval(const Geo& g, const Fld& f, const double o[3], const double d[3],
@@ -439,10 +440,10 @@ __device__ void march_amr_interval(const Geo& g, const Fld& f, const double o[3]
   float rmin = __builtin_huge_valf(), rmax = -__builtin_huge_valf();
   int nvis_total = 0, lmax = -1;
   double t = ta;
-  for (int it = 0; it < g.max_blocks && t < tb; ++it) {
-    int F[3];
+  int F[3];  // finest-lattice cell of the point just after t
 #pragma unroll
-    for (int a = 0; a < 3; ++a) F[a] = fine_at(g, o, d, a, t, true);
+  for (int a = 0; a < 3; ++a) F[a] = fine_at(g, o, d, a, t, true);
+  for (int it = 0; it < g.max_blocks && t < tb; ++it) {
     int b, l;
     if (f.leaf_map) {  // the leaf of the point's finest-level block position
       const uint32_t* lm = reinterpret_cast<const uint32_t*>(static_cast<const char*>(f.packed) + f.leaf_off);
@@ -457,19 +458,36 @@ __device__ void march_amr_interval(const Geo& g, const Fld& f, const double o[3]
 #pragma unroll
     for (int a = 0; a < 3; ++a) bc[a] = (F[a] >> (mL - l)) >> lbs;
     const double scale = 1.0 / (double)(1 << l);
-    double t_exit = __builtin_huge_val();
+    double t_exit = __builtin_huge_val(), te[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       const double hl = g.h[a] * scale;
+      te[a] = __builtin_huge_val();
       if (d[a] > 0.0)
-        t_exit = fmin(t_exit, (g.lo[a] + (double)((bc[a] + 1) * bs) * hl - o[a]) * inv_d[a]);
+        te[a] = (g.lo[a] + (double)((bc[a] + 1) * bs) * hl - o[a]) * inv_d[a];
       else if (d[a] < 0.0)
-        t_exit = fmin(t_exit, (g.lo[a] + (double)(bc[a] * bs) * hl - o[a]) * inv_d[a]);
+        te[a] = (g.lo[a] + (double)(bc[a] * bs) * hl - o[a]) * inv_d[a];
+      t_exit = fmin(t_exit, te[a]);
     }
     const double t_end = fmin(t_exit, tb);
-    if (!(t_end > t)) {  // entered at its exit: step over the corner
+    if (!(t_end > t)) {  // entered at its exit (rounding): step over the corner
       t = nextafter(t, __builtin_huge_val());
+#pragma unroll
+      for (int a = 0; a < 3; ++a) F[a] = fine_at(g, o, d, a, t, true);
       continue;
+    }
+    // the next block's cell: across each face the ray leaves by, the first
+    // cell past the face (not the rounded position at t_end, which can fall
+    // back into this block and cost one step of one ulp per retry when the
+    // ray nearly grazes the face); along the other axes the cell at t_end
+    int Fn[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      if (te[a] <= t_end)  // finite: d[a] != 0, and t_end = t_exit < tb or equal
+        Fn[a] = d[a] > 0.0 ? ((bc[a] + 1) * bs) << (mL - l) : ((bc[a] * bs) << (mL - l)) - 1;
+      else
+        Fn[a] = fine_at(g, o, d, a, t_end, true);
+      Fn[a] = min(max(Fn[a], 0), g.nf[a] - 1);
     }
     // cells of the block between t and t_end, and the DDA constants
     int c[3], st[3], nvis = 1;
@@ -507,6 +525,8 @@ __device__ void march_amr_interval(const Geo& g, const Fld& f, const double o[3]
     nvis_total += nvis;
     lmax = max(lmax, l);
     t = t_end;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) F[a] = Fn[a];
   }
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
