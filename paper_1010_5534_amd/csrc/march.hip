@@ -425,8 +425,8 @@ __device__ __forceinline__ int leaf_of(const Geo& g, int fx, int fy, int fz, int
 // table), walk its cells at its level's spacing up to the block exit, and
 // continue from there.  Crossing parameters restart at every block entry.
 // At most g.max_blocks blocks are visited, so every lane terminates; the
-// block after an exit is the one across the face the ray leaves by; a block
-// entered exactly at its exit (a rounding corner) is stepped over by one ulp.
+// block after an exit is the one across the face the ray leaves by (also
+// for a block entered, by rounding, at or past its exit).
 template <int NB, int FK, bool RANGE, bool BF>
 __device__ void march_amr_interval(const Geo& g, const Fld& f, const double o[3], const double d[3],
                                    const double inv_d[3], double ta, double tb, Seg<NB>& r) {
@@ -470,24 +470,26 @@ __device__ void march_amr_interval(const Geo& g, const Fld& f, const double o[3]
       t_exit = fmin(t_exit, te[a]);
     }
     const double t_end = fmin(t_exit, tb);
-    if (!(t_end > t)) {  // entered at its exit (rounding): step over the corner
-      t = nextafter(t, __builtin_huge_val());
-#pragma unroll
-      for (int a = 0; a < 3; ++a) F[a] = fine_at(g, o, d, a, t, true);
-      continue;
-    }
     // the next block's cell: across each face the ray leaves by, the first
-    // cell past the face (not the rounded position at t_end, which can fall
-    // back into this block and cost one step of one ulp per retry when the
-    // ray nearly grazes the face); along the other axes the cell at t_end
+    // cell past the face (not the rounded position at the exit, which can
+    // fall back into this block, and for a ray that nearly grazes the face
+    // would take many one-ulp retries); along the other axes the cell at the
+    // exit.  A block entered at (by rounding, past) its exit is left at once
+    // across the faces already passed.
+    const bool passed = !(t_end > t);
     int Fn[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      if (te[a] <= t_end)  // finite: d[a] != 0, and t_end = t_exit < tb or equal
+      if (te[a] <= t_end)  // finite: d[a] != 0 and the ray leaves by this face at t_end
         Fn[a] = d[a] > 0.0 ? ((bc[a] + 1) * bs) << (mL - l) : ((bc[a] * bs) << (mL - l)) - 1;
       else
-        Fn[a] = fine_at(g, o, d, a, t_end, true);
+        Fn[a] = passed ? F[a] : fine_at(g, o, d, a, t_end, true);
       Fn[a] = min(max(Fn[a], 0), g.nf[a] - 1);
+    }
+    if (passed) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) F[a] = Fn[a];
+      continue;
     }
     // cells of the block between t and t_end, and the DDA constants
     int c[3], st[3], nvis = 1;
