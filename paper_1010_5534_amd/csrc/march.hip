@@ -300,31 +300,58 @@ __device__ __forceinline__ int cells_between(const Geo& g, const double o[3], co
 // integrate batch n.  The next batch is issued unconditionally (past the
 // last cell the walk stays on it), so every iteration has the same loads in
 // flight and the waits count only the older batch.
-#define AIR_MARCH_CELLS()                                                 \
+#define AIR_MARCH_CELLS_WITH(DDA)                                         \
   {                                                                       \
     int offA[KB], offB[KB];                                               \
     float dsA[KB], dsB[KB];                                               \
     Raw<FK> rawA[KB], rawB[KB];                                           \
-    AIR_DDA_BATCH(0, offA, dsA, rawA)                                     \
+    DDA(0, offA, dsA, rawA)                                               \
     for (int v0 = 0;;) {                                                  \
-      AIR_DDA_BATCH(v0 + KB, offB, dsB, rawB)                             \
+      DDA(v0 + KB, offB, dsB, rawB)                                       \
       AIR_INTEGRATE(v0, dsA, rawA)                                        \
       v0 += KB;                                                           \
       if (v0 >= nvis) break;                                              \
-      AIR_DDA_BATCH(v0 + KB, offA, dsA, rawA)                             \
+      DDA(v0 + KB, offA, dsA, rawA)                                       \
       AIR_INTEGRATE(v0, dsB, rawB)                                        \
       v0 += KB;                                                           \
       if (v0 >= nvis) break;                                              \
-      AIR_DDA_BATCH(v0 + KB, offB, dsB, rawB)                             \
+      DDA(v0 + KB, offB, dsB, rawB)                                       \
       AIR_INTEGRATE(v0, dsA, rawA)                                        \
       v0 += KB;                                                           \
       if (v0 >= nvis) break;                                              \
-      AIR_DDA_BATCH(v0 + KB, offA, dsA, rawA)                             \
+      DDA(v0 + KB, offA, dsA, rawA)                                       \
       AIR_INTEGRATE(v0, dsB, rawB)                                        \
       v0 += KB;                                                           \
       if (v0 >= nvis) break;                                              \
     }                                                                     \
   }
+#define AIR_MARCH_CELLS() AIR_MARCH_CELLS_WITH(AIR_DDA_BATCH)
+
+// The walk of a ray that moves along one axis only (the other two direction
+// components zero, the axis the same for the whole wave): the general walk's
+// minimum of the three crossings is then always this axis's, so the same
+// crossings, lengths and cells come from one axis update per step, with the
+// record index updated along that axis (bitwise the same values).  Expects
+// in scope tA, kA, DA, TA0 (the axis's crossing state and constants), cA, sA,
+// nA (its cell, step and clamp bound), ibase, istr, ibit (the record index
+// without this axis's part, the brick stride and bit position along it) and
+// the general walk's idx, tc, S1, nvis.
+#define AIR_DDA_BATCH1(V0, OFF, DS, RAW)                                  \
+  _Pragma("unroll") for (int q = 0; q < KB; ++q) {                        \
+    OFF[q] = idx;                                                         \
+    const bool last = (V0) + q >= nvis - 1;                               \
+    const float tn = last ? S1 : tA;                                      \
+    DS[q] = tn - tc;                                                      \
+    tc = tn;                                                              \
+    if (!last) {                                                          \
+      kA += 1.0f;                                                         \
+      tA = __builtin_fmaf(kA, DA, TA0);                                   \
+      cA = min(max(cA + sA, 0), nA - 1);                                  \
+      idx = ibase + (cA >> 1) * istr + ((cA & 1) << ibit);                \
+    }                                                                     \
+  }                                                                       \
+  _Pragma("unroll") for (int q = 0; q < KB; ++q) RAW[q] = load_raw<FK>(R, OFF[q]); \
+  __builtin_amdgcn_sched_barrier(0);
 
 // March the sub-interval [ta, tb] of the ray x(t) = o + t d (d unit) through
 // the uniform grid: DDA from the cell just after ta to the cell just before
@@ -336,7 +363,7 @@ __device__ __forceinline__ int cells_between(const Geo& g, const double o[3], co
 // freshly rounded values.
 // BF: branch-free cell walk (rays of a wave step different axes: coarse
 // levels) or one uniform branch per step (coherent rays); same arithmetic
-template <int NB, int FK, bool RANGE, bool BF>
+template <int NB, int FK, bool RANGE, bool BF, bool AX1 = true>
 __device__ void march_interval(const Geo& g, const Fld& f, const double o[3], const double d[3],
                                const double inv_d[3], double ta, double tb, Seg<NB>& r) {
   int c[3], st[3], nvis = 1;
@@ -376,7 +403,26 @@ __device__ void march_interval(const Geo& g, const Fld& f, const double o[3], co
   float tc = 0.0f;
 #define AIR_CELL_INDEX() brick_index(cx, cy, cz, bnx, bny)
   int idx = AIR_CELL_INDEX();
-  AIR_MARCH_CELLS()
+  // rays along one axis, the same for every lane of the wave: one axis update per step
+  const int nz_axes = (d[0] != 0.0) + (d[1] != 0.0) + (d[2] != 0.0);
+  const int ax = d[0] != 0.0 ? 0 : (d[1] != 0.0 ? 1 : 2);
+  const int ax0 = __builtin_amdgcn_readfirstlane(ax);
+  if (AX1 && __all(nz_axes == 1 && ax == ax0)) {
+    float tA, DA, TA0, kA = 0.0f;
+    int cA, sA, nA, istr;
+    if (ax0 == 0) {
+      tA = t0, DA = D0, TA0 = T00, cA = cx, sA = s0, nA = nx, istr = 8;
+    } else if (ax0 == 1) {
+      tA = t1, DA = D1, TA0 = T01, cA = cy, sA = s1, nA = ny, istr = 8 * bnx;
+    } else {
+      tA = t2, DA = D2, TA0 = T02, cA = cz, sA = s2, nA = nz, istr = 8 * bnx * bny;
+    }
+    const int ibit = ax0;
+    const int ibase = idx - ((cA >> 1) * istr + ((cA & 1) << ibit));
+    AIR_MARCH_CELLS_WITH(AIR_DDA_BATCH1)
+  } else {
+    AIR_MARCH_CELLS()
+  }
 #undef AIR_CELL_INDEX
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
@@ -575,7 +621,7 @@ struct TileLds {
 // of pixel (i, j)'s ray at level L (S a power of two: k/S is exact, so the
 // split depends only on the ray and S, fixed per grid).  Returns whether the
 // ray meets the grid; nvis = its uniform-grid cell count when k == 0.
-template <int NB, int FK, int GK, bool RANGE, bool BF>
+template <int NB, int FK, int GK, bool RANGE, bool BF, bool AX1 = true>
 __device__ __forceinline__ bool march_lane(const MarchArgs& A, bool live, uint32_t v, int L, uint32_t i, uint32_t j,
                                            int k, int sh, Seg<NB>& sg, int& nvis) {
   const int S = 1 << sh;
@@ -599,7 +645,7 @@ __device__ __forceinline__ bool march_lane(const MarchArgs& A, bool live, uint32
       const double ta = k == 0 ? t0 : t0 + len * ((double)k * inv_s);
       const double tb = k == S - 1 ? t1 : t0 + len * ((double)(k + 1) * inv_s);
       if constexpr (GK == AIR_GRID_UNIFORM)
-        march_interval<NB, FK, RANGE, BF>(A.g, A.f, o, V.d, V.inv_d, ta, tb, sg);
+        march_interval<NB, FK, RANGE, BF, AX1>(A.g, A.f, o, V.d, V.inv_d, ta, tb, sg);
       else
         march_amr_interval<NB, FK, RANGE, BF>(A.g, A.f, o, V.d, V.inv_d, ta, tb, sg);
     }
@@ -616,13 +662,13 @@ __device__ __forceinline__ bool march_lane(const MarchArgs& A, bool live, uint32
 // which is exact for piecewise-constant cells; a ray's result does not
 // depend on which block or kernel traced it.  Every thread of the block
 // calls this; the result is valid in wave 0.
-template <int NB, int FK, int GK, bool RANGE, bool BF>
+template <int NB, int FK, int GK, bool RANGE, bool BF, bool AX1 = true>
 __device__ __forceinline__ void trace_tile(const MarchArgs& A, TileLds<NB>& T, bool live, uint32_t v, int L,
                                            uint32_t i, uint32_t j, int sh, RayRes<NB>& r) {
   const int S = 1 << sh, lane = threadIdx.x & (WAVE - 1), k = threadIdx.x / WAVE;
   Seg<NB> sg;
   int nvis;
-  const bool hit = march_lane<NB, FK, GK, RANGE, BF>(A, live, v, L, i, j, k, sh, sg, nvis);
+  const bool hit = march_lane<NB, FK, GK, RANGE, BF, AX1>(A, live, v, L, i, j, k, sh, sg, nvis);
   __syncthreads();  // the previous tile's fold has read the staging area
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
@@ -1143,7 +1189,9 @@ __global__ __launch_bounds__(64 * MAX_SEG) void k_march_fixed(MarchArgs A, int L
       coords_of(key, L, A.img.N0, i, j);
     }
     RayRes<NB> r;
-    trace_tile<NB, FK, GK, false, false>(A, T, live, v, L, i, j, sh, r);
+    // the fixed image keeps the one general walk (its register budget holds
+    // four waves per SIMD only without the single-axis copy)
+    trace_tile<NB, FK, GK, false, false, false>(A, T, live, v, L, i, j, sh, r);
     if (threadIdx.x < WAVE && live) {
       if (images) {
         float* img = images + (int64_t)v * (A.f.nb + 1) * R2 + (int64_t)j * R + i;
