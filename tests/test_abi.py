@@ -103,6 +103,23 @@ def test_packed_bytes_without_device():
     g.n[:] = [5, 8, 3]
     f.n_bands = 9
     assert air.lib().air_field_packed_bytes(C.addressof(g), C.addressof(f)) == air.AIR_EINVAL
+    # block AMR: 2^3 base blocks of 4^3 cells and 8 children (16 blocks, 1024
+    # cells of 16 B), then the leaf map of the 4^3 finest block lattice
+    # (4 B each) at the next multiple of 256 bytes; no map for a lattice
+    # above 2^26 positions
+    a = air.air_grid()
+    a.kind, a.bs, a.max_level, a.n_blocks = 1, 4, 1, 16
+    a.n[:] = [2, 2, 2]
+    a.hi[:] = [1.0, 1.0, 1.0]
+    a.block_level, a.block_coord, a.block_child = 16, 16, 16  # non-NULL, never dereferenced
+    f.n_bands = 1
+    assert air.lib().air_field_packed_bytes(C.addressof(a), C.addressof(f)) == 1024 * 16 + 64 * 4
+    f.n_bands = 2  # (rho, T): 8 B per cell
+    assert air.lib().air_field_packed_bytes(C.addressof(a), C.addressof(f)) == 1024 * 8 + 64 * 4
+    a.n_blocks, a.bs = 9, 2  # 9 * 8 * 8 = 576 bytes of records: the map at 768
+    assert air.lib().air_field_packed_bytes(C.addressof(a), C.addressof(f)) == 768 + 64 * 4
+    a.n_blocks, a.max_level, a.bs = 16, 8, 2  # (2 << 8)^3 = 2^27 lattice positions: no map
+    assert air.lib().air_field_packed_bytes(C.addressof(a), C.addressof(f)) == 16 * 8 * 8
 
 
 def test_null_context_is_rejected_without_device_work():
