@@ -106,6 +106,21 @@ def test_uniform_as_amr_matches_uniform(ctx):
     assert parity.rel_err(a[1], b[1]).max() <= 2e-5
 
 
+@pytest.mark.parametrize("direction", [(0.8, 1e-6, 0.6), (1e-7, 0.6, -0.8), (0.5, -0.5, 3e-5)])
+def test_amr_grazing_rays_match_oracle(ctx, amr_small, direction):
+    """Rays nearly parallel to block faces: a block is left across the face
+    the ray exits by, so the walk neither stalls nor skips cells where the
+    rounded exit position falls back into the block just left."""
+    g, f, scene = amr_small
+    v = inputs.view_for(direction)
+    say(f"fixed amr_winds 64/8 L2 grazing dir={direction} N0=16 L=3")
+    img, flux, st = ctx.render_fixed(scene, [v], 16, 3)
+    ref = oracle.render_fixed(g, f, v, 16, 3)
+    gi = img[0].cpu().numpy().astype(np.float64)
+    assert parity.rel_err(gi[0], ref["I"][0]).max() <= 1e-5
+    assert parity.rel_err(gi[1], ref["N"]).max() <= 1e-5
+
+
 def test_amr_trace_pixels_matches_oracle(ctx, amr_small):
     g, f, scene = amr_small
     v = inputs.view_for((0.2, 0.9, -0.4))
