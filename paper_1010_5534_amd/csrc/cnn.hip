@@ -503,7 +503,9 @@ int conv_blocks(int n, int h, int w) {
 // not depend on IT.  The last layer's logits go through LDS to the depth
 // choice, one thread per pixel.  IT = 16 for large maps; 8 when the 16x16
 // tiles would not give every compute unit a block (the four layers of a
-// tile run one after another, so small tiles shorten the launch).
+// tile run one after another, so small tiles shorten the launch); 4 when
+// even the 8x8 tiles would fill under a quarter of the compute units (one
+// 32x32 map), though their halos are recomputed about 9 times.
 template <int IT, int CS, int RW>
 __device__ __forceinline__ void fused_layer(const uint16_t* __restrict__ wmat, const float* __restrict__ bias,
                                             int nbias, const uint16_t* in, int rin, uint16_t* out, float* zout,
@@ -738,9 +740,13 @@ hipError_t infer_depth(const Net& net, const uint16_t* x, int n, int h, int w, i
   if (tiles16 >= 256) {
     hipLaunchKernelGGL(k_infer<16>, dim3(tiles16), dim3(256), 0, s, P, net.theta, x, h, w, dmax, c_ray, c_sweep, depth,
                        spec_off, spec_total);
-  } else {
+  } else if (((w + 7) / 8) * ((h + 7) / 8) * n >= 64) {
     const int tiles8 = ((w + 7) / 8) * ((h + 7) / 8) * n;
     hipLaunchKernelGGL(k_infer<8>, dim3(tiles8), dim3(256), 0, s, P, net.theta, x, h, w, dmax, c_ray, c_sweep, depth,
+                       spec_off, spec_total);
+  } else {
+    const int tiles4 = ((w + 3) / 4) * ((h + 3) / 4) * n;
+    hipLaunchKernelGGL(k_infer<4>, dim3(tiles4), dim3(256), 0, s, P, net.theta, x, h, w, dmax, c_ray, c_sweep, depth,
                        spec_off, spec_total);
   }
   return hipGetLastError();
