@@ -293,11 +293,13 @@ def test_learned_equals_plain_bitwise(ctx, c_ray, c_sweep):
     net.close()
 
 
-@pytest.mark.parametrize("n0,nviews", [(16, 3), (64, 16)])
+@pytest.mark.parametrize("n0,nviews", [(16, 3), (32, 8), (64, 16)])
 def test_fused_inference_tile_sizes(ctx, n0, nviews):
-    """The fused inference runs 8x8 tiles on small maps (3 views of 16^2)
-    and 16x16 tiles on large ones (16 views of 64^2: 256 tiles): the chosen
-    depths follow the reference decision on the layer-by-layer logits."""
+    """The fused inference runs 4x4 tiles on the smallest launches (3 views
+    of 16^2: 12 tiles of 8x8), 8x8 tiles on small ones (8 views of 32^2: 128)
+    and 16x16 tiles on large ones (16 views of 64^2: 256 tiles of 16x16):
+    the chosen depths follow the reference decision on the layer-by-layer
+    logits."""
     from paper_1010_5534_amd import air
     g, f = inputs.winds2(seed=6, n=64)
     scene = ctx.prepare(air.upload(g, f))
