@@ -431,7 +431,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the adaptive render of one scene runs on one device; "
-              "multi-GPU sharding is described in DESIGN.md and not run here", file=sys.stderr)
+              "sharding over several GPUs is not built here", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

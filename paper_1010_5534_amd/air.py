@@ -90,7 +90,7 @@ def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
-            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with python paper_1010_5534_amd/build.py")
         L = C.CDLL(LIB_PATH)
         vp = C.c_void_p
         L.air_create.argtypes = [C.POINTER(vp), C.c_int32]

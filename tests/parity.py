@@ -246,11 +246,11 @@ def summary(rep):
 
 
 def _record(rep):
-    """Append the report to gpurun_out/parity_flips.jsonl when that folder
-    exists (GPU runs), so listed flips can be collected after the run."""
-    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-    d = os.path.join(root, "gpurun_out")
-    if not os.path.isdir(d):
+    """Append the report to parity_flips.jsonl in the folder that the
+    AIR_PARITY_LOG environment variable names, when it is set, so listed
+    flips can be collected after a run (the test output prints them too)."""
+    d = os.environ.get("AIR_PARITY_LOG")
+    if not d or not os.path.isdir(d):
         return
     rec = {k: v for k, v in rep.items()}
     with open(os.path.join(d, "parity_flips.jsonl"), "a") as fh:
