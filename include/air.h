@@ -45,7 +45,7 @@ typedef int32_t air_status;
 #define AIR_ENOMEM (-2)    /* device allocation failed */
 #define AIR_EDEVICE (-3)   /* a HIP call failed; air_last_error() has its text */
 #define AIR_ECAPACITY (-4) /* an output buffer is too small: tree->n_nodes holds the size needed */
-#define AIR_ENOTSUP (-5)   /* combination not supported by this build */
+#define AIR_ENOTSUP (-5)   /* combination the library does not support */
 
 #define AIR_MAX_LEVELS 12 /* image levels 0..11 */
 #define AIR_MAX_BANDS 8
