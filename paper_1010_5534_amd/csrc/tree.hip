@@ -23,6 +23,14 @@ __device__ __forceinline__ uint32_t state_or(uint8_t* state, int64_t p, uint32_t
   uint32_t old = atomicOr(reinterpret_cast<uint32_t*>(state + (p - (p & 3))), bits << sh);
   return (old >> sh) & 0xffu;
 }
+// state_or where on is true; elsewhere an OR of nothing (p must still be a
+// valid position) that returns `bits`, as if already set.  Issued without a
+// branch, so several claims can be in flight together.
+__device__ __forceinline__ uint32_t state_or_if(uint8_t* state, int64_t p, bool on, uint32_t bits) {
+  const uint32_t sh = 8u * (uint32_t)(p & 3);
+  const uint32_t old = atomicOr(reinterpret_cast<uint32_t*>(state + (p - (p & 3))), on ? bits << sh : 0u);
+  return on ? (old >> sh) & 0xffu : bits;
+}
 
 // Eq. 3 on a 3x3 stencil p[(b+1)*3 + (a+1)], a along u, b along v:
 // squared second differences (the mixed one for both orderings) over the
@@ -154,9 +162,10 @@ __global__ __launch_bounds__(RB) void k_refine(MarchArgs A, int L, float xcI, fl
         const uint32_t k0 = okx ? key_of((uint32_t)ai, (uint32_t)pj, l - 1, N0) : 0u;
         const uint32_t k1 = oky ? key_of((uint32_t)pi, (uint32_t)aj, l - 1, N0) : 0u;
         const uint32_t k2 = okx && oky ? key_of((uint32_t)ai, (uint32_t)aj, l - 1, N0) : 0u;
-        const uint32_t o0 = okx ? state_or(A.w.state, lb + k0, AIR_NODE_REFINED) : AIR_NODE_REFINED;
-        const uint32_t o1 = oky ? state_or(A.w.state, lb + k1, AIR_NODE_REFINED) : AIR_NODE_REFINED;
-        const uint32_t o2 = okx && oky ? state_or(A.w.state, lb + k2, AIR_NODE_REFINED) : AIR_NODE_REFINED;
+        // a neighbour off the image claims nothing (at key 0, a valid position)
+        const uint32_t o0 = state_or_if(A.w.state, lb + k0, okx, AIR_NODE_REFINED);
+        const uint32_t o1 = state_or_if(A.w.state, lb + k1, oky, AIR_NODE_REFINED);
+        const uint32_t o2 = state_or_if(A.w.state, lb + k2, okx && oky, AIR_NODE_REFINED);
         if (!(o0 & AIR_NODE_REFINED)) {
           stk_key[sp][tid] = k0;
           stk_lev[sp][tid] = (uint8_t)(l - 1);
