@@ -77,6 +77,11 @@ __global__ __launch_bounds__(RB) void k_refine(MarchArgs A, int L, float xcI, fl
   __shared__ uint8_t bal_lev[BALQ][RB];
   __shared__ unsigned wcnt[RB / WAVE];
   __shared__ unsigned long long bbase;
+  // level offsets for the closure, whose levels differ per thread (read
+  // from the kernel arguments that would be one memory round trip each)
+  __shared__ int64_t s_off[MAXL + 1];
+  if (threadIdx.x <= MAXL) s_off[threadIdx.x] = A.img.off[threadIdx.x];
+  __syncthreads();
   unsigned long long* ctr = A.w.ctr;
   const unsigned long long qs = ctr[CTR_LSTART + L], qe = ctr[CTR_LSTART + L + 1];
   const int N0 = A.img.N0, nb = A.f.nb;
@@ -158,7 +163,7 @@ __global__ __launch_bounds__(RB) void k_refine(MarchArgs A, int L, float xcI, fl
         const int ai = pi + ((ni & 1) ? 1 : -1), aj = pj + ((nj & 1) ? 1 : -1);
         const int R1 = N0 << (l - 1);
         const bool okx = ai >= 0 && ai < R1, oky = aj >= 0 && aj < R1;
-        const int64_t lb = vb + A.img.off[l - 1];
+        const int64_t lb = vb + s_off[l - 1];
         const uint32_t k0 = okx ? key_of((uint32_t)ai, (uint32_t)pj, l - 1, N0) : 0u;
         const uint32_t k1 = oky ? key_of((uint32_t)pi, (uint32_t)aj, l - 1, N0) : 0u;
         const uint32_t k2 = okx && oky ? key_of((uint32_t)ai, (uint32_t)aj, l - 1, N0) : 0u;
@@ -192,7 +197,7 @@ __global__ __launch_bounds__(RB) void k_refine(MarchArgs A, int L, float xcI, fl
           coords_of(kq, l, N0, qi, qj);
           around(l, qi, qj);
         }
-        atomicOr(reinterpret_cast<uint32_t*>(A.w.state + vb + A.img.off[l + 1] + 4ll * kq),
+        atomicOr(reinterpret_cast<uint32_t*>(A.w.state + vb + s_off[l + 1] + 4ll * kq),
                  0x01010101u * (AIR_NODE_EXIST | AIR_NODE_BALANCE));
         if (nbal < BALQ) {
           bal_key[nbal][tid] = kq;
