@@ -523,18 +523,29 @@ __global__ __launch_bounds__(256) void k_count(MarchArgs A, unsigned long long* 
   if (flux_partial) {  // uniform
     const int64_t VS = (int64_t)A.img.V * A.img.S;
     const double px = A.views[cp.v].width / (double)((int64_t)A.img.N0 << cp.L), area = px * px;
-    double f[MAXB];
-#pragma unroll
-    for (int b = 0; b < MAXB; ++b) f[b] = 0.0;
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    unsigned leaves = 0;  // bit k: position p0 + k is a leaf
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
       const uint8_t st = byte_of(q4, k);
-      if ((st & AIR_NODE_EXIST) && !(st & AIR_NODE_REFINED))
-        for (int b = 0; b < nb; ++b) f[b] += area * (double)A.w.valI[b * VS + p0 + k];
+      leaves |= ((st & AIR_NODE_EXIST) && !(st & AIR_NODE_REFINED)) ? 1u << k : 0u;
     }
     for (int b = 0; b < nb; ++b) {
-      const double x = wave_sum_f64(f[b]);
-      if ((threadIdx.x & (WAVE - 1)) == 0) shf[b][w] = x;
+      // a thread with leaves reads its 16 values in four 16-byte loads issued
+      // together (every position of the chunk lies inside the maps), then
+      // adds its leaves in position order
+      f4 x[PPT / 4];
+      if (leaves) {
+        const f4* src = reinterpret_cast<const f4*>(A.w.valI + b * VS + p0);
+#pragma unroll
+        for (int u = 0; u < PPT / 4; ++u) x[u] = src[u];
+      }
+      double f = 0.0;
+#pragma unroll
+      for (int k = 0; k < PPT; ++k)
+        if (leaves & (1u << k)) f += area * (double)x[k >> 2][k & 3];
+      const double t = wave_sum_f64(f);
+      if ((threadIdx.x & (WAVE - 1)) == 0) shf[b][w] = t;
     }
   }
   __syncthreads();
