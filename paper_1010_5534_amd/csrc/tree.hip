@@ -704,9 +704,14 @@ __global__ __launch_bounds__(256) void k_emit(MarchArgs A, const unsigned long l
 __global__ __launch_bounds__(256) void k_write_tree(MarchArgs A, const unsigned long long* chunk_off, int64_t n_chunks,
                                                     const int32_t* id_map, const uint64_t* node_pos,
                                                     const TreeOut* outs) {
+  // level offsets for per-thread levels (a kernel-argument read with a
+  // per-thread index is a memory round trip)
+  __shared__ int64_t s_off[MAXL + 1];
+  if (threadIdx.x <= MAXL) s_off[threadIdx.x] = A.img.off[threadIdx.x];
+  __syncthreads();
   const unsigned long long total = chunk_off[n_chunks];
   const int64_t S = A.img.S, VS = (int64_t)A.img.V * S, cpv = S / CHUNK;
-  const int N0 = A.img.N0, nb = A.f.nb;
+  const int N0 = A.img.N0, nb = A.f.nb, Lm = A.img.Lmax;
   for (unsigned long long g = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x; g < total;
        g += (unsigned long long)gridDim.x * blockDim.x) {
     const int64_t p = (int64_t)node_pos[g];
@@ -714,33 +719,42 @@ __global__ __launch_bounds__(256) void k_write_tree(MarchArgs A, const unsigned 
     const int64_t local = p - (int64_t)v * S;
     const int L = level_of(A.img, local);
     const uint32_t key = (uint32_t)(local - A.img.off[L]);
-    const TreeOut& T = outs[v];
+    // Everything this node writes is read first, in one round: the output
+    // table entry and the node's values.  (The compiler cannot tell that
+    // the outputs alias none of them, so a read placed after a store would
+    // wait for the store's turn.)
+    const TreeOut T = outs[v];
     const int64_t base = (int64_t)chunk_off[v * cpv];
-    const int64_t id = (int64_t)g - base;
-    if (id >= T.capacity) continue;
     const int64_t vb = (int64_t)v * S;
     const uint8_t s = A.w.state[p];
+    const int32_t par = L > 0 ? id_map[vb + s_off[L > 0 ? L - 1 : 0] + (key >> 2)] : 0;
+    const int32_t fch = L < Lm ? id_map[vb + s_off[L < Lm ? L + 1 : L] + 4ll * key] : 0;
+    float vI[MAXB];
+#pragma unroll
+    for (int b = 0; b < MAXB; ++b) vI[b] = b < nb ? A.w.valI[b * VS + p] : 0.0f;
+    const float vN = A.w.valN[p], xI = A.w.xiI[p], xN = A.w.xiN[p];
+    const int32_t vis = A.w.visits[p];
+    const int64_t id = (int64_t)g - base;
+    if (id >= T.capacity) continue;
     uint32_t i, j;
     coords_of(key, L, N0, i, j);
     // write-once outputs: streaming stores
     if (T.level) __builtin_nontemporal_store((int8_t)L, T.level + id);
     if (T.ix) __builtin_nontemporal_store((int32_t)i, T.ix + id);
     if (T.iy) __builtin_nontemporal_store((int32_t)j, T.iy + id);
-    if (T.parent)
-      __builtin_nontemporal_store(L == 0 ? -1 : (int32_t)(id_map[vb + A.img.off[L - 1] + (key >> 2)] - base),
-                                  T.parent + id);
+    if (T.parent) __builtin_nontemporal_store(L == 0 ? -1 : (int32_t)(par - base), T.parent + id);
     if (T.first_child)
-      __builtin_nontemporal_store(
-          (s & AIR_NODE_REFINED) ? (int32_t)(id_map[vb + A.img.off[L + 1] + 4ll * key] - base) : -1,
-          T.first_child + id);
+      __builtin_nontemporal_store((s & AIR_NODE_REFINED) ? (int32_t)(fch - base) : -1, T.first_child + id);
     if (T.state) __builtin_nontemporal_store((uint8_t)(s & (uint8_t)~(ST_TRACED | ST_SPEC)), T.state + id);
     if (T.I)
-      for (int b = 0; b < nb; ++b) __builtin_nontemporal_store(A.w.valI[b * VS + p], T.I + b * T.capacity + id);
-    if (T.N) __builtin_nontemporal_store(A.w.valN[p], T.N + id);
+#pragma unroll
+      for (int b = 0; b < MAXB; ++b)
+        if (b < nb) __builtin_nontemporal_store(vI[b], T.I + b * T.capacity + id);
+    if (T.N) __builtin_nontemporal_store(vN, T.N + id);
     const bool ev = (s & AIR_NODE_EVALUATED) != 0;
-    if (T.xi_I) __builtin_nontemporal_store(ev ? A.w.xiI[p] : __builtin_nanf(""), T.xi_I + id);
-    if (T.xi_N) __builtin_nontemporal_store(ev ? A.w.xiN[p] : __builtin_nanf(""), T.xi_N + id);
-    if (T.visits) __builtin_nontemporal_store(A.w.visits[p], T.visits + id);
+    if (T.xi_I) __builtin_nontemporal_store(ev ? xI : __builtin_nanf(""), T.xi_I + id);
+    if (T.xi_N) __builtin_nontemporal_store(ev ? xN : __builtin_nanf(""), T.xi_N + id);
+    if (T.visits) __builtin_nontemporal_store(vis, T.visits + id);
   }
 }
 
